@@ -1,0 +1,139 @@
+"""Seeded synthetic inputs shared by the FP64 oracle and the HIP library.
+
+This module draws random numbers and lays out input arrays.  It holds none of
+the method's arithmetic: no basis, no Hamiltonian, no FFT, no kernel.  Every
+consumer computes the plane-wave basis size itself and passes it in.
+
+The systems stand in for the paper's workloads (which need pseudopotentials,
+DFT ground states and PDEP bases that are not available): a periodic cell with
+attractive Gaussian sites replaces the crystal, and a random orthonormal
+G-space basis with prescribed eigenvalues replaces the PDEP eigenpotentials of
+the screened interaction W (Eq. 3).
+
+Draw order from one ``numpy.random.Generator(PCG64(seed))`` stream:
+site positions -> depths -> widths -> PDEP Gaussian matrix -> trial block.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = ["Config", "CONFIGS", "get_config", "make_system", "diamond_sites",
+           "honeycomb_sites"]
+
+
+@dataclasses.dataclass(frozen=True)
+class Config:
+    name: str
+    cell: tuple            # orthorhombic lengths (bohr)
+    grid: tuple            # FFT grid
+    ecut: float            # Ha, sphere |G|^2/2 <= ecut
+    n_val: int             # occupied orbitals N_v
+    n_pdep: int            # PDEP rank
+    lam_scale: float       # lambda_i = lam_scale * exp(-i / lam_decay), i = 0..n_pdep-1
+    lam_decay: float
+    sites: str             # "uniform:<n>", "diamond:<cells>", "honeycomb"
+    depth: tuple = (1.0, 3.0)   # U(lo, hi) Ha
+    width: tuple = (0.8, 1.5)   # U(lo, hi) bohr
+    seed: int = 0
+    n_states: int = 1      # excitons requested
+    n_block: int = 8       # trial vectors per apply block in throughput runs
+
+
+CONFIGS = {
+    # micro system for every dense check
+    "m0": Config("m0", (8.0, 8.0, 8.0), (12, 12, 12), 4.0, 4, 8, -0.8, 2.0,
+                 "uniform:3", seed=11),
+    # tiny plain FP64 system: 8 random Gaussian sites, N_v = 16, N_pdep = 64
+    "c1": Config("c1", (10.0, 10.0, 10.0), (24, 24, 24), 10.0, 16, 64, -0.8, 16.0,
+                 "uniform:8", seed=1000),
+    # defect supercell: 3x3x3 diamond cells (216 sites) with one removed
+    "c2": Config("c2", (20.2, 20.2, 20.2), (72, 72, 72), 14.2, 432, 512, -0.85, 96.0,
+                 "diamond:3", seed=2000, n_states=4, n_block=8),
+}
+
+
+def get_config(name: str) -> Config:
+    return CONFIGS[name]
+
+
+def diamond_sites(cells: int, a: float, drop_origin: bool = True) -> np.ndarray:
+    """Conventional diamond cells (8 sites each) tiled cells^3, optionally
+    without the site at the origin (the vacancy)."""
+    basis = np.array([[0, 0, 0], [0, .5, .5], [.5, 0, .5], [.5, .5, 0],
+                      [.25, .25, .25], [.25, .75, .75], [.75, .25, .75],
+                      [.75, .75, .25]])
+    pts = []
+    for i in range(cells):
+        for j in range(cells):
+            for k in range(cells):
+                for b in basis:
+                    pts.append((np.array([i, j, k]) + b) * a)
+    pts = np.array(pts)
+    if drop_origin:
+        keep = np.linalg.norm(pts, axis=1) > 1e-12
+        pts = pts[keep]
+    return pts
+
+
+def honeycomb_sites(nx: int, ny: int, nn: float, z: float) -> np.ndarray:
+    """Rectangular honeycomb layer: nx x ny rectangular cells of 4 sites."""
+    a = nn * math.sqrt(3.0)
+    bx, by = a, 3.0 * nn
+    base = np.array([[0, 0], [a / 2, nn / 2], [a / 2, 1.5 * nn], [0, 2 * nn]])
+    pts = []
+    for i in range(nx):
+        for j in range(ny):
+            for b in base:
+                pts.append([i * bx + b[0], j * by + b[1], z])
+    return np.array(pts)
+
+
+def make_system(cfg: Config | str, n_pw: int, *, seed: int | None = None,
+                n_trial: int = 0) -> dict:
+    """Draw one synthetic system.
+
+    n_pw     size of the plane-wave sphere, computed by the caller.
+    n_trial  number of random trial vectors [n_trial][n_val][n_pw] (N(0,1)).
+
+    Returns a dict of float64 arrays: cell, grid, ecut, site_xyz [n][3],
+    site_depth [n], site_width [n], lam [n_pdep], pdep [n_pw][n_pdep]
+    (orthonormal columns, row 0 -- the G = 0 coefficient -- zero), trial.
+    """
+    if isinstance(cfg, str):
+        cfg = get_config(cfg)
+    s = cfg.seed if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(s))
+    cell = np.array(cfg.cell, dtype=np.float64)
+    kind, _, arg = cfg.sites.partition(":")
+    if kind == "uniform":
+        n = int(arg)
+        xyz = rng.random((n, 3)) * cell
+    elif kind == "diamond":
+        cells = int(arg)
+        xyz = diamond_sites(cells, cell[0] / cells)
+    elif kind == "honeycomb":
+        xyz = honeycomb_sites(10, 5, 2.733, cell[2] / 2)
+    else:
+        raise ValueError(cfg.sites)
+    n_sites = xyz.shape[0]
+    depth = rng.uniform(cfg.depth[0], cfg.depth[1], n_sites)
+    width = rng.uniform(cfg.width[0], cfg.width[1], n_sites)
+    lam = cfg.lam_scale * np.exp(-np.arange(cfg.n_pdep) / cfg.lam_decay)
+    if cfg.n_pdep > n_pw - 1:
+        raise ValueError("n_pdep must be below n_pw - 1")
+    g = rng.standard_normal((n_pw, cfg.n_pdep))
+    g[0, :] = 0.0
+    q, r = np.linalg.qr(g)
+    q = q * np.sign(np.diag(r))[None, :]
+    q[0, :] = 0.0
+    out = dict(cell=cell, grid=np.array(cfg.grid, dtype=np.int32),
+               ecut=float(cfg.ecut), n_val=cfg.n_val,
+               site_xyz=np.ascontiguousarray(xyz, dtype=np.float64),
+               site_depth=depth, site_width=width, lam=lam,
+               pdep=np.ascontiguousarray(q), seed=s)
+    if n_trial:
+        out["trial"] = rng.standard_normal((n_trial, cfg.n_val, n_pw))
+    return out
