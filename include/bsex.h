@@ -1,0 +1,220 @@
+/*
+ * bsex.h -- C ABI of the MI355X (gfx950) library for plane-wave analytical
+ * excited-state forces from the Bethe-Salpeter equation (Tamm-Dancoff
+ * approximation, density-matrix perturbation theory, no empty states).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Return value: 0 (BSE_OK) or a positive bse_status code.  Nothing throws or
+ * aborts across the ABI; bse_last_error() returns a thread-local message for
+ * the last non-zero return of the calling thread.
+ *
+ * Basis: the real orthonormal plane-wave basis of the Gamma-point sphere
+ * S = {G : |G|^2/2 <= ecut} of an orthorhombic cell (lengths L, volume
+ * Omega): e_0 = Omega^-1/2, then for every G of the half sphere (first
+ * non-zero Miller index positive) c_G = sqrt(2/Omega) cos(G.r) followed by
+ * s_G = sqrt(2/Omega) sin(G.r).  The half sphere is ordered by
+ * (|n|^2, n1, n2, n3).  The FFT grid N1 x N2 x N3 must hold the sphere
+ * strictly (every |n_i| < N_i/2).  Inner products are plain dot products of
+ * coefficient vectors.  n_pw = 1 + 2 * (half-sphere size).
+ *
+ * Layout: row-major, plane-wave index fastest.  An orbital block is
+ * [n_val][n_pw]; a block of trial vectors is [n_b][n_val][n_pw].  All double.
+ *
+ * Pointers: arguments named *_dev are device pointers (hipMalloc or a torch
+ * CUDA tensor on the context's device); *_host are host pointers.  The
+ * caller owns every buffer it passes; the library copies host inputs during
+ * bse_init_system and never frees caller memory.  A context owns its device
+ * allocations until bse_free.
+ *
+ * Streams: every call is ordered on desc.stream and returns after its work
+ * on that stream has finished.  A context is not thread-safe.
+ *
+ * Units: Hartree and bohr.
+ */
+#ifndef BSEX_H
+#define BSEX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BSEX_ABI_VERSION 1
+
+typedef enum {
+  BSE_OK = 0,
+  BSE_EINVAL = 1,   /* bad argument, descriptor, shape or non-finite input     */
+  BSE_ENOMEM = 2,   /* device allocation failed or tau cache over its budget  */
+  BSE_EHIP = 3,     /* a HIP runtime call failed                             */
+  BSE_ENOCONV = 4,  /* iteration limit reached; outputs hold the last iterate */
+  BSE_EGAP = 5,     /* Kohn-Sham gap eps_{n_val+1} - eps_{n_val} below gap_min */
+  BSE_EABI = 6,     /* desc.abi_version differs from BSEX_ABI_VERSION          */
+  BSE_ESTATE = 7    /* call not valid in the context's current state          */
+} bse_status;
+
+/* which terms of M = D + s K1e - K1d the operator applies (test hook) */
+enum {
+  BSE_K_D = 1,         /* D: P_c (H - eps_v + scissor)                        */
+  BSE_K_1E = 2,        /* K1e: bare-Coulomb exchange-like term (Eq. 2b)         */
+  BSE_K_1D_BARE = 4,   /* K1d, bare v_c part of W                             */
+  BSE_K_1D_PDEP = 8,   /* K1d, low-rank PDEP part of W (Eq. 3)                 */
+  BSE_K_ALL = 15
+};
+
+enum { BSE_FP64 = 0 };                      /* precision of the operator apply  */
+enum { BSE_TAU_AUTO = 0, BSE_TAU_CACHE = 1, BSE_TAU_REBUILD = 2 };
+
+typedef struct bse_ctx bse_ctx;
+
+/*
+ * System description.  Defines the synthetic Kohn-Sham Hamiltonian
+ * H = |G|^2/2 + V(r), V a sum of Gaussian wells
+ *   V_I(r) = -depth_I exp(-|r - R_I|^2 / (2 width_I^2)),
+ * periodised in G space on every grid frequency with the Nyquist planes set
+ * to zero, and the screened interaction of Eq. 3,
+ *   W = v_c + v_c^1/2 [sum_a phi_a lambda_a/(1-lambda_a) phi_a^T] v_c^1/2,
+ * v_c(G) = 4 pi/|G|^2 on every grid frequency (minimum image), v_c(0) = 0.
+ */
+typedef struct {
+  int32_t abi_version;        /* BSEX_ABI_VERSION                                 */
+  double cell[3];             /* orthorhombic cell lengths (bohr), > 0            */
+  int32_t grid[3];            /* FFT grid; each a product of 2, 3 and 5, 4..512   */
+  double ecut;                /* Ha                                               */
+  int32_t n_sites;            /* >= 0                                             */
+  const double *site_xyz;     /* host [n_sites][3] bohr                          */
+  const double *site_depth;   /* host [n_sites] Ha                               */
+  const double *site_width;   /* host [n_sites] bohr, > 0                         */
+  int32_t n_val;              /* occupied orbitals N_v, 1 <= n_val < n_pw          */
+  int32_t n_pdep;             /* PDEP rank, 0 <= n_pdep < n_pw                     */
+  const double *pdep;         /* host [n_pw][n_pdep], orthonormal columns, row 0 zero */
+  const double *lambda;       /* host [n_pdep], each < 1                           */
+  double scissor;             /* Delta (Ha); shifts omega only                    */
+  double spin_factor;         /* s in D + s K1e - K1d; 2 for a singlet            */
+  int32_t precision;          /* BSE_FP64                                         */
+  int32_t tau_policy;         /* BSE_TAU_*: cache W(phi_v phi_v') or rebuild it   */
+  int64_t tau_budget_bytes;   /* device bytes allowed for the tau cache; 0 = auto */
+  double gap_min;             /* Ha; EGAP below it (<= 0 disables the check)      */
+  int32_t kernel_mask;        /* BSE_K_*; 0 means BSE_K_ALL                        */
+  int32_t n_orb;              /* orbitals supplied (>= n_val), or 0 to solve H    */
+  const double *orbitals;     /* host [n_orb][n_pw] orthonormal eigenvectors      */
+  const double *eps;          /* host [n_orb] eigenvalues, ascending              */
+  int32_t n_extra;            /* extra (conduction) states the solver computes    */
+  double gs_tol;              /* eigen-residual target of the solver (0: 1e-10)   */
+  void *stream;               /* hipStream_t, NULL for the null stream            */
+} bse_system_desc;
+
+/* Library ABI version (BSEX_ABI_VERSION of the build). */
+int32_t bse_abi_version(void);
+
+/* Thread-local message of the last failing call ("" when none). */
+const char *bse_last_error(void);
+
+/* Host-only basis queries (no device needed).  n_pw of the sphere; EINVAL if
+ * the sphere does not fit the grid. */
+int bse_basis_size(const double cell[3], const int32_t grid[3], double ecut,
+                   int32_t *n_pw);
+
+/* Miller indices [n_pw][3] and kind [n_pw] (0 = G0, 1 = cos, 2 = sin) of the
+ * basis functions in library order.  Either output may be NULL. */
+int bse_basis_gvectors(const double cell[3], const int32_t grid[3], double ecut,
+                       int32_t *miller_host, int8_t *kind_host);
+
+/* Build a context: copy inputs to the device, take or compute the occupied
+ * orbitals (lowest eigenpairs of H), check the Kohn-Sham gap, cache phi(r)
+ * and build (or plan) the pair potentials tau_{v'v} = W(phi_v' phi_v) of
+ * Eq. 2c.  On failure *out is NULL and nothing leaks. */
+int bse_init_system(const bse_system_desc *desc, bse_ctx **out);
+
+typedef struct {
+  int32_t n_pw, n_val, n_pdep, n_orb;
+  int32_t grid[3];
+  int32_t tau_policy;         /* policy in effect                                */
+  int64_t tau_blocks;         /* 8x8 pair blocks of the upper triangle            */
+  int64_t tau_blocks_cached;  /* blocks held in the cache                        */
+  int64_t tau_bytes;          /* bytes of the cache                              */
+  double gs_resid;            /* max eigen-residual of the supplied/solved orbitals */
+  double ks_gap;              /* eps_{n_val+1} - eps_{n_val} when known, else -1  */
+} bse_info;
+
+int bse_get_info(bse_ctx *ctx, bse_info *info);
+
+/* Copy the occupied orbitals [n_val][n_pw] (device) and eigenvalues [n_val]
+ * (host).  Either pointer may be NULL.  With orbitals solved by the library,
+ * extra conduction states are returned when n > n_val: orbitals_dev must
+ * then hold [n][n_pw] and eps_host [n], n <= n_orb. */
+int bse_get_orbitals(bse_ctx *ctx, int32_t n, double *orbitals_dev, double *eps_host);
+
+/* The operator of Eqs. 1-2 (scissor form of Table S-I):
+ *   Y = P_c (D + s K1e - K1d) P_c X   for n_b trial vectors
+ *   (D A)_v   = P_c (H - eps_v + scissor) a_v
+ *   (K1e A)_v = P_c (v_c * Drho) phi_v,     Drho = sum_v phi_v a_v
+ *   (K1d A)_v = P_c sum_v' tau_{v'v} a_v'
+ * X_dev, Y_dev: device [n_b][n_val][n_pw], must not overlap.  n_b >= 0
+ * (0 is a no-op).  The input is projected first, so the operator is
+ * symmetric on the whole space and maps occupied directions to zero. */
+int bse_apply(bse_ctx *ctx, int32_t n_b, const double *X_dev, double *Y_dev);
+
+typedef struct {
+  double tol;                 /* residual target; 0 -> 1e-8                        */
+  int32_t max_iter;           /* 0 -> 300 (Davidson) / 5000 (CG)                   */
+  int32_t block;              /* Davidson block; 0 -> n_states + 4                 */
+  int32_t max_subspace;       /* 0 -> 8 * block                                    */
+  const double *x0_dev;       /* optional initial guess, [k][n_val][n_pw]         */
+  int32_t n_x0;               /* vectors in x0_dev                                 */
+  const double *z0_dev;       /* optional Z-vector initial guess [n_val][n_pw]    */
+} bse_solver_opts;
+
+typedef struct {
+  int32_t iters;              /* iterations performed                             */
+  int32_t applies;            /* operator applications (vectors)                  */
+  double resid[16];           /* final residual norms (first 16 states)           */
+  double t_ms;                /* wall time of the call                            */
+} bse_solver_stats;
+
+/* Lowest n_states eigenpairs of P_c M P_c (Eq. 1) by block Davidson with a
+ * shifted kinetic preconditioner.  Residual ||M x - omega x||_2 with
+ * ||x||_2 = 1 must reach opts->tol for every requested state.
+ * omega_host [n_states]; X_dev [n_states][n_val][n_pw]; stats may be NULL.
+ * ENOCONV after max_iter with the last Ritz pairs in the outputs. */
+int bse_davidson(bse_ctx *ctx, int32_t n_states, const bse_solver_opts *opts,
+                 double *omega_host, double *X_dev, bse_solver_stats *stats);
+
+/* U vector of SM Sec. I for one normalised exciton A (Xs_dev [n_val][n_pw]):
+ *   u_v = P_c[ s (v_c*Drho) a_v - sum_v' W(a_v' a_v) phi_v' ] - sum_v' S_vv' a_v'
+ *   S_vv' = <phi_v | [(s K1e - K1d) A]_v'>   (kernel part before P_c).
+ * U_dev [n_val][n_pw]. */
+int bse_u_vector(bse_ctx *ctx, const double *Xs_dev, double *U_dev);
+
+/* Z-vector equation (Eq. 7) for the synthetic Hamiltonian, whose KS response
+ * kernels vanish:  P_c (H - eps_v) P_c Z_v = -u_v  for every band, by block
+ * PCG with per-band steps, until ||D Z + U||_F / ||U||_F <= opts->tol.
+ * Computes U from Xs_dev first.  Z_dev [n_val][n_pw]. */
+int bse_zvector_solve(bse_ctx *ctx, const double *Xs_dev, const bse_solver_opts *opts,
+                      double *Z_dev, bse_solver_stats *stats);
+
+/* d omega / d R of Eq. 4 with the densities of Eqs. 5-6:
+ *   dw/dR_{I,a} = Omega sum_G Re[ conj(-i G_a V_I(G)) rho_t(G) ],
+ *   rho_t = sum_v a_v^2 - sum_vv' phi_v phi_v' <a_v'|a_v> + 2 sum_v Z_v phi_v.
+ * dwdR_host [n_sites][3].  The excitation-energy force is -dwdR. */
+int bse_forces(bse_ctx *ctx, const double *Xs_dev, const double *Z_dev, double *dwdR_host);
+
+/* Per-phase device time of the calls since the last reset, measured with HIP
+ * events on the context's stream while enabled (off by default). */
+typedef struct {
+  int32_t n_phase;
+  const char *name[16];
+  double ms[16];
+  int64_t count[16];
+} bse_phase_times;
+
+int bse_set_profiling(bse_ctx *ctx, int32_t on);
+int bse_get_phase_times(bse_ctx *ctx, bse_phase_times *out, int32_t reset);
+
+int bse_free(bse_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSEX_H */

@@ -1,0 +1,312 @@
+"""Thin ctypes binding of libbsex.so (the C ABI declared in include/bsex.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device buffers are torch CUDA tensors (float64, contiguous) on the
+library's device; host arrays are numpy.  The library must be built
+(``python -m paper_2607_20728_amd.build`` or ``__graft_entry__.build()``);
+loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsex.so")
+
+ABI_VERSION = 1
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, EGAP, EABI, ESTATE = range(8)
+K_D, K_1E, K_1D_BARE, K_1D_PDEP, K_ALL = 1, 2, 4, 8, 15
+FP64 = 0
+TAU_AUTO, TAU_CACHE, TAU_REBUILD = 0, 1, 2
+
+SYMBOLS = ("bse_abi_version", "bse_last_error", "bse_basis_size", "bse_basis_gvectors",
+           "bse_init_system", "bse_get_info", "bse_get_orbitals", "bse_apply",
+           "bse_davidson", "bse_u_vector", "bse_zvector_solve", "bse_forces",
+           "bse_set_profiling", "bse_get_phase_times", "bse_free")
+
+
+class BseError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bsex error {code}: {msg}")
+        self.code = code
+
+
+class SystemDesc(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("cell", C.c_double * 3), ("grid", C.c_int32 * 3),
+                ("ecut", C.c_double), ("n_sites", C.c_int32),
+                ("site_xyz", C.POINTER(C.c_double)), ("site_depth", C.POINTER(C.c_double)),
+                ("site_width", C.POINTER(C.c_double)), ("n_val", C.c_int32),
+                ("n_pdep", C.c_int32), ("pdep", C.POINTER(C.c_double)),
+                ("lambda_", C.POINTER(C.c_double)), ("scissor", C.c_double),
+                ("spin_factor", C.c_double), ("precision", C.c_int32),
+                ("tau_policy", C.c_int32), ("tau_budget_bytes", C.c_int64),
+                ("gap_min", C.c_double), ("kernel_mask", C.c_int32), ("n_orb", C.c_int32),
+                ("orbitals", C.POINTER(C.c_double)), ("eps", C.POINTER(C.c_double)),
+                ("n_extra", C.c_int32), ("gs_tol", C.c_double), ("stream", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_pw", C.c_int32), ("n_val", C.c_int32), ("n_pdep", C.c_int32),
+                ("n_orb", C.c_int32), ("grid", C.c_int32 * 3), ("tau_policy", C.c_int32),
+                ("tau_blocks", C.c_int64), ("tau_blocks_cached", C.c_int64),
+                ("tau_bytes", C.c_int64), ("gs_resid", C.c_double), ("ks_gap", C.c_double)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("block", C.c_int32),
+                ("max_subspace", C.c_int32), ("x0_dev", C.c_void_p), ("n_x0", C.c_int32),
+                ("z0_dev", C.c_void_p)]
+
+
+class SolverStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("applies", C.c_int32), ("resid", C.c_double * 16),
+                ("t_ms", C.c_double)]
+
+
+class PhaseTimes(C.Structure):
+    _fields_ = [("n_phase", C.c_int32), ("name", C.c_char_p * 16), ("ms", C.c_double * 16),
+                ("count", C.c_int64 * 16)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libbsex.so once; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2607_20728_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    dp = C.POINTER(C.c_double)
+    L.bse_abi_version.restype = C.c_int32
+    L.bse_last_error.restype = C.c_char_p
+    L.bse_basis_size.argtypes = [dp, C.POINTER(C.c_int32), C.c_double, C.POINTER(C.c_int32)]
+    L.bse_basis_gvectors.argtypes = [dp, C.POINTER(C.c_int32), C.c_double,
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int8)]
+    L.bse_init_system.argtypes = [C.POINTER(SystemDesc), C.POINTER(C.c_void_p)]
+    L.bse_get_info.argtypes = [C.c_void_p, C.POINTER(Info)]
+    L.bse_get_orbitals.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, dp]
+    L.bse_apply.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+    L.bse_davidson.argtypes = [C.c_void_p, C.c_int32, C.POINTER(SolverOpts), dp, C.c_void_p,
+                               C.POINTER(SolverStats)]
+    L.bse_u_vector.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.bse_zvector_solve.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(SolverOpts), C.c_void_p,
+                                    C.POINTER(SolverStats)]
+    L.bse_forces.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp]
+    L.bse_set_profiling.argtypes = [C.c_void_p, C.c_int32]
+    L.bse_get_phase_times.argtypes = [C.c_void_p, C.POINTER(PhaseTimes), C.c_int32]
+    L.bse_free.argtypes = [C.c_void_p]
+    if L.bse_abi_version() != ABI_VERSION:
+        raise RuntimeError("libbsex ABI version mismatch")
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != OK:
+        raise BseError(rc, lib().bse_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dev(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+def basis_size(cell, grid, ecut):
+    c = _f64(cell)
+    g = np.ascontiguousarray(grid, dtype=np.int32)
+    n = C.c_int32()
+    _check(lib().bse_basis_size(_dptr(c), g.ctypes.data_as(C.POINTER(C.c_int32)), float(ecut),
+                                C.byref(n)))
+    return n.value
+
+
+def basis_gvectors(cell, grid, ecut):
+    n = basis_size(cell, grid, ecut)
+    c = _f64(cell)
+    g = np.ascontiguousarray(grid, dtype=np.int32)
+    mill = np.zeros((n, 3), dtype=np.int32)
+    kind = np.zeros(n, dtype=np.int8)
+    _check(lib().bse_basis_gvectors(_dptr(c), g.ctypes.data_as(C.POINTER(C.c_int32)),
+                                    float(ecut), mill.ctypes.data_as(C.POINTER(C.c_int32)),
+                                    kind.ctypes.data_as(C.POINTER(C.c_int8))))
+    return mill, kind
+
+
+class Context:
+    """Owns one bse_ctx; host inputs are kept alive for the init call only."""
+
+    def __init__(self, handle):
+        self.h = C.c_void_p(handle)
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().bse_free(self.h)
+            self.h = C.c_void_p(None)
+
+
+def init_system(cell, grid, ecut, site_xyz, site_depth, site_width, n_val, pdep, lam, *,
+                scissor=0.0, spin_factor=2.0, tau_policy=TAU_AUTO, tau_budget_bytes=0,
+                gap_min=0.0, kernel_mask=K_ALL, orbitals=None, eps=None, n_extra=8,
+                gs_tol=1e-10, stream=None):
+    """bse_init_system.  orbitals [n_orb][n_pw] / eps [n_orb] (host) or None to
+    let the library solve the ground state."""
+    import torch
+    xyz, dep, wid = _f64(site_xyz).reshape(-1, 3), _f64(site_depth), _f64(site_width)
+    P, lm = _f64(pdep), _f64(lam)
+    d = SystemDesc()
+    d.abi_version = ABI_VERSION
+    d.cell[:] = [float(x) for x in cell]
+    d.grid[:] = [int(x) for x in grid]
+    d.ecut = float(ecut)
+    d.n_sites = len(dep)
+    d.site_xyz, d.site_depth, d.site_width = _dptr(xyz), _dptr(dep), _dptr(wid)
+    d.n_val = int(n_val)
+    d.n_pdep = P.shape[1] if P.ndim == 2 else 0
+    d.pdep, d.lambda_ = _dptr(P), _dptr(lm)
+    d.scissor = float(scissor)
+    d.spin_factor = float(spin_factor)
+    d.precision = FP64
+    d.tau_policy = int(tau_policy)
+    d.tau_budget_bytes = int(tau_budget_bytes)
+    d.gap_min = float(gap_min)
+    d.kernel_mask = int(kernel_mask)
+    keep = [xyz, dep, wid, P, lm]
+    if orbitals is not None:
+        O, E = _f64(orbitals), _f64(eps)
+        keep += [O, E]
+        d.n_orb = O.shape[0]
+        d.orbitals, d.eps = _dptr(O), _dptr(E)
+    d.n_extra = int(n_extra)
+    d.gs_tol = float(gs_tol)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    d.stream = C.c_void_p(stream)
+    h = C.c_void_p()
+    _check(lib().bse_init_system(C.byref(d), C.byref(h)))
+    ctx = Context(h.value)
+    return ctx
+
+
+def init_from_synth(sysd, **kw):
+    """init_system from a ``synth.make_system`` dict."""
+    return init_system(sysd["cell"], sysd["grid"], sysd["ecut"], sysd["site_xyz"],
+                       sysd["site_depth"], sysd["site_width"], sysd["n_val"], sysd["pdep"],
+                       sysd["lam"], **kw)
+
+
+def get_info(ctx):
+    i = Info()
+    _check(lib().bse_get_info(ctx.h, C.byref(i)))
+    return dict(n_pw=i.n_pw, n_val=i.n_val, n_pdep=i.n_pdep, n_orb=i.n_orb, grid=tuple(i.grid),
+                tau_policy=i.tau_policy, tau_blocks=i.tau_blocks,
+                tau_blocks_cached=i.tau_blocks_cached, tau_bytes=i.tau_bytes,
+                gs_resid=i.gs_resid, ks_gap=i.ks_gap)
+
+
+def get_orbitals(ctx, n=None):
+    import torch
+    info = get_info(ctx)
+    n = info["n_val"] if n is None else n
+    out = torch.empty((n, info["n_pw"]), dtype=torch.float64, device="cuda")
+    e = np.zeros(n)
+    _check(lib().bse_get_orbitals(ctx.h, n, _dev(out, "orbitals"), _dptr(e)))
+    return out, e
+
+
+def apply(ctx, X, Y=None):
+    """bse_apply: Y = P_c M P_c X for X [n_b][n_val][n_pw] (CUDA float64)."""
+    import torch
+    if Y is None:
+        Y = torch.empty_like(X)
+    nb = X.shape[0] if X.dim() == 3 else 1
+    _check(lib().bse_apply(ctx.h, nb, _dev(X, "X"), _dev(Y, "Y")))
+    return Y
+
+
+def _opts(tol=0.0, max_iter=0, block=0, max_subspace=0, x0=None, z0=None):
+    o = SolverOpts()
+    o.tol, o.max_iter, o.block, o.max_subspace = float(tol), int(max_iter), int(block), int(max_subspace)
+    if x0 is not None:
+        o.x0_dev = _dev(x0, "x0").value
+        o.n_x0 = x0.shape[0]
+    if z0 is not None:
+        o.z0_dev = _dev(z0, "z0").value
+    return o
+
+
+def _stats(s):
+    return dict(iters=s.iters, applies=s.applies, resid=list(s.resid), t_ms=s.t_ms)
+
+
+def davidson(ctx, n_states=1, *, tol=1e-8, max_iter=0, block=0, max_subspace=0, x0=None,
+             check=True):
+    import torch
+    info = get_info(ctx)
+    X = torch.empty((n_states, info["n_val"], info["n_pw"]), dtype=torch.float64, device="cuda")
+    w = np.zeros(n_states)
+    o = _opts(tol, max_iter, block, max_subspace, x0=x0)
+    s = SolverStats()
+    rc = lib().bse_davidson(ctx.h, n_states, C.byref(o), _dptr(w), _dev(X, "X"), C.byref(s))
+    if check:
+        _check(rc)
+    return w, X, dict(_stats(s), rc=rc)
+
+
+def u_vector(ctx, Xs):
+    import torch
+    U = torch.empty_like(Xs)
+    _check(lib().bse_u_vector(ctx.h, _dev(Xs, "Xs"), _dev(U, "U")))
+    return U
+
+
+def zvector_solve(ctx, Xs, *, tol=1e-8, max_iter=0, z0=None, check=True):
+    import torch
+    Z = torch.empty_like(Xs)
+    o = _opts(tol, max_iter, z0=z0)
+    s = SolverStats()
+    rc = lib().bse_zvector_solve(ctx.h, _dev(Xs, "Xs"), C.byref(o), _dev(Z, "Z"), C.byref(s))
+    if check:
+        _check(rc)
+    return Z, dict(_stats(s), rc=rc)
+
+
+def forces(ctx, Xs, Z, n_sites):
+    out = np.zeros((max(n_sites, 1), 3))
+    _check(lib().bse_forces(ctx.h, _dev(Xs, "Xs"), _dev(Z, "Z"), _dptr(out)))
+    return out[:n_sites]
+
+
+def set_profiling(ctx, on=True):
+    _check(lib().bse_set_profiling(ctx.h, 1 if on else 0))
+
+
+def phase_times(ctx, reset=False):
+    p = PhaseTimes()
+    _check(lib().bse_get_phase_times(ctx.h, C.byref(p), 1 if reset else 0))
+    return {p.name[i].decode(): (p.ms[i], p.count[i]) for i in range(p.n_phase)}
+
+
+def free(ctx):
+    ctx.free()

@@ -1,0 +1,433 @@
+// C ABI entry points: validation, context set-up, dispatch to the solvers.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "context.h"
+
+namespace bsex {
+const char* last_error();
+int davidson(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double* Xout,
+             bse_solver_stats* stats);
+int u_vector(bse_ctx* c, const double* Xs, double* U);
+int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
+            bse_solver_stats* stats);
+int forces(bse_ctx* c, const double* Xs, const double* Zin, double* dwdR_host);
+}  // namespace bsex
+
+using namespace bsex;
+
+namespace {
+
+bool finite_all(const double* p, long n) {
+  for (long i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+void ctx_destroy(bse_ctx* c) {
+  if (!c) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  for (auto& b : c->allocs) (void)hipFree(b.p);
+  c->allocs.clear();
+  fft_plan_free(&c->fft);
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int upload(bse_ctx* c, void* dst, const void* src, size_t bytes) {
+  BSE_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->st));
+  BSE_HIP(hipStreamSynchronize(c->st));
+  return BSE_OK;
+}
+
+int validate(const bse_system_desc* d) {
+  if (!d) return fail(BSE_EINVAL, "desc is NULL");
+  if (d->abi_version != BSEX_ABI_VERSION)
+    return fail(BSE_EABI, "desc.abi_version %d, library %d", d->abi_version, BSEX_ABI_VERSION);
+  if (d->n_sites < 0) return fail(BSE_EINVAL, "n_sites < 0");
+  if (d->n_sites > 0) {
+    if (!d->site_xyz || !d->site_depth || !d->site_width)
+      return fail(BSE_EINVAL, "site arrays must be given when n_sites > 0");
+    if (!finite_all(d->site_xyz, 3L * d->n_sites) || !finite_all(d->site_depth, d->n_sites) ||
+        !finite_all(d->site_width, d->n_sites))
+      return fail(BSE_EINVAL, "non-finite site data");
+    for (int i = 0; i < d->n_sites; ++i)
+      if (!(d->site_width[i] > 0)) return fail(BSE_EINVAL, "site_width[%d] must be positive", i);
+  }
+  if (d->n_val < 1) return fail(BSE_EINVAL, "n_val must be >= 1");
+  if (d->n_pdep < 0) return fail(BSE_EINVAL, "n_pdep < 0");
+  if (d->n_pdep > 0 && (!d->pdep || !d->lambda))
+    return fail(BSE_EINVAL, "pdep and lambda must be given when n_pdep > 0");
+  if (!std::isfinite(d->scissor) || !std::isfinite(d->spin_factor))
+    return fail(BSE_EINVAL, "scissor and spin_factor must be finite");
+  if (d->precision != BSE_FP64) return fail(BSE_EINVAL, "precision %d unsupported", d->precision);
+  if (d->tau_policy < BSE_TAU_AUTO || d->tau_policy > BSE_TAU_REBUILD)
+    return fail(BSE_EINVAL, "tau_policy %d unknown", d->tau_policy);
+  if (d->tau_budget_bytes < 0) return fail(BSE_EINVAL, "tau_budget_bytes < 0");
+  if (d->kernel_mask < 0 || d->kernel_mask > BSE_K_ALL)
+    return fail(BSE_EINVAL, "kernel_mask %d out of range", d->kernel_mask);
+  if (d->n_orb < 0 || (d->n_orb > 0 && d->n_orb < d->n_val))
+    return fail(BSE_EINVAL, "n_orb must be 0 or >= n_val");
+  if (d->n_orb > 0 && (!d->orbitals || !d->eps))
+    return fail(BSE_EINVAL, "orbitals and eps must be given when n_orb > 0");
+  if (d->n_extra < 0) return fail(BSE_EINVAL, "n_extra < 0");
+  if (!std::isfinite(d->gap_min) || !std::isfinite(d->gs_tol) || d->gs_tol < 0)
+    return fail(BSE_EINVAL, "gap_min / gs_tol invalid");
+  return BSE_OK;
+}
+
+int plan_tau(bse_ctx* c, const bse_system_desc* d) {
+  const long nr = c->basis.nr, npw = c->basis.npw;
+  const long nB = (c->nv + 7) / 8;
+  c->nblk = nB * (nB + 1) / 2;
+  std::vector<int2> ij;
+  for (long I = 0; I < nB; ++I)
+    for (long J = I; J < nB; ++J) ij.push_back(make_int2((int)I, (int)J));
+  BSE_TRY(ctx_alloc_t(c, &c->blkIJ, ij.size()));
+  BSE_TRY(upload(c, c->blkIJ, ij.data(), sizeof(int2) * ij.size()));
+  // stream kernel geometry from the device LDS size
+  int dev = 0;
+  BSE_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  BSE_HIP(hipGetDeviceProperties(&prop, dev));
+  c->max_lds = prop.sharedMemPerBlock;
+  c->R = (tau_stream_lds(c->nv, 2) <= c->max_lds) ? 2 : 1;
+  if (tau_stream_lds(c->nv, c->R) > c->max_lds)
+    return fail(BSE_EINVAL, "n_val %d too large for the device LDS (%zu bytes)", c->nv, c->max_lds);
+  BSE_TRY(tau_stream_set_lds_limit(c->max_lds));
+  const bool need_k1d = (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) != 0;
+  // work for one apply chunk of 8 vectors
+  BSE_TRY(ensure_apply_work(c, 8));
+  // tile buffers: grids, rho_S, PDEP coefficients, result, rebuild copy
+  const double blk_tile_bytes =
+      8.0 * 64 * (2.0 * nr + 2.0 * npw + std::max(c->npdep, 1));
+  size_t freeb = 0, totalb = 0;
+  BSE_HIP(hipMemGetInfo(&freeb, &totalb));
+  const double tile_target = std::max(1.0e9, 0.06 * (double)totalb);
+  c->tile_blk = std::max(1L, std::min(c->nblk, (long)(tile_target / blk_tile_bytes)));
+  const long te = c->tile_blk * 64;
+  BSE_TRY(ctx_alloc_t(c, &c->tile_grids, (size_t)c->tile_blk * 32 * nr));
+  BSE_TRY(ctx_alloc_t(c, &c->rebuild_buf, (size_t)c->tile_blk * 64 * nr));
+  if (c->npdep > 0) {
+    BSE_TRY(ctx_alloc_t(c, &c->tile_RS, (size_t)te * npw));
+    BSE_TRY(ctx_alloc_t(c, &c->tile_F, (size_t)te * npw));
+    BSE_TRY(ctx_alloc_t(c, &c->tile_T, (size_t)te * c->npdep));
+  }
+  // cache
+  c->tau_policy = d->tau_policy;
+  const double blk_bytes = 8.0 * 64 * nr;
+  long ncache = 0;
+  if (need_k1d && d->tau_policy != BSE_TAU_REBUILD) {
+    BSE_HIP(hipMemGetInfo(&freeb, &totalb));
+    // keep room for a Davidson subspace of 64 vectors plus 4 GB
+    const double reserve = 4.0e9 + 2.0 * 72 * 8.0 * c->nv * npw;
+    double budget = (double)freeb - reserve;
+    if (d->tau_budget_bytes > 0) budget = std::min(budget, (double)d->tau_budget_bytes);
+    long fit = budget > 0 ? (long)(budget / blk_bytes) : 0;
+    if (d->tau_policy == BSE_TAU_CACHE && fit < c->nblk)
+      return fail(BSE_ENOMEM, "tau cache needs %.1f GB, %.1f GB available",
+                  c->nblk * blk_bytes / 1e9, std::max(budget, 0.0) / 1e9);
+    ncache = std::min(fit, c->nblk);
+  }
+  c->nblk_cached = ncache;
+  if (ncache > 0) {
+    BSE_TRY(ctx_alloc_t(c, &c->tau_cache, (size_t)ncache * 64 * nr));
+    PhaseScope ps(c, PH_INIT_TAU);
+    for (long gb0 = 0; gb0 < ncache; gb0 += c->tile_blk) {
+      const long nt = std::min(c->tile_blk, ncache - gb0);
+      BSE_TRY(tau_build_range(c, c->phir, gb0, nt, c->tau_cache, ncache, gb0, c->kmask));
+    }
+  }
+  if (c->nblk_cached == c->nblk && c->nblk > 0)
+    c->tau_policy = BSE_TAU_CACHE;
+  else if (need_k1d)
+    c->tau_policy = (c->nblk_cached == 0) ? BSE_TAU_REBUILD : BSE_TAU_AUTO;
+  return BSE_OK;
+}
+
+int init_impl(const bse_system_desc* d, bse_ctx* c) {
+  BSE_TRY(validate(d));
+  BSE_TRY(basis_build(d->cell, d->grid, d->ecut, &c->basis));
+  const long npw = c->basis.npw, nr = c->basis.nr;
+  if (d->n_val >= npw) return fail(BSE_EINVAL, "n_val %d must be below n_pw %ld", d->n_val, npw);
+  if (d->n_pdep >= npw) return fail(BSE_EINVAL, "n_pdep %d must be below n_pw %ld", d->n_pdep, npw);
+  if (d->n_orb > npw) return fail(BSE_EINVAL, "n_orb above n_pw");
+  if (d->n_pdep > 0) {
+    if (!finite_all(d->pdep, npw * d->n_pdep) || !finite_all(d->lambda, d->n_pdep))
+      return fail(BSE_EINVAL, "non-finite PDEP data");
+    for (int a = 0; a < d->n_pdep; ++a)
+      if (!(d->lambda[a] < 1.0)) return fail(BSE_EINVAL, "lambda[%d] must be below 1", a);
+  }
+  if (d->n_orb > 0 && (!finite_all(d->orbitals, (long)d->n_orb * npw) || !finite_all(d->eps, d->n_orb)))
+    return fail(BSE_EINVAL, "non-finite orbitals");
+  c->st = (hipStream_t)d->stream;
+  c->nv = d->n_val;
+  c->nvh = (c->nv + 1) / 2;
+  c->npdep = d->n_pdep;
+  c->nsites = d->n_sites;
+  c->kmask = d->kernel_mask ? d->kernel_mask : BSE_K_ALL;
+  c->scissor = d->scissor;
+  c->spin = d->spin_factor;
+  c->gap_min = d->gap_min;
+  c->gs_tol = d->gs_tol > 0 ? d->gs_tol : 1e-10;
+  c->n_extra = d->n_extra;
+  BSE_TRY(fft_plan_init(&c->fft, d->grid));
+  // basis maps and kinetic energy
+  BSE_TRY(ctx_alloc_t(c, &c->idx_p, c->basis.nhalf + 1));
+  BSE_TRY(ctx_alloc_t(c, &c->idx_m, c->basis.nhalf + 1));
+  BSE_TRY(upload(c, c->idx_p, c->basis.idx_p.data(), sizeof(int) * c->basis.nhalf));
+  BSE_TRY(upload(c, c->idx_m, c->basis.idx_m.data(), sizeof(int) * c->basis.nhalf));
+  std::vector<double> T(npw);
+  for (long j = 0; j < npw; ++j) T[j] = 0.5 * c->basis.g2[j];
+  BSE_TRY(ctx_alloc_t(c, &c->T, npw));
+  BSE_TRY(upload(c, c->T, T.data(), sizeof(double) * npw));
+  c->map = SphereMap{c->idx_p, c->idx_m, c->basis.nhalf, (int)npw, nr, c->basis.omega};
+  // sites, potential, Coulomb kernel
+  const int ns = std::max(1, c->nsites);
+  c->site_h.assign(5 * (size_t)ns, 0.0);
+  for (int i = 0; i < c->nsites; ++i) {
+    for (int a = 0; a < 3; ++a) c->site_h[3 * i + a] = d->site_xyz[3 * i + a];
+    c->site_h[3 * c->nsites + i] = d->site_depth[i];
+    c->site_h[4 * c->nsites + i] = d->site_width[i];
+  }
+  BSE_TRY(ctx_alloc_t(c, &c->sites, c->site_h.size()));
+  BSE_TRY(upload(c, c->sites, c->site_h.data(), sizeof(double) * c->site_h.size()));
+  {
+    double2* vg = nullptr;
+    BSE_TRY(ctx_alloc_t(c, &vg, nr));
+    BSE_TRY(site_potential(c->sites, c->sites + 3 * c->nsites, c->sites + 4 * c->nsites,
+                           c->nsites, c->basis.grid, c->basis.cell, vg, c->st));
+    BSE_TRY(fft3d(c->fft, vg, 1, +1, c->st));
+    BSE_TRY(ctx_alloc_t(c, &c->Vr, nr));
+    BSE_TRY(real_part(vg, nr, c->Vr, c->st));
+    BSE_HIP(hipStreamSynchronize(c->st));
+    ctx_release(c, vg);
+  }
+  BSE_TRY(ctx_alloc_t(c, &c->vc, nr));
+  BSE_TRY(coulomb_kernel(c->basis.grid, c->basis.cell, c->vc, c->st));
+  // PDEP: Pt = v_c^1/2 P, Ptc = v_c^1/2 P c
+  if (c->npdep > 0) {
+    std::vector<double> pt((size_t)npw * c->npdep), ptc((size_t)npw * c->npdep);
+    for (long j = 0; j < npw; ++j) {
+      const double vs = j == 0 ? 0.0 : std::sqrt(4.0 * M_PI / c->basis.g2[j]);
+      for (int a = 0; a < c->npdep; ++a) {
+        const double ca = d->lambda[a] / (1.0 - d->lambda[a]);
+        const double x = vs * d->pdep[j * c->npdep + a];
+        pt[(size_t)j * c->npdep + a] = x;
+        ptc[(size_t)j * c->npdep + a] = x * ca;
+      }
+    }
+    BSE_TRY(ctx_alloc_t(c, &c->Pt, pt.size()));
+    BSE_TRY(ctx_alloc_t(c, &c->Ptc, ptc.size()));
+    BSE_TRY(upload(c, c->Pt, pt.data(), sizeof(double) * pt.size()));
+    BSE_TRY(upload(c, c->Ptc, ptc.data(), sizeof(double) * ptc.size()));
+  }
+  // occupied orbitals
+  if (d->n_orb > 0) {
+    c->norb = d->n_orb;
+    BSE_TRY(ctx_alloc_t(c, &c->Phi, (size_t)c->norb * npw));
+    BSE_TRY(ctx_alloc_t(c, &c->eps_d, (size_t)c->norb));
+    BSE_TRY(upload(c, c->Phi, d->orbitals, sizeof(double) * c->norb * npw));
+    BSE_TRY(upload(c, c->eps_d, d->eps, sizeof(double) * c->norb));
+    c->eps_h.assign(d->eps, d->eps + c->norb);
+  } else {
+    const int extra = d->n_extra > 0 ? d->n_extra : 8;
+    const int want = (int)std::min<long>(npw, (long)c->nv + extra);
+    BSE_TRY(ground_state(c, want, c->gs_tol));
+  }
+  if (c->norb > c->nv) {
+    c->ks_gap = c->eps_h[c->nv] - c->eps_h[c->nv - 1];
+    if (c->gap_min > 0 && c->ks_gap < c->gap_min)
+      return fail(BSE_EGAP, "Kohn-Sham gap %.3e Ha below gap_min %.3e", c->ks_gap, c->gap_min);
+  }
+  // phi(r)
+  BSE_TRY(ctx_alloc_t(c, &c->phir, (size_t)c->nvh * nr));
+  BSE_TRY(to_grid(c, c->Phi, c->nv, 1, c->phir));
+  BSE_TRY(plan_tau(c, d));
+  BSE_HIP(hipStreamSynchronize(c->st));
+  return BSE_OK;
+}
+
+template <typename F>
+int guarded(bse_ctx* c, F f) {
+  try {
+    int rc = f();
+    if (c) {
+      int rc2 = prof_collect(c);
+      if (rc == BSE_OK) rc = rc2;
+    }
+    return rc;
+  } catch (const std::bad_alloc&) {
+    return fail(BSE_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(BSE_EINVAL, "unexpected exception");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t bse_abi_version(void) { return BSEX_ABI_VERSION; }
+
+const char* bse_last_error(void) { return last_error(); }
+
+int bse_basis_size(const double cell[3], const int32_t grid[3], double ecut, int32_t* n_pw) {
+  if (!cell || !grid || !n_pw) return fail(BSE_EINVAL, "NULL argument");
+  Basis b;
+  const int g[3] = {grid[0], grid[1], grid[2]};
+  BSE_TRY(basis_build(cell, g, ecut, &b));
+  *n_pw = b.npw;
+  return BSE_OK;
+}
+
+int bse_basis_gvectors(const double cell[3], const int32_t grid[3], double ecut,
+                       int32_t* miller_host, int8_t* kind_host) {
+  if (!cell || !grid) return fail(BSE_EINVAL, "NULL argument");
+  Basis b;
+  const int g[3] = {grid[0], grid[1], grid[2]};
+  BSE_TRY(basis_build(cell, g, ecut, &b));
+  if (miller_host) {
+    for (int a = 0; a < 3; ++a) miller_host[a] = 0;
+    for (int s = 0; s < b.nhalf; ++s)
+      for (int q = 0; q < 2; ++q)
+        for (int a = 0; a < 3; ++a) miller_host[3 * (1 + 2 * s + q) + a] = b.mill_half[3 * s + a];
+  }
+  if (kind_host) {
+    kind_host[0] = 0;
+    for (int s = 0; s < b.nhalf; ++s) {
+      kind_host[1 + 2 * s] = 1;
+      kind_host[2 + 2 * s] = 2;
+    }
+  }
+  return BSE_OK;
+}
+
+int bse_init_system(const bse_system_desc* desc, bse_ctx** out) {
+  if (!out) return fail(BSE_EINVAL, "out is NULL");
+  *out = nullptr;
+  bse_ctx* c = nullptr;
+  try {
+    c = new bse_ctx();
+  } catch (...) {
+    return fail(BSE_ENOMEM, "host allocation failed");
+  }
+  int rc = guarded(nullptr, [&] { return init_impl(desc, c); });
+  if (rc != BSE_OK) {
+    std::string keep = last_error();
+    ctx_destroy(c);
+    set_error("%s", keep.c_str());
+    return rc;
+  }
+  *out = c;
+  return BSE_OK;
+}
+
+int bse_get_info(bse_ctx* c, bse_info* info) {
+  if (!c || !info) return fail(BSE_EINVAL, "NULL argument");
+  info->n_pw = c->basis.npw;
+  info->n_val = c->nv;
+  info->n_pdep = c->npdep;
+  info->n_orb = c->norb;
+  for (int a = 0; a < 3; ++a) info->grid[a] = c->basis.grid[a];
+  info->tau_policy = c->tau_policy;
+  info->tau_blocks = c->nblk;
+  info->tau_blocks_cached = c->nblk_cached;
+  info->tau_bytes = (int64_t)c->nblk_cached * 64 * c->basis.nr * 8;
+  info->gs_resid = c->gs_resid;
+  info->ks_gap = c->ks_gap;
+  return BSE_OK;
+}
+
+int bse_get_orbitals(bse_ctx* c, int32_t n, double* orbitals_dev, double* eps_host) {
+  if (!c) return fail(BSE_EINVAL, "ctx is NULL");
+  if (n < 1 || n > c->norb) return fail(BSE_EINVAL, "n must be in 1..%d", c->norb);
+  return guarded(c, [&]() -> int {
+    if (orbitals_dev) {
+      BSE_HIP(hipMemcpyAsync(orbitals_dev, c->Phi, sizeof(double) * n * c->basis.npw,
+                             hipMemcpyDeviceToDevice, c->st));
+      BSE_HIP(hipStreamSynchronize(c->st));
+    }
+    if (eps_host) std::copy(c->eps_h.begin(), c->eps_h.begin() + n, eps_host);
+    return BSE_OK;
+  });
+}
+
+int bse_apply(bse_ctx* c, int32_t n_b, const double* X, double* Y) {
+  if (!c) return fail(BSE_EINVAL, "ctx is NULL");
+  if (n_b < 0) return fail(BSE_EINVAL, "n_b < 0");
+  if (n_b == 0) return BSE_OK;
+  if (!X || !Y) return fail(BSE_EINVAL, "NULL vector");
+  const size_t bytes = sizeof(double) * (size_t)n_b * c->nv * c->basis.npw;
+  const char* xa = (const char*)X;
+  const char* ya = (const char*)Y;
+  if (xa < ya + bytes && ya < xa + bytes) return fail(BSE_EINVAL, "X and Y overlap");
+  return guarded(c, [&]() -> int {
+    const long L = (long)c->nv * c->basis.npw;
+    for (long i = 0; i < n_b; i += c->nbc) {
+      const int k = (int)std::min<long>(c->nbc, n_b - i);
+      BSE_TRY(apply_chunk(c, k, X + i * L, Y + i * L));
+    }
+    BSE_HIP(hipStreamSynchronize(c->st));
+    return BSE_OK;
+  });
+}
+
+int bse_davidson(bse_ctx* c, int32_t n_states, const bse_solver_opts* opts, double* omega_host,
+                 double* X_dev, bse_solver_stats* stats) {
+  if (!c || !omega_host) return fail(BSE_EINVAL, "NULL argument");
+  if (n_states < 1 || n_states > 16) return fail(BSE_EINVAL, "n_states must be 1..16");
+  if (opts && opts->block > 0 && opts->block < n_states)
+    return fail(BSE_EINVAL, "block below n_states");
+  return guarded(c, [&] { return davidson(c, n_states, opts, omega_host, X_dev, stats); });
+}
+
+int bse_u_vector(bse_ctx* c, const double* Xs, double* U) {
+  if (!c || !Xs || !U) return fail(BSE_EINVAL, "NULL argument");
+  return guarded(c, [&] { return u_vector(c, Xs, U); });
+}
+
+int bse_zvector_solve(bse_ctx* c, const double* Xs, const bse_solver_opts* opts, double* Z,
+                      bse_solver_stats* stats) {
+  if (!c || !Xs || !Z) return fail(BSE_EINVAL, "NULL argument");
+  return guarded(c, [&] { return zvector(c, Xs, opts, Z, stats); });
+}
+
+int bse_forces(bse_ctx* c, const double* Xs, const double* Z, double* dwdR_host) {
+  if (!c || !Xs || !Z || (!dwdR_host && c->nsites > 0)) return fail(BSE_EINVAL, "NULL argument");
+  return guarded(c, [&] { return forces(c, Xs, Z, dwdR_host); });
+}
+
+int bse_set_profiling(bse_ctx* c, int32_t on) {
+  if (!c) return fail(BSE_EINVAL, "ctx is NULL");
+  c->prof = on != 0;
+  return BSE_OK;
+}
+
+int bse_get_phase_times(bse_ctx* c, bse_phase_times* out, int32_t reset) {
+  if (!c || !out) return fail(BSE_EINVAL, "NULL argument");
+  static const char* names[PH_COUNT] = {"proj",    "fft_inv", "k1e",    "tau_stream", "tau_build",
+                                        "combine", "fft_fwd", "solver", "init_tau",   "ground_state"};
+  out->n_phase = PH_COUNT;
+  for (int i = 0; i < PH_COUNT; ++i) {
+    out->name[i] = names[i];
+    out->ms[i] = c->ph_ms[i];
+    out->count[i] = c->ph_n[i];
+    if (reset) {
+      c->ph_ms[i] = 0;
+      c->ph_n[i] = 0;
+    }
+  }
+  return BSE_OK;
+}
+
+int bse_free(bse_ctx* c) {
+  if (!c) return BSE_OK;
+  ctx_destroy(c);
+  return BSE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal declarations of the bsex library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bsex.h"
+
+namespace bsex {
+
+// ---- error reporting --------------------------------------------------------
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+
+#define BSE_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return ::bsex::fail(BSE_EHIP, "%s failed: %s (%s:%d)", #call,          \
+                          hipGetErrorString(e_), __FILE__, __LINE__);        \
+  } while (0)
+
+#define BSE_TRY(call)                 \
+  do {                                \
+    int rc_ = (call);                 \
+    if (rc_ != BSE_OK) return rc_;    \
+  } while (0)
+
+// ---- basis (host) -------------------------------------------------------------
+struct Basis {
+  double cell[3];
+  int grid[3];
+  double ecut, omega;
+  long nr;
+  int npw, nhalf;
+  std::vector<int> mill_half;   // [nhalf][3]
+  std::vector<int> idx_p, idx_m;  // linear grid index of +G / -G
+  std::vector<double> g2;       // |G|^2 per basis function [npw]
+};
+int basis_build(const double cell[3], const int grid[3], double ecut, Basis* b);
+
+// ---- FFT ------------------------------------------------------------------------
+struct FftAxis {
+  int n = 0;
+  int nrad = 0;
+  int rad[8] = {0};
+  double2* tw = nullptr;  // device, exp(-2 pi i k / n), k < n
+};
+struct FftPlan {
+  int N[3] = {0, 0, 0};
+  long nr = 0;
+  FftAxis ax[3];
+};
+int fft_plan_init(FftPlan* p, const int grid[3]);
+void fft_plan_free(FftPlan* p);
+// In-place batched 3-D complex transform of [batch][N1][N2][N3] (N3 fastest).
+// dir = -1: sum_r f(r) exp(-i G.r); dir = +1: sum_G f(G) exp(+i G.r).  No scaling.
+int fft3d(const FftPlan& p, double2* data, long batch, int dir, hipStream_t st);
+
+// ---- GEMM -----------------------------------------------------------------------
+// C[M][N] = alpha op(A) op(B) + beta C, row-major, FP64 MFMA.
+// op(A) = A[M][K] (ta = 0) or A^T with A[K][M] (ta = 1); op(B) likewise.
+int dgemm(int ta, int tb, long M, long N, long K, double alpha, const double* A, long lda,
+          const double* B, long ldb, double beta, double* C, long ldc, hipStream_t st);
+// C[M][N] = alpha A[M][K] B[N][K]^T + beta C for small M, N and long K
+// (split over K with a fixed-order reduction; work buffer owned by the caller).
+int dgemm_tall(long M, long N, long K, double alpha, const double* A, long lda,
+               const double* B, long ldb, double beta, double* C, long ldc,
+               double* work, long work_len, hipStream_t st);
+long dgemm_tall_work(long M, long N, long K);
+
+// ---- host dense linear algebra ------------------------------------------------------
+// Symmetric eigen-decomposition: A[n][n] row-major (overwritten by eigenvectors,
+// column j = vector j), w ascending.
+int host_syev(int n, double* A, double* w);
+// Lower Cholesky in place; returns non-zero when not positive definite.
+int host_cholesky(int n, double* A);
+}  // namespace bsex

@@ -1,0 +1,110 @@
+// The library context: device-resident system data, work buffers, tau cache.
+#pragma once
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace bsex {
+
+enum Phase {
+  PH_PROJ = 0,   // occupied projector (overlap and update GEMMs)
+  PH_FFT_INV,    // sphere -> grid scatter and inverse transforms
+  PH_K1E,        // transition density and Poisson solve
+  PH_TAU_STREAM, // tau contraction (K1d)
+  PH_TAU_BUILD,  // tau tiles rebuilt during an apply
+  PH_COMBINE,    // V a + s v_c*Drho phi - y
+  PH_FFT_FWD,    // forward transforms and gather (with the diagonal term)
+  PH_SOLVER,     // Davidson / CG bookkeeping (dots, small GEMMs)
+  PH_INIT_TAU,   // tau cache build at init
+  PH_GS,         // ground-state eigensolver
+  PH_COUNT
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace bsex
+
+struct bse_ctx {
+  bsex::Basis basis;
+  int nv = 0, nvh = 0, npdep = 0, nsites = 0, kmask = 0, norb = 0, n_extra = 0;
+  double scissor = 0, spin = 2, gap_min = 0, gs_tol = 1e-10, gs_resid = -1, ks_gap = -1;
+  hipStream_t st = nullptr;
+  bsex::FftPlan fft;
+  bsex::SphereMap map{};
+  std::vector<bsex::DevBuf> allocs;
+  // device system data
+  int *idx_p = nullptr, *idx_m = nullptr;
+  double* T = nullptr;        // [npw] |G|^2/2
+  double* Vr = nullptr;       // [nr] V(r)
+  double* vc = nullptr;       // [nr] 4 pi/|G|^2 (0 at G = 0)
+  double* Phi = nullptr;      // [norb][npw]
+  double* eps_d = nullptr;    // [norb]
+  double2* phir = nullptr;    // [nvh][nr]
+  double* Pt = nullptr;       // [npw][npdep] v_c^1/2 P
+  double* Ptc = nullptr;      // [npw][npdep] v_c^1/2 P c
+  double* sites = nullptr;    // xyz[3n] | depth[n] | width[n]
+  int2* blkIJ = nullptr;      // [nblk]
+  std::vector<double> eps_h;  // [norb]
+  std::vector<double> site_h; // same layout as sites
+  // tau
+  int R = 1;
+  size_t max_lds = 65536;
+  long nblk = 0, nblk_cached = 0, tile_blk = 0;
+  int tau_policy = BSE_TAU_AUTO;
+  double* tau_cache = nullptr;
+  double2* tile_grids = nullptr;
+  double *tile_RS = nullptr, *tile_T = nullptr, *tile_F = nullptr;
+  double* rebuild_buf = nullptr;
+  // apply work, chunks of at most nbc vectors
+  int nbc = 0;
+  double *A_s = nullptr, *Zs = nullptr, *Ov = nullptr;
+  double2 *agrid = nullptr, *ygrid = nullptr, *drho = nullptr;
+  double* gw = nullptr;
+  long gw_len = 0;
+  // profiling
+  bool prof = false;
+  double ph_ms[bsex::PH_COUNT] = {0};
+  long ph_n[bsex::PH_COUNT] = {0};
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;
+  size_t ev_used = 0;
+};
+
+namespace bsex {
+int ctx_alloc(bse_ctx* c, void** p, size_t bytes);
+template <typename T>
+int ctx_alloc_t(bse_ctx* c, T** p, size_t count) {
+  return ctx_alloc(c, reinterpret_cast<void**>(p), sizeof(T) * count);
+}
+void ctx_release(bse_ctx* c, void* p);
+
+// profiling
+struct PhaseScope {
+  bse_ctx* c;
+  int ph;
+  hipEvent_t e1 = nullptr;
+  PhaseScope(bse_ctx* c_, int ph_);
+  ~PhaseScope();
+};
+int prof_collect(bse_ctx* c);
+
+// operator pieces (device, stream ordered)
+int proj_c(bse_ctx* c, const double* X, double* Y, int nset);
+int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y);
+int apply_H(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double2* grids,
+            double shift, const double* eps, int project);
+int to_grid(bse_ctx* c, const double* X, int nvs, int nset, double2* grids);
+int kernel_part(bse_ctx* c, const double2* agrid, double* Kt);
+int sigma_phi(bse_ctx* c, const double2* agrid, double2* y);
+int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len, double* tmp,
+               int passes, double drop);
+int ensure_apply_work(bse_ctx* c, int nbc);
+int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double* dst,
+                    long dst_nblk, long dst_blk0, int mask);
+int ground_state(bse_ctx* c, int n_want, double tol);
+int gram_tall(bse_ctx* c, const double* A, long m, const double* B, long n, long len, double* C);
+}  // namespace bsex

@@ -1,0 +1,86 @@
+// Launchers of the element-wise, transform-side and tau kernels.
+#pragma once
+#include "common.h"
+
+namespace bsex {
+
+// Orbitals are stored as rows of n_pw real coefficients.  A "set" is a block
+// of `nv` orbitals; `nset` sets are stored back to back.  Real-space grids
+// hold two orbitals of one set per complex grid (packed: x = orbital 2p,
+// y = orbital 2p+1), nvh = ceil(nv/2) grids per set.
+struct SphereMap {
+  const int* idx_p;   // [nhalf] linear grid index of +G
+  const int* idx_m;   // [nhalf] linear grid index of -G
+  int nhalf;
+  int npw;
+  long nr;
+  double omega;
+};
+
+// grid[set][p][r] = packed coefficients of X (grid must be zero first unless
+// accumulate = 1, in which case the coefficients are added).
+int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, double2* grid,
+                 int accumulate, hipStream_t st);
+// Y[set][v][j] = scale * <e_j | grid>  (+ (T_j + shift - eps_v) * A[set][v][j] if A)
+// (+ beta * Y).  The grid holds N_r times the Fourier coefficients when it
+// comes straight from a forward transform, so callers pass scale = 1/N_r.
+int gather_sets(const SphereMap& m, const double2* grid, int nv, int nset, double scale,
+                const double* A, const double* T, const double* eps, double shift, double beta,
+                double* Y, hipStream_t st);
+// grid[g][r] *= f[r] * scale  (real field f of length nr)
+int mul_real_field(double2* grid, long ngrid, long nr, const double* f, double scale,
+                   hipStream_t st);
+// out[r] = Re(grid[r]) for one grid
+int real_part(const double2* grid, long nr, double* out, hipStream_t st);
+// drho[b/2][r] packed over vectors: drho_b(r) = sum_v phi_v(r) a_{b,v}(r)
+int transition_density(const double2* phir, const double2* a, int nv, int nb, long nr,
+                       double2* drho, hipStream_t st);
+// z = kD * V a + s * Vdrho_b phi - y   (y may be NULL, vdrho may be NULL); in place into y or out
+int combine(const double2* a, const double2* phir, const double* V, const double2* vdrho,
+            const double2* y, double2* out, int nv, int nb, long nr, double s, int with_v,
+            hipStream_t st);
+// pair densities of 8x8 blocks [blk0, blk0 + nblk) of the upper triangle
+int pair_density(const double2* phir, int nv, const int2* blkIJ, long nblk, long nr,
+                 double2* grids, hipStream_t st);
+// natural tau tile (packed grids, 64 elements per block) -> blocked stream layout
+int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R, double* dst,
+              long dst_nblk, long dst_blk0, hipStream_t st);
+// y[b][v] (+)= sum_v' tau_{vv'} a[b][v'] over the blocks of one buffer
+int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
+               const double2* a, double2* y, int nb, int nv, long nr, int accumulate,
+               size_t max_lds, hipStream_t st);
+size_t tau_stream_lds(int nv, int R);
+// raise the dynamic-LDS limit of the stream kernels (bytes <= device maximum)
+int tau_stream_set_lds_limit(size_t bytes);
+
+// potential V(G) of Gaussian sites on the full grid (Nyquist zero), complex
+int site_potential(const double* xyz, const double* depth, const double* width, int nsites,
+                   const int grid[3], const double cell[3], double2* out, hipStream_t st);
+// Coulomb kernel 4 pi/|G|^2 on every grid frequency (minimum image), 0 at G = 0
+int coulomb_kernel(const int grid[3], const double cell[3], double* out, hipStream_t st);
+// rho_t(r) = sum_v a_v^2 - phi_v phit_v + 2 z_v phi_v  (one set of nv orbitals)
+int force_density(const double2* a, const double2* phit, const double2* z, const double2* phir,
+                  int nv, long nr, double2* rho, hipStream_t st);
+// partial sums for dw/dR: out[site][3] (host) from the forward transform of rho
+int force_reduce(const double2* rhoG, const double* xyz, const double* depth,
+                 const double* width, int nsites, const int grid[3], const double cell[3],
+                 double* part, long part_len, double* out_dev, hipStream_t st);
+long force_reduce_work(int nsites, long nr);
+
+// ---- vector helpers for the solvers (deterministic reductions) --------------------------
+// out[i] = sum_j A[i*ld + j] * B[i*ld + j], i < rows
+int row_dots(const double* A, const double* B, long rows, long len, double* out, hipStream_t st);
+// Y[i][j] = a[i] * X[i][j] + b[i] * Y[i][j]  (a or b NULL means 1)
+int row_axpby(const double* a, const double* X, const double* b, double* Y, long rows, long len,
+              hipStream_t st);
+// Y[i][j] *= s[i]
+int row_scale(const double* s, double* Y, long rows, long len, hipStream_t st);
+// Y = alpha X + beta Y over n elements
+int axpby(double alpha, const double* X, double beta, double* Y, long n, hipStream_t st);
+// Davidson preconditioner: T[k][v][j] = R[k][v][j] / clamp(Tk_j - eps_v + shift - theta_k)
+int precond_davidson(const double* R, double* T, const double* Tk, const double* eps,
+                     const double* theta, double shift, int nk, int nv, int npw, hipStream_t st);
+// CG preconditioner: T[v][j] = R[v][j] / max(Tk_j - eps_v + shift, 0.1)
+int precond_cg(const double* R, double* T, const double* Tk, const double* eps, double shift,
+               int nv, int npw, hipStream_t st);
+}  // namespace bsex

@@ -1,0 +1,753 @@
+// Element-wise, sphere<->grid and tau kernels of the DMPT BSE operator (FP64).
+#include <cmath>
+
+#include "kernels.h"
+
+namespace bsex {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned nblocks(long n, int tpb = TPB) {
+  long b = (n + tpb - 1) / tpb;
+  if (b > 1048576) b = 1048576;  // grid-stride loops cover the rest
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+__device__ __forceinline__ long gtid() { return (long)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ long gstride() { return (long)gridDim.x * blockDim.x; }
+
+// ---------------------------------------------------------------------------
+// sphere <-> grid (two real orbitals per complex grid)
+//   f(0) = x0/sqrt(Omega), f(+G) = (xc - i xs)/sqrt(2 Omega), f(-G) = conj(f(+G));
+//   grid of orbitals u (real part) and w (imaginary part): H = U + i W.
+// ---------------------------------------------------------------------------
+__global__ void k_scatter(const int* __restrict__ idx_p, const int* __restrict__ idx_m, int nhalf,
+                          int npw, long nr, const double* __restrict__ X, int nv, int nvh,
+                          long ngrid, double2* __restrict__ grid, int acc, double s0, double s1) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > nhalf) return;
+  for (long g = blockIdx.y; g < ngrid; g += gridDim.y) {
+    const long set = g / nvh;
+    const int p = (int)(g % nvh);
+    const int v1 = 2 * p, v2 = 2 * p + 1;
+    const double* x1 = X + (set * nv + v1) * (long)npw;
+    const double* x2 = (v2 < nv) ? X + (set * nv + v2) * (long)npw : nullptr;
+    double2* G = grid + g * nr;
+    if (t == 0) {
+      double2 h = make_double2(x1[0] * s0, x2 ? x2[0] * s0 : 0.0);
+      if (acc) {
+        h.x += G[0].x;
+        h.y += G[0].y;
+      }
+      G[0] = h;
+    } else {
+      const int k = t - 1;
+      const double c1 = x1[1 + 2 * k], q1 = x1[2 + 2 * k];
+      const double c2 = x2 ? x2[1 + 2 * k] : 0.0, q2 = x2 ? x2[2 + 2 * k] : 0.0;
+      double2 hp = make_double2((c1 + q2) * s1, (c2 - q1) * s1);
+      double2 hm = make_double2((c1 - q2) * s1, (q1 + c2) * s1);
+      const int ip = idx_p[k], im = idx_m[k];
+      if (acc) {
+        const double2 op = G[ip], om = G[im];
+        hp.x += op.x;
+        hp.y += op.y;
+        hm.x += om.x;
+        hm.y += om.y;
+      }
+      G[ip] = hp;
+      G[im] = hm;
+    }
+  }
+}
+
+__global__ void k_gather(const int* __restrict__ idx_p, const int* __restrict__ idx_m, int nhalf,
+                         int npw, long nr, const double2* __restrict__ grid, int nv, int nvh,
+                         long ngrid, double c0, double c1, const double* __restrict__ A,
+                         const double* __restrict__ T, const double* __restrict__ eps,
+                         double shift, double beta, double* __restrict__ Y) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > nhalf) return;
+  for (long g = blockIdx.y; g < ngrid; g += gridDim.y) {
+    const long set = g / nvh;
+    const int p = (int)(g % nvh);
+    const int v1 = 2 * p, v2 = 2 * p + 1;
+    const double2* G = grid + g * nr;
+    double a1, b1, a2 = 0, b2 = 0;  // (cos, sin) or (G0, unused)
+    int j1, j2;
+    if (t == 0) {
+      const double2 h = G[0];
+      a1 = c0 * h.x;
+      a2 = c0 * h.y;
+      j1 = 0;
+      j2 = -1;
+    } else {
+      const int k = t - 1;
+      const double2 hp = G[idx_p[k]], hm = G[idx_m[k]];
+      a1 = 0.5 * c1 * (hp.x + hm.x);    // orbital 1, cos
+      b1 = -0.5 * c1 * (hp.y - hm.y);   // orbital 1, sin
+      a2 = 0.5 * c1 * (hp.y + hm.y);    // orbital 2, cos
+      b2 = 0.5 * c1 * (hp.x - hm.x);    // orbital 2, sin
+      j1 = 1 + 2 * k;
+      j2 = 2 + 2 * k;
+    }
+    for (int o = 0; o < 2; ++o) {
+      const int v = o ? v2 : v1;
+      if (v >= nv) break;
+      const long row = (set * nv + v) * (long)npw;
+      const double va = o ? a2 : a1;
+      const double vb = o ? b2 : b1;
+      for (int q = 0; q < 2; ++q) {
+        const int j = q ? j2 : j1;
+        if (j < 0) break;
+        double val = q ? vb : va;
+        if (A) val += (T[j] + shift - (eps ? eps[v] : 0.0)) * A[row + j];
+        if (beta != 0.0) val += beta * Y[row + j];
+        Y[row + j] = val;
+      }
+    }
+  }
+}
+
+__global__ void k_mul_real(double2* __restrict__ g, long n, long nr, const double* __restrict__ f,
+                           double scale) {
+  for (long e = gtid(); e < n; e += gstride()) {
+    const double m = f[e % nr] * scale;
+    double2 x = g[e];
+    x.x *= m;
+    x.y *= m;
+    g[e] = x;
+  }
+}
+
+__global__ void k_real_part(const double2* __restrict__ g, long nr, double* __restrict__ out) {
+  for (long e = gtid(); e < nr; e += gstride()) out[e] = g[e].x;
+}
+
+__global__ void k_transition_density(const double2* __restrict__ phir, const double2* __restrict__ a,
+                                     int nvh, int nb, long nr, double2* __restrict__ drho) {
+  const long nbh = (nb + 1) / 2;
+  for (long e = gtid(); e < nbh * nr; e += gstride()) {
+    const long r = e % nr;
+    const int bp = (int)(e / nr);
+    double s[2] = {0.0, 0.0};
+    for (int o = 0; o < 2; ++o) {
+      const int b = 2 * bp + o;
+      if (b >= nb) break;
+      const double2* ab = a + (long)b * nvh * nr + r;
+      double acc = 0.0;
+      for (int p = 0; p < nvh; ++p) {
+        const double2 f = phir[(long)p * nr + r];
+        const double2 x = ab[(long)p * nr];
+        acc += f.x * x.x + f.y * x.y;
+      }
+      s[o] = acc;
+    }
+    drho[e] = make_double2(s[0], s[1]);
+  }
+}
+
+__global__ void k_combine(const double2* __restrict__ a, const double2* __restrict__ phir,
+                          const double* __restrict__ V, const double2* __restrict__ vdrho,
+                          const double2* y, double2* out, int nvh, int nb, long nr, double s,
+                          int with_v) {
+  const long n = (long)nb * nvh * nr;
+  for (long e = gtid(); e < n; e += gstride()) {
+    const long r = e % nr;
+    const long bp = e / nr;
+    const int p = (int)(bp % nvh);
+    const int b = (int)(bp / nvh);
+    double2 z = make_double2(0.0, 0.0);
+    if (with_v) {
+      const double v = V[r];
+      const double2 x = a[e];
+      z.x = v * x.x;
+      z.y = v * x.y;
+    }
+    if (vdrho) {
+      const double2 d = vdrho[(long)(b >> 1) * nr + r];
+      const double w = s * ((b & 1) ? d.y : d.x);
+      const double2 f = phir[(long)p * nr + r];
+      z.x += w * f.x;
+      z.y += w * f.y;
+    }
+    if (y) {
+      const double2 q = y[e];
+      z.x -= q.x;
+      z.y -= q.y;
+    }
+    out[e] = z;
+  }
+}
+
+__device__ __forceinline__ double orb_at(const double2* __restrict__ phir, int v, int nv, long nr,
+                                         long r) {
+  if (v >= nv) return 0.0;
+  const double2 f = phir[(long)(v >> 1) * nr + r];
+  return (v & 1) ? f.y : f.x;
+}
+
+// grid q of a tile holds elements 2q, 2q+1 of the 64 per block, element
+// e = j*8 + i is the pair (8I + i, 8J + j)
+__global__ void k_pair_density(const double2* __restrict__ phir, int nv, const int2* __restrict__ IJ,
+                               long nblk, long nr, double2* __restrict__ grids) {
+  const long n = nblk * 32 * nr;
+  for (long e = gtid(); e < n; e += gstride()) {
+    const long r = e % nr;
+    const long q = e / nr;
+    const long blk = q / 32;
+    const int qq = (int)(q % 32);
+    const int j = qq >> 2;
+    const int i0 = 2 * (qq & 3);
+    const int2 b = IJ[blk];
+    const double w = orb_at(phir, 8 * b.y + j, nv, nr, r);
+    const double u0 = orb_at(phir, 8 * b.x + i0, nv, nr, r);
+    const double u1 = orb_at(phir, 8 * b.x + i0 + 1, nv, nr, r);
+    grids[e] = make_double2(u0 * w, u1 * w);
+  }
+}
+
+// dst[rb][dst_blk0 + blk][j][ri][i] from the packed tile
+__global__ void k_tau_store(const double2* __restrict__ grids, const int2* __restrict__ IJ,
+                            long nblk, long nr, int R, double* __restrict__ dst, long dst_nblk,
+                            long dst_blk0) {
+  const long per_rb = nblk * 64 * R;
+  const long nrb = nr / R;
+  const long n = nrb * per_rb;
+  for (long e = gtid(); e < n; e += gstride()) {
+    const long rb = e / per_rb;
+    long w = e % per_rb;
+    const int i = (int)(w % 8);
+    w /= 8;
+    const int ri = (int)(w % R);
+    w /= R;
+    const int j = (int)(w % 8);
+    const long blk = w / 8;
+    const long el = blk * 64 + j * 8 + i;
+    const double2 g = grids[(el >> 1) * nr + rb * R + ri];
+    double v = (el & 1) ? g.y : g.x;
+    const int2 b = IJ[blk];
+    if (b.x == b.y) {
+      if (i > j)
+        v = 0.0;
+      else if (i == j)
+        v *= 0.5;
+    }
+    dst[rb * dst_nblk * 64 * R + (dst_blk0 + blk) * 64 * R + (j * R + ri) * 8 + i] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tau stream: for every grid point r, y[b][v](r) += sum_v' tau_{vv'}(r) a[b][v'](r)
+// with tau stored once per unordered pair as 8x8 blocks (diagonal blocks hold
+// the upper triangle with the diagonal halved).  A workgroup owns R points;
+// a and the y accumulators of those points live in LDS; each lane takes one
+// block at one point and applies it in both directions.
+// ---------------------------------------------------------------------------
+constexpr int NBT = 8;
+
+template <int R>
+__global__ __launch_bounds__(256) void k_tau_stream(const double* __restrict__ tau, long rb_stride,
+                                                    long nblk, const int2* __restrict__ IJ,
+                                                    const double2* __restrict__ a, double2* y,
+                                                    int nb, int nv, int nvh, long nr, int nv8,
+                                                    int accumulate) {
+  extern __shared__ double lds[];
+  double* as = lds;
+  double* ys = lds + (long)nv8 * NBT * R;
+  const long rb = blockIdx.x;
+  const long r0 = rb * R;
+  const int n_el = nv8 * NBT * R;
+  for (int e = threadIdx.x; e < n_el; e += 256) {
+    const int ri = e % R;
+    const int b = (e / R) % NBT;
+    const int v = e / (R * NBT);
+    double av = 0.0, yv = 0.0;
+    if (v < nv && b < nb) {
+      const long gi = ((long)b * nvh + (v >> 1)) * nr + r0 + ri;
+      av = reinterpret_cast<const double*>(a + gi)[v & 1];
+      if (accumulate) yv = reinterpret_cast<const double*>(y + gi)[v & 1];
+    }
+    as[e] = av;
+    ys[e] = yv;
+  }
+  __syncthreads();
+  const int slot = threadIdx.x / R;
+  const int ri = threadIdx.x % R;
+  constexpr int NSLOT = 256 / R;
+  const double* tb = tau + rb * rb_stride;
+  for (long blk = slot; blk < nblk; blk += NSLOT) {
+    const int2 bij = IJ[blk];
+    const double* tp = tb + blk * 64 * R + ri * 8;
+    double aI[8][NBT], acc[8][NBT];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int b = 0; b < NBT; ++b) {
+        aI[i][b] = as[((bij.x * 8 + i) * NBT + b) * R + ri];
+        acc[i][b] = 0.0;
+      }
+#pragma unroll 2
+    for (int j = 0; j < 8; ++j) {
+      double t[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t[i] = tp[j * 8 * R + i];
+      const int wv = bij.y * 8 + j;
+      double aj[NBT], tr[NBT];
+#pragma unroll
+      for (int b = 0; b < NBT; ++b) {
+        aj[b] = as[(wv * NBT + b) * R + ri];
+        tr[b] = 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+          acc[i][b] = fma(t[i], aj[b], acc[i][b]);
+          tr[b] = fma(t[i], aI[i][b], tr[b]);
+        }
+#pragma unroll
+      for (int b = 0; b < NBT; ++b) atomicAdd(&ys[(wv * NBT + b) * R + ri], tr[b]);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int b = 0; b < NBT; ++b) atomicAdd(&ys[((bij.x * 8 + i) * NBT + b) * R + ri], acc[i][b]);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n_el; e += 256) {
+    const int rr = e % R;
+    const int b = (e / R) % NBT;
+    const int v = e / (R * NBT);
+    if (v < nv && b < nb) {
+      const long gi = ((long)b * nvh + (v >> 1)) * nr + r0 + rr;
+      reinterpret_cast<double*>(y + gi)[v & 1] = ys[e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// potential, Coulomb kernel, forces
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int min_image(int i, int n) { return (i < (n + 1) / 2) ? i : i - n; }
+
+__global__ void k_site_potential(const double* __restrict__ xyz, const double* __restrict__ depth,
+                                 const double* __restrict__ width, int nsites, int N1, int N2,
+                                 int N3, double L1, double L2, double L3, double omega,
+                                 double2* __restrict__ out) {
+  const long nr = (long)N1 * N2 * N3;
+  const double tp = 6.283185307179586477;
+  for (long e = gtid(); e < nr; e += gstride()) {
+    const int i3 = (int)(e % N3);
+    const int i2 = (int)((e / N3) % N2);
+    const int i1 = (int)(e / ((long)N2 * N3));
+    const int n1 = min_image(i1, N1), n2 = min_image(i2, N2), n3 = min_image(i3, N3);
+    const bool nyq = ((N1 % 2 == 0) && n1 == -N1 / 2) || ((N2 % 2 == 0) && n2 == -N2 / 2) ||
+                     ((N3 % 2 == 0) && n3 == -N3 / 2);
+    double re = 0.0, im = 0.0;
+    if (!nyq) {
+      const double gx = tp * n1 / L1, gy = tp * n2 / L2, gz = tp * n3 / L3;
+      const double g2 = gx * gx + gy * gy + gz * gz;
+      for (int s = 0; s < nsites; ++s) {
+        const double w = width[s];
+        const double amp = -(depth[s] / omega) * pow(tp * w * w, 1.5) * exp(-0.5 * w * w * g2);
+        const double th = gx * xyz[3 * s] + gy * xyz[3 * s + 1] + gz * xyz[3 * s + 2];
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        re += amp * cs;
+        im -= amp * sn;
+      }
+    }
+    out[e] = make_double2(re, im);
+  }
+}
+
+__global__ void k_coulomb(int N1, int N2, int N3, double L1, double L2, double L3,
+                          double* __restrict__ out) {
+  const long nr = (long)N1 * N2 * N3;
+  const double tp = 6.283185307179586477;
+  for (long e = gtid(); e < nr; e += gstride()) {
+    const int i3 = (int)(e % N3);
+    const int i2 = (int)((e / N3) % N2);
+    const int i1 = (int)(e / ((long)N2 * N3));
+    const double gx = tp * min_image(i1, N1) / L1, gy = tp * min_image(i2, N2) / L2,
+                 gz = tp * min_image(i3, N3) / L3;
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    out[e] = (e == 0) ? 0.0 : 4.0 * M_PI / g2;
+  }
+}
+
+__global__ void k_force_density(const double2* __restrict__ a, const double2* __restrict__ phit,
+                                const double2* __restrict__ z, const double2* __restrict__ phir,
+                                int nvh, long nr, double2* __restrict__ rho) {
+  for (long r = gtid(); r < nr; r += gstride()) {
+    double s = 0.0;
+    for (int p = 0; p < nvh; ++p) {
+      const long i = (long)p * nr + r;
+      const double2 x = a[i], t = phit[i], q = z[i], f = phir[i];
+      s += x.x * x.x + x.y * x.y - (f.x * t.x + f.y * t.y) + 2.0 * (q.x * f.x + q.y * f.y);
+    }
+    rho[r] = make_double2(s, 0.0);
+  }
+}
+
+// part[site][chunk][3]; G over chunk ranges; fixed-order tree reduction
+__global__ __launch_bounds__(256) void k_force_partial(
+    const double2* __restrict__ rhoG, const double* __restrict__ xyz,
+    const double* __restrict__ depth, const double* __restrict__ width, int N1, int N2, int N3,
+    double L1, double L2, double L3, double omega, long chunk, double* __restrict__ part) {
+  __shared__ double red[3][256];
+  const int site = blockIdx.y;
+  const long nr = (long)N1 * N2 * N3;
+  const long g0 = (long)blockIdx.x * chunk;
+  const long g1 = min(nr, g0 + chunk);
+  const double tp = 6.283185307179586477;
+  const double w = width[site];
+  const double cI = (depth[site] / omega) * pow(tp * w * w, 1.5);
+  const double R0 = xyz[3 * site], R1 = xyz[3 * site + 1], R2 = xyz[3 * site + 2];
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (long e = g0 + threadIdx.x; e < g1; e += 256) {
+    const int i3 = (int)(e % N3);
+    const int i2 = (int)((e / N3) % N2);
+    const int i1 = (int)(e / ((long)N2 * N3));
+    const int n1 = min_image(i1, N1), n2 = min_image(i2, N2), n3 = min_image(i3, N3);
+    const bool nyq = ((N1 % 2 == 0) && n1 == -N1 / 2) || ((N2 % 2 == 0) && n2 == -N2 / 2) ||
+                     ((N3 % 2 == 0) && n3 == -N3 / 2);
+    if (nyq) continue;
+    const double gx = tp * n1 / L1, gy = tp * n2 / L2, gz = tp * n3 / L3;
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    double sn, cs;
+    sincos(gx * R0 + gy * R1 + gz * R2, &sn, &cs);
+    const double2 rg = rhoG[e];
+    const double f = cI * exp(-0.5 * w * w * g2) * (sn * rg.x + cs * rg.y);
+    s0 += gx * f;
+    s1 += gy * f;
+    s2 += gz * f;
+  }
+  red[0][threadIdx.x] = s0;
+  red[1][threadIdx.x] = s1;
+  red[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 3; ++c) part[((long)site * gridDim.x + blockIdx.x) * 3 + c] = red[c][0];
+}
+
+__global__ void k_force_final(const double* __restrict__ part, int nsites, int nchunk, double scale,
+                              double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nsites * 3) return;
+  const int site = e / 3, c = e % 3;
+  double s = 0.0;
+  for (int k = 0; k < nchunk; ++k) s += part[((long)site * nchunk + k) * 3 + c];
+  out[e] = scale * s;
+}
+
+// ---------------------------------------------------------------------------
+// solver vector helpers
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_row_dots(const double* __restrict__ A,
+                                                  const double* __restrict__ B, long len,
+                                                  double* __restrict__ out) {
+  __shared__ double red[256];
+  const long row = blockIdx.x;
+  const double* a = A + row * len;
+  const double* b = B + row * len;
+  double s = 0.0;
+  for (long j = threadIdx.x; j < len; j += 256) s += a[j] * b[j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[row] = red[0];
+}
+
+__global__ void k_row_axpby(const double* __restrict__ a, const double* __restrict__ X,
+                            const double* __restrict__ b, double* __restrict__ Y, long rows,
+                            long len) {
+  for (long e = gtid(); e < rows * len; e += gstride()) {
+    const long r = e / len;
+    const double av = a ? a[r] : 1.0;
+    const double bv = b ? b[r] : 1.0;
+    Y[e] = av * X[e] + bv * Y[e];
+  }
+}
+
+__global__ void k_row_scale(const double* __restrict__ s, double* __restrict__ Y, long rows,
+                            long len) {
+  for (long e = gtid(); e < rows * len; e += gstride()) Y[e] *= s[e / len];
+}
+
+__global__ void k_axpby(double alpha, const double* __restrict__ X, double beta,
+                        double* __restrict__ Y, long n) {
+  for (long e = gtid(); e < n; e += gstride()) Y[e] = alpha * X[e] + (beta == 0.0 ? 0.0 : beta * Y[e]);
+}
+
+__global__ void k_precond_davidson(const double* __restrict__ R, double* __restrict__ T,
+                                   const double* __restrict__ Tk, const double* __restrict__ eps,
+                                   const double* __restrict__ theta, double shift, int nk, int nv,
+                                   int npw) {
+  const long n = (long)nk * nv * npw;
+  for (long e = gtid(); e < n; e += gstride()) {
+    const int j = (int)(e % npw);
+    const int v = (int)((e / npw) % nv);
+    const int k = (int)(e / ((long)npw * nv));
+    double den = Tk[j] - eps[v] + shift - theta[k];
+    if (fabs(den) < 0.1) den = (den < 0.0) ? -0.1 : 0.1;
+    T[e] = R[e] / den;
+  }
+}
+
+__global__ void k_precond_cg(const double* __restrict__ R, double* __restrict__ T,
+                             const double* __restrict__ Tk, const double* __restrict__ eps,
+                             double shift, int nv, int npw) {
+  const long n = (long)nv * npw;
+  for (long e = gtid(); e < n; e += gstride()) {
+    const int j = (int)(e % npw);
+    const int v = (int)(e / npw);
+    const double den = fmax(Tk[j] - eps[v] + shift, 0.1);
+    T[e] = R[e] / den;
+  }
+}
+
+}  // namespace
+
+// ============================================================================
+// launchers
+// ============================================================================
+#define CHECK_LAUNCH() BSE_HIP(hipGetLastError())
+
+int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, double2* grid,
+                 int accumulate, hipStream_t st) {
+  const int nvh = (nv + 1) / 2;
+  const long ngrid = (long)nset * nvh;
+  if (ngrid <= 0) return BSE_OK;
+  const dim3 g((unsigned)((m.nhalf + 1 + TPB - 1) / TPB), (unsigned)std::min(ngrid, 65535L));
+  hipLaunchKernelGGL(k_scatter, g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr, X,
+                     nv, nvh, ngrid, grid, accumulate, 1.0 / std::sqrt(m.omega),
+                     1.0 / std::sqrt(2.0 * m.omega));
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int gather_sets(const SphereMap& m, const double2* grid, int nv, int nset, double scale,
+                const double* A, const double* T, const double* eps, double shift, double beta,
+                double* Y, hipStream_t st) {
+  const int nvh = (nv + 1) / 2;
+  const long ngrid = (long)nset * nvh;
+  if (ngrid <= 0) return BSE_OK;
+  const dim3 g((unsigned)((m.nhalf + 1 + TPB - 1) / TPB), (unsigned)std::min(ngrid, 65535L));
+  hipLaunchKernelGGL(k_gather, g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr, grid,
+                     nv, nvh, ngrid, scale * std::sqrt(m.omega), scale * std::sqrt(2.0 * m.omega),
+                     A, T, eps, shift, beta, Y);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int mul_real_field(double2* grid, long ngrid, long nr, const double* f, double scale,
+                   hipStream_t st) {
+  const long n = ngrid * nr;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_mul_real, dim3(nblocks(n)), dim3(TPB), 0, st, grid, n, nr, f, scale);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int real_part(const double2* grid, long nr, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_real_part, dim3(nblocks(nr)), dim3(TPB), 0, st, grid, nr, out);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int transition_density(const double2* phir, const double2* a, int nv, int nb, long nr,
+                       double2* drho, hipStream_t st) {
+  const long n = (long)((nb + 1) / 2) * nr;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_transition_density, dim3(nblocks(n)), dim3(TPB), 0, st, phir, a,
+                     (nv + 1) / 2, nb, nr, drho);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int combine(const double2* a, const double2* phir, const double* V, const double2* vdrho,
+            const double2* y, double2* out, int nv, int nb, long nr, double s, int with_v,
+            hipStream_t st) {
+  const long n = (long)nb * ((nv + 1) / 2) * nr;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_combine, dim3(nblocks(n)), dim3(TPB), 0, st, a, phir, V, vdrho, y, out,
+                     (nv + 1) / 2, nb, nr, s, with_v);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int pair_density(const double2* phir, int nv, const int2* blkIJ, long nblk, long nr,
+                 double2* grids, hipStream_t st) {
+  const long n = nblk * 32 * nr;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_pair_density, dim3(nblocks(n)), dim3(TPB), 0, st, phir, nv, blkIJ, nblk, nr,
+                     grids);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R, double* dst,
+              long dst_nblk, long dst_blk0, hipStream_t st) {
+  const long n = (nr / R) * nblk * 64 * R;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_tau_store, dim3(nblocks(n)), dim3(TPB), 0, st, grids, blkIJ, nblk, nr, R,
+                     dst, dst_nblk, dst_blk0);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+size_t tau_stream_lds(int nv, int R) {
+  const int nv8 = (nv + 7) / 8 * 8;
+  return 2 * sizeof(double) * (size_t)nv8 * NBT * R;
+}
+
+int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
+               const double2* a, double2* y, int nb, int nv, long nr, int accumulate,
+               size_t max_lds, hipStream_t st) {
+  if (nb > NBT) return fail(BSE_EINVAL, "tau_stream: at most %d vectors per call", NBT);
+  if (nr % R) return fail(BSE_EINVAL, "tau_stream: grid size not a multiple of %d", R);
+  const size_t shm = tau_stream_lds(nv, R);
+  if (shm > max_lds) return fail(BSE_EINVAL, "tau_stream: %zu bytes of LDS exceed %zu", shm, max_lds);
+  const int nv8 = (nv + 7) / 8 * 8;
+  const long nrb = nr / R;
+  if (nrb > 0x7fffffffL) return fail(BSE_EINVAL, "tau_stream: grid too large");
+  const long stride = buf_nblk * 64 * R;
+  if (R == 2) {
+    hipLaunchKernelGGL(k_tau_stream<2>, dim3((unsigned)nrb), dim3(256), shm, st, tau, stride, nblk,
+                       blkIJ, a, y, nb, nv, (nv + 1) / 2, nr, nv8, accumulate);
+  } else if (R == 1) {
+    hipLaunchKernelGGL(k_tau_stream<1>, dim3((unsigned)nrb), dim3(256), shm, st, tau, stride, nblk,
+                       blkIJ, a, y, nb, nv, (nv + 1) / 2, nr, nv8, accumulate);
+  } else {
+    return fail(BSE_EINVAL, "tau_stream: R = %d unsupported", R);
+  }
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int tau_stream_set_lds_limit(size_t bytes) {
+  BSE_HIP(hipFuncSetAttribute((const void*)k_tau_stream<2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  BSE_HIP(hipFuncSetAttribute((const void*)k_tau_stream<1>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return BSE_OK;
+}
+
+int site_potential(const double* xyz, const double* depth, const double* width, int nsites,
+                   const int grid[3], const double cell[3], double2* out, hipStream_t st) {
+  const long nr = (long)grid[0] * grid[1] * grid[2];
+  hipLaunchKernelGGL(k_site_potential, dim3(nblocks(nr)), dim3(TPB), 0, st, xyz, depth, width,
+                     nsites, grid[0], grid[1], grid[2], cell[0], cell[1], cell[2],
+                     cell[0] * cell[1] * cell[2], out);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int coulomb_kernel(const int grid[3], const double cell[3], double* out, hipStream_t st) {
+  const long nr = (long)grid[0] * grid[1] * grid[2];
+  hipLaunchKernelGGL(k_coulomb, dim3(nblocks(nr)), dim3(TPB), 0, st, grid[0], grid[1], grid[2],
+                     cell[0], cell[1], cell[2], out);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int force_density(const double2* a, const double2* phit, const double2* z, const double2* phir,
+                  int nv, long nr, double2* rho, hipStream_t st) {
+  hipLaunchKernelGGL(k_force_density, dim3(nblocks(nr)), dim3(TPB), 0, st, a, phit, z, phir,
+                     (nv + 1) / 2, nr, rho);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+static long force_chunks(long nr) {
+  long c = (nr + 4095) / 4096;
+  if (c > 256) c = 256;
+  if (c < 1) c = 1;
+  return c;
+}
+
+long force_reduce_work(int nsites, long nr) { return (long)nsites * force_chunks(nr) * 3; }
+
+int force_reduce(const double2* rhoG, const double* xyz, const double* depth, const double* width,
+                 int nsites, const int grid[3], const double cell[3], double* part,
+                 long part_len, double* out_dev, hipStream_t st) {
+  if (nsites <= 0) return BSE_OK;
+  const long nr = (long)grid[0] * grid[1] * grid[2];
+  const long nch = force_chunks(nr);
+  if (nsites * nch * 3 > part_len) return fail(BSE_EINVAL, "force_reduce: work too small");
+  const long chunk = (nr + nch - 1) / nch;
+  const double omega = cell[0] * cell[1] * cell[2];
+  hipLaunchKernelGGL(k_force_partial, dim3((unsigned)nch, (unsigned)nsites), dim3(256), 0, st,
+                     rhoG, xyz, depth, width, grid[0], grid[1], grid[2], cell[0], cell[1],
+                     cell[2], omega, chunk, part);
+  CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_force_final, dim3((unsigned)((nsites * 3 + 255) / 256)), dim3(256), 0, st,
+                     part, nsites, (int)nch, omega / (double)nr, out_dev);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int row_dots(const double* A, const double* B, long rows, long len, double* out, hipStream_t st) {
+  if (rows <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_row_dots, dim3((unsigned)rows), dim3(256), 0, st, A, B, len, out);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int row_axpby(const double* a, const double* X, const double* b, double* Y, long rows, long len,
+              hipStream_t st) {
+  const long n = rows * len;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_row_axpby, dim3(nblocks(n)), dim3(TPB), 0, st, a, X, b, Y, rows, len);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int row_scale(const double* s, double* Y, long rows, long len, hipStream_t st) {
+  const long n = rows * len;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_row_scale, dim3(nblocks(n)), dim3(TPB), 0, st, s, Y, rows, len);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int axpby(double alpha, const double* X, double beta, double* Y, long n, hipStream_t st) {
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(TPB), 0, st, alpha, X, beta, Y, n);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int precond_davidson(const double* R, double* T, const double* Tk, const double* eps,
+                     const double* theta, double shift, int nk, int nv, int npw, hipStream_t st) {
+  const long n = (long)nk * nv * npw;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_precond_davidson, dim3(nblocks(n)), dim3(TPB), 0, st, R, T, Tk, eps, theta,
+                     shift, nk, nv, npw);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int precond_cg(const double* R, double* T, const double* Tk, const double* eps, double shift,
+               int nv, int npw, hipStream_t st) {
+  const long n = (long)nv * npw;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_precond_cg, dim3(nblocks(n)), dim3(TPB), 0, st, R, T, Tk, eps, shift, nv,
+                     npw);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+}  // namespace bsex

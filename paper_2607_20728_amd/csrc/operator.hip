@@ -1,0 +1,283 @@
+// The DMPT BSE operator on the device: projector, transforms, K1e, tau
+// build and stream, combine, diagonal term (Eqs. 1-3).
+#include <cmath>
+
+#include "context.h"
+
+namespace bsex {
+
+// ---------------------------------------------------------------------------
+// allocation and profiling helpers
+// ---------------------------------------------------------------------------
+int ctx_alloc(bse_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BSE_ENOMEM, "device allocation of %zu bytes failed (%s)", bytes,
+                hipGetErrorString(e));
+  }
+  c->allocs.push_back(DevBuf{q, bytes});
+  *p = q;
+  return BSE_OK;
+}
+
+void ctx_release(bse_ctx* c, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < c->allocs.size(); ++i)
+    if (c->allocs[i].p == p) {
+      (void)hipFree(p);
+      c->allocs.erase(c->allocs.begin() + i);
+      return;
+    }
+}
+
+static hipEvent_t ev_get(bse_ctx* c) {
+  if (c->ev_used < c->ev_pool.size()) return c->ev_pool[c->ev_used++];
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  c->ev_pool.push_back(e);
+  ++c->ev_used;
+  return e;
+}
+
+PhaseScope::PhaseScope(bse_ctx* c_, int ph_) : c(c_), ph(ph_) {
+  if (!c->prof) return;
+  e1 = ev_get(c);
+  if (e1) (void)hipEventRecord(e1, c->st);
+}
+
+PhaseScope::~PhaseScope() {
+  if (!c->prof || !e1) return;
+  hipEvent_t e2 = ev_get(c);
+  if (!e2) return;
+  (void)hipEventRecord(e2, c->st);
+  c->ev_open.push_back({ph, {e1, e2}});
+}
+
+int prof_collect(bse_ctx* c) {
+  if (c->ev_open.empty()) {
+    c->ev_used = 0;
+    return BSE_OK;
+  }
+  BSE_HIP(hipStreamSynchronize(c->st));
+  for (auto& o : c->ev_open) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, o.second.first, o.second.second) == hipSuccess) {
+      c->ph_ms[o.first] += ms;
+      c->ph_n[o.first] += 1;
+    }
+  }
+  c->ev_open.clear();
+  c->ev_used = 0;
+  return BSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// projector P_c = 1 - sum_v |phi_v><phi_v| on nset sets of nv orbitals
+// ---------------------------------------------------------------------------
+static int ensure_ov(bse_ctx* c, int nset) {
+  const size_t need = (size_t)c->nv * c->nv * nset;
+  static_assert(sizeof(double) == 8, "");
+  for (auto& b : c->allocs)
+    if (b.p == c->Ov && b.bytes >= need * sizeof(double)) return BSE_OK;
+  ctx_release(c, c->Ov);
+  c->Ov = nullptr;
+  return ctx_alloc_t(c, &c->Ov, need);
+}
+
+int proj_c(bse_ctx* c, const double* X, double* Y, int nset) {
+  if (nset <= 0) return BSE_OK;
+  PhaseScope ps(c, PH_PROJ);
+  BSE_TRY(ensure_ov(c, nset));
+  const long npw = c->basis.npw, nv = c->nv, n = (long)nset * nv;
+  // Ov[w][(s,v)] = <phi_w | x_{s,v}>
+  BSE_TRY(dgemm(0, 1, nv, n, npw, 1.0, c->Phi, npw, X, npw, 0.0, c->Ov, n, c->st));
+  if (Y != X) BSE_HIP(hipMemcpyAsync(Y, X, sizeof(double) * n * npw, hipMemcpyDeviceToDevice, c->st));
+  // Y -= Ov^T Phi
+  BSE_TRY(dgemm(1, 0, n, npw, nv, -1.0, c->Ov, n, c->Phi, npw, 1.0, Y, npw, c->st));
+  return BSE_OK;
+}
+
+// grid values of nset sets of nvs orbitals (two orbitals per complex grid)
+int to_grid(bse_ctx* c, const double* X, int nvs, int nset, double2* grids) {
+  PhaseScope ps(c, PH_FFT_INV);
+  const long ng = (long)nset * ((nvs + 1) / 2);
+  BSE_HIP(hipMemsetAsync(grids, 0, sizeof(double2) * ng * c->basis.nr, c->st));
+  BSE_TRY(scatter_sets(c->map, X, nvs, nset, grids, 0, c->st));
+  BSE_TRY(fft3d(c->fft, grids, ng, +1, c->st));
+  return BSE_OK;
+}
+
+// Y = (T + shift - eps_v) X + <e| V(r) x(r)> on nset sets of nvs orbitals
+// (eps indexed by position in the set, NULL for none), optionally projected
+// by P_c (then nvs must be c->nv).
+int apply_H(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double2* grids,
+            double shift, const double* eps, int project) {
+  BSE_TRY(to_grid(c, X, nvs, nset, grids));
+  const long ng = (long)nset * ((nvs + 1) / 2);
+  {
+    PhaseScope ps(c, PH_COMBINE);
+    BSE_TRY(mul_real_field(grids, ng, c->basis.nr, c->Vr, 1.0, c->st));
+  }
+  {
+    PhaseScope ps(c, PH_FFT_FWD);
+    BSE_TRY(fft3d(c->fft, grids, ng, -1, c->st));
+    BSE_TRY(gather_sets(c->map, grids, nvs, nset, 1.0 / (double)c->basis.nr, X, c->T, eps, shift,
+                        0.0, Y, c->st));
+  }
+  if (project) BSE_TRY(proj_c(c, Y, Y, nset));
+  return BSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tau_{vv'} = W(orb_v orb_v') for the 8x8 blocks [gb0, gb0 + nblk)
+//   bare part: v_c(G) on every grid frequency; PDEP part (Eq. 3):
+//   sum_j e_j [V^1/2 P C P^T V^1/2 rho_S]_j  via two GEMMs per tile.
+// ---------------------------------------------------------------------------
+int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double* dst,
+                    long dst_nblk, long dst_blk0, int mask) {
+  if (nblk <= 0) return BSE_OK;
+  if (nblk > c->tile_blk) return fail(BSE_EINVAL, "tau build: tile of %ld blocks too large", nblk);
+  const long nr = c->basis.nr, npw = c->basis.npw;
+  const long ng = nblk * 32, ne = nblk * 64;
+  BSE_TRY(pair_density(orbr, c->nv, c->blkIJ + gb0, nblk, nr, c->tile_grids, c->st));
+  BSE_TRY(fft3d(c->fft, c->tile_grids, ng, -1, c->st));
+  SphereMap m64 = c->map;
+  const bool pdep = (mask & BSE_K_1D_PDEP) && c->npdep > 0;
+  if (pdep) {
+    // rho_S[e][j] = <e_j | rho_e>
+    BSE_TRY(gather_sets(m64, c->tile_grids, 64, (int)nblk, 1.0 / (double)nr, nullptr, nullptr,
+                        nullptr, 0.0, 0.0, c->tile_RS, c->st));
+    BSE_TRY(dgemm(0, 0, ne, c->npdep, npw, 1.0, c->tile_RS, npw, c->Pt, c->npdep, 0.0, c->tile_T,
+                  c->npdep, c->st));
+    BSE_TRY(dgemm(0, 1, ne, npw, c->npdep, 1.0, c->tile_T, c->npdep, c->Ptc, c->npdep, 0.0,
+                  c->tile_F, npw, c->st));
+  }
+  if (mask & BSE_K_1D_BARE)
+    BSE_TRY(mul_real_field(c->tile_grids, ng, nr, c->vc, 1.0 / (double)nr, c->st));
+  else
+    BSE_HIP(hipMemsetAsync(c->tile_grids, 0, sizeof(double2) * ng * nr, c->st));
+  if (pdep) BSE_TRY(scatter_sets(m64, c->tile_F, 64, (int)nblk, c->tile_grids, 1, c->st));
+  BSE_TRY(fft3d(c->fft, c->tile_grids, ng, +1, c->st));
+  BSE_TRY(tau_store(c->tile_grids, c->blkIJ + gb0, nblk, nr, c->R, dst, dst_nblk, dst_blk0, c->st));
+  return BSE_OK;
+}
+
+// y[b][v] = sum_v' tau_{vv'} a[b][v'] over all pairs: cached blocks, then
+// tiles rebuilt on the fly.  orbr are the orbitals tau is built from.
+static int tau_contract(bse_ctx* c, const double2* orbr, const double2* a, double2* y, int nb,
+                        int mask, bool use_cache) {
+  int first = 1;
+  const long nr = c->basis.nr;
+  long start = 0;
+  if (use_cache && c->nblk_cached > 0) {
+    PhaseScope ps(c, PH_TAU_STREAM);
+    BSE_TRY(tau_stream(c->tau_cache, c->nblk_cached, c->nblk_cached, c->blkIJ, c->R, a, y, nb,
+                       c->nv, nr, 0, c->max_lds, c->st));
+    first = 0;
+    start = c->nblk_cached;
+  }
+  for (long gb0 = start; gb0 < c->nblk; gb0 += c->tile_blk) {
+    const long nt = std::min(c->tile_blk, c->nblk - gb0);
+    {
+      PhaseScope ps(c, PH_TAU_BUILD);
+      BSE_TRY(tau_build_range(c, orbr, gb0, nt, c->rebuild_buf, nt, 0, mask));
+    }
+    PhaseScope ps(c, PH_TAU_STREAM);
+    BSE_TRY(tau_stream(c->rebuild_buf, nt, nt, c->blkIJ + gb0, c->R, a, y, nb, c->nv, nr,
+                       first ? 0 : 1, c->max_lds, c->st));
+    first = 0;
+  }
+  return BSE_OK;
+}
+
+int ensure_apply_work(bse_ctx* c, int nbc) {
+  if (c->nbc >= nbc) return BSE_OK;
+  ctx_release(c, c->A_s);
+  ctx_release(c, c->Zs);
+  ctx_release(c, c->agrid);
+  ctx_release(c, c->ygrid);
+  ctx_release(c, c->drho);
+  c->A_s = c->Zs = nullptr;
+  c->agrid = c->ygrid = c->drho = nullptr;
+  c->nbc = 0;
+  const size_t npw = c->basis.npw, nr = c->basis.nr;
+  BSE_TRY(ctx_alloc_t(c, &c->A_s, (size_t)nbc * c->nv * npw));
+  BSE_TRY(ctx_alloc_t(c, &c->Zs, (size_t)nbc * c->nv * npw));
+  BSE_TRY(ctx_alloc_t(c, &c->agrid, (size_t)nbc * c->nvh * nr));
+  BSE_TRY(ctx_alloc_t(c, &c->ygrid, (size_t)nbc * c->nvh * nr));
+  BSE_TRY(ctx_alloc_t(c, &c->drho, (size_t)((nbc + 1) / 2) * nr));
+  c->nbc = nbc;
+  return BSE_OK;
+}
+
+// Y = P_c (D + s K1e - K1d) P_c X for nb <= c->nbc vectors
+int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
+  const long nr = c->basis.nr;
+  BSE_TRY(proj_c(c, X, c->A_s, nb));
+  BSE_TRY(to_grid(c, c->A_s, c->nv, nb, c->agrid));
+  const double2* vdrho = nullptr;
+  if (c->kmask & BSE_K_1E) {
+    PhaseScope ps(c, PH_K1E);
+    const long nbh = (nb + 1) / 2;
+    BSE_TRY(transition_density(c->phir, c->agrid, c->nv, nb, nr, c->drho, c->st));
+    BSE_TRY(fft3d(c->fft, c->drho, nbh, -1, c->st));
+    BSE_TRY(mul_real_field(c->drho, nbh, nr, c->vc, 1.0 / (double)nr, c->st));
+    BSE_TRY(fft3d(c->fft, c->drho, nbh, +1, c->st));
+    vdrho = c->drho;
+  }
+  const double2* y = nullptr;
+  if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
+    BSE_TRY(tau_contract(c, c->phir, c->agrid, c->ygrid, nb, c->kmask, true));
+    y = c->ygrid;
+  }
+  {
+    PhaseScope ps(c, PH_COMBINE);
+    BSE_TRY(combine(c->agrid, c->phir, c->Vr, vdrho, y, c->ygrid, c->nv, nb, nr, c->spin,
+                    (c->kmask & BSE_K_D) ? 1 : 0, c->st));
+  }
+  {
+    PhaseScope ps(c, PH_FFT_FWD);
+    BSE_TRY(fft3d(c->fft, c->ygrid, (long)nb * c->nvh, -1, c->st));
+    BSE_TRY(gather_sets(c->map, c->ygrid, c->nv, nb, 1.0 / (double)nr,
+                        (c->kmask & BSE_K_D) ? c->A_s : nullptr, c->T, c->eps_d, c->scissor, 0.0,
+                        c->Zs, c->st));
+  }
+  BSE_TRY(proj_c(c, c->Zs, Y, nb));
+  return BSE_OK;
+}
+
+// kernel part of the operator on one exciton, before P_c, gathered:
+//   Kt_v = <e| s (v_c*Drho) phi_v - sum_v' tau_{v'v} a_v' >
+int kernel_part(bse_ctx* c, const double2* agrid, double* Kt) {
+  const long nr = c->basis.nr;
+  const double2* vdrho = nullptr;
+  if (c->kmask & BSE_K_1E) {
+    BSE_TRY(transition_density(c->phir, agrid, c->nv, 1, nr, c->drho, c->st));
+    BSE_TRY(fft3d(c->fft, c->drho, 1, -1, c->st));
+    BSE_TRY(mul_real_field(c->drho, 1, nr, c->vc, 1.0 / (double)nr, c->st));
+    BSE_TRY(fft3d(c->fft, c->drho, 1, +1, c->st));
+    vdrho = c->drho;
+  }
+  const double2* y = nullptr;
+  if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
+    BSE_TRY(tau_contract(c, c->phir, agrid, c->ygrid, 1, c->kmask, true));
+    y = c->ygrid;
+  }
+  BSE_TRY(combine(agrid, c->phir, c->Vr, vdrho, y, c->ygrid, c->nv, 1, nr, c->spin, 0, c->st));
+  BSE_TRY(fft3d(c->fft, c->ygrid, c->nvh, -1, c->st));
+  BSE_TRY(gather_sets(c->map, c->ygrid, c->nv, 1, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0,
+                      0.0, Kt, c->st));
+  return BSE_OK;
+}
+
+// sigma term of U:  y_v = sum_v' W(a_v' a_v) phi_v'  (sigma built from a,
+// contracted with phi), tiles rebuilt for every block.
+int sigma_phi(bse_ctx* c, const double2* agrid, double2* y) {
+  return tau_contract(c, agrid, c->phir, y, 1, c->kmask, false);
+}
+
+}  // namespace bsex

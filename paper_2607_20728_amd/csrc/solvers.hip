@@ -1,0 +1,561 @@
+// Solvers driving the operator: block Davidson for the excitons (Eq. 1),
+// the U vector (SM Sec. I), the Z-vector CG (Eq. 7 with the KS kernels of
+// the local synthetic Hamiltonian zero), the force contraction (Eqs. 4-6)
+// and a Chebyshev-filtered subspace eigensolver for the ground state.
+//
+// All long vectors stay on the device; only small projected matrices and
+// per-band scalars cross to the host.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+#include <random>
+#include <vector>
+
+#include "context.h"
+
+namespace bsex {
+
+constexpr double kPrecondShift = 0.25;  // Ha, kinetic preconditioner shift
+
+int gram_tall(bse_ctx* c, const double* A, long m, const double* B, long n, long len, double* C) {
+  const long need = dgemm_tall_work(m, n, len);
+  if (need > c->gw_len) {
+    ctx_release(c, c->gw);
+    c->gw = nullptr;
+    c->gw_len = 0;
+    BSE_TRY(ctx_alloc_t(c, &c->gw, (size_t)need));
+    c->gw_len = need;
+  }
+  return dgemm_tall(m, n, len, 1.0, A, len, B, len, 0.0, C, n, c->gw, c->gw_len, c->st);
+}
+
+namespace {
+
+struct DVec {  // scoped device scratch owned by the context
+  bse_ctx* c;
+  double* p = nullptr;
+  explicit DVec(bse_ctx* c_) : c(c_) {}
+  int alloc(size_t n) { return ctx_alloc_t(c, &p, n); }
+  ~DVec() { ctx_release(c, p); }
+  DVec(const DVec&) = delete;
+  DVec& operator=(const DVec&) = delete;
+};
+
+int to_host(bse_ctx* c, const double* d, double* h, size_t n) {
+  if (n == 0) return BSE_OK;
+  BSE_HIP(hipMemcpyAsync(h, d, sizeof(double) * n, hipMemcpyDeviceToHost, c->st));
+  BSE_HIP(hipStreamSynchronize(c->st));
+  return BSE_OK;
+}
+
+int to_dev(bse_ctx* c, const double* h, double* d, size_t n) {
+  if (n == 0) return BSE_OK;
+  BSE_HIP(hipMemcpyAsync(d, h, sizeof(double) * n, hipMemcpyHostToDevice, c->st));
+  BSE_HIP(hipStreamSynchronize(c->st));
+  return BSE_OK;
+}
+
+int copy_dev(bse_ctx* c, const double* s, double* d, size_t n) {
+  if (n == 0 || s == d) return BSE_OK;
+  BSE_HIP(hipMemcpyAsync(d, s, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  return BSE_OK;
+}
+
+int dots_host(bse_ctx* c, const double* A, const double* B, long rows, long len, double* scratch,
+              std::vector<double>& out) {
+  BSE_TRY(row_dots(A, B, rows, len, scratch, c->st));
+  out.resize(rows);
+  return to_host(c, scratch, out.data(), rows);
+}
+
+double elapsed_ms(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// apply the operator to n vectors in chunks of at most c->nbc
+int apply_n(bse_ctx* c, long n, const double* X, double* Y) {
+  const long L = (long)c->nv * c->basis.npw;
+  for (long i = 0; i < n; i += c->nbc) {
+    const int k = (int)std::min<long>(c->nbc, n - i);
+    BSE_TRY(apply_chunk(c, k, X + i * L, Y + i * L));
+  }
+  return BSE_OK;
+}
+
+}  // namespace
+
+// Orthonormalise the rows of W[k][len] against V[m][len] and among
+// themselves.  Rows are normalised first; two rounds of (project out V,
+// then orthonormalise through the eigen-decomposition of the Gram matrix)
+// follow.  Directions with Gram eigenvalue below drop^2 are dropped in the
+// first round.  Surviving rows are compacted to the front of W; returns
+// their number, or a negative status.
+int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len, double* tmp,
+               int passes, double drop) {
+  if (k <= 0) return 0;
+  PhaseScope ps(c, PH_SOLVER);
+  DVec sm(c);
+  const size_t smn = (size_t)k * (size_t)std::max(m, k) + (size_t)k * k + 2 * (size_t)k + 16;
+  if (sm.alloc(smn) != BSE_OK) return -BSE_ENOMEM;
+  double* Cm = sm.p;                                     // [k][m]
+  double* Bm = sm.p + (size_t)k * std::max(m, k);        // [k][k]
+  double* vec = Bm + (size_t)k * k;                      // [2k]
+  std::vector<double> nrm;
+  if (dots_host(c, W, W, k, len, vec, nrm) != BSE_OK) return -BSE_EHIP;
+  std::vector<double> sc(k);
+  for (long i = 0; i < k; ++i) sc[i] = nrm[i] > 0 ? 1.0 / std::sqrt(nrm[i]) : 0.0;
+  if (to_dev(c, sc.data(), vec, k) != BSE_OK) return -BSE_EHIP;
+  if (row_scale(vec, W, k, len, c->st) != BSE_OK) return -BSE_EHIP;
+  long kk = k;
+  for (int pass = 0; pass < passes; ++pass) {
+    if (m > 0) {
+      if (gram_tall(c, W, kk, V, m, len, Cm) != BSE_OK) return -BSE_EHIP;
+      if (dgemm(0, 0, kk, len, m, -1.0, Cm, m, V, len, 1.0, W, len, c->st) != BSE_OK)
+        return -BSE_EHIP;
+    }
+    if (gram_tall(c, W, kk, W, kk, len, Bm) != BSE_OK) return -BSE_EHIP;
+    std::vector<double> G((size_t)kk * kk), lam(kk);
+    if (to_host(c, Bm, G.data(), (size_t)kk * kk) != BSE_OK) return -BSE_EHIP;
+    if (host_syev((int)kk, G.data(), lam.data())) return -fail(BSE_EINVAL, "Gram eigensolver failed");
+    const double thr = (pass == 0) ? drop * drop : 1e-300;
+    std::vector<double> Bh;
+    long knew = 0;
+    for (long j = kk - 1; j >= 0; --j) {  // largest first
+      if (!(lam[j] > thr)) continue;
+      const double s = 1.0 / std::sqrt(lam[j]);
+      for (long i = 0; i < kk; ++i) Bh.push_back(s * G[(size_t)i * kk + j]);
+      ++knew;
+    }
+    if (knew == 0) return 0;
+    if (to_dev(c, Bh.data(), Bm, Bh.size()) != BSE_OK) return -BSE_EHIP;
+    if (dgemm(0, 0, knew, len, kk, 1.0, Bm, kk, W, len, 0.0, tmp, len, c->st) != BSE_OK)
+      return -BSE_EHIP;
+    if (copy_dev(c, tmp, W, (size_t)knew * len) != BSE_OK) return -BSE_EHIP;
+    kk = knew;
+  }
+  return (int)kk;
+}
+
+// ---------------------------------------------------------------------------
+// Davidson (the paper names no eigensolver; its target is the lowest
+// eigenpairs of P_c M P_c)
+// ---------------------------------------------------------------------------
+int davidson(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double* Xout,
+             bse_solver_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
+  const int maxit = (o && o->max_iter > 0) ? o->max_iter : 300;
+  int nb = (o && o->block > 0) ? o->block : ns + 4;
+  if (nb < ns) nb = ns;
+  int maxsub = (o && o->max_subspace > 0) ? o->max_subspace : 8 * nb;
+  if (maxsub < 3 * nb) maxsub = 3 * nb;
+  const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
+  BSE_TRY(ensure_apply_work(c, std::min(nb, 8)));
+  DVec V(c), AV(c), W(c), AW(c), X(c), AX(c), sm(c);
+  BSE_TRY(V.alloc((size_t)maxsub * L));
+  BSE_TRY(AV.alloc((size_t)maxsub * L));
+  BSE_TRY(W.alloc((size_t)2 * nb * L));
+  BSE_TRY(AW.alloc((size_t)2 * nb * L));
+  BSE_TRY(X.alloc((size_t)nb * L));
+  BSE_TRY(AX.alloc((size_t)nb * L));
+  BSE_TRY(sm.alloc((size_t)maxsub * maxsub + 4 * (size_t)maxsub + 64));
+  double* Cd = sm.p;                              // [m][k] coefficients
+  double* vecd = sm.p + (size_t)maxsub * maxsub;  // small vectors
+  int applies = 0;
+
+  // ---- initial block: user vectors, then lowest bare transitions ----------
+  BSE_HIP(hipMemsetAsync(W.p, 0, sizeof(double) * (size_t)nb * L, c->st));
+  int k = 0;
+  if (o && o->x0_dev && o->n_x0 > 0) {
+    k = std::min(o->n_x0, nb);
+    BSE_TRY(copy_dev(c, o->x0_dev, W.p, (size_t)k * L));
+  }
+  const int nc = c->norb - c->nv;
+  if (k < nb && nc > 0) {
+    std::vector<std::pair<double, long>> tr;
+    for (long v = 0; v < nv; ++v)
+      for (long cc = 0; cc < nc; ++cc) tr.push_back({c->eps_h[nv + cc] - c->eps_h[v], v * nc + cc});
+    std::stable_sort(tr.begin(), tr.end(),
+                     [](const auto& a, const auto& b) { return a.first < b.first; });
+    for (size_t q = 0; q < tr.size() && k < nb; ++q, ++k) {
+      const long v = tr[q].second / nc, cc = tr[q].second % nc;
+      BSE_TRY(copy_dev(c, c->Phi + (nv + cc) * npw, W.p + (size_t)k * L + v * npw, npw));
+    }
+  }
+  if (k < nb) {  // plane waves of lowest kinetic model, kept if they survive P_c
+    std::vector<std::pair<double, long>> d;
+    for (long v = 0; v < nv; ++v)
+      for (long j = 0; j < npw; ++j)
+        d.push_back({0.5 * c->basis.g2[j] - c->eps_h[v] + c->scissor + kPrecondShift, v * npw + j});
+    std::stable_sort(d.begin(), d.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    size_t q = 0;
+    std::vector<double> one(1, 1.0), nrm;
+    while (k < nb && q < d.size()) {
+      double* w = W.p + (size_t)k * L;
+      BSE_HIP(hipMemsetAsync(w, 0, sizeof(double) * L, c->st));
+      BSE_TRY(to_dev(c, one.data(), w + d[q].second, 1));
+      ++q;
+      BSE_TRY(proj_c(c, w, w, 1));
+      BSE_TRY(dots_host(c, w, w, 1, L, vecd, nrm));
+      if (std::sqrt(nrm[0]) > 0.3) ++k;
+    }
+  }
+  BSE_TRY(proj_c(c, W.p, W.p, k));
+  int m = orth_block(c, V.p, 0, W.p, k, L, AW.p, 2, 1e-8);
+  if (m <= 0) return m < 0 ? -m : fail(BSE_EINVAL, "Davidson: empty initial block");
+  BSE_TRY(copy_dev(c, W.p, V.p, (size_t)m * L));
+  BSE_TRY(apply_n(c, m, V.p, AV.p));
+  applies += m;
+  std::vector<double> Hs((size_t)maxsub * maxsub, 0.0);
+  auto refresh_rows = [&](long r0, long r1) -> int {  // Hs rows/cols r0..r1-1 against 0..r1-1
+    const long nr_ = r1 - r0;
+    BSE_TRY(gram_tall(c, V.p + (size_t)r0 * L, nr_, AV.p, r1, L, Cd));
+    std::vector<double> blk((size_t)nr_ * r1);
+    BSE_TRY(to_host(c, Cd, blk.data(), blk.size()));
+    for (long i = 0; i < nr_; ++i)
+      for (long j = 0; j < r1; ++j) {
+        Hs[(size_t)(r0 + i) * maxsub + j] = blk[(size_t)i * r1 + j];
+        if (j < r0) Hs[(size_t)j * maxsub + r0 + i] = blk[(size_t)i * r1 + j];
+      }
+    return BSE_OK;
+  };
+  BSE_TRY(refresh_rows(0, m));
+
+  std::vector<double> theta, rn(nb, 0.0);
+  int it = 0;
+  bool conv = false;
+  for (it = 0; it < maxit; ++it) {
+    std::vector<double> A((size_t)m * m), w(m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j)
+        A[(size_t)i * m + j] = 0.5 * (Hs[(size_t)i * maxsub + j] + Hs[(size_t)j * maxsub + i]);
+    if (host_syev(m, A.data(), w.data())) return fail(BSE_EINVAL, "Davidson: small eigensolver failed");
+    const int kr = std::min(nb, m);
+    std::vector<double> Ck((size_t)m * kr);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < kr; ++j) Ck[(size_t)i * kr + j] = A[(size_t)i * m + j];
+    BSE_TRY(to_dev(c, Ck.data(), Cd, Ck.size()));
+    {
+      PhaseScope ps(c, PH_SOLVER);
+      BSE_TRY(dgemm(1, 0, kr, L, m, 1.0, Cd, kr, V.p, L, 0.0, X.p, L, c->st));
+      BSE_TRY(dgemm(1, 0, kr, L, m, 1.0, Cd, kr, AV.p, L, 0.0, AX.p, L, c->st));
+    }
+    std::vector<double> negth(kr);
+    for (int i = 0; i < kr; ++i) negth[i] = -w[i];
+    BSE_TRY(to_dev(c, negth.data(), vecd, kr));
+    BSE_TRY(copy_dev(c, AX.p, W.p, (size_t)kr * L));           // R = AX - theta X
+    BSE_TRY(row_axpby(vecd, X.p, nullptr, W.p, kr, L, c->st));
+    std::vector<double> r2;
+    BSE_TRY(dots_host(c, W.p, W.p, kr, L, vecd + maxsub, r2));
+    for (int i = 0; i < kr; ++i) rn[i] = std::sqrt(std::max(0.0, r2[i]));
+    theta.assign(w.begin(), w.begin() + std::min(ns, m));
+    bool all = (m >= ns);
+    for (int i = 0; i < ns && i < kr; ++i) all = all && (rn[i] <= tol);
+    if (all) {
+      conv = true;
+      break;
+    }
+    // preconditioned residuals of the unconverged Ritz vectors
+    std::vector<int> todo;
+    for (int i = 0; i < kr; ++i)
+      if (rn[i] > tol) todo.push_back(i);
+    const int nt = (int)todo.size();
+    for (int q = 0; q < nt; ++q)
+      if (todo[q] != q) BSE_TRY(copy_dev(c, W.p + (size_t)todo[q] * L, W.p + (size_t)q * L, L));
+    std::vector<double> th(nt);
+    for (int q = 0; q < nt; ++q) th[q] = w[todo[q]];
+    BSE_TRY(to_dev(c, th.data(), vecd, nt));
+    BSE_TRY(precond_davidson(W.p, W.p, c->T, c->eps_d, vecd, c->scissor + kPrecondShift, nt,
+                             (int)nv, (int)npw, c->st));
+    BSE_TRY(proj_c(c, W.p, W.p, nt));
+    if (m + nt > maxsub) {  // thick restart on the lowest 2 nb Ritz vectors
+      const int keep = std::min(2 * nb, m);
+      std::vector<double> Ckeep((size_t)m * keep);
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < keep; ++j) Ckeep[(size_t)i * keep + j] = A[(size_t)i * m + j];
+      BSE_TRY(to_dev(c, Ckeep.data(), Cd, Ckeep.size()));
+      PhaseScope ps(c, PH_SOLVER);
+      // AW holds 2 nb rows: use it as the staging buffer
+      BSE_TRY(dgemm(1, 0, keep, L, m, 1.0, Cd, keep, V.p, L, 0.0, AW.p, L, c->st));
+      BSE_TRY(copy_dev(c, AW.p, V.p, (size_t)keep * L));
+      BSE_TRY(dgemm(1, 0, keep, L, m, 1.0, Cd, keep, AV.p, L, 0.0, AW.p, L, c->st));
+      BSE_TRY(copy_dev(c, AW.p, AV.p, (size_t)keep * L));
+      m = keep;
+      std::fill(Hs.begin(), Hs.end(), 0.0);
+      BSE_TRY(refresh_rows(0, m));
+    }
+    const int kn = orth_block(c, V.p, m, W.p, nt, L, AW.p, 2, 1e-8);
+    if (kn < 0) return -kn;
+    if (kn == 0) break;
+    BSE_TRY(apply_n(c, kn, W.p, AW.p));
+    applies += kn;
+    BSE_TRY(copy_dev(c, W.p, V.p + (size_t)m * L, (size_t)kn * L));
+    BSE_TRY(copy_dev(c, AW.p, AV.p + (size_t)m * L, (size_t)kn * L));
+    BSE_TRY(refresh_rows(m, m + kn));
+    m += kn;
+  }
+  for (int i = 0; i < ns; ++i) omega[i] = i < (int)theta.size() ? theta[i] : NAN;
+  if (Xout) BSE_TRY(copy_dev(c, X.p, Xout, (size_t)ns * L));
+  BSE_HIP(hipStreamSynchronize(c->st));
+  if (stats) {
+    stats->iters = it;
+    stats->applies = applies;
+    for (int i = 0; i < 16; ++i) stats->resid[i] = i < nb ? rn[i] : 0.0;
+    stats->t_ms = elapsed_ms(t0);
+  }
+  if (!conv) return fail(BSE_ENOCONV, "Davidson: no convergence in %d iterations", it);
+  return BSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// U vector:  u_v = P_c[ s (v_c*Drho) a_v - sum_v' W(a_v' a_v) phi_v' ] - sum_v' S_vv' a_v'
+// ---------------------------------------------------------------------------
+int u_vector(bse_ctx* c, const double* Xs, double* U) {
+  const long npw = c->basis.npw, nv = c->nv, L = nv * npw, nr = c->basis.nr;
+  BSE_TRY(ensure_apply_work(c, 1));
+  DVec S(c), G(c);
+  BSE_TRY(S.alloc((size_t)nv * nv));
+  BSE_TRY(G.alloc((size_t)L));
+  double* A = c->A_s;
+  BSE_TRY(proj_c(c, Xs, A, 1));
+  BSE_TRY(to_grid(c, A, c->nv, 1, c->agrid));
+  // kernel part before P_c, and S = <phi | K~ A>
+  BSE_TRY(kernel_part(c, c->agrid, c->Zs));
+  BSE_TRY(dgemm(0, 1, nv, nv, npw, 1.0, c->Phi, npw, c->Zs, npw, 0.0, S.p, nv, c->st));
+  // g(r) = s (v_c*Drho) a - sum_v' sigma_{v'v} phi_v'  (drho holds v_c*Drho from kernel_part)
+  const double2* y = nullptr;
+  if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
+    BSE_TRY(sigma_phi(c, c->agrid, c->ygrid));
+    y = c->ygrid;
+  }
+  const double2* vd = (c->kmask & BSE_K_1E) ? c->drho : nullptr;
+  BSE_TRY(combine(c->phir, c->agrid, c->Vr, vd, y, c->ygrid, c->nv, 1, nr, c->spin, 0, c->st));
+  BSE_TRY(fft3d(c->fft, c->ygrid, c->nvh, -1, c->st));
+  BSE_TRY(gather_sets(c->map, c->ygrid, c->nv, 1, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0,
+                      0.0, G.p, c->st));
+  BSE_TRY(proj_c(c, G.p, U, 1));
+  BSE_TRY(dgemm(0, 0, nv, npw, nv, -1.0, S.p, nv, A, npw, 1.0, U, npw, c->st));
+  BSE_HIP(hipStreamSynchronize(c->st));
+  return BSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Z-vector:  P_c (H - eps_v) P_c Z_v = -u_v, block PCG with per-band steps
+// ---------------------------------------------------------------------------
+int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
+            bse_solver_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
+  const int maxit = (o && o->max_iter > 0) ? o->max_iter : 5000;
+  const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
+  BSE_TRY(ensure_apply_work(c, 1));
+  DVec U(c), R(c), P(c), AP(c), Zr(c), sv(c);
+  BSE_TRY(U.alloc(L));
+  BSE_TRY(R.alloc(L));
+  BSE_TRY(P.alloc(L));
+  BSE_TRY(AP.alloc(L));
+  BSE_TRY(Zr.alloc(L));
+  BSE_TRY(sv.alloc(4 * (size_t)nv + 16));
+  BSE_TRY(u_vector(c, Xs, U.p));
+  BSE_TRY(proj_c(c, U.p, U.p, 1));
+  std::vector<double> d;
+  BSE_TRY(dots_host(c, U.p, U.p, nv, npw, sv.p, d));
+  const double nu = std::sqrt(std::accumulate(d.begin(), d.end(), 0.0));
+  auto applyD = [&](const double* in, double* out) -> int {
+    BSE_TRY(proj_c(c, in, Zr.p, 1));
+    return apply_H(c, (int)nv, 1, Zr.p, out, c->agrid, 0.0, c->eps_d, 1);
+  };
+  if (o && o->z0_dev) {
+    BSE_TRY(proj_c(c, o->z0_dev, Z, 1));
+  } else {
+    BSE_HIP(hipMemsetAsync(Z, 0, sizeof(double) * L, c->st));
+  }
+  BSE_TRY(applyD(Z, AP.p));
+  BSE_TRY(axpby(-1.0, U.p, 0.0, R.p, L, c->st));
+  BSE_TRY(axpby(-1.0, AP.p, 1.0, R.p, L, c->st));
+  BSE_TRY(precond_cg(R.p, Zr.p, c->T, c->eps_d, kPrecondShift, (int)nv, (int)npw, c->st));
+  BSE_TRY(proj_c(c, Zr.p, P.p, 1));
+  std::vector<double> rz, pap, rzn, rr;
+  BSE_TRY(dots_host(c, R.p, P.p, nv, npw, sv.p, rz));
+  double rel = 0.0;
+  int it = 0;
+  bool conv = false;
+  for (it = 0; it < maxit; ++it) {
+    BSE_TRY(dots_host(c, R.p, R.p, nv, npw, sv.p, rr));
+    rel = nu > 0 ? std::sqrt(std::accumulate(rr.begin(), rr.end(), 0.0)) / nu : 0.0;
+    if (rel <= tol) {
+      conv = true;
+      break;
+    }
+    BSE_TRY(applyD(P.p, AP.p));
+    BSE_TRY(dots_host(c, P.p, AP.p, nv, npw, sv.p, pap));
+    std::vector<double> al(nv), nal(nv);
+    for (long v = 0; v < nv; ++v) {
+      al[v] = pap[v] != 0.0 ? rz[v] / pap[v] : 0.0;
+      nal[v] = -al[v];
+    }
+    BSE_TRY(to_dev(c, al.data(), sv.p + nv, nv));
+    BSE_TRY(to_dev(c, nal.data(), sv.p + 2 * nv, nv));
+    BSE_TRY(row_axpby(sv.p + nv, P.p, nullptr, Z, nv, npw, c->st));
+    BSE_TRY(row_axpby(sv.p + 2 * nv, AP.p, nullptr, R.p, nv, npw, c->st));
+    BSE_TRY(precond_cg(R.p, AP.p, c->T, c->eps_d, kPrecondShift, (int)nv, (int)npw, c->st));
+    BSE_TRY(proj_c(c, AP.p, Zr.p, 1));
+    BSE_TRY(dots_host(c, R.p, Zr.p, nv, npw, sv.p, rzn));
+    std::vector<double> be(nv);
+    for (long v = 0; v < nv; ++v) be[v] = rz[v] != 0.0 ? rzn[v] / rz[v] : 0.0;
+    BSE_TRY(to_dev(c, be.data(), sv.p + 3 * nv, nv));
+    BSE_TRY(row_axpby(nullptr, Zr.p, sv.p + 3 * nv, P.p, nv, npw, c->st));
+    rz = rzn;
+  }
+  BSE_HIP(hipStreamSynchronize(c->st));
+  if (stats) {
+    stats->iters = it;
+    stats->applies = it + 1;
+    stats->resid[0] = rel;
+    stats->t_ms = elapsed_ms(t0);
+  }
+  if (!conv) return fail(BSE_ENOCONV, "Z-vector CG: no convergence in %d iterations", it);
+  return BSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// d omega / d R (Eqs. 4-6)
+// ---------------------------------------------------------------------------
+int forces(bse_ctx* c, const double* Xs, const double* Zin, double* dwdR_host) {
+  const long npw = c->basis.npw, nv = c->nv, L = nv * npw, nr = c->basis.nr;
+  BSE_TRY(ensure_apply_work(c, 2));
+  DVec O(c), Pt(c), Zp(c), part(c), outd(c);
+  BSE_TRY(O.alloc((size_t)nv * nv));
+  BSE_TRY(Pt.alloc(L));
+  BSE_TRY(Zp.alloc(L));
+  const long pl = force_reduce_work(c->nsites, nr);
+  BSE_TRY(part.alloc((size_t)std::max(pl, 1L)));
+  BSE_TRY(outd.alloc((size_t)3 * std::max(c->nsites, 1)));
+  BSE_TRY(proj_c(c, Xs, c->A_s, 1));
+  BSE_TRY(proj_c(c, Zin, Zp.p, 1));
+  BSE_TRY(gram_tall(c, c->A_s, nv, c->A_s, nv, npw, O.p));  // O[v][v'] = <a_v|a_v'>
+  BSE_TRY(dgemm(0, 0, nv, npw, nv, 1.0, O.p, nv, c->Phi, npw, 0.0, Pt.p, npw, c->st));
+  const long gs = (long)c->nvh * nr;
+  BSE_TRY(to_grid(c, c->A_s, c->nv, 1, c->agrid));
+  BSE_TRY(to_grid(c, Pt.p, c->nv, 1, c->agrid + gs));
+  BSE_TRY(to_grid(c, Zp.p, c->nv, 1, c->ygrid));
+  BSE_TRY(force_density(c->agrid, c->agrid + gs, c->ygrid, c->phir, c->nv, nr, c->drho, c->st));
+  BSE_TRY(fft3d(c->fft, c->drho, 1, -1, c->st));
+  if (c->nsites > 0) {
+    BSE_TRY(force_reduce(c->drho, c->sites, c->sites + 3 * c->nsites, c->sites + 4 * c->nsites,
+                         c->nsites, c->basis.grid, c->basis.cell, part.p, pl, outd.p, c->st));
+    BSE_TRY(to_host(c, outd.p, dwdR_host, (size_t)3 * c->nsites));
+  }
+  BSE_HIP(hipStreamSynchronize(c->st));
+  return BSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Ground state: lowest n_want eigenpairs of H = T + V by Chebyshev-filtered
+// subspace iteration (the scaled three-term filter of Zhou, Saad, Tiago and
+// Chelikowsky, J. Comput. Phys. 219, 172 (2006)) with Rayleigh-Ritz.
+// ---------------------------------------------------------------------------
+int ground_state(bse_ctx* c, int n_want, double tol) {
+  PhaseScope ps(c, PH_GS);
+  const long npw = c->basis.npw;
+  int ns = n_want + std::max(8, n_want / 10);
+  if (ns > npw) ns = (int)npw;
+  if (n_want > ns) return fail(BSE_EINVAL, "ground state: %d states exceed the basis", n_want);
+  const long nsl = ns;
+  DVec X(c), Y(c), Z(c), HX(c), sm(c);
+  BSE_TRY(X.alloc(nsl * npw));
+  BSE_TRY(Y.alloc(nsl * npw));
+  BSE_TRY(Z.alloc(nsl * npw));
+  BSE_TRY(HX.alloc(nsl * npw));
+  BSE_TRY(sm.alloc(nsl * nsl + 4 * nsl + 16));
+  double2* grids = nullptr;
+  BSE_TRY(ctx_alloc_t(c, &grids, (size_t)((ns + 1) / 2) * c->basis.nr));
+  struct Rel {
+    bse_ctx* c;
+    void* p;
+    ~Rel() { ctx_release(c, p); }
+  } rel_g{c, grids};
+  double* Cd = sm.p;
+  double* vec = sm.p + nsl * nsl;
+  // random start (fixed seed), smooth: divided by (1 + |G|^2/2)
+  {
+    std::mt19937_64 gen(12345);
+    std::normal_distribution<double> nd;
+    std::vector<double> h(nsl * npw);
+    for (long i = 0; i < nsl; ++i)
+      for (long j = 0; j < npw; ++j) h[i * npw + j] = nd(gen) / (1.0 + 0.5 * c->basis.g2[j]);
+    BSE_TRY(to_dev(c, h.data(), X.p, h.size()));
+  }
+  auto Happly = [&](const double* in, double* out, double shift) -> int {
+    return apply_H(c, ns, 1, in, out, grids, shift, nullptr, 0);
+  };
+  std::vector<double> theta(ns);
+  auto rayleigh_ritz = [&]() -> int {
+    int k = orth_block(c, nullptr, 0, X.p, nsl, npw, Z.p, 2, 1e-12);
+    if (k < 0) return -k;
+    if (k < ns) return fail(BSE_EINVAL, "ground state: subspace collapsed (%d of %d)", k, ns);
+    BSE_TRY(Happly(X.p, HX.p, 0.0));
+    BSE_TRY(gram_tall(c, X.p, nsl, HX.p, nsl, npw, Cd));
+    std::vector<double> Hs(nsl * nsl);
+    BSE_TRY(to_host(c, Cd, Hs.data(), Hs.size()));
+    if (host_syev(ns, Hs.data(), theta.data())) return fail(BSE_EINVAL, "ground state: RR failed");
+    BSE_TRY(to_dev(c, Hs.data(), Cd, Hs.size()));
+    BSE_TRY(dgemm(1, 0, nsl, npw, nsl, 1.0, Cd, nsl, X.p, npw, 0.0, Z.p, npw, c->st));
+    BSE_TRY(copy_dev(c, Z.p, X.p, nsl * npw));
+    BSE_TRY(dgemm(1, 0, nsl, npw, nsl, 1.0, Cd, nsl, HX.p, npw, 0.0, Z.p, npw, c->st));
+    BSE_TRY(copy_dev(c, Z.p, HX.p, nsl * npw));
+    return BSE_OK;
+  };
+  // upper bound of the spectrum: |G|^2/2 <= ecut and <x|V|x> <= max V(r)
+  std::vector<double> vr(c->basis.nr);
+  BSE_TRY(to_host(c, c->Vr, vr.data(), vr.size()));
+  const double vmax = *std::max_element(vr.begin(), vr.end());
+  const double bup = c->basis.ecut + std::max(0.0, vmax) + 0.5;
+  BSE_TRY(rayleigh_ritz());
+  const int degree = 16;
+  double resid = 1e300;
+  for (int it = 0; it < 200; ++it) {
+    // residuals of the wanted states
+    std::vector<double> nt(n_want);
+    for (int i = 0; i < n_want; ++i) nt[i] = -theta[i];
+    BSE_TRY(to_dev(c, nt.data(), vec, n_want));
+    BSE_TRY(copy_dev(c, HX.p, Z.p, (size_t)n_want * npw));
+    BSE_TRY(row_axpby(vec, X.p, nullptr, Z.p, n_want, npw, c->st));
+    std::vector<double> r2;
+    BSE_TRY(dots_host(c, Z.p, Z.p, n_want, npw, vec, r2));
+    resid = 0;
+    for (double x : r2) resid = std::max(resid, std::sqrt(std::max(0.0, x)));
+    if (resid <= tol) break;
+    // filter [a, bup] out, amplify below a
+    const double a = theta[ns - 1], a0 = theta[0];
+    const double e = 0.5 * (bup - a), cc = 0.5 * (bup + a);
+    double sigma = e / (a0 - cc);
+    const double tau = 2.0 / sigma;
+    // Y = (H - cc) X * sigma / e
+    BSE_TRY(Happly(X.p, Y.p, -cc));
+    BSE_TRY(axpby(0.0, X.p, sigma / e, Y.p, nsl * npw, c->st));
+    for (int d = 2; d <= degree; ++d) {
+      const double sn = 1.0 / (tau - sigma);
+      BSE_TRY(Happly(Y.p, Z.p, -cc));
+      // Z = 2 sn/e (H - cc) Y - sigma sn X
+      BSE_TRY(axpby(-sigma * sn, X.p, 2.0 * sn / e, Z.p, nsl * npw, c->st));
+      std::swap(X.p, Y.p);  // X <- Y
+      std::swap(Y.p, Z.p);  // Y <- Z, Z free
+      sigma = sn;
+    }
+    std::swap(X.p, Y.p);
+    BSE_TRY(rayleigh_ritz());
+  }
+  c->gs_resid = resid;
+  if (resid > tol) return fail(BSE_ENOCONV, "ground state: residual %.3e above %.3e", resid, tol);
+  c->norb = n_want;
+  BSE_TRY(ctx_alloc_t(c, &c->Phi, (size_t)n_want * npw));
+  BSE_TRY(ctx_alloc_t(c, &c->eps_d, (size_t)n_want));
+  BSE_TRY(copy_dev(c, X.p, c->Phi, (size_t)n_want * npw));
+  c->eps_h.assign(theta.begin(), theta.begin() + n_want);
+  BSE_TRY(to_dev(c, c->eps_h.data(), c->eps_d, n_want));
+  return BSE_OK;
+}
+
+}  // namespace bsex
