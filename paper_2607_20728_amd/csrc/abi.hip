@@ -409,8 +409,9 @@ int bse_set_profiling(bse_ctx* c, int32_t on) {
 
 int bse_get_phase_times(bse_ctx* c, bse_phase_times* out, int32_t reset) {
   if (!c || !out) return fail(BSE_EINVAL, "NULL argument");
-  static const char* names[PH_COUNT] = {"proj",    "fft_inv", "k1e",    "tau_stream", "tau_build",
-                                        "combine", "fft_fwd", "solver", "init_tau",   "ground_state"};
+  static const char* names[PH_COUNT] = {"proj",      "fft_inv", "k1e",    "tau_stream",
+                                        "tau_tile",  "tau_build", "combine", "fft_fwd",
+                                        "solver",    "init_tau",  "ground_state"};
   out->n_phase = PH_COUNT;
   for (int i = 0; i < PH_COUNT; ++i) {
     out->name[i] = names[i];

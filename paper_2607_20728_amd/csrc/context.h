@@ -11,7 +11,8 @@ enum Phase {
   PH_PROJ = 0,   // occupied projector (overlap and update GEMMs)
   PH_FFT_INV,    // sphere -> grid scatter and inverse transforms
   PH_K1E,        // transition density and Poisson solve
-  PH_TAU_STREAM, // tau contraction (K1d)
+  PH_TAU_STREAM, // tau contraction over the cached blocks (K1d)
+  PH_TAU_TILE,   // tau contraction over blocks rebuilt during the call
   PH_TAU_BUILD,  // tau tiles rebuilt during an apply
   PH_COMBINE,    // V a + s v_c*Drho phi - y
   PH_FFT_FWD,    // forward transforms and gather (with the diagonal term)

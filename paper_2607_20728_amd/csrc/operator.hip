@@ -186,7 +186,7 @@ static int tau_contract(bse_ctx* c, const double2* orbr, const double2* a, doubl
       PhaseScope ps(c, PH_TAU_BUILD);
       BSE_TRY(tau_build_range(c, orbr, gb0, nt, c->rebuild_buf, nt, 0, mask));
     }
-    PhaseScope ps(c, PH_TAU_STREAM);
+    PhaseScope ps(c, PH_TAU_TILE);
     BSE_TRY(tau_stream(c->rebuild_buf, nt, nt, c->blkIJ + gb0, c->R, a, y, nb, c->nv, nr,
                        first ? 0 : 1, c->max_lds, c->st));
     first = 0;
