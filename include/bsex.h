@@ -94,7 +94,8 @@ typedef struct {
   double spin_factor;         /* s in D + s K1e - K1d; 2 for a singlet            */
   int32_t precision;          /* BSE_FP64                                         */
   int32_t tau_policy;         /* BSE_TAU_*: cache W(phi_v phi_v') or rebuild it   */
-  int64_t tau_budget_bytes;   /* device bytes allowed for the tau cache; 0 = auto */
+  int64_t tau_budget_bytes;   /* cap on tau cache bytes; 0 = auto, keeping ~14 GB for solver work;
+                                 > 0 also drops that reserve to 1 GB (apply-only use) */
   double gap_min;             /* Ha; EGAP below it (<= 0 disables the check)      */
   int32_t kernel_mask;        /* BSE_K_*; 0 means BSE_K_ALL                        */
   int32_t n_orb;              /* orbitals supplied (>= n_val), or 0 to solve H    */

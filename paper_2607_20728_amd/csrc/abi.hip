@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -95,19 +96,43 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   BSE_HIP(hipGetDeviceProperties(&prop, dev));
   c->max_lds = prop.sharedMemPerBlock;
   c->R = (tau_stream_lds(c->nv, 2) <= c->max_lds) ? 2 : 1;
+  // tuning knobs of the stream kernel (points per workgroup, lanes per point)
+  if (const char* e = getenv("BSEX_TAU_R")) c->R = (atoi(e) == 1) ? 1 : c->R;
+  if (const char* e = getenv("BSEX_TAU_BL")) tau_stream_set_variant(atoi(e));
   if (tau_stream_lds(c->nv, c->R) > c->max_lds)
     return fail(BSE_EINVAL, "n_val %d too large for the device LDS (%zu bytes)", c->nv, c->max_lds);
   BSE_TRY(tau_stream_set_lds_limit(c->max_lds));
   const bool need_k1d = (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) != 0;
-  // work for one apply chunk of 8 vectors
+  // work for one apply chunk of 8 vectors (a(r) buffer; z is written in place)
   BSE_TRY(ensure_apply_work(c, 8));
-  // tile buffers: grids, rho_S, PDEP coefficients, result, rebuild copy
-  const double blk_tile_bytes =
-      8.0 * 64 * (2.0 * nr + 2.0 * npw + std::max(c->npdep, 1));
+  c->tau_policy = d->tau_policy;
+  if (!need_k1d) return BSE_OK;
+  // per 8x8 block: tau (64 N_r doubles) and, for a build tile, the complex
+  // grids, rho_S, the PDEP coefficients and the result
+  const double blk_bytes = 8.0 * 64 * nr;
+  const double blk_tile_bytes = 8.0 * 64 * (2.0 * nr + 2.0 * npw + std::max(c->npdep, 1));
   size_t freeb = 0, totalb = 0;
   BSE_HIP(hipMemGetInfo(&freeb, &totalb));
-  const double tile_target = std::max(1.0e9, 0.06 * (double)totalb);
-  c->tile_blk = std::max(1L, std::min(c->nblk, (long)(tile_target / blk_tile_bytes)));
+  const bool has_budget = d->tau_budget_bytes > 0;
+  // without an explicit budget, keep room for a 64-vector Davidson subspace
+  const double reserve = has_budget ? 1.0e9 : 4.0e9 + 2.0 * 72 * 8.0 * c->nv * npw;
+  const long small_tile = std::min(c->nblk, 4L);
+  bool full = false;
+  if (d->tau_policy != BSE_TAU_REBUILD) {
+    double cap = (double)freeb - reserve - small_tile * blk_tile_bytes;
+    if (has_budget) cap = std::min(cap, (double)d->tau_budget_bytes);
+    full = c->nblk * blk_bytes <= cap;
+  }
+  if (d->tau_policy == BSE_TAU_CACHE && !full)
+    return fail(BSE_ENOMEM, "tau cache needs %.1f GB, %.1f GB free", c->nblk * blk_bytes / 1e9,
+                (double)freeb / 1e9);
+  if (full) {
+    c->tile_blk = small_tile;
+  } else {
+    BSE_TRY(ensure_ygrid(c));  // accumulation across launches
+    const double tile_target = std::max(1.0e9, 0.06 * (double)totalb);
+    c->tile_blk = std::max(1L, std::min(c->nblk, (long)(tile_target / blk_tile_bytes)));
+  }
   const long te = c->tile_blk * 64;
   BSE_TRY(ctx_alloc_t(c, &c->tile_grids, (size_t)c->tile_blk * 32 * nr));
   BSE_TRY(ctx_alloc_t(c, &c->rebuild_buf, (size_t)c->tile_blk * 64 * nr));
@@ -116,20 +141,14 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
     BSE_TRY(ctx_alloc_t(c, &c->tile_F, (size_t)te * npw));
     BSE_TRY(ctx_alloc_t(c, &c->tile_T, (size_t)te * c->npdep));
   }
-  // cache
-  c->tau_policy = d->tau_policy;
-  const double blk_bytes = 8.0 * 64 * nr;
   long ncache = 0;
-  if (need_k1d && d->tau_policy != BSE_TAU_REBUILD) {
+  if (full) {
+    ncache = c->nblk;
+  } else if (d->tau_policy != BSE_TAU_REBUILD) {
     BSE_HIP(hipMemGetInfo(&freeb, &totalb));
-    // keep room for a Davidson subspace of 64 vectors plus 4 GB
-    const double reserve = 4.0e9 + 2.0 * 72 * 8.0 * c->nv * npw;
     double budget = (double)freeb - reserve;
-    if (d->tau_budget_bytes > 0) budget = std::min(budget, (double)d->tau_budget_bytes);
-    long fit = budget > 0 ? (long)(budget / blk_bytes) : 0;
-    if (d->tau_policy == BSE_TAU_CACHE && fit < c->nblk)
-      return fail(BSE_ENOMEM, "tau cache needs %.1f GB, %.1f GB available",
-                  c->nblk * blk_bytes / 1e9, std::max(budget, 0.0) / 1e9);
+    if (has_budget) budget = std::min(budget, (double)d->tau_budget_bytes);
+    const long fit = budget > 0 ? (long)(budget / blk_bytes) : 0;
     ncache = std::min(fit, c->nblk);
   }
   c->nblk_cached = ncache;

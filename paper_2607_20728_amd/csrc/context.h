@@ -104,6 +104,7 @@ int sigma_phi(bse_ctx* c, const double2* agrid, double2* y);
 int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len, double* tmp,
                int passes, double drop);
 int ensure_apply_work(bse_ctx* c, int nbc);
+int ensure_ygrid(bse_ctx* c);
 int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double* dst,
                     long dst_nblk, long dst_blk0, int mask);
 int ground_state(bse_ctx* c, int n_want, double tol);

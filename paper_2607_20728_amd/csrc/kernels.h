@@ -45,13 +45,25 @@ int pair_density(const double2* phir, int nv, const int2* blkIJ, long nblk, long
 // natural tau tile (packed grids, 64 elements per block) -> blocked stream layout
 int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R, double* dst,
               long dst_nblk, long dst_blk0, hipStream_t st);
-// y[b][v] (+)= sum_v' tau_{vv'} a[b][v'] over the blocks of one buffer
+// optional epilogue of the last stream launch: write z = with_v V a +
+// s (v_c*Drho_b) phi - y (vdrho may be NULL) instead of y
+struct FuseArgs {
+  const double* V;
+  const double2* vdrho;
+  const double2* phir;
+  double s;
+  int with_v;
+};
+// y[b][v] (+)= sum_v' tau_{vv'} a[b][v'] over the blocks of one buffer; with
+// fuse != NULL, y receives z instead and may alias a.
 int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                const double2* a, double2* y, int nb, int nv, long nr, int accumulate,
-               size_t max_lds, hipStream_t st);
+               size_t max_lds, hipStream_t st, const FuseArgs* fuse = nullptr);
 size_t tau_stream_lds(int nv, int R);
 // raise the dynamic-LDS limit of the stream kernels (bytes <= device maximum)
 int tau_stream_set_lds_limit(size_t bytes);
+// lanes sharing one grid point's 8 trial vectors in the stream kernel (2 or 4)
+void tau_stream_set_variant(int bl);
 
 // potential V(G) of Gaussian sites on the full grid (Nyquist zero), complex
 int site_potential(const double* xyz, const double* depth, const double* width, int nsites,

@@ -242,25 +242,36 @@ __global__ void k_tau_store(const double2* __restrict__ grids, const int2* __res
 // ---------------------------------------------------------------------------
 // tau stream: for every grid point r, y[b][v](r) += sum_v' tau_{vv'}(r) a[b][v'](r)
 // with tau stored once per unordered pair as 8x8 blocks (diagonal blocks hold
-// the upper triangle with the diagonal halved).  A workgroup owns R points;
-// a and the y accumulators of those points live in LDS; each lane takes one
-// block at one point and applies it in both directions.
+// the upper triangle with the diagonal halved), blocks in row-major order of
+// the block triangle.  A workgroup owns R grid points; a and the y
+// accumulators of those points live in LDS.  The NBT = 8 trial vectors are
+// split over BL adjacent lanes; a unit of BL lanes owns one grid point and a
+// contiguous run of blocks, so along a run the row block I changes rarely:
+// its accumulator y[I] and a[I] stay in registers and are flushed to LDS only
+// when I changes, while the transposed contribution y[J] goes to LDS with one
+// atomic add per (j, b).
 // ---------------------------------------------------------------------------
 constexpr int NBT = 8;
+constexpr int NSLOT = 128;
 
-template <int R>
-__global__ __launch_bounds__(256) void k_tau_stream(const double* __restrict__ tau, long rb_stride,
-                                                    long nblk, const int2* __restrict__ IJ,
-                                                    const double2* __restrict__ a, double2* y,
-                                                    int nb, int nv, int nvh, long nr, int nv8,
-                                                    int accumulate) {
+// FUSE: the epilogue writes z = V a + s (v_c*Drho_b) phi - y instead of y
+// (into `y`, which may alias `a`: every workgroup reads its points of a into
+// LDS before any write and no other workgroup touches them).
+template <int R, int BL, bool FUSE>
+__global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
+    const double* __restrict__ tau, long rb_stride, long nblk, const int2* __restrict__ IJ,
+    const double2* a, double2* y, int nb, int nv, int nvh, long nr, int nv8, int accumulate,
+    const double* __restrict__ V, const double2* __restrict__ vdrho,
+    const double2* __restrict__ phir, double s, int with_v) {
+  constexpr int NT = NSLOT * R * BL;
+  constexpr int NBL = NBT / BL;
   extern __shared__ double lds[];
   double* as = lds;
   double* ys = lds + (long)nv8 * NBT * R;
   const long rb = blockIdx.x;
   const long r0 = rb * R;
   const int n_el = nv8 * NBT * R;
-  for (int e = threadIdx.x; e < n_el; e += 256) {
+  for (int e = threadIdx.x; e < n_el; e += NT) {
     const int ri = e % R;
     const int b = (e / R) % NBT;
     const int v = e / (R * NBT);
@@ -274,56 +285,84 @@ __global__ __launch_bounds__(256) void k_tau_stream(const double* __restrict__ t
     ys[e] = yv;
   }
   __syncthreads();
-  const int slot = threadIdx.x / R;
-  const int ri = threadIdx.x % R;
-  constexpr int NSLOT = 256 / R;
-  const double* tb = tau + rb * rb_stride;
-  for (long blk = slot; blk < nblk; blk += NSLOT) {
+  const int bl = threadIdx.x % BL;
+  const int ri = (threadIdx.x / BL) % R;
+  const int slot = threadIdx.x / (BL * R);
+  const long b0 = nblk * slot / NSLOT, b1 = nblk * (slot + 1) / NSLOT;
+  const double* tb = tau + rb * rb_stride + ri * 8;
+  const int bo = bl * NBL;
+  int curI = -1;
+  double aI[8][NBL], acc[8][NBL];
+  for (long blk = b0; blk < b1; ++blk) {
     const int2 bij = IJ[blk];
-    const double* tp = tb + blk * 64 * R + ri * 8;
-    double aI[8][NBT], acc[8][NBT];
+    if (bij.x != curI) {
+      if (curI >= 0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 8; ++i)
 #pragma unroll
-      for (int b = 0; b < NBT; ++b) {
-        aI[i][b] = as[((bij.x * 8 + i) * NBT + b) * R + ri];
-        acc[i][b] = 0.0;
+          for (int b = 0; b < NBL; ++b)
+            atomicAdd(&ys[((curI * 8 + i) * NBT + bo + b) * R + ri], acc[i][b]);
       }
+      curI = bij.x;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int b = 0; b < NBL; ++b) {
+          aI[i][b] = as[((curI * 8 + i) * NBT + bo + b) * R + ri];
+          acc[i][b] = 0.0;
+        }
+    }
+    const double* tp = tb + blk * 64 * R;
 #pragma unroll 2
     for (int j = 0; j < 8; ++j) {
       double t[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) t[i] = tp[j * 8 * R + i];
       const int wv = bij.y * 8 + j;
-      double aj[NBT], tr[NBT];
+      double aj[NBL], tr[NBL];
 #pragma unroll
-      for (int b = 0; b < NBT; ++b) {
-        aj[b] = as[(wv * NBT + b) * R + ri];
+      for (int b = 0; b < NBL; ++b) {
+        aj[b] = as[(wv * NBT + bo + b) * R + ri];
         tr[b] = 0.0;
       }
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int b = 0; b < NBT; ++b) {
+        for (int b = 0; b < NBL; ++b) {
           acc[i][b] = fma(t[i], aj[b], acc[i][b]);
           tr[b] = fma(t[i], aI[i][b], tr[b]);
         }
 #pragma unroll
-      for (int b = 0; b < NBT; ++b) atomicAdd(&ys[(wv * NBT + b) * R + ri], tr[b]);
+      for (int b = 0; b < NBL; ++b) atomicAdd(&ys[(wv * NBT + bo + b) * R + ri], tr[b]);
     }
+  }
+  if (curI >= 0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
-      for (int b = 0; b < NBT; ++b) atomicAdd(&ys[((bij.x * 8 + i) * NBT + b) * R + ri], acc[i][b]);
+      for (int b = 0; b < NBL; ++b)
+        atomicAdd(&ys[((curI * 8 + i) * NBT + bo + b) * R + ri], acc[i][b]);
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < n_el; e += 256) {
+  for (int e = threadIdx.x; e < n_el; e += NT) {
     const int rr = e % R;
     const int b = (e / R) % NBT;
     const int v = e / (R * NBT);
     if (v < nv && b < nb) {
       const long gi = ((long)b * nvh + (v >> 1)) * nr + r0 + rr;
-      reinterpret_cast<double*>(y + gi)[v & 1] = ys[e];
+      double out = ys[e];
+      if (FUSE) {
+        const long r = r0 + rr;
+        double z = -out;
+        if (with_v) z += V[r] * as[e];
+        if (vdrho) {
+          const double d = reinterpret_cast<const double*>(vdrho + (long)(b >> 1) * nr + r)[b & 1];
+          const double f = reinterpret_cast<const double*>(phir + (long)(v >> 1) * nr + r)[v & 1];
+          z += s * d * f;
+        }
+        out = z;
+      }
+      reinterpret_cast<double*>(y + gi)[v & 1] = out;
     }
   }
 }
@@ -613,9 +652,23 @@ size_t tau_stream_lds(int nv, int R) {
   return 2 * sizeof(double) * (size_t)nv8 * NBT * R;
 }
 
+static int g_tau_bl = 4;  // trial vectors split over this many lanes (2 or 4)
+
+void tau_stream_set_variant(int bl) { g_tau_bl = (bl == 2) ? 2 : 4; }
+
+template <int R, int BL, bool F>
+static void launch_stream(long nrb, size_t shm, hipStream_t st, const double* tau, long stride,
+                          long nblk, const int2* blkIJ, const double2* a, double2* y, int nb, int nv,
+                          long nr, int nv8, int accumulate, const double* V,
+                          const double2* vdrho, const double2* phir, double s, int with_v) {
+  hipLaunchKernelGGL((k_tau_stream<R, BL, F>), dim3((unsigned)nrb), dim3(NSLOT * R * BL), shm, st,
+                     tau, stride, nblk, blkIJ, a, y, nb, nv, (nv + 1) / 2, nr, nv8, accumulate, V,
+                     vdrho, phir, s, with_v);
+}
+
 int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                const double2* a, double2* y, int nb, int nv, long nr, int accumulate,
-               size_t max_lds, hipStream_t st) {
+               size_t max_lds, hipStream_t st, const FuseArgs* fuse) {
   if (nb > NBT) return fail(BSE_EINVAL, "tau_stream: at most %d vectors per call", NBT);
   if (nr % R) return fail(BSE_EINVAL, "tau_stream: grid size not a multiple of %d", R);
   const size_t shm = tau_stream_lds(nv, R);
@@ -624,24 +677,42 @@ int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, i
   const long nrb = nr / R;
   if (nrb > 0x7fffffffL) return fail(BSE_EINVAL, "tau_stream: grid too large");
   const long stride = buf_nblk * 64 * R;
-  if (R == 2) {
-    hipLaunchKernelGGL(k_tau_stream<2>, dim3((unsigned)nrb), dim3(256), shm, st, tau, stride, nblk,
-                       blkIJ, a, y, nb, nv, (nv + 1) / 2, nr, nv8, accumulate);
-  } else if (R == 1) {
-    hipLaunchKernelGGL(k_tau_stream<1>, dim3((unsigned)nrb), dim3(256), shm, st, tau, stride, nblk,
-                       blkIJ, a, y, nb, nv, (nv + 1) / 2, nr, nv8, accumulate);
-  } else {
+  const double* V = fuse ? fuse->V : nullptr;
+  const double2* vd = fuse ? fuse->vdrho : nullptr;
+  const double2* ph = fuse ? fuse->phir : nullptr;
+  const double sf = fuse ? fuse->s : 0.0;
+  const int wv = fuse ? fuse->with_v : 0;
+#define GO(R_, BL_)                                                                            \
+  do {                                                                                         \
+    if (fuse)                                                                                  \
+      launch_stream<R_, BL_, true>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,    \
+                                   nv8, accumulate, V, vd, ph, sf, wv);                        \
+    else                                                                                       \
+      launch_stream<R_, BL_, false>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,   \
+                                    nv8, accumulate, V, vd, ph, sf, wv);                       \
+  } while (0)
+  if (R == 2 && g_tau_bl == 4)
+    GO(2, 4);
+  else if (R == 2)
+    GO(2, 2);
+  else if (R == 1 && g_tau_bl == 4)
+    GO(1, 4);
+  else if (R == 1)
+    GO(1, 2);
+  else
     return fail(BSE_EINVAL, "tau_stream: R = %d unsupported", R);
-  }
+#undef GO
   CHECK_LAUNCH();
   return BSE_OK;
 }
 
 int tau_stream_set_lds_limit(size_t bytes) {
-  BSE_HIP(hipFuncSetAttribute((const void*)k_tau_stream<2>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  BSE_HIP(hipFuncSetAttribute((const void*)k_tau_stream<1>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  const void* fns[] = {(const void*)k_tau_stream<2, 4, false>, (const void*)k_tau_stream<2, 2, false>,
+                       (const void*)k_tau_stream<1, 4, false>, (const void*)k_tau_stream<1, 2, false>,
+                       (const void*)k_tau_stream<2, 4, true>,  (const void*)k_tau_stream<2, 2, true>,
+                       (const void*)k_tau_stream<1, 4, true>,  (const void*)k_tau_stream<1, 2, true>};
+  for (const void* f : fns)
+    BSE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   return BSE_OK;
 }
 

@@ -169,14 +169,16 @@ int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double
 // y[b][v] = sum_v' tau_{vv'} a[b][v'] over all pairs: cached blocks, then
 // tiles rebuilt on the fly.  orbr are the orbitals tau is built from.
 static int tau_contract(bse_ctx* c, const double2* orbr, const double2* a, double2* y, int nb,
-                        int mask, bool use_cache) {
+                        int mask, bool use_cache, const FuseArgs* fuse = nullptr) {
   int first = 1;
   const long nr = c->basis.nr;
   long start = 0;
+  if (fuse && !(use_cache && c->nblk_cached == c->nblk))
+    return fail(BSE_EINVAL, "fused tau stream needs the whole cache");
   if (use_cache && c->nblk_cached > 0) {
     PhaseScope ps(c, PH_TAU_STREAM);
     BSE_TRY(tau_stream(c->tau_cache, c->nblk_cached, c->nblk_cached, c->blkIJ, c->R, a, y, nb,
-                       c->nv, nr, 0, c->max_lds, c->st));
+                       c->nv, nr, 0, c->max_lds, c->st, fuse));
     first = 0;
     start = c->nblk_cached;
   }
@@ -199,19 +201,27 @@ int ensure_apply_work(bse_ctx* c, int nbc) {
   ctx_release(c, c->A_s);
   ctx_release(c, c->Zs);
   ctx_release(c, c->agrid);
-  ctx_release(c, c->ygrid);
   ctx_release(c, c->drho);
   c->A_s = c->Zs = nullptr;
-  c->agrid = c->ygrid = c->drho = nullptr;
+  c->agrid = c->drho = nullptr;
   c->nbc = 0;
   const size_t npw = c->basis.npw, nr = c->basis.nr;
   BSE_TRY(ctx_alloc_t(c, &c->A_s, (size_t)nbc * c->nv * npw));
   BSE_TRY(ctx_alloc_t(c, &c->Zs, (size_t)nbc * c->nv * npw));
   BSE_TRY(ctx_alloc_t(c, &c->agrid, (size_t)nbc * c->nvh * nr));
-  BSE_TRY(ctx_alloc_t(c, &c->ygrid, (size_t)nbc * c->nvh * nr));
   BSE_TRY(ctx_alloc_t(c, &c->drho, (size_t)((nbc + 1) / 2) * nr));
   c->nbc = nbc;
+  if (c->ygrid) {  // keep the accumulation buffer as large as the chunk
+    ctx_release(c, c->ygrid);
+    c->ygrid = nullptr;
+    BSE_TRY(ensure_ygrid(c));
+  }
   return BSE_OK;
+}
+
+int ensure_ygrid(bse_ctx* c) {
+  if (c->ygrid) return BSE_OK;
+  return ctx_alloc_t(c, &c->ygrid, (size_t)c->nbc * c->nvh * c->basis.nr);
 }
 
 // Y = P_c (D + s K1e - K1d) P_c X for nb <= c->nbc vectors
@@ -229,22 +239,31 @@ int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
     BSE_TRY(fft3d(c->fft, c->drho, nbh, +1, c->st));
     vdrho = c->drho;
   }
-  const double2* y = nullptr;
+  const int with_v = (c->kmask & BSE_K_D) ? 1 : 0;
+  double2* zg = c->agrid;
   if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
-    BSE_TRY(tau_contract(c, c->phir, c->agrid, c->ygrid, nb, c->kmask, true));
-    y = c->ygrid;
-  }
-  {
+    if (c->nblk_cached == c->nblk) {
+      // whole tau cached: one launch, combine fused, z written over a(r)
+      FuseArgs f{c->Vr, vdrho, c->phir, c->spin, with_v};
+      BSE_TRY(tau_contract(c, c->phir, c->agrid, c->agrid, nb, c->kmask, true, &f));
+    } else {
+      BSE_TRY(ensure_ygrid(c));
+      BSE_TRY(tau_contract(c, c->phir, c->agrid, c->ygrid, nb, c->kmask, true));
+      PhaseScope ps(c, PH_COMBINE);
+      BSE_TRY(combine(c->agrid, c->phir, c->Vr, vdrho, c->ygrid, c->ygrid, c->nv, nb, nr, c->spin,
+                      with_v, c->st));
+      zg = c->ygrid;
+    }
+  } else {
     PhaseScope ps(c, PH_COMBINE);
-    BSE_TRY(combine(c->agrid, c->phir, c->Vr, vdrho, y, c->ygrid, c->nv, nb, nr, c->spin,
-                    (c->kmask & BSE_K_D) ? 1 : 0, c->st));
+    BSE_TRY(combine(c->agrid, c->phir, c->Vr, vdrho, nullptr, c->agrid, c->nv, nb, nr, c->spin,
+                    with_v, c->st));
   }
   {
     PhaseScope ps(c, PH_FFT_FWD);
-    BSE_TRY(fft3d(c->fft, c->ygrid, (long)nb * c->nvh, -1, c->st));
-    BSE_TRY(gather_sets(c->map, c->ygrid, c->nv, nb, 1.0 / (double)nr,
-                        (c->kmask & BSE_K_D) ? c->A_s : nullptr, c->T, c->eps_d, c->scissor, 0.0,
-                        c->Zs, c->st));
+    BSE_TRY(fft3d(c->fft, zg, (long)nb * c->nvh, -1, c->st));
+    BSE_TRY(gather_sets(c->map, zg, c->nv, nb, 1.0 / (double)nr, with_v ? c->A_s : nullptr, c->T,
+                        c->eps_d, c->scissor, 0.0, c->Zs, c->st));
   }
   BSE_TRY(proj_c(c, c->Zs, Y, nb));
   return BSE_OK;
@@ -252,8 +271,10 @@ int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
 
 // kernel part of the operator on one exciton, before P_c, gathered:
 //   Kt_v = <e| s (v_c*Drho) phi_v - sum_v' tau_{v'v} a_v' >
+// a(r) in agrid set 0; set 1 is scratch; drho keeps v_c*Drho afterwards.
 int kernel_part(bse_ctx* c, const double2* agrid, double* Kt) {
   const long nr = c->basis.nr;
+  double2* y = c->agrid + (long)c->nvh * nr;
   const double2* vdrho = nullptr;
   if (c->kmask & BSE_K_1E) {
     BSE_TRY(transition_density(c->phir, agrid, c->nv, 1, nr, c->drho, c->st));
@@ -262,15 +283,15 @@ int kernel_part(bse_ctx* c, const double2* agrid, double* Kt) {
     BSE_TRY(fft3d(c->fft, c->drho, 1, +1, c->st));
     vdrho = c->drho;
   }
-  const double2* y = nullptr;
+  const double2* yk = nullptr;
   if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
-    BSE_TRY(tau_contract(c, c->phir, agrid, c->ygrid, 1, c->kmask, true));
-    y = c->ygrid;
+    BSE_TRY(tau_contract(c, c->phir, agrid, y, 1, c->kmask, true));
+    yk = y;
   }
-  BSE_TRY(combine(agrid, c->phir, c->Vr, vdrho, y, c->ygrid, c->nv, 1, nr, c->spin, 0, c->st));
-  BSE_TRY(fft3d(c->fft, c->ygrid, c->nvh, -1, c->st));
-  BSE_TRY(gather_sets(c->map, c->ygrid, c->nv, 1, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0,
-                      0.0, Kt, c->st));
+  BSE_TRY(combine(agrid, c->phir, c->Vr, vdrho, yk, y, c->nv, 1, nr, c->spin, 0, c->st));
+  BSE_TRY(fft3d(c->fft, y, c->nvh, -1, c->st));
+  BSE_TRY(gather_sets(c->map, y, c->nv, 1, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0, 0.0,
+                      Kt, c->st));
   return BSE_OK;
 }
 

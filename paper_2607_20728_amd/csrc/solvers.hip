@@ -313,7 +313,7 @@ int davidson(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double
 // ---------------------------------------------------------------------------
 int u_vector(bse_ctx* c, const double* Xs, double* U) {
   const long npw = c->basis.npw, nv = c->nv, L = nv * npw, nr = c->basis.nr;
-  BSE_TRY(ensure_apply_work(c, 1));
+  BSE_TRY(ensure_apply_work(c, 2));
   DVec S(c), G(c);
   BSE_TRY(S.alloc((size_t)nv * nv));
   BSE_TRY(G.alloc((size_t)L));
@@ -324,15 +324,16 @@ int u_vector(bse_ctx* c, const double* Xs, double* U) {
   BSE_TRY(kernel_part(c, c->agrid, c->Zs));
   BSE_TRY(dgemm(0, 1, nv, nv, npw, 1.0, c->Phi, npw, c->Zs, npw, 0.0, S.p, nv, c->st));
   // g(r) = s (v_c*Drho) a - sum_v' sigma_{v'v} phi_v'  (drho holds v_c*Drho from kernel_part)
+  double2* g1 = c->agrid + (long)c->nvh * nr;   // set 1: scratch
   const double2* y = nullptr;
   if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
-    BSE_TRY(sigma_phi(c, c->agrid, c->ygrid));
-    y = c->ygrid;
+    BSE_TRY(sigma_phi(c, c->agrid, g1));
+    y = g1;
   }
   const double2* vd = (c->kmask & BSE_K_1E) ? c->drho : nullptr;
-  BSE_TRY(combine(c->phir, c->agrid, c->Vr, vd, y, c->ygrid, c->nv, 1, nr, c->spin, 0, c->st));
-  BSE_TRY(fft3d(c->fft, c->ygrid, c->nvh, -1, c->st));
-  BSE_TRY(gather_sets(c->map, c->ygrid, c->nv, 1, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0,
+  BSE_TRY(combine(c->phir, c->agrid, c->Vr, vd, y, g1, c->nv, 1, nr, c->spin, 0, c->st));
+  BSE_TRY(fft3d(c->fft, g1, c->nvh, -1, c->st));
+  BSE_TRY(gather_sets(c->map, g1, c->nv, 1, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0,
                       0.0, G.p, c->st));
   BSE_TRY(proj_c(c, G.p, U, 1));
   BSE_TRY(dgemm(0, 0, nv, npw, nv, -1.0, S.p, nv, A, npw, 1.0, U, npw, c->st));
@@ -424,7 +425,7 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
 // ---------------------------------------------------------------------------
 int forces(bse_ctx* c, const double* Xs, const double* Zin, double* dwdR_host) {
   const long npw = c->basis.npw, nv = c->nv, L = nv * npw, nr = c->basis.nr;
-  BSE_TRY(ensure_apply_work(c, 2));
+  BSE_TRY(ensure_apply_work(c, 3));
   DVec O(c), Pt(c), Zp(c), part(c), outd(c);
   BSE_TRY(O.alloc((size_t)nv * nv));
   BSE_TRY(Pt.alloc(L));
@@ -439,8 +440,9 @@ int forces(bse_ctx* c, const double* Xs, const double* Zin, double* dwdR_host) {
   const long gs = (long)c->nvh * nr;
   BSE_TRY(to_grid(c, c->A_s, c->nv, 1, c->agrid));
   BSE_TRY(to_grid(c, Pt.p, c->nv, 1, c->agrid + gs));
-  BSE_TRY(to_grid(c, Zp.p, c->nv, 1, c->ygrid));
-  BSE_TRY(force_density(c->agrid, c->agrid + gs, c->ygrid, c->phir, c->nv, nr, c->drho, c->st));
+  BSE_TRY(to_grid(c, Zp.p, c->nv, 1, c->agrid + 2 * gs));
+  BSE_TRY(force_density(c->agrid, c->agrid + gs, c->agrid + 2 * gs, c->phir, c->nv, nr, c->drho,
+                        c->st));
   BSE_TRY(fft3d(c->fft, c->drho, 1, -1, c->st));
   if (c->nsites > 0) {
     BSE_TRY(force_reduce(c->drho, c->sites, c->sites + 3 * c->nsites, c->sites + 4 * c->nsites,
