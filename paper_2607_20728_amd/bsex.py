@@ -161,8 +161,9 @@ class Context:
         self.free()
 
     def free(self):
-        if getattr(self, "h", None) and self.h.value:
-            lib().bse_free(self.h)
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.bse_free(h)
             self.h = C.c_void_p(None)
 
 

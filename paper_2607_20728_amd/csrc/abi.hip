@@ -34,6 +34,7 @@ void ctx_destroy(bse_ctx* c) {
   for (auto& b : c->allocs) (void)hipFree(b.p);
   c->allocs.clear();
   fft_plan_free(&c->fft);
+  sphere_plan_free(&c->sp);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
@@ -203,7 +204,10 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
   for (long j = 0; j < npw; ++j) T[j] = 0.5 * c->basis.g2[j];
   BSE_TRY(ctx_alloc_t(c, &c->T, npw));
   BSE_TRY(upload(c, c->T, T.data(), sizeof(double) * npw));
-  c->map = SphereMap{c->idx_p, c->idx_m, c->basis.nhalf, (int)npw, nr, c->basis.omega};
+  c->map = SphereMap{c->idx_p, c->idx_m, c->basis.nhalf, (int)npw, nr, c->basis.omega, 0};
+  BSE_TRY(sphere_plan_build(c->fft, c->basis, &c->sp));
+  c->cmap = SphereMap{c->sp.e_plus, c->sp.e_minus, c->basis.nhalf, (int)npw, npw, c->basis.omega,
+                      c->sp.e_zero};
   // sites, potential, Coulomb kernel
   const int ns = std::max(1, c->nsites);
   c->site_h.assign(5 * (size_t)ns, 0.0);

@@ -52,6 +52,8 @@ struct FftAxis {
 struct FftPlan {
   int N[3] = {0, 0, 0};
   long nr = 0;
+  size_t max_lds = 65536;
+  bool ct_plane = false, ct_axis = false;  // compile-time kernels available
   FftAxis ax[3];
 };
 int fft_plan_init(FftPlan* p, const int grid[3]);
@@ -60,11 +62,36 @@ void fft_plan_free(FftPlan* p);
 // dir = -1: sum_r f(r) exp(-i G.r); dir = +1: sum_G f(G) exp(+i G.r).  No scaling.
 int fft3d(const FftPlan& p, double2* data, long batch, int dir, hipStream_t st);
 
+// Sphere <-> grid maps of the pruned transforms: the full sphere (+G and -G
+// of every half-sphere vector, and G = 0) grouped by plane i1.
+struct SpherePlan {
+  int nplanes = 0, nent = 0, e_zero = 0, nmax1 = 0;
+  int *plane_i1 = nullptr, *plane_off = nullptr, *ent_pos = nullptr, *ent_code = nullptr;
+  int *e_plus = nullptr, *e_minus = nullptr;  // entry index of +G_k / -G_k
+};
+int sphere_plan_build(const FftPlan& p, const Basis& b, SpherePlan* sp);
+void sphere_plan_free(SpherePlan* sp);
+// grid[set][p] = sum_G f(G) e^{iGr} of orbitals 2p, 2p+1 of each set (packed),
+// f(0) = x0/sqrt(Omega), f(+-G) = (xc -+ i xs)/sqrt(2 Omega).  Planes that miss
+// the sphere are left unwritten by the first kernel and read as zero.
+int sphere_to_grid(const FftPlan& p, const SpherePlan& sp, double omega, const double* X, int nv,
+                   int nset, double2* grid, hipStream_t st);
+// compact[g][e] = sum_r grid[g](r) e^{-i G_e.r} for the sphere entries e only
+// (the grid is overwritten).
+int grid_to_compact(const FftPlan& p, const SpherePlan& sp, double2* grid, long batch,
+                    double2* compact, hipStream_t st);
+
 // ---- GEMM -----------------------------------------------------------------------
 // C[M][N] = alpha op(A) op(B) + beta C, row-major, FP64 MFMA.
 // op(A) = A[M][K] (ta = 0) or A^T with A[K][M] (ta = 1); op(B) likewise.
 int dgemm(int ta, int tb, long M, long N, long K, double alpha, const double* A, long lda,
           const double* B, long ldb, double beta, double* C, long ldc, hipStream_t st);
+// dgemm with K split across workgroups when the output tiles are too few to
+// fill the device (partials in `work`, summed in a fixed order)
+int dgemm_ws(int ta, int tb, long M, long N, long K, double alpha, const double* A, long lda,
+             const double* B, long ldb, double beta, double* C, long ldc, double* work,
+             long work_len, hipStream_t st);
+long dgemm_work(long M, long N, long K);
 // C[M][N] = alpha A[M][K] B[N][K]^T + beta C for small M, N and long K
 // (split over K with a fixed-order reduction; work buffer owned by the caller).
 int dgemm_tall(long M, long N, long K, double alpha, const double* A, long lda,

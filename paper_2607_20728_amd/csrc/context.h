@@ -35,7 +35,11 @@ struct bse_ctx {
   double scissor = 0, spin = 2, gap_min = 0, gs_tol = 1e-10, gs_resid = -1, ks_gap = -1;
   hipStream_t st = nullptr;
   bsex::FftPlan fft;
-  bsex::SphereMap map{};
+  bsex::SphereMap map{};     // sphere <-> full grid
+  bsex::SpherePlan sp;        // pruned transforms
+  bsex::SphereMap cmap{};    // sphere <-> compact transform output
+  double2* compact = nullptr;
+  long compact_grids = 0;
   std::vector<bsex::DevBuf> allocs;
   // device system data
   int *idx_p = nullptr, *idx_m = nullptr;
@@ -95,10 +99,16 @@ int prof_collect(bse_ctx* c);
 
 // operator pieces (device, stream ordered)
 int proj_c(bse_ctx* c, const double* X, double* Y, int nset);
+int gemm(bse_ctx* c, int ta, int tb, long M, long N, long K, double alpha, const double* A,
+         long lda, const double* B, long ldb, double beta, double* C, long ldc);
 int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y);
 int apply_H(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double2* grids,
             double shift, const double* eps, int project);
 int to_grid(bse_ctx* c, const double* X, int nvs, int nset, double2* grids);
+// forward transform of packed grids and projection onto the sphere rows Y,
+// plus (T + shift - eps_v) A when A is given
+int from_grid(bse_ctx* c, double2* grids, int nvs, int nset, const double* A, const double* eps,
+              double shift, double* Y);
 int kernel_part(bse_ctx* c, const double2* agrid, double* Kt);
 int sigma_phi(bse_ctx* c, const double2* agrid, double2* y);
 int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len, double* tmp,

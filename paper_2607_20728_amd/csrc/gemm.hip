@@ -8,6 +8,8 @@
 // The tall variant splits a long K across workgroups (C = A B^T with small
 // M, N) and sums the partial tiles in a fixed order, so results repeat
 // bitwise.
+#include <algorithm>
+
 #include "common.h"
 
 namespace bsex {
@@ -138,6 +140,50 @@ int dgemm(int ta, int tb, long M, long N, long K, double alpha, const double* A,
   else
     LAUNCH(1, 1);
 #undef LAUNCH
+  BSE_HIP(hipGetLastError());
+  return BSE_OK;
+}
+
+// split-K factor for an op(A) op(B) product whose tile grid is small
+static long k_splits(long M, long N, long K) {
+  const long tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  if (tiles >= 512 || K < 2048) return 1;
+  long s = std::min((K + 1023) / 1024, std::max(1L, 1024 / tiles));
+  return std::max(s, 1L);
+}
+
+long dgemm_work(long M, long N, long K) {
+  const long s = k_splits(M, N, K);
+  return s > 1 ? s * M * N : 0;
+}
+
+int dgemm_ws(int ta, int tb, long M, long N, long K, double alpha, const double* A, long lda,
+             const double* B, long ldb, double beta, double* C, long ldc, double* work,
+             long work_len, hipStream_t st) {
+  long s = k_splits(M, N, K);
+  if (s <= 1 || !work || s * M * N > work_len)
+    return dgemm(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, st);
+  long kc = (K + s - 1) / s;
+  kc = ((kc + BK - 1) / BK) * BK;
+  s = (K + kc - 1) / kc;
+  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)s);
+  if (grid.y > 65535) return fail(BSE_EINVAL, "dgemm: M too large for the grid");
+#define LAUNCH(TA_, TB_)                                                                       \
+  hipLaunchKernelGGL((k_dgemm<TA_, TB_>), grid, dim3(256), 0, st, M, N, K, 1.0, A, lda, B, ldb, \
+                     0.0, work, N, kc, M * N)
+  if (!ta && !tb)
+    LAUNCH(0, 0);
+  else if (!ta && tb)
+    LAUNCH(0, 1);
+  else if (ta && !tb)
+    LAUNCH(1, 0);
+  else
+    LAUNCH(1, 1);
+#undef LAUNCH
+  BSE_HIP(hipGetLastError());
+  const long tot = M * N;
+  hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,
+                     (int)s, work, M * N, alpha, beta, C, ldc);
   BSE_HIP(hipGetLastError());
   return BSE_OK;
 }

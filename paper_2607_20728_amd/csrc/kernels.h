@@ -9,12 +9,13 @@ namespace bsex {
 // hold two orbitals of one set per complex grid (packed: x = orbital 2p,
 // y = orbital 2p+1), nvh = ceil(nv/2) grids per set.
 struct SphereMap {
-  const int* idx_p;   // [nhalf] linear grid index of +G
-  const int* idx_m;   // [nhalf] linear grid index of -G
+  const int* idx_p;   // [nhalf] position of +G in a grid (or compact array)
+  const int* idx_m;   // [nhalf] position of -G
   int nhalf;
   int npw;
-  long nr;
+  long nr;            // stride between grids
   double omega;
+  long zero = 0;      // position of G = 0
 };
 
 // grid[set][p][r] = packed coefficients of X (grid must be zero first unless

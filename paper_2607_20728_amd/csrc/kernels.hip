@@ -25,8 +25,9 @@ __device__ __forceinline__ long gstride() { return (long)gridDim.x * blockDim.x;
 //   grid of orbitals u (real part) and w (imaginary part): H = U + i W.
 // ---------------------------------------------------------------------------
 __global__ void k_scatter(const int* __restrict__ idx_p, const int* __restrict__ idx_m, int nhalf,
-                          int npw, long nr, const double* __restrict__ X, int nv, int nvh,
-                          long ngrid, double2* __restrict__ grid, int acc, double s0, double s1) {
+                          int npw, long nr, long zero, const double* __restrict__ X, int nv,
+                          int nvh, long ngrid, double2* __restrict__ grid, int acc, double s0,
+                          double s1) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t > nhalf) return;
   for (long g = blockIdx.y; g < ngrid; g += gridDim.y) {
@@ -39,10 +40,10 @@ __global__ void k_scatter(const int* __restrict__ idx_p, const int* __restrict__
     if (t == 0) {
       double2 h = make_double2(x1[0] * s0, x2 ? x2[0] * s0 : 0.0);
       if (acc) {
-        h.x += G[0].x;
-        h.y += G[0].y;
+        h.x += G[zero].x;
+        h.y += G[zero].y;
       }
-      G[0] = h;
+      G[zero] = h;
     } else {
       const int k = t - 1;
       const double c1 = x1[1 + 2 * k], q1 = x1[2 + 2 * k];
@@ -64,7 +65,8 @@ __global__ void k_scatter(const int* __restrict__ idx_p, const int* __restrict__
 }
 
 __global__ void k_gather(const int* __restrict__ idx_p, const int* __restrict__ idx_m, int nhalf,
-                         int npw, long nr, const double2* __restrict__ grid, int nv, int nvh,
+                         int npw, long nr, long zero, const double2* __restrict__ grid, int nv,
+                         int nvh,
                          long ngrid, double c0, double c1, const double* __restrict__ A,
                          const double* __restrict__ T, const double* __restrict__ eps,
                          double shift, double beta, double* __restrict__ Y) {
@@ -78,7 +80,7 @@ __global__ void k_gather(const int* __restrict__ idx_p, const int* __restrict__ 
     double a1, b1, a2 = 0, b2 = 0;  // (cos, sin) or (G0, unused)
     int j1, j2;
     if (t == 0) {
-      const double2 h = G[0];
+      const double2 h = G[zero];
       a1 = c0 * h.x;
       a2 = c0 * h.y;
       j1 = 0;
@@ -570,8 +572,8 @@ int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, double2*
   const long ngrid = (long)nset * nvh;
   if (ngrid <= 0) return BSE_OK;
   const dim3 g((unsigned)((m.nhalf + 1 + TPB - 1) / TPB), (unsigned)std::min(ngrid, 65535L));
-  hipLaunchKernelGGL(k_scatter, g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr, X,
-                     nv, nvh, ngrid, grid, accumulate, 1.0 / std::sqrt(m.omega),
+  hipLaunchKernelGGL(k_scatter, g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr,
+                     m.zero, X, nv, nvh, ngrid, grid, accumulate, 1.0 / std::sqrt(m.omega),
                      1.0 / std::sqrt(2.0 * m.omega));
   CHECK_LAUNCH();
   return BSE_OK;
@@ -584,8 +586,8 @@ int gather_sets(const SphereMap& m, const double2* grid, int nv, int nset, doubl
   const long ngrid = (long)nset * nvh;
   if (ngrid <= 0) return BSE_OK;
   const dim3 g((unsigned)((m.nhalf + 1 + TPB - 1) / TPB), (unsigned)std::min(ngrid, 65535L));
-  hipLaunchKernelGGL(k_gather, g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr, grid,
-                     nv, nvh, ngrid, scale * std::sqrt(m.omega), scale * std::sqrt(2.0 * m.omega),
+  hipLaunchKernelGGL(k_gather, g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr,
+                     m.zero, grid, nv, nvh, ngrid, scale * std::sqrt(m.omega), scale * std::sqrt(2.0 * m.omega),
                      A, T, eps, shift, beta, Y);
   CHECK_LAUNCH();
   return BSE_OK;

@@ -88,13 +88,27 @@ static int ensure_ov(bse_ctx* c, int nset) {
   return ctx_alloc_t(c, &c->Ov, need);
 }
 
+// GEMM with a context-owned split-K workspace
+int gemm(bse_ctx* c, int ta, int tb, long M, long N, long K, double alpha, const double* A,
+         long lda, const double* B, long ldb, double beta, double* C, long ldc) {
+  const long need = dgemm_work(M, N, K);
+  if (need > c->gw_len) {
+    ctx_release(c, c->gw);
+    c->gw = nullptr;
+    c->gw_len = 0;
+    BSE_TRY(ctx_alloc_t(c, &c->gw, (size_t)need));
+    c->gw_len = need;
+  }
+  return dgemm_ws(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, c->gw, c->gw_len, c->st);
+}
+
 int proj_c(bse_ctx* c, const double* X, double* Y, int nset) {
   if (nset <= 0) return BSE_OK;
   PhaseScope ps(c, PH_PROJ);
   BSE_TRY(ensure_ov(c, nset));
   const long npw = c->basis.npw, nv = c->nv, n = (long)nset * nv;
   // Ov[w][(s,v)] = <phi_w | x_{s,v}>
-  BSE_TRY(dgemm(0, 1, nv, n, npw, 1.0, c->Phi, npw, X, npw, 0.0, c->Ov, n, c->st));
+  BSE_TRY(gemm(c, 0, 1, nv, n, npw, 1.0, c->Phi, npw, X, npw, 0.0, c->Ov, n));
   if (Y != X) BSE_HIP(hipMemcpyAsync(Y, X, sizeof(double) * n * npw, hipMemcpyDeviceToDevice, c->st));
   // Y -= Ov^T Phi
   BSE_TRY(dgemm(1, 0, n, npw, nv, -1.0, c->Ov, n, c->Phi, npw, 1.0, Y, npw, c->st));
@@ -104,11 +118,27 @@ int proj_c(bse_ctx* c, const double* X, double* Y, int nset) {
 // grid values of nset sets of nvs orbitals (two orbitals per complex grid)
 int to_grid(bse_ctx* c, const double* X, int nvs, int nset, double2* grids) {
   PhaseScope ps(c, PH_FFT_INV);
-  const long ng = (long)nset * ((nvs + 1) / 2);
-  BSE_HIP(hipMemsetAsync(grids, 0, sizeof(double2) * ng * c->basis.nr, c->st));
-  BSE_TRY(scatter_sets(c->map, X, nvs, nset, grids, 0, c->st));
-  BSE_TRY(fft3d(c->fft, grids, ng, +1, c->st));
+  return sphere_to_grid(c->fft, c->sp, c->basis.omega, X, nvs, nset, grids, c->st);
+}
+
+static int ensure_compact(bse_ctx* c, long ngrids) {
+  if (c->compact_grids >= ngrids) return BSE_OK;
+  ctx_release(c, c->compact);
+  c->compact = nullptr;
+  c->compact_grids = 0;
+  BSE_TRY(ctx_alloc_t(c, &c->compact, (size_t)ngrids * c->basis.npw));
+  c->compact_grids = ngrids;
   return BSE_OK;
+}
+
+int from_grid(bse_ctx* c, double2* grids, int nvs, int nset, const double* A, const double* eps,
+              double shift, double* Y) {
+  PhaseScope ps(c, PH_FFT_FWD);
+  const long ng = (long)nset * ((nvs + 1) / 2);
+  BSE_TRY(ensure_compact(c, ng));
+  BSE_TRY(grid_to_compact(c->fft, c->sp, grids, ng, c->compact, c->st));
+  return gather_sets(c->cmap, c->compact, nvs, nset, 1.0 / (double)c->basis.nr, A, c->T, eps,
+                     shift, 0.0, Y, c->st);
 }
 
 // Y = (T + shift - eps_v) X + <e| V(r) x(r)> on nset sets of nvs orbitals
@@ -122,12 +152,7 @@ int apply_H(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double2* 
     PhaseScope ps(c, PH_COMBINE);
     BSE_TRY(mul_real_field(grids, ng, c->basis.nr, c->Vr, 1.0, c->st));
   }
-  {
-    PhaseScope ps(c, PH_FFT_FWD);
-    BSE_TRY(fft3d(c->fft, grids, ng, -1, c->st));
-    BSE_TRY(gather_sets(c->map, grids, nvs, nset, 1.0 / (double)c->basis.nr, X, c->T, eps, shift,
-                        0.0, Y, c->st));
-  }
+  BSE_TRY(from_grid(c, grids, nvs, nset, X, eps, shift, Y));
   if (project) BSE_TRY(proj_c(c, Y, Y, nset));
   return BSE_OK;
 }
@@ -151,8 +176,8 @@ int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double
     // rho_S[e][j] = <e_j | rho_e>
     BSE_TRY(gather_sets(m64, c->tile_grids, 64, (int)nblk, 1.0 / (double)nr, nullptr, nullptr,
                         nullptr, 0.0, 0.0, c->tile_RS, c->st));
-    BSE_TRY(dgemm(0, 0, ne, c->npdep, npw, 1.0, c->tile_RS, npw, c->Pt, c->npdep, 0.0, c->tile_T,
-                  c->npdep, c->st));
+    BSE_TRY(gemm(c, 0, 0, ne, c->npdep, npw, 1.0, c->tile_RS, npw, c->Pt, c->npdep, 0.0,
+                 c->tile_T, c->npdep));
     BSE_TRY(dgemm(0, 1, ne, npw, c->npdep, 1.0, c->tile_T, c->npdep, c->Ptc, c->npdep, 0.0,
                   c->tile_F, npw, c->st));
   }
@@ -259,12 +284,7 @@ int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
     BSE_TRY(combine(c->agrid, c->phir, c->Vr, vdrho, nullptr, c->agrid, c->nv, nb, nr, c->spin,
                     with_v, c->st));
   }
-  {
-    PhaseScope ps(c, PH_FFT_FWD);
-    BSE_TRY(fft3d(c->fft, zg, (long)nb * c->nvh, -1, c->st));
-    BSE_TRY(gather_sets(c->map, zg, c->nv, nb, 1.0 / (double)nr, with_v ? c->A_s : nullptr, c->T,
-                        c->eps_d, c->scissor, 0.0, c->Zs, c->st));
-  }
+  BSE_TRY(from_grid(c, zg, c->nv, nb, with_v ? c->A_s : nullptr, c->eps_d, c->scissor, c->Zs));
   BSE_TRY(proj_c(c, c->Zs, Y, nb));
   return BSE_OK;
 }
@@ -289,9 +309,7 @@ int kernel_part(bse_ctx* c, const double2* agrid, double* Kt) {
     yk = y;
   }
   BSE_TRY(combine(agrid, c->phir, c->Vr, vdrho, yk, y, c->nv, 1, nr, c->spin, 0, c->st));
-  BSE_TRY(fft3d(c->fft, y, c->nvh, -1, c->st));
-  BSE_TRY(gather_sets(c->map, y, c->nv, 1, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0, 0.0,
-                      Kt, c->st));
+  BSE_TRY(from_grid(c, y, c->nv, 1, nullptr, nullptr, 0.0, Kt));
   return BSE_OK;
 }
 

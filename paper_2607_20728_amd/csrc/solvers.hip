@@ -332,9 +332,7 @@ int u_vector(bse_ctx* c, const double* Xs, double* U) {
   }
   const double2* vd = (c->kmask & BSE_K_1E) ? c->drho : nullptr;
   BSE_TRY(combine(c->phir, c->agrid, c->Vr, vd, y, g1, c->nv, 1, nr, c->spin, 0, c->st));
-  BSE_TRY(fft3d(c->fft, g1, c->nvh, -1, c->st));
-  BSE_TRY(gather_sets(c->map, g1, c->nv, 1, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0,
-                      0.0, G.p, c->st));
+  BSE_TRY(from_grid(c, g1, c->nv, 1, nullptr, nullptr, 0.0, G.p));
   BSE_TRY(proj_c(c, G.p, U, 1));
   BSE_TRY(dgemm(0, 0, nv, npw, nv, -1.0, S.p, nv, A, npw, 1.0, U, npw, c->st));
   BSE_HIP(hipStreamSynchronize(c->st));
