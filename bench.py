@@ -98,6 +98,57 @@ def cpu_baseline(cfg_name, n_b, n_pairs_sample=32):
                         f"block of {n_b} extrapolated to {t_block:.0f} s"))
 
 
+def time_to_force(args):
+    """FP64 time-to-force at C2: device ground state, tau cache (partial, the
+    rest rebuilt per apply), Davidson for the lowest n_states excitons to a
+    residual of 1e-6, U and the Z-vector CG to 1e-6, forces for exciton 1."""
+    import torch
+
+    import synth
+    from paper_2607_20728_amd import bsex
+
+    torch.cuda.set_device(0)
+    cfg = synth.get_config(args.config)
+    n_pw = bsex.basis_size(cfg.cell, cfg.grid, cfg.ecut)
+    d = synth.make_system(cfg, n_pw, seed=args.seed)
+    t0 = time.perf_counter()
+    prec = bsex.MIXED if args.precision == "mixed" else bsex.FP64
+    ctx = bsex.init_from_synth(d, n_extra=8, gs_tol=1e-10, gap_min=args.gap_min, precision=prec)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    info = bsex.get_info(ctx)
+    log(f"[ttf] init {t_init:.1f} s, gap {info['ks_gap']:.3e}, cached "
+        f"{info['tau_blocks_cached']}/{info['tau_blocks']}")
+    t1 = time.perf_counter()
+    w, X, ds = bsex.davidson(ctx, cfg.n_states, tol=args.tol, check=False)
+    t2 = time.perf_counter()
+    log(f"[ttf] davidson {t2 - t1:.1f} s, {ds['iters']} iters, {ds['applies']} applies "
+        f"({ds['applies_fp64']} FP64), "
+        f"omega {w}, resid {ds['resid'][:cfg.n_states]}")
+    Z, zs = bsex.zvector_solve(ctx, X[0], tol=args.tol, check=False)
+    t3 = time.perf_counter()
+    log(f"[ttf] U + Z {t3 - t2:.1f} s, {zs['iters']} iters, resid {zs['resid'][0]:.2e}")
+    F = bsex.forces(ctx, X[0], Z, len(d["site_depth"]))
+    t4 = time.perf_counter()
+    out = dict(metric=f"time-to-force @{args.tol:g} resid ({args.precision})",
+               value=round(t4 - t0, 2), unit="s", higher_is_better=False,
+               dtype="f32+f64" if prec == bsex.MIXED else "f64", data="synthetic",
+               seed=d["seed"],
+               config=dict(workload=cfg.name, n_states=cfg.n_states,
+                           tau_blocks_cached=info["tau_blocks_cached"],
+                           tau_blocks=info["tau_blocks"], ks_gap_ha=info["ks_gap"]),
+               split_s=dict(init=round(t_init, 2), davidson=round(t2 - t1, 2),
+                            u_z=round(t3 - t2, 2), forces=round(t4 - t3, 3)),
+               davidson=dict(iters=ds["iters"], applies=ds["applies"],
+                             applies_fp64=ds["applies_fp64"], rc=ds["rc"],
+                             omega=list(map(float, w)), resid=ds["resid"][:cfg.n_states]),
+               zvector=dict(iters=zs["iters"], applies_fp64=zs["applies_fp64"],
+                            resid=zs["resid"][0], rc=zs["rc"]),
+               max_abs_dwdR=float(np.abs(F).max()), sum_dwdR=list(map(float, F.sum(0))))
+    ctx.free()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,11 +160,20 @@ def main():
     # would otherwise keep in reserve (this run only applies the operator)
     ap.add_argument("--tau-budget-gb", type=float, default=1000.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ttf", action="store_true", help="time-to-force run instead")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--gap-min", type=float, default=0.0)
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "sharding of this path is a design note, not a measured run.", file=sys.stderr)
         sys.exit(2)
+
+    if args.ttf:
+        time_to_force(args)
+        return
 
     import torch
 
@@ -131,8 +191,10 @@ def main():
     Y = torch.empty_like(X)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    mixed = args.precision == "mixed"
     ctx = bsex.init_from_synth(d, n_extra=8, gs_tol=1e-10,
-                               tau_budget_bytes=int(args.tau_budget_gb * 1e9))
+                               tau_budget_bytes=int(args.tau_budget_gb * 1e9),
+                               precision=bsex.MIXED if mixed else bsex.FP64)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
     info = bsex.get_info(ctx)
@@ -161,8 +223,11 @@ def main():
     nB = (nv + 7) // 8
     blocks = [(I, J) for I in range(nB) for J in range(I, nB)]
     ncached = info["tau_blocks_cached"]
-    tau_bytes = 8.0 * pair_count(nv, blocks[:ncached]) * nr
-    av_bytes = 2 * 8.0 * args.nb * nv * nr          # a read + y write
+    esz = 4.0 if mixed else 8.0
+    if mixed:  # the FP32 cache holds every block
+        ncached = info["tau_blocks"]
+    tau_bytes = esz * pair_count(nv, blocks[:ncached]) * nr
+    av_bytes = 2 * esz * args.nb * nv * nr          # a read + y write
     ms_stream, n_stream = ph.get("tau_stream", (0.0, 0))
     roofline = None
     if n_stream:
@@ -170,18 +235,20 @@ def main():
         ach = (tau_bytes + av_bytes) / dur / 1e9
         roofline = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
-                        kernel="k_tau_stream (cached blocks)",
+                        kernel=f"k_tau_stream ({'FP32' if mixed else 'FP64'} cached blocks)",
                         bytes_per_launch=tau_bytes + av_bytes,
                         avg_launch_ms=round(1e3 * dur, 3))
     phases = {k: dict(ms_per_step=round(v[0] / args.steps, 3), launches=v[1])
               for k, v in ph.items() if v[1]}
     out = dict(metric=METRIC, value=round(value, 3), unit="applies/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_step, 2),
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
-               data="synthetic",
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32+f64" if mixed else "f64", data="synthetic",
                config=dict(workload=("defect supercell: cubic 20.2 bohr, 72^3 grid, "
                                      "21,079 plane waves, N_v=432, N_pdep=512, 215 Gaussian "
-                                     "sites (3x3x3 diamond minus one), FP64"),
+                                     "sites (3x3x3 diamond minus one), " +
+                                     ("mixed: FP32 grids, FFTs and tau cache, FP64 projector "
+                                      "and diagonal" if mixed else "FP64")),
                            n_b=args.nb, n_pw=n_pw, tau_blocks=info["tau_blocks"],
                            tau_blocks_cached=ncached,
                            tau_policy={0: "auto", 1: "cache", 2: "rebuild"}[info["tau_policy"]],

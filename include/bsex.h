@@ -63,7 +63,15 @@ enum {
   BSE_K_ALL = 15
 };
 
-enum { BSE_FP64 = 0 };                      /* precision of the operator apply  */
+/* Precision of the operator apply (SM Sec. IV discusses single precision for
+ * the kernel terms).  BSE_FP64: every step in FP64.  BSE_MIXED: the grids,
+ * FFTs, pair potentials tau (cached in FP32) and the kernel terms K1e, K1d in
+ * FP32 with FP32 accumulation of the tau contraction; the projector P_c,
+ * the diagonal term D, the Davidson Rayleigh-Ritz and every reduction of the
+ * solvers stay in FP64.  A BSE_MIXED context also holds the FP64 operator
+ * (tau rebuilt on the fly); bse_davidson confirms its result with it and
+ * bse_zvector_solve uses it for the outer residual of iterative refinement. */
+enum { BSE_FP64 = 0, BSE_MIXED = 1 };
 enum { BSE_TAU_AUTO = 0, BSE_TAU_CACHE = 1, BSE_TAU_REBUILD = 2 };
 
 typedef struct bse_ctx bse_ctx;
@@ -92,10 +100,13 @@ typedef struct {
   const double *lambda;       /* host [n_pdep], each < 1                           */
   double scissor;             /* Delta (Ha); shifts omega only                    */
   double spin_factor;         /* s in D + s K1e - K1d; 2 for a singlet            */
-  int32_t precision;          /* BSE_FP64                                         */
+  int32_t precision;          /* BSE_FP64 or BSE_MIXED                            */
   int32_t tau_policy;         /* BSE_TAU_*: cache W(phi_v phi_v') or rebuild it   */
-  int64_t tau_budget_bytes;   /* cap on tau cache bytes; 0 = auto, keeping ~14 GB for solver work;
-                                 > 0 also drops that reserve to 1 GB (apply-only use) */
+  int64_t tau_budget_bytes;   /* cap on tau cache bytes (FP32 and FP64 caches together);
+                                 0 = auto, keeping ~14 GB for solver work; > 0 also drops
+                                 that reserve to 1 GB (apply-only use).  BSE_MIXED needs
+                                 the whole FP32 cache (ENOMEM otherwise) and gives the
+                                 FP64 cache what is left. */
   double gap_min;             /* Ha; EGAP below it (<= 0 disables the check)      */
   int32_t kernel_mask;        /* BSE_K_*; 0 means BSE_K_ALL                        */
   int32_t n_orb;              /* orbitals supplied (>= n_val), or 0 to solve H    */
@@ -133,10 +144,13 @@ typedef struct {
   int32_t grid[3];
   int32_t tau_policy;         /* policy in effect                                */
   int64_t tau_blocks;         /* 8x8 pair blocks of the upper triangle            */
-  int64_t tau_blocks_cached;  /* blocks held in the cache                        */
-  int64_t tau_bytes;          /* bytes of the cache                              */
+  int64_t tau_blocks_cached;  /* blocks held in the FP64 cache                   */
+  int64_t tau_bytes;          /* bytes of the FP64 cache                         */
   double gs_resid;            /* max eigen-residual of the supplied/solved orbitals */
   double ks_gap;              /* eps_{n_val+1} - eps_{n_val} when known, else -1  */
+  int32_t precision;          /* precision the context was built with            */
+  int32_t active_precision;   /* precision bse_apply uses now                    */
+  int64_t tau_bytes_f32;      /* bytes of the FP32 tau cache (BSE_MIXED), else 0 */
 } bse_info;
 
 int bse_get_info(bse_ctx *ctx, bse_info *info);
@@ -172,6 +186,7 @@ typedef struct {
   int32_t applies;            /* operator applications (vectors)                  */
   double resid[16];           /* final residual norms (first 16 states)           */
   double t_ms;                /* wall time of the call                            */
+  int32_t applies_fp64;       /* of `applies`, those made with the FP64 operator  */
 } bse_solver_stats;
 
 /* Lowest n_states eigenpairs of P_c M P_c (Eq. 1) by block Davidson with a
@@ -209,6 +224,10 @@ typedef struct {
   double ms[16];
   int64_t count[16];
 } bse_phase_times;
+
+/* Select the precision of bse_apply on a context built with BSE_MIXED
+ * (BSE_FP64 or BSE_MIXED).  ESTATE on an FP64 context asked for BSE_MIXED. */
+int bse_set_precision(bse_ctx *ctx, int32_t precision);
 
 int bse_set_profiling(bse_ctx *ctx, int32_t on);
 int bse_get_phase_times(bse_ctx *ctx, bse_phase_times *out, int32_t reset);

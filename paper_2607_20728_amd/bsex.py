@@ -19,13 +19,13 @@ LIB_PATH = os.path.join(_HERE, "libbsex.so")
 ABI_VERSION = 1
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, EGAP, EABI, ESTATE = range(8)
 K_D, K_1E, K_1D_BARE, K_1D_PDEP, K_ALL = 1, 2, 4, 8, 15
-FP64 = 0
+FP64, MIXED = 0, 1
 TAU_AUTO, TAU_CACHE, TAU_REBUILD = 0, 1, 2
 
 SYMBOLS = ("bse_abi_version", "bse_last_error", "bse_basis_size", "bse_basis_gvectors",
            "bse_init_system", "bse_get_info", "bse_get_orbitals", "bse_apply",
            "bse_davidson", "bse_u_vector", "bse_zvector_solve", "bse_forces",
-           "bse_set_profiling", "bse_get_phase_times", "bse_free")
+           "bse_set_precision", "bse_set_profiling", "bse_get_phase_times", "bse_free")
 
 
 class BseError(RuntimeError):
@@ -52,7 +52,9 @@ class Info(C.Structure):
     _fields_ = [("n_pw", C.c_int32), ("n_val", C.c_int32), ("n_pdep", C.c_int32),
                 ("n_orb", C.c_int32), ("grid", C.c_int32 * 3), ("tau_policy", C.c_int32),
                 ("tau_blocks", C.c_int64), ("tau_blocks_cached", C.c_int64),
-                ("tau_bytes", C.c_int64), ("gs_resid", C.c_double), ("ks_gap", C.c_double)]
+                ("tau_bytes", C.c_int64), ("gs_resid", C.c_double), ("ks_gap", C.c_double),
+                ("precision", C.c_int32), ("active_precision", C.c_int32),
+                ("tau_bytes_f32", C.c_int64)]
 
 
 class SolverOpts(C.Structure):
@@ -63,7 +65,7 @@ class SolverOpts(C.Structure):
 
 class SolverStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("applies", C.c_int32), ("resid", C.c_double * 16),
-                ("t_ms", C.c_double)]
+                ("t_ms", C.c_double), ("applies_fp64", C.c_int32)]
 
 
 class PhaseTimes(C.Structure):
@@ -99,6 +101,7 @@ def lib():
     L.bse_zvector_solve.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(SolverOpts), C.c_void_p,
                                     C.POINTER(SolverStats)]
     L.bse_forces.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp]
+    L.bse_set_precision.argtypes = [C.c_void_p, C.c_int32]
     L.bse_set_profiling.argtypes = [C.c_void_p, C.c_int32]
     L.bse_get_phase_times.argtypes = [C.c_void_p, C.POINTER(PhaseTimes), C.c_int32]
     L.bse_free.argtypes = [C.c_void_p]
@@ -170,7 +173,7 @@ class Context:
 def init_system(cell, grid, ecut, site_xyz, site_depth, site_width, n_val, pdep, lam, *,
                 scissor=0.0, spin_factor=2.0, tau_policy=TAU_AUTO, tau_budget_bytes=0,
                 gap_min=0.0, kernel_mask=K_ALL, orbitals=None, eps=None, n_extra=8,
-                gs_tol=1e-10, stream=None):
+                gs_tol=1e-10, precision=FP64, stream=None):
     """bse_init_system.  orbitals [n_orb][n_pw] / eps [n_orb] (host) or None to
     let the library solve the ground state."""
     import torch
@@ -188,7 +191,7 @@ def init_system(cell, grid, ecut, site_xyz, site_depth, site_width, n_val, pdep,
     d.pdep, d.lambda_ = _dptr(P), _dptr(lm)
     d.scissor = float(scissor)
     d.spin_factor = float(spin_factor)
-    d.precision = FP64
+    d.precision = int(precision)
     d.tau_policy = int(tau_policy)
     d.tau_budget_bytes = int(tau_budget_bytes)
     d.gap_min = float(gap_min)
@@ -223,7 +226,8 @@ def get_info(ctx):
     return dict(n_pw=i.n_pw, n_val=i.n_val, n_pdep=i.n_pdep, n_orb=i.n_orb, grid=tuple(i.grid),
                 tau_policy=i.tau_policy, tau_blocks=i.tau_blocks,
                 tau_blocks_cached=i.tau_blocks_cached, tau_bytes=i.tau_bytes,
-                gs_resid=i.gs_resid, ks_gap=i.ks_gap)
+                gs_resid=i.gs_resid, ks_gap=i.ks_gap, precision=i.precision,
+                active_precision=i.active_precision, tau_bytes_f32=i.tau_bytes_f32)
 
 
 def get_orbitals(ctx, n=None):
@@ -258,7 +262,8 @@ def _opts(tol=0.0, max_iter=0, block=0, max_subspace=0, x0=None, z0=None):
 
 
 def _stats(s):
-    return dict(iters=s.iters, applies=s.applies, resid=list(s.resid), t_ms=s.t_ms)
+    return dict(iters=s.iters, applies=s.applies, resid=list(s.resid), t_ms=s.t_ms,
+                applies_fp64=s.applies_fp64)
 
 
 def davidson(ctx, n_states=1, *, tol=1e-8, max_iter=0, block=0, max_subspace=0, x0=None,
@@ -297,6 +302,11 @@ def forces(ctx, Xs, Z, n_sites):
     out = np.zeros((max(n_sites, 1), 3))
     _check(lib().bse_forces(ctx.h, _dev(Xs, "Xs"), _dev(Z, "Z"), _dptr(out)))
     return out[:n_sites]
+
+
+def set_precision(ctx, precision):
+    """bse_set_precision: FP64 or MIXED for the applies of a MIXED context."""
+    _check(lib().bse_set_precision(ctx.h, int(precision)))
 
 
 def set_profiling(ctx, on=True):

@@ -65,7 +65,10 @@ int validate(const bse_system_desc* d) {
     return fail(BSE_EINVAL, "pdep and lambda must be given when n_pdep > 0");
   if (!std::isfinite(d->scissor) || !std::isfinite(d->spin_factor))
     return fail(BSE_EINVAL, "scissor and spin_factor must be finite");
-  if (d->precision != BSE_FP64) return fail(BSE_EINVAL, "precision %d unsupported", d->precision);
+  if (d->precision != BSE_FP64 && d->precision != BSE_MIXED)
+    return fail(BSE_EINVAL, "precision %d unsupported", d->precision);
+  if (d->precision == BSE_MIXED && d->tau_policy == BSE_TAU_REBUILD)
+    return fail(BSE_EINVAL, "BSE_MIXED keeps the FP32 tau cache; tau_policy REBUILD conflicts");
   if (d->tau_policy < BSE_TAU_AUTO || d->tau_policy > BSE_TAU_REBUILD)
     return fail(BSE_EINVAL, "tau_policy %d unknown", d->tau_policy);
   if (d->tau_budget_bytes < 0) return fail(BSE_EINVAL, "tau_budget_bytes < 0");
@@ -102,10 +105,15 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   if (const char* e = getenv("BSEX_TAU_BL")) tau_stream_set_variant(atoi(e));
   if (tau_stream_lds(c->nv, c->R) > c->max_lds)
     return fail(BSE_EINVAL, "n_val %d too large for the device LDS (%zu bytes)", c->nv, c->max_lds);
+  const bool mixed = c->precision == BSE_MIXED;
+  c->Rf = (tau_stream_lds(c->nv, 2, sizeof(float)) <= c->max_lds) ? 2 : 1;
+  if (mixed && tau_stream_lds(c->nv, c->Rf, sizeof(float)) > c->max_lds)
+    return fail(BSE_EINVAL, "n_val %d too large for the device LDS (%zu bytes)", c->nv, c->max_lds);
   BSE_TRY(tau_stream_set_lds_limit(c->max_lds));
   const bool need_k1d = (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) != 0;
   // work for one apply chunk of 8 vectors (a(r) buffer; z is written in place)
   BSE_TRY(ensure_apply_work(c, 8));
+  if (mixed) BSE_TRY(ensure_mixed_work(c, c->nbc));
   c->tau_policy = d->tau_policy;
   if (!need_k1d) return BSE_OK;
   // per 8x8 block: tau (64 N_r doubles) and, for a build tile, the complex
@@ -118,10 +126,23 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   // without an explicit budget, keep room for a 64-vector Davidson subspace
   const double reserve = has_budget ? 1.0e9 : 4.0e9 + 2.0 * 72 * 8.0 * c->nv * npw;
   const long small_tile = std::min(c->nblk, 4L);
+  double budget_left = has_budget ? (double)d->tau_budget_bytes : 0.0;
+  if (mixed) {
+    // the whole FP32 cache first; the FP64 cache gets what is left
+    const double fbytes = 4.0 * 64 * nr * c->nblk;
+    double cap = (double)freeb - reserve - std::max(1.0e9, 0.06 * (double)totalb);
+    if (has_budget) cap = std::min(cap, budget_left);
+    if (fbytes > cap)
+      return fail(BSE_ENOMEM, "FP32 tau cache needs %.1f GB, %.1f GB free", fbytes / 1e9,
+                  (double)freeb / 1e9);
+    BSE_TRY(ctx_alloc_t(c, &c->tau_f, (size_t)c->nblk * 64 * nr));
+    budget_left -= fbytes;
+    BSE_HIP(hipMemGetInfo(&freeb, &totalb));
+  }
   bool full = false;
   if (d->tau_policy != BSE_TAU_REBUILD) {
     double cap = (double)freeb - reserve - small_tile * blk_tile_bytes;
-    if (has_budget) cap = std::min(cap, (double)d->tau_budget_bytes);
+    if (has_budget) cap = std::min(cap, budget_left);
     full = c->nblk * blk_bytes <= cap;
   }
   if (d->tau_policy == BSE_TAU_CACHE && !full)
@@ -148,17 +169,23 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   } else if (d->tau_policy != BSE_TAU_REBUILD) {
     BSE_HIP(hipMemGetInfo(&freeb, &totalb));
     double budget = (double)freeb - reserve;
-    if (has_budget) budget = std::min(budget, (double)d->tau_budget_bytes);
+    if (has_budget) budget = std::min(budget, budget_left);
     const long fit = budget > 0 ? (long)(budget / blk_bytes) : 0;
     ncache = std::min(fit, c->nblk);
   }
   c->nblk_cached = ncache;
-  if (ncache > 0) {
-    BSE_TRY(ctx_alloc_t(c, &c->tau_cache, (size_t)ncache * 64 * nr));
+  if (ncache > 0) BSE_TRY(ctx_alloc_t(c, &c->tau_cache, (size_t)ncache * 64 * nr));
+  // one build feeds both caches: blocks below ncache go to the FP64 cache,
+  // every block to the FP32 cache of a mixed context
+  const long nbuild = mixed ? c->nblk : ncache;
+  if (nbuild > 0) {
     PhaseScope ps(c, PH_INIT_TAU);
-    for (long gb0 = 0; gb0 < ncache; gb0 += c->tile_blk) {
-      const long nt = std::min(c->tile_blk, ncache - gb0);
-      BSE_TRY(tau_build_range(c, c->phir, gb0, nt, c->tau_cache, ncache, gb0, c->kmask));
+    for (long gb0 = 0; gb0 < nbuild;) {
+      long nt = std::min(c->tile_blk, nbuild - gb0);
+      if (gb0 < ncache) nt = std::min(nt, ncache - gb0);
+      BSE_TRY(tau_build_range(c, c->phir, gb0, nt, gb0 < ncache ? c->tau_cache : nullptr, ncache,
+                              gb0, c->kmask, c->tau_f));
+      gb0 += nt;
     }
   }
   if (c->nblk_cached == c->nblk && c->nblk > 0)
@@ -269,7 +296,17 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
   // phi(r)
   BSE_TRY(ctx_alloc_t(c, &c->phir, (size_t)c->nvh * nr));
   BSE_TRY(to_grid(c, c->Phi, c->nv, 1, c->phir));
+  c->precision = d->precision;
+  if (c->precision == BSE_MIXED) {  // FP32 copies of the real-space fields
+    BSE_TRY(ctx_alloc_t(c, &c->phir_f, (size_t)c->nvh * nr));
+    BSE_TRY(ctx_alloc_t(c, &c->Vr_f, (size_t)nr));
+    BSE_TRY(ctx_alloc_t(c, &c->vc_f, (size_t)nr));
+    BSE_TRY(to_f32((const double*)c->phir, (float*)c->phir_f, 2L * c->nvh * nr, c->st));
+    BSE_TRY(to_f32(c->Vr, c->Vr_f, nr, c->st));
+    BSE_TRY(to_f32(c->vc, c->vc_f, nr, c->st));
+  }
   BSE_TRY(plan_tau(c, d));
+  c->active = c->precision;
   BSE_HIP(hipStreamSynchronize(c->st));
   return BSE_OK;
 }
@@ -360,6 +397,9 @@ int bse_get_info(bse_ctx* c, bse_info* info) {
   info->tau_blocks = c->nblk;
   info->tau_blocks_cached = c->nblk_cached;
   info->tau_bytes = (int64_t)c->nblk_cached * 64 * c->basis.nr * 8;
+  info->precision = c->precision;
+  info->active_precision = c->active;
+  info->tau_bytes_f32 = c->tau_f ? (int64_t)c->nblk * 64 * c->basis.nr * 4 : 0;
   info->gs_resid = c->gs_resid;
   info->ks_gap = c->ks_gap;
   return BSE_OK;
@@ -392,11 +432,21 @@ int bse_apply(bse_ctx* c, int32_t n_b, const double* X, double* Y) {
     const long L = (long)c->nv * c->basis.npw;
     for (long i = 0; i < n_b; i += c->nbc) {
       const int k = (int)std::min<long>(c->nbc, n_b - i);
-      BSE_TRY(apply_chunk(c, k, X + i * L, Y + i * L));
+      BSE_TRY(apply_any(c, k, X + i * L, Y + i * L));
     }
     BSE_HIP(hipStreamSynchronize(c->st));
     return BSE_OK;
   });
+}
+
+int bse_set_precision(bse_ctx* c, int32_t precision) {
+  if (!c) return fail(BSE_EINVAL, "ctx is NULL");
+  if (precision != BSE_FP64 && precision != BSE_MIXED)
+    return fail(BSE_EINVAL, "precision %d unknown", precision);
+  if (precision == BSE_MIXED && c->precision != BSE_MIXED)
+    return fail(BSE_ESTATE, "context was built without BSE_MIXED");
+  c->active = precision;
+  return BSE_OK;
 }
 
 int bse_davidson(bse_ctx* c, int32_t n_states, const bse_solver_opts* opts, double* omega_host,

@@ -48,12 +48,13 @@ struct FftAxis {
   int nrad = 0;
   int rad[8] = {0};
   double2* tw = nullptr;  // device, exp(-2 pi i k / n), k < n
+  float2* twf = nullptr;  // the same in FP32
 };
 struct FftPlan {
   int N[3] = {0, 0, 0};
   long nr = 0;
   size_t max_lds = 65536;
-  bool ct_plane = false, ct_axis = false;  // compile-time kernels available
+  bool ct_plane[2] = {false, false}, ct_axis[2] = {false, false};  // [FP64, FP32]
   FftAxis ax[3];
 };
 int fft_plan_init(FftPlan* p, const int grid[3]);
@@ -61,6 +62,7 @@ void fft_plan_free(FftPlan* p);
 // In-place batched 3-D complex transform of [batch][N1][N2][N3] (N3 fastest).
 // dir = -1: sum_r f(r) exp(-i G.r); dir = +1: sum_G f(G) exp(+i G.r).  No scaling.
 int fft3d(const FftPlan& p, double2* data, long batch, int dir, hipStream_t st);
+int fft3d(const FftPlan& p, float2* data, long batch, int dir, hipStream_t st);
 
 // Sphere <-> grid maps of the pruned transforms: the full sphere (+G and -G
 // of every half-sphere vector, and G = 0) grouped by plane i1.
@@ -76,10 +78,14 @@ void sphere_plan_free(SpherePlan* sp);
 // the sphere are left unwritten by the first kernel and read as zero.
 int sphere_to_grid(const FftPlan& p, const SpherePlan& sp, double omega, const double* X, int nv,
                    int nset, double2* grid, hipStream_t st);
+int sphere_to_grid(const FftPlan& p, const SpherePlan& sp, double omega, const double* X, int nv,
+                   int nset, float2* grid, hipStream_t st);
 // compact[g][e] = sum_r grid[g](r) e^{-i G_e.r} for the sphere entries e only
 // (the grid is overwritten).
 int grid_to_compact(const FftPlan& p, const SpherePlan& sp, double2* grid, long batch,
                     double2* compact, hipStream_t st);
+int grid_to_compact(const FftPlan& p, const SpherePlan& sp, float2* grid, long batch,
+                    float2* compact, hipStream_t st);
 
 // ---- GEMM -----------------------------------------------------------------------
 // C[M][N] = alpha op(A) op(B) + beta C, row-major, FP64 MFMA.

@@ -70,6 +70,17 @@ struct bse_ctx {
   double2 *agrid = nullptr, *ygrid = nullptr, *drho = nullptr;
   double* gw = nullptr;
   long gw_len = 0;
+  // mixed precision (FP32 grids, FFTs and tau; FP64 projector, diagonal, solvers)
+  int precision = BSE_FP64;   // capability the context was built with
+  int active = BSE_FP64;      // precision of the operator applies
+  int Rf = 2;                 // grid points per stream workgroup, FP32 layout
+  float2* phir_f = nullptr;   // [nvh][nr]
+  float* Vr_f = nullptr;      // [nr]
+  float* vc_f = nullptr;      // [nr]
+  float* tau_f = nullptr;     // [nr/Rf][nblk][64 Rf] FP32 cache (always whole)
+  float2 *agrid_f = nullptr, *drho_f = nullptr, *compact_f = nullptr;
+  int nbc_f = 0;
+  long compact_f_grids = 0;
   // profiling
   bool prof = false;
   double ph_ms[bsex::PH_COUNT] = {0};
@@ -115,8 +126,16 @@ int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len,
                int passes, double drop);
 int ensure_apply_work(bse_ctx* c, int nbc);
 int ensure_ygrid(bse_ctx* c);
+// tau of blocks [gb0, gb0 + nblk) stored into dst (FP64, R points per row,
+// a buffer of dst_nblk blocks from dst_blk0) and/or dstf (the whole FP32
+// cache, Rf points per row, at block gb0); either may be null
 int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double* dst,
-                    long dst_nblk, long dst_blk0, int mask);
+                    long dst_nblk, long dst_blk0, int mask, float* dstf = nullptr);
+int apply_chunk_mixed(bse_ctx* c, int nb, const double* X, double* Y);
+int apply_any(bse_ctx* c, int nb, const double* X, double* Y);
+int apply_H_f(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double shift,
+              const double* eps, int project);
+int ensure_mixed_work(bse_ctx* c, int nbc);
 int ground_state(bse_ctx* c, int n_want, double tol);
 int gram_tall(bse_ctx* c, const double* A, long m, const double* B, long n, long len, double* C);
 }  // namespace bsex

@@ -1,0 +1,754 @@
+// Precision-generic part of the batched 3-D FFT.  Included once per
+// precision inside a namespace that defines `real`, `cplx`, `mk(re, im)`,
+// BSEX_FFT_PREC (0 FP64, 1 FP32) and BSEX_FFT_TW(axis) (its twiddle table).
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxN = 512;
+
+struct AxisArgs {
+  int n;
+  int nrad;
+  int rad[8];
+  const cplx* tw;
+};
+
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) {
+  return mk(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ cplx csub(cplx a, cplx b) {
+  return mk(a.x - b.x, a.y - b.y);
+}
+// multiply by -i (dir = -1) or +i (dir = +1)
+template <int DIR>
+__device__ __forceinline__ cplx mul_i(cplx a) {
+  return DIR < 0 ? mk(a.y, -a.x) : mk(-a.y, a.x);
+}
+
+// In-register DFT of length R: v[m] <- sum_r v[r] exp(DIR 2 pi i r m / R).
+template <int DIR>
+__device__ __forceinline__ void dft2(cplx* v) {
+  const cplx a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+template <int DIR>
+__device__ __forceinline__ void dft3(cplx* v) {
+  const real s3 = (real)0.86602540378443864676;  // sin(2 pi/3)
+  const cplx t1 = cadd(v[1], v[2]);
+  const cplx t2 = mk(v[0].x - (real)0.5 * t1.x, v[0].y - (real)0.5 * t1.y);
+  const cplx d = csub(v[1], v[2]);
+  const cplx t3 = mul_i<DIR>(mk(s3 * d.x, s3 * d.y));
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(t2, t3);
+  v[2] = csub(t2, t3);
+}
+template <int DIR>
+__device__ __forceinline__ void dft4(cplx* v) {
+  const cplx a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  const cplx c = cadd(v[1], v[3]), d = mul_i<DIR>(csub(v[1], v[3]));
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, d);
+  v[3] = csub(b, d);
+}
+template <int DIR>
+__device__ __forceinline__ void dft5(cplx* v) {
+  // cos/sin of 2 pi/5 and 4 pi/5 from their closed forms
+  const real c1 = (real)0.30901699437494742410, c2 = (real)-0.80901699437494742410;
+  const real s1 = (real)0.95105651629515357212, s2 = (real)0.58778525229247312917;
+  const cplx t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+  const cplx t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+  const cplx a1 = mk(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+  const cplx a2 = mk(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+  const cplx b1 = mul_i<DIR>(mk(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
+  const cplx b2 = mul_i<DIR>(mk(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
+  v[0] = cadd(v[0], cadd(t1, t2));
+  v[1] = cadd(a1, b1);
+  v[4] = csub(a1, b1);
+  v[2] = cadd(a2, b2);
+  v[3] = csub(a2, b2);
+}
+
+// One Stockham pass of radix R over L lines: element k of line l is read
+// at in[k*iks + l*ils] and written at out[k*oks + l*ols].  Lines l >= nl
+// are skipped.
+template <int R, int DIR>
+__device__ __forceinline__ void spass(const cplx* __restrict__ in, int iks, int ils,
+                                      cplx* __restrict__ out, int oks, int ols, int n, int L,
+                                      int nl, int ns, const cplx* __restrict__ tw, int nthr) {
+  const int nq = n / R;
+  const int tstride = n / (ns * R);
+  for (int u = threadIdx.x; u < nq * L; u += nthr) {
+    const int l = u % L;
+    if (l >= nl) continue;
+    const int j = u / L;
+    const int k = j % ns;
+    cplx v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cplx x = in[(j + r * nq) * iks + l * ils];
+      if (r > 0 && k > 0) {
+        cplx w = tw[k * r * tstride];
+        if (DIR > 0) w.y = -w.y;
+        x = cmul(x, w);
+      }
+      v[r] = x;
+    }
+    if (R == 2) dft2<DIR>(v);
+    if (R == 3) dft3<DIR>(v);
+    if (R == 4) dft4<DIR>(v);
+    if (R == 5) dft5<DIR>(v);
+    const int base = (j / ns) * ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[(base + r * ns) * oks + l * ols] = v[r];
+  }
+}
+
+template <int DIR>
+__device__ __forceinline__ void spass_any(int R, const cplx* in, int iks, int ils, cplx* out,
+                                          int oks, int ols, int n, int L, int nl, int ns,
+                                          const cplx* tw, int nthr) {
+  if (R == 4)
+    spass<4, DIR>(in, iks, ils, out, oks, ols, n, L, nl, ns, tw, nthr);
+  else if (R == 2)
+    spass<2, DIR>(in, iks, ils, out, oks, ols, n, L, nl, ns, tw, nthr);
+  else if (R == 3)
+    spass<3, DIR>(in, iks, ils, out, oks, ols, n, L, nl, ns, tw, nthr);
+  else
+    spass<5, DIR>(in, iks, ils, out, oks, ols, n, L, nl, ns, tw, nthr);
+}
+
+// Transform all nlines lines of a plane held in LDS (element k of line l at
+// P[k*ks + l*ls]), LB lines at a time: the first pass reads P, the middle
+// passes ping-pong between the scratch buffers S0/S1 ([k][l] layout) and the
+// last pass writes back into P.
+template <int DIR>
+__device__ void plane_lines(cplx* P, int ks, int ls, int nlines, const AxisArgs& ax,
+                            cplx* S0, cplx* S1, int LB, int nthr) {
+  const int n = ax.n;
+  for (int l0 = 0; l0 < nlines; l0 += LB) {
+    const int nl = min(LB, nlines - l0);
+    cplx* base = P + l0 * ls;
+    int ns = 1;
+    const cplx* src = base;
+    int iks = ks, ils = ls;
+    cplx* bufs[2] = {S0, S1};
+    int which = 0;
+    for (int p = 0; p < ax.nrad; ++p) {
+      const bool last = (p == ax.nrad - 1);
+      cplx* dst = last ? base : bufs[which];
+      const int oks = last ? ks : LB, ols = last ? ls : 1;
+      if (ax.nrad == 1) {  // single pass cannot run in place: go through S0
+        spass_any<DIR>(ax.rad[p], src, iks, ils, S0, LB, 1, n, LB, nl, ns, ax.tw, nthr);
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * LB; e += nthr) {
+          const int k = e / LB, l = e % LB;
+          if (l < nl) base[k * ks + l * ls] = S0[e];
+        }
+        __syncthreads();
+        break;
+      }
+      spass_any<DIR>(ax.rad[p], src, iks, ils, dst, oks, ols, n, LB, nl, ns, ax.tw, nthr);
+      __syncthreads();
+      ns *= ax.rad[p];
+      src = dst;
+      iks = LB;
+      ils = 1;
+      which ^= 1;
+    }
+  }
+}
+
+// Strided single-axis pass.  Lines: base = o1 * s_o1 + o2 * s_o2 + inner * s_in,
+// elements at base + k * es.  A workgroup takes L consecutive inner lines of
+// one (o1, o2).  Elements with |n(k)| > ld_lim are not read (taken as zero)
+// and elements with |n(k)| > st_lim are not written (n = minimum image of k).
+template <int DIR>
+__global__ __launch_bounds__(kThreads) void k_fft_axis(cplx* __restrict__ data, AxisArgs ax,
+                                                       int es, int n_inner, long s_in, int n_o2,
+                                                       long s_o2, long s_o1, int L, int ld_lim,
+                                                       int st_lim) {
+  extern __shared__ cplx lds[];
+  const int n = ax.n;
+  cplx* b0 = lds;
+  cplx* b1 = lds + (long)n * L;
+  const int tiles = (n_inner + L - 1) / L;
+  long w = blockIdx.x;
+  const int tile = (int)(w % tiles);
+  w /= tiles;
+  const int o2 = (int)(w % n_o2);
+  const long o1 = w / n_o2;
+  const int i0 = tile * L;
+  const int nl = min(L, n_inner - i0);
+  cplx* base = data + o1 * s_o1 + (long)o2 * s_o2 + (long)i0 * s_in;
+  const bool contiguous = (es == 1);
+  for (int e = threadIdx.x; e < n * L; e += kThreads) {
+    int k, l;
+    if (contiguous) {
+      l = e / n;
+      k = e % n;
+    } else {
+      k = e / L;
+      l = e % L;
+    }
+    const int nk = (k < (n + 1) / 2) ? k : k - n;
+    cplx x = mk(0.0, 0.0);
+    if (l < nl && abs(nk) <= ld_lim) x = base[(long)l * s_in + (long)k * es];
+    b0[k * L + l] = x;
+  }
+  __syncthreads();
+  int ns = 1;
+  cplx* src = b0;
+  cplx* dst = b1;
+  for (int p = 0; p < ax.nrad; ++p) {
+    spass_any<DIR>(ax.rad[p], src, L, 1, dst, L, 1, n, L, L, ns, ax.tw, kThreads);
+    ns *= ax.rad[p];
+    __syncthreads();
+    cplx* t = src;
+    src = dst;
+    dst = t;
+  }
+  for (int e = threadIdx.x; e < n * L; e += kThreads) {
+    int k, l;
+    if (contiguous) {
+      l = e / n;
+      k = e % n;
+    } else {
+      k = e / L;
+      l = e % L;
+    }
+    const int nk = (k < (n + 1) / 2) ? k : k - n;
+    if (l < nl && abs(nk) <= st_lim) base[(long)l * s_in + (long)k * es] = src[k * L + l];
+  }
+}
+
+// Both in-plane axes (2 and 3) of one N2 x N3 plane (fixed i1) in LDS.
+// IN = 0: the plane is read from the grid; IN = 1: it is built from sphere
+// coefficients (two real orbitals per grid, entries of this plane only).
+// OUT = 0: the plane is written back; OUT = 1: only its sphere entries are
+// written to the compact array (n_pw complex values per grid).
+constexpr int kPlaneThreads = 512;
+
+struct PlaneArgs {
+  int N1, N2, N3;
+  long nr;
+  int nplanes;            // planes per grid processed
+  const int* plane_i1;    // NULL: plane p is i1 = p
+  const int* plane_off;   // [nplanes + 1] entry ranges (sphere modes)
+  const int* ent_pos;     // in-plane position i2 * N3 + i3
+  const int* ent_code;    // 0: G = 0; k + 1: +G_k; -(k + 1): -G_k
+  int nent;               // entries per grid (= n_pw)
+  const double* X;        // sphere input [set][nv][npw]
+  int nv, nvh, npw;
+  double s0, s1;          // 1/sqrt(Omega), 1/sqrt(2 Omega)
+  cplx* compact;       // [grid][nent]
+  int LB;                 // lines per scratch batch
+};
+
+template <int DIR, int IN, int OUT>
+__global__ __launch_bounds__(kPlaneThreads) void k_fft_plane(cplx* data, PlaneArgs pa,
+                                                              AxisArgs ay, AxisArgs az) {
+  extern __shared__ cplx lds[];
+  const int N2 = pa.N2, N3 = pa.N3, np2 = N2 * N3;
+  cplx* P = lds;
+  const int nmax = max(N2, N3);
+  cplx* S0 = P + np2;
+  cplx* S1 = S0 + (long)pa.LB * nmax;
+  const long g = blockIdx.x / pa.nplanes;
+  const int pl = (int)(blockIdx.x % pa.nplanes);
+  const int i1 = pa.plane_i1 ? pa.plane_i1[pl] : pl;
+  cplx* gp = data + g * pa.nr + (long)i1 * np2;
+  if (IN == 0) {
+    for (int e = threadIdx.x; e < np2; e += kPlaneThreads) P[e] = gp[e];
+  } else {
+    for (int e = threadIdx.x; e < np2; e += kPlaneThreads) P[e] = mk(0.0, 0.0);
+    __syncthreads();
+    const long set = g / pa.nvh;
+    const int p = (int)(g % pa.nvh);
+    const double* x1 = pa.X + (set * pa.nv + 2 * p) * (long)pa.npw;
+    const double* x2 = (2 * p + 1 < pa.nv) ? x1 + pa.npw : nullptr;
+    for (int e = pa.plane_off[pl] + threadIdx.x; e < pa.plane_off[pl + 1]; e += kPlaneThreads) {
+      const int code = pa.ent_code[e];
+      cplx h;
+      if (code == 0) {
+        h = mk(x1[0] * pa.s0, x2 ? x2[0] * pa.s0 : 0.0);
+      } else {
+        const int k = abs(code) - 1;
+        const double c1 = x1[1 + 2 * k], q1 = x1[2 + 2 * k];
+        const double c2 = x2 ? x2[1 + 2 * k] : 0.0, q2 = x2 ? x2[2 + 2 * k] : 0.0;
+        h = code > 0 ? mk((c1 + q2) * pa.s1, (c2 - q1) * pa.s1)
+                     : mk((c1 - q2) * pa.s1, (q1 + c2) * pa.s1);
+      }
+      P[pa.ent_pos[e]] = h;
+    }
+  }
+  __syncthreads();
+  // axis 3 (rows, contiguous) and axis 2 (columns, stride N3)
+  plane_lines<DIR>(P, 1, N3, N2, az, S0, S1, pa.LB, kPlaneThreads);
+  plane_lines<DIR>(P, N3, 1, N3, ay, S0, S1, pa.LB, kPlaneThreads);
+  if (OUT == 0) {
+    for (int e = threadIdx.x; e < np2; e += kPlaneThreads) gp[e] = P[e];
+  } else {
+    cplx* cg = pa.compact + g * (long)pa.nent;
+    for (int e = pa.plane_off[pl] + threadIdx.x; e < pa.plane_off[pl + 1]; e += kPlaneThreads)
+      cg[e] = P[pa.ent_pos[e]];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time versions for the grid lengths in use: the factorisation,
+// pass strides, line counts and LDS strides are constants, so all index
+// arithmetic reduces to shifts and constant multiplies.
+// ---------------------------------------------------------------------------
+struct Fac {
+  int n;
+  int r[8];
+};
+constexpr Fac factor(int N) {
+  Fac f{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+  int m = N;
+  const int rs[4] = {4, 2, 3, 5};
+  for (int q = 0; q < 4; ++q)
+    while (m % rs[q] == 0) {
+      f.r[f.n++] = rs[q];
+      m /= rs[q];
+    }
+  return f;
+}
+
+template <int R, int DIR, int N, int NS, int L, int IKS, int ILS, int OKS, int OLS, int NT>
+__device__ __forceinline__ void spass_ct(const cplx* __restrict__ in, cplx* __restrict__ out,
+                                         int nl, const cplx* __restrict__ tw) {
+  constexpr int NQ = N / R;
+  constexpr int TS = N / (NS * R);
+#pragma unroll 2
+  for (int u = threadIdx.x; u < NQ * L; u += NT) {
+    const int l = u % L;
+    if (l >= nl) continue;
+    const int j = u / L;
+    const int k = j % NS;
+    cplx v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cplx x = in[(j + r * NQ) * IKS + l * ILS];
+      if (r > 0 && NS > 1) {
+        cplx w = tw[k * r * TS];
+        if (DIR > 0) w.y = -w.y;
+        x = cmul(x, w);
+      }
+      v[r] = x;
+    }
+    if (R == 2) dft2<DIR>(v);
+    if (R == 3) dft3<DIR>(v);
+    if (R == 4) dft4<DIR>(v);
+    if (R == 5) dft5<DIR>(v);
+    const int base = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[(base + r * NS) * OKS + l * OLS] = v[r];
+  }
+}
+
+// Passes P.. of a length-N transform of L lines: the first reads `src`
+// with strides (IKS, ILS); intermediate results ping-pong between S0 and S1
+// ([k][l] layout); the last pass writes `dst` with strides (OKS, OLS).
+template <int N, int DIR, int L, int NT, int P, int NS, int IKS, int ILS, int OKS, int OLS>
+__device__ __forceinline__ void ct_passes(const cplx* src, cplx* S0, cplx* S1,
+                                          cplx* dst, int nl, const cplx* tw) {
+  constexpr Fac F = factor(N);
+  if constexpr (P < F.n) {
+    constexpr int R = F.r[P];
+    constexpr bool last = (P == F.n - 1);
+    constexpr int oks = last ? OKS : L;
+    constexpr int ols = last ? OLS : 1;
+    cplx* out = last ? dst : ((P % 2 == 0) ? S0 : S1);
+    spass_ct<R, DIR, N, NS, L, IKS, ILS, oks, ols, NT>(src, out, nl, tw);
+    __syncthreads();
+    ct_passes<N, DIR, L, NT, P + 1, NS * R, L, 1, OKS, OLS>(out, S0, S1, dst, nl, tw);
+  }
+}
+
+template <int N2, int N3>
+constexpr int plane_lb() {
+  // lines per scratch batch: largest power of two (<= 32) fitting 160 KB
+  int lb = 32;
+  const int nmax = N2 > N3 ? N2 : N3;
+  while (lb > 4 && (int)sizeof(cplx) * (N2 * N3 + 2 * lb * nmax) > 163840) lb /= 2;
+  return lb;
+}
+
+template <int N2, int N3, int DIR, int IN, int OUT>
+__global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_ct(cplx* data, PlaneArgs pa,
+                                                                 AxisArgs ay, AxisArgs az) {
+  constexpr int NP2 = N2 * N3;
+  constexpr int LB = plane_lb<N2, N3>();
+  constexpr int NM = N2 > N3 ? N2 : N3;
+  constexpr int NT = kPlaneThreads;
+  static_assert(factor(N2).n >= 2 && factor(N3).n >= 2, "plane lengths need two passes");
+  extern __shared__ cplx lds[];
+  cplx* P = lds;
+  cplx* S0 = P + NP2;
+  cplx* S1 = S0 + LB * NM;
+  const long g = blockIdx.x / pa.nplanes;
+  const int pl = (int)(blockIdx.x % pa.nplanes);
+  const int i1 = pa.plane_i1 ? pa.plane_i1[pl] : pl;
+  cplx* gp = data + g * pa.nr + (long)i1 * NP2;
+  if (IN == 0) {
+#pragma unroll 4
+    for (int e = threadIdx.x; e < NP2; e += NT) P[e] = gp[e];
+  } else {
+    for (int e = threadIdx.x; e < NP2; e += NT) P[e] = mk(0.0, 0.0);
+    __syncthreads();
+    const long set = g / pa.nvh;
+    const int p = (int)(g % pa.nvh);
+    const double* x1 = pa.X + (set * pa.nv + 2 * p) * (long)pa.npw;
+    const double* x2 = (2 * p + 1 < pa.nv) ? x1 + pa.npw : nullptr;
+    for (int e = pa.plane_off[pl] + threadIdx.x; e < pa.plane_off[pl + 1]; e += NT) {
+      const int code = pa.ent_code[e];
+      cplx h;
+      if (code == 0) {
+        h = mk(x1[0] * pa.s0, x2 ? x2[0] * pa.s0 : 0.0);
+      } else {
+        const int k = abs(code) - 1;
+        const double c1 = x1[1 + 2 * k], q1 = x1[2 + 2 * k];
+        const double c2 = x2 ? x2[1 + 2 * k] : 0.0, q2 = x2 ? x2[2 + 2 * k] : 0.0;
+        h = code > 0 ? mk((c1 + q2) * pa.s1, (c2 - q1) * pa.s1)
+                     : mk((c1 - q2) * pa.s1, (q1 + c2) * pa.s1);
+      }
+      P[pa.ent_pos[e]] = h;
+    }
+  }
+  __syncthreads();
+  // rows (axis 3): element stride 1, line stride N3
+#pragma unroll 1
+  for (int l0 = 0; l0 < N2; l0 += LB)
+    ct_passes<N3, DIR, LB, NT, 0, 1, 1, N3, 1, N3>(P + l0 * N3, S0, S1, P + l0 * N3,
+                                                  min(LB, N2 - l0), az.tw);
+  // columns (axis 2): element stride N3, line stride 1
+#pragma unroll 1
+  for (int l0 = 0; l0 < N3; l0 += LB)
+    ct_passes<N2, DIR, LB, NT, 0, 1, N3, 1, N3, 1>(P + l0, S0, S1, P + l0, min(LB, N3 - l0), ay.tw);
+  if (OUT == 0) {
+#pragma unroll 4
+    for (int e = threadIdx.x; e < NP2; e += NT) gp[e] = P[e];
+  } else {
+    cplx* cg = pa.compact + g * (long)pa.nent;
+    for (int e = pa.plane_off[pl] + threadIdx.x; e < pa.plane_off[pl + 1]; e += NT)
+      cg[e] = P[pa.ent_pos[e]];
+  }
+}
+
+template <int N>
+constexpr int axis_l() {
+  int L = 32;
+  while (L > 4 && 2 * (int)sizeof(cplx) * N * L > 40960) L /= 2;
+  return L;
+}
+
+template <int N, int DIR>
+__global__ __launch_bounds__(kThreads) void k_fft_axis_ct(cplx* __restrict__ data, AxisArgs ax,
+                                                          int es, int n_inner, long s_in, int n_o2,
+                                                          long s_o2, long s_o1, int ld_lim,
+                                                          int st_lim) {
+  constexpr int L = axis_l<N>();
+  constexpr Fac F = factor(N);
+  static_assert(F.n >= 1, "");
+  extern __shared__ cplx lds[];
+  cplx* b0 = lds;
+  cplx* b1 = lds + N * L;
+  const int tiles = (n_inner + L - 1) / L;
+  long w = blockIdx.x;
+  const int tile = (int)(w % tiles);
+  w /= tiles;
+  const int o2 = (int)(w % n_o2);
+  const long o1 = w / n_o2;
+  const int i0 = tile * L;
+  const int nl = min(L, n_inner - i0);
+  cplx* base = data + o1 * s_o1 + (long)o2 * s_o2 + (long)i0 * s_in;
+#pragma unroll 4
+  for (int e = threadIdx.x; e < N * L; e += kThreads) {
+    const int k = e / L, l = e % L;
+    const int nk = (k < (N + 1) / 2) ? k : k - N;
+    cplx x = mk(0.0, 0.0);
+    if (l < nl && abs(nk) <= ld_lim) x = base[(long)l * s_in + (long)k * es];
+    b0[e] = x;
+  }
+  __syncthreads();
+  // passes ping-pong b0 -> b1 -> b0 ...; the result lands in b0 or b1
+  cplx* res = (F.n % 2 == 1) ? b1 : b0;
+  cplx* other = (F.n % 2 == 1) ? b0 : b1;
+  // all passes use the [k][l] layout; the last writes `res`
+  ct_passes<N, DIR, L, kThreads, 0, 1, L, 1, L, 1>(b0, b1, b0, res, L, ax.tw);
+  (void)other;
+#pragma unroll 4
+  for (int e = threadIdx.x; e < N * L; e += kThreads) {
+    const int k = e / L, l = e % L;
+    const int nk = (k < (N + 1) / 2) ? k : k - N;
+    if (l < nl && abs(nk) <= st_lim) base[(long)l * s_in + (long)k * es] = res[e];
+  }
+}
+
+int lines_per_group(int n) {
+  // about 16 KB of LDS per buffer; at least 4 lines
+  int L = 16384 / ((int)sizeof(cplx) * n);
+  if (L < 4) L = 4;
+  if (L > 32) L = 32;
+  return L;
+}
+
+AxisArgs axis_args(const FftAxis& a) {
+  AxisArgs ax;
+  ax.n = a.n;
+  ax.nrad = a.nrad;
+  for (int i = 0; i < 8; ++i) ax.rad[i] = a.rad[i];
+  ax.tw = BSEX_FFT_TW(a);
+  return ax;
+}
+
+#define BSEX_AXIS_SIZES(X) \
+  X(8) X(12) X(16) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(60) X(64) X(72) X(80) X(96) X(120) X(128)
+#define BSEX_PLANE_SIZES(X) \
+  X(12, 12) X(16, 16) X(24, 24) X(32, 32) X(40, 40) X(48, 48) X(64, 64) X(72, 72) X(48, 120) X(120, 120)
+
+bool axis_ct_supported(int n) {
+#define C(N) \
+  if (n == N) return true;
+  BSEX_AXIS_SIZES(C)
+#undef C
+  return false;
+}
+
+bool plane_ct_supported(int n2, int n3) {
+#define C(A, B) \
+  if (n2 == A && n3 == B) return true;
+  BSEX_PLANE_SIZES(C)
+#undef C
+  return false;
+}
+
+size_t plane_ct_lds(int n2, int n3) {
+#define C(A, B) \
+  if (n2 == A && n3 == B) return sizeof(cplx) * (size_t)(A * B + 2 * plane_lb<A, B>() * (A > B ? A : B));
+  BSEX_PLANE_SIZES(C)
+#undef C
+  return 0;
+}
+
+size_t axis_ct_lds(int n) {
+#define C(N) \
+  if (n == N) return 2 * sizeof(cplx) * (size_t)N * axis_l<N>();
+  BSEX_AXIS_SIZES(C)
+#undef C
+  return 0;
+}
+
+int axis_ct_lines(int n) {
+#define C(N) \
+  if (n == N) return axis_l<N>();
+  BSEX_AXIS_SIZES(C)
+#undef C
+  return 0;
+}
+
+void launch_axis_ct(int n, int dir, dim3 grid, size_t shm, hipStream_t st, cplx* data,
+                    AxisArgs ax, int es, int n_inner, long s_in, int n_o2, long s_o2, long s_o1,
+                    int ld_lim, int st_lim) {
+#define C(N)                                                                                 \
+  if (n == N) {                                                                              \
+    if (dir < 0)                                                                             \
+      hipLaunchKernelGGL((k_fft_axis_ct<N, -1>), grid, dim3(kThreads), shm, st, data, ax, es, \
+                         n_inner, s_in, n_o2, s_o2, s_o1, ld_lim, st_lim);                    \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_fft_axis_ct<N, 1>), grid, dim3(kThreads), shm, st, data, ax, es,  \
+                         n_inner, s_in, n_o2, s_o2, s_o1, ld_lim, st_lim);                    \
+    return;                                                                                  \
+  }
+  BSEX_AXIS_SIZES(C)
+#undef C
+}
+
+template <int DIR, int IN, int OUT>
+void launch_plane_ct(int n2, int n3, dim3 grid, size_t shm, hipStream_t st, cplx* data,
+                     PlaneArgs pa, AxisArgs ay, AxisArgs az) {
+#define C(A, B)                                                                               \
+  if (n2 == A && n3 == B) {                                                                   \
+    hipLaunchKernelGGL((k_fft_plane_ct<A, B, DIR, IN, OUT>), grid, dim3(kPlaneThreads), shm,  \
+                       st, data, pa, ay, az);                                                 \
+    return;                                                                                   \
+  }
+  BSEX_PLANE_SIZES(C)
+#undef C
+}
+
+int set_ct_lds_limits(int n2, int n3, int n1) {
+#define C(A, B)                                                                                  \
+  if (n2 == A && n3 == B) {                                                                      \
+    const int need = (int)plane_ct_lds(A, B);                                                    \
+    const void* fns[] = {(const void*)k_fft_plane_ct<A, B, -1, 0, 0>,                            \
+                         (const void*)k_fft_plane_ct<A, B, 1, 0, 0>,                             \
+                         (const void*)k_fft_plane_ct<A, B, 1, 1, 0>,                             \
+                         (const void*)k_fft_plane_ct<A, B, -1, 0, 1>};                           \
+    for (const void* f : fns)                                                                    \
+      BSE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, need));         \
+  }
+  BSEX_PLANE_SIZES(C)
+#undef C
+#define C(N)                                                                                    \
+  if (n1 == N) {                                                                                \
+    const int need = (int)axis_ct_lds(N);                                                       \
+    BSE_HIP(hipFuncSetAttribute((const void*)k_fft_axis_ct<N, -1>,                              \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, need));             \
+    BSE_HIP(hipFuncSetAttribute((const void*)k_fft_axis_ct<N, 1>,                               \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, need));             \
+  }
+  BSEX_AXIS_SIZES(C)
+#undef C
+  return BSE_OK;
+}
+
+}  // namespace
+
+size_t fft_plane_lds(const FftPlan& p, int* LB) {
+  const size_t plane = sizeof(cplx) * (size_t)p.N[1] * p.N[2];
+  const int nmax = std::max(p.N[1], p.N[2]);
+  int lb = 32;
+  while (lb > 4 && plane + 2 * sizeof(cplx) * (size_t)lb * nmax > p.max_lds) lb /= 2;
+  if (LB) *LB = lb;
+  return plane + 2 * sizeof(cplx) * (size_t)lb * nmax;
+}
+
+static int launch_axis(const FftAxis& a, cplx* data, int dir, int es, int n_inner, long s_in,
+                       int n_o2, long s_o2, long n_o1, long s_o1, int ld_lim, int st_lim,
+                       hipStream_t st, bool ct) {
+  const AxisArgs ax = axis_args(a);
+  if (ct) {
+    const int L = axis_ct_lines(a.n);
+    const long tiles = (n_inner + L - 1) / L;
+    const long groups = tiles * n_o2 * n_o1;
+    if (groups <= 0) return BSE_OK;
+    if (groups > 0x7fffffffL) return fail(BSE_EINVAL, "FFT batch too large");
+    launch_axis_ct(a.n, dir, dim3((unsigned)groups), axis_ct_lds(a.n), st, data, ax, es, n_inner,
+                   s_in, n_o2, s_o2, s_o1, ld_lim, st_lim);
+    BSE_HIP(hipGetLastError());
+    return BSE_OK;
+  }
+  const int L = lines_per_group(a.n);
+  const long tiles = (n_inner + L - 1) / L;
+  const long groups = tiles * n_o2 * n_o1;
+  if (groups <= 0) return BSE_OK;
+  if (groups > 0x7fffffffL) return fail(BSE_EINVAL, "FFT batch too large");
+  const size_t shm = 2 * sizeof(cplx) * a.n * L;
+  if (dir < 0)
+    hipLaunchKernelGGL(k_fft_axis<-1>, dim3((unsigned)groups), dim3(kThreads), shm, st, data, ax,
+                       es, n_inner, s_in, n_o2, s_o2, s_o1, L, ld_lim, st_lim);
+  else
+    hipLaunchKernelGGL(k_fft_axis<1>, dim3((unsigned)groups), dim3(kThreads), shm, st, data, ax,
+                       es, n_inner, s_in, n_o2, s_o2, s_o1, L, ld_lim, st_lim);
+  BSE_HIP(hipGetLastError());
+  return BSE_OK;
+}
+
+// axis-1 pass over [batch][N1][N2][N3]
+static int x_pass(const FftPlan& p, cplx* data, long batch, int dir, int ld_lim, int st_lim,
+                  hipStream_t st) {
+  const int N2 = p.N[1], N3 = p.N[2];
+  return launch_axis(p.ax[0], data, dir, N2 * N3, N3, 1, N2, N3, batch, p.nr, ld_lim, st_lim, st,
+                     p.ct_axis[BSEX_FFT_PREC]);
+}
+
+template <int DIR, int IN, int OUT>
+static int launch_plane(const FftPlan& p, cplx* data, long batch, PlaneArgs pa, hipStream_t st) {
+  int lb = 0;
+  const size_t shm = fft_plane_lds(p, &lb);
+  pa.N1 = p.N[0];
+  pa.N2 = p.N[1];
+  pa.N3 = p.N[2];
+  pa.nr = p.nr;
+  pa.LB = lb;
+  const long groups = batch * pa.nplanes;
+  if (groups <= 0) return BSE_OK;
+  if (groups > 0x7fffffffL) return fail(BSE_EINVAL, "FFT batch too large");
+  if (p.ct_plane[BSEX_FFT_PREC])
+    launch_plane_ct<DIR, IN, OUT>(p.N[1], p.N[2], dim3((unsigned)groups), plane_ct_lds(p.N[1], p.N[2]),
+                                  st, data, pa, axis_args(p.ax[1]), axis_args(p.ax[2]));
+  else
+    hipLaunchKernelGGL((k_fft_plane<DIR, IN, OUT>), dim3((unsigned)groups), dim3(kPlaneThreads),
+                       shm, st, data, pa, axis_args(p.ax[1]), axis_args(p.ax[2]));
+  BSE_HIP(hipGetLastError());
+  return BSE_OK;
+}
+
+int init_kernels(FftPlan* p) {
+  int lb = 0;
+  const size_t need = fft_plane_lds(*p, &lb);
+  if (need > p->max_lds)
+    return fail(BSE_EINVAL, "FFT plane %dx%d does not fit the device LDS", p->N[1], p->N[2]);
+  const void* fns[] = {(const void*)k_fft_plane<-1, 0, 0>, (const void*)k_fft_plane<1, 0, 0>,
+                       (const void*)k_fft_plane<1, 1, 0>, (const void*)k_fft_plane<-1, 0, 1>};
+  for (const void* f : fns)
+    BSE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+  bool ctp = plane_ct_supported(p->N[1], p->N[2]) && plane_ct_lds(p->N[1], p->N[2]) <= p->max_lds;
+  bool cta = axis_ct_supported(p->N[0]);
+  if (const char* e = getenv("BSEX_FFT_RUNTIME")) {
+    if (atoi(e)) ctp = cta = false;
+  }
+  p->ct_plane[BSEX_FFT_PREC] = ctp;
+  p->ct_axis[BSEX_FFT_PREC] = cta;
+  return set_ct_lds_limits(ctp ? p->N[1] : -1, ctp ? p->N[2] : -1, cta ? p->N[0] : -1);
+}
+
+int fft3d(const FftPlan& p, cplx* data, long batch, int dir, hipStream_t st) {
+  if (batch <= 0) return BSE_OK;
+  PlaneArgs pa{};
+  pa.nplanes = p.N[0];
+  const int all = p.N[0];
+  if (dir > 0) {
+    BSE_TRY((launch_plane<1, 0, 0>(p, data, batch, pa, st)));
+    BSE_TRY(x_pass(p, data, batch, +1, all, all, st));
+  } else {
+    BSE_TRY(x_pass(p, data, batch, -1, all, all, st));
+    BSE_TRY((launch_plane<-1, 0, 0>(p, data, batch, pa, st)));
+  }
+  return BSE_OK;
+}
+
+int sphere_to_grid(const FftPlan& p, const SpherePlan& sp, double omega, const double* X, int nv,
+                   int nset, cplx* grid, hipStream_t st) {
+  const int nvh = (nv + 1) / 2;
+  const long batch = (long)nset * nvh;
+  if (batch <= 0) return BSE_OK;
+  PlaneArgs pa{};
+  pa.nplanes = sp.nplanes;
+  pa.plane_i1 = sp.plane_i1;
+  pa.plane_off = sp.plane_off;
+  pa.ent_pos = sp.ent_pos;
+  pa.ent_code = sp.ent_code;
+  pa.nent = sp.nent;
+  pa.X = X;
+  pa.nv = nv;
+  pa.nvh = nvh;
+  pa.npw = sp.nent;
+  pa.s0 = 1.0 / std::sqrt(omega);
+  pa.s1 = 1.0 / std::sqrt(2.0 * omega);
+  BSE_TRY((launch_plane<1, 1, 0>(p, grid, batch, pa, st)));
+  return x_pass(p, grid, batch, +1, sp.nmax1, p.N[0], st);
+}
+
+int grid_to_compact(const FftPlan& p, const SpherePlan& sp, cplx* grid, long batch,
+                    cplx* compact, hipStream_t st) {
+  if (batch <= 0) return BSE_OK;
+  BSE_TRY(x_pass(p, grid, batch, -1, p.N[0], sp.nmax1, st));
+  PlaneArgs pa{};
+  pa.nplanes = sp.nplanes;
+  pa.plane_i1 = sp.plane_i1;
+  pa.plane_off = sp.plane_off;
+  pa.ent_pos = sp.ent_pos;
+  pa.ent_code = sp.ent_code;
+  pa.nent = sp.nent;
+  pa.compact = compact;
+  return launch_plane<-1, 0, 1>(p, grid, batch, pa, st);
+}
+

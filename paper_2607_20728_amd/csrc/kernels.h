@@ -28,23 +28,37 @@ int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, double2*
 int gather_sets(const SphereMap& m, const double2* grid, int nv, int nset, double scale,
                 const double* A, const double* T, const double* eps, double shift, double beta,
                 double* Y, hipStream_t st);
+int gather_sets(const SphereMap& m, const float2* grid, int nv, int nset, double scale,
+                const double* A, const double* T, const double* eps, double shift, double beta,
+                double* Y, hipStream_t st);
 // grid[g][r] *= f[r] * scale  (real field f of length nr)
 int mul_real_field(double2* grid, long ngrid, long nr, const double* f, double scale,
                    hipStream_t st);
+int mul_real_field(float2* grid, long ngrid, long nr, const float* f, float scale,
+                   hipStream_t st);
+// y[i] = (float)x[i]
+int to_f32(const double* x, float* y, long n, hipStream_t st);
 // out[r] = Re(grid[r]) for one grid
 int real_part(const double2* grid, long nr, double* out, hipStream_t st);
 // drho[b/2][r] packed over vectors: drho_b(r) = sum_v phi_v(r) a_{b,v}(r)
 int transition_density(const double2* phir, const double2* a, int nv, int nb, long nr,
                        double2* drho, hipStream_t st);
+int transition_density(const float2* phir, const float2* a, int nv, int nb, long nr, float2* drho,
+                       hipStream_t st);
 // z = kD * V a + s * Vdrho_b phi - y   (y may be NULL, vdrho may be NULL); in place into y or out
 int combine(const double2* a, const double2* phir, const double* V, const double2* vdrho,
             const double2* y, double2* out, int nv, int nb, long nr, double s, int with_v,
+            hipStream_t st);
+int combine(const float2* a, const float2* phir, const float* V, const float2* vdrho,
+            const float2* y, float2* out, int nv, int nb, long nr, double s, int with_v,
             hipStream_t st);
 // pair densities of 8x8 blocks [blk0, blk0 + nblk) of the upper triangle
 int pair_density(const double2* phir, int nv, const int2* blkIJ, long nblk, long nr,
                  double2* grids, hipStream_t st);
 // natural tau tile (packed grids, 64 elements per block) -> blocked stream layout
 int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R, double* dst,
+              long dst_nblk, long dst_blk0, hipStream_t st);
+int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R, float* dst,
               long dst_nblk, long dst_blk0, hipStream_t st);
 // optional epilogue of the last stream launch: write z = with_v V a +
 // s (v_c*Drho_b) phi - y (vdrho may be NULL) instead of y
@@ -55,12 +69,23 @@ struct FuseArgs {
   double s;
   int with_v;
 };
+struct FuseArgsF {
+  const float* V;
+  const float2* vdrho;
+  const float2* phir;
+  double s;
+  int with_v;
+};
 // y[b][v] (+)= sum_v' tau_{vv'} a[b][v'] over the blocks of one buffer; with
 // fuse != NULL, y receives z instead and may alias a.
 int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                const double2* a, double2* y, int nb, int nv, long nr, int accumulate,
                size_t max_lds, hipStream_t st, const FuseArgs* fuse = nullptr);
-size_t tau_stream_lds(int nv, int R);
+// FP32 variant (tau, a, y and accumulation in FP32)
+int tau_stream(const float* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
+               const float2* a, float2* y, int nb, int nv, long nr, int accumulate,
+               size_t max_lds, hipStream_t st, const FuseArgsF* fuse = nullptr);
+size_t tau_stream_lds(int nv, int R, size_t elem = sizeof(double));
 // raise the dynamic-LDS limit of the stream kernels (bytes <= device maximum)
 int tau_stream_set_lds_limit(size_t bytes);
 // lanes sharing one grid point's 8 trial vectors in the stream kernel (2 or 4)

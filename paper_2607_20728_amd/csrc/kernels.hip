@@ -64,8 +64,9 @@ __global__ void k_scatter(const int* __restrict__ idx_p, const int* __restrict__
   }
 }
 
+template <typename V2>
 __global__ void k_gather(const int* __restrict__ idx_p, const int* __restrict__ idx_m, int nhalf,
-                         int npw, long nr, long zero, const double2* __restrict__ grid, int nv,
+                         int npw, long nr, long zero, const V2* __restrict__ grid, int nv,
                          int nvh,
                          long ngrid, double c0, double c1, const double* __restrict__ A,
                          const double* __restrict__ T, const double* __restrict__ eps,
@@ -76,18 +77,20 @@ __global__ void k_gather(const int* __restrict__ idx_p, const int* __restrict__ 
     const long set = g / nvh;
     const int p = (int)(g % nvh);
     const int v1 = 2 * p, v2 = 2 * p + 1;
-    const double2* G = grid + g * nr;
+    const V2* G = grid + g * nr;
     double a1, b1, a2 = 0, b2 = 0;  // (cos, sin) or (G0, unused)
     int j1, j2;
     if (t == 0) {
-      const double2 h = G[zero];
+      const V2 hv = G[zero];
+      const double2 h = make_double2(hv.x, hv.y);
       a1 = c0 * h.x;
       a2 = c0 * h.y;
       j1 = 0;
       j2 = -1;
     } else {
       const int k = t - 1;
-      const double2 hp = G[idx_p[k]], hm = G[idx_m[k]];
+      const V2 hpv = G[idx_p[k]], hmv = G[idx_m[k]];
+      const double2 hp = make_double2(hpv.x, hpv.y), hm = make_double2(hmv.x, hmv.y);
       a1 = 0.5 * c1 * (hp.x + hm.x);    // orbital 1, cos
       b1 = -0.5 * c1 * (hp.y - hm.y);   // orbital 1, sin
       a2 = 0.5 * c1 * (hp.y + hm.y);    // orbital 2, cos
@@ -113,11 +116,11 @@ __global__ void k_gather(const int* __restrict__ idx_p, const int* __restrict__ 
   }
 }
 
-__global__ void k_mul_real(double2* __restrict__ g, long n, long nr, const double* __restrict__ f,
-                           double scale) {
+template <typename V2, typename R>
+__global__ void k_mul_real(V2* __restrict__ g, long n, long nr, const R* __restrict__ f, R scale) {
   for (long e = gtid(); e < n; e += gstride()) {
-    const double m = f[e % nr] * scale;
-    double2 x = g[e];
+    const R m = f[e % nr] * scale;
+    V2 x = g[e];
     x.x *= m;
     x.y *= m;
     g[e] = x;
@@ -128,55 +131,61 @@ __global__ void k_real_part(const double2* __restrict__ g, long nr, double* __re
   for (long e = gtid(); e < nr; e += gstride()) out[e] = g[e].x;
 }
 
-__global__ void k_transition_density(const double2* __restrict__ phir, const double2* __restrict__ a,
-                                     int nvh, int nb, long nr, double2* __restrict__ drho) {
+template <typename V2, typename R>
+__global__ void k_transition_density(const V2* __restrict__ phir, const V2* __restrict__ a,
+                                     int nvh, int nb, long nr, V2* __restrict__ drho) {
   const long nbh = (nb + 1) / 2;
   for (long e = gtid(); e < nbh * nr; e += gstride()) {
     const long r = e % nr;
     const int bp = (int)(e / nr);
-    double s[2] = {0.0, 0.0};
+    R s[2] = {0, 0};
     for (int o = 0; o < 2; ++o) {
       const int b = 2 * bp + o;
       if (b >= nb) break;
-      const double2* ab = a + (long)b * nvh * nr + r;
-      double acc = 0.0;
+      const V2* ab = a + (long)b * nvh * nr + r;
+      R acc = 0;
       for (int p = 0; p < nvh; ++p) {
-        const double2 f = phir[(long)p * nr + r];
-        const double2 x = ab[(long)p * nr];
+        const V2 f = phir[(long)p * nr + r];
+        const V2 x = ab[(long)p * nr];
         acc += f.x * x.x + f.y * x.y;
       }
       s[o] = acc;
     }
-    drho[e] = make_double2(s[0], s[1]);
+    V2 out;
+    out.x = s[0];
+    out.y = s[1];
+    drho[e] = out;
   }
 }
 
-__global__ void k_combine(const double2* __restrict__ a, const double2* __restrict__ phir,
-                          const double* __restrict__ V, const double2* __restrict__ vdrho,
-                          const double2* y, double2* out, int nvh, int nb, long nr, double s,
-                          int with_v) {
+template <typename V2, typename R>
+__global__ void k_combine(const V2* __restrict__ a, const V2* __restrict__ phir,
+                          const R* __restrict__ V, const V2* __restrict__ vdrho, const V2* y,
+                          V2* out, int nvh, int nb, long nr, R s, int with_v) {
   const long n = (long)nb * nvh * nr;
   for (long e = gtid(); e < n; e += gstride()) {
     const long r = e % nr;
     const long bp = e / nr;
     const int p = (int)(bp % nvh);
     const int b = (int)(bp / nvh);
-    double2 z = make_double2(0.0, 0.0);
+    V2 z;
+    z.x = 0;
+    z.y = 0;
     if (with_v) {
-      const double v = V[r];
-      const double2 x = a[e];
+      const R v = V[r];
+      const V2 x = a[e];
       z.x = v * x.x;
       z.y = v * x.y;
     }
     if (vdrho) {
-      const double2 d = vdrho[(long)(b >> 1) * nr + r];
-      const double w = s * ((b & 1) ? d.y : d.x);
-      const double2 f = phir[(long)p * nr + r];
+      const V2 d = vdrho[(long)(b >> 1) * nr + r];
+      const R w = s * ((b & 1) ? d.y : d.x);
+      const V2 f = phir[(long)p * nr + r];
       z.x += w * f.x;
       z.y += w * f.y;
     }
     if (y) {
-      const double2 q = y[e];
+      const V2 q = y[e];
       z.x -= q.x;
       z.y -= q.y;
     }
@@ -212,8 +221,9 @@ __global__ void k_pair_density(const double2* __restrict__ phir, int nv, const i
 }
 
 // dst[rb][dst_blk0 + blk][j][ri][i] from the packed tile
+template <typename TD>
 __global__ void k_tau_store(const double2* __restrict__ grids, const int2* __restrict__ IJ,
-                            long nblk, long nr, int R, double* __restrict__ dst, long dst_nblk,
+                            long nblk, long nr, int R, TD* __restrict__ dst, long dst_nblk,
                             long dst_blk0) {
   const long per_rb = nblk * 64 * R;
   const long nrb = nr / R;
@@ -237,7 +247,7 @@ __global__ void k_tau_store(const double2* __restrict__ grids, const int2* __res
       else if (i == j)
         v *= 0.5;
     }
-    dst[rb * dst_nblk * 64 * R + (dst_blk0 + blk) * 64 * R + (j * R + ri) * 8 + i] = v;
+    dst[rb * dst_nblk * 64 * R + (dst_blk0 + blk) * 64 * R + (j * R + ri) * 8 + i] = (TD)v;
   }
 }
 
@@ -259,17 +269,42 @@ constexpr int NSLOT = 128;
 // FUSE: the epilogue writes z = V a + s (v_c*Drho_b) phi - y instead of y
 // (into `y`, which may alias `a`: every workgroup reads its points of a into
 // LDS before any write and no other workgroup touches them).
-template <int R, int BL, bool FUSE>
+template <typename T>
+struct vec2_of;
+template <>
+struct vec2_of<double> {
+  using type = double2;
+};
+template <>
+struct vec2_of<float> {
+  using type = float2;
+};
+
+// LDS rows (one per orbital v) hold NBT * R values plus SPAD of padding: the
+// slots of a wave work on unrelated rows, and an unpadded row of 16 words
+// would put the same word of every row in the same bank.
+constexpr int SPAD = 1;
+
+// T: storage and arithmetic type of tau, a and y.  The LDS accumulators of y
+// are FP64 for both types: the LDS FP32 atomic add is several times slower
+// than the FP64 one on gfx950, and FP64 sums lose nothing.
+template <int R, int BL, bool FUSE, typename T>
 __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
-    const double* __restrict__ tau, long rb_stride, long nblk, const int2* __restrict__ IJ,
-    const double2* a, double2* y, int nb, int nv, int nvh, long nr, int nv8, int accumulate,
-    const double* __restrict__ V, const double2* __restrict__ vdrho,
-    const double2* __restrict__ phir, double s, int with_v) {
+    const T* __restrict__ tau, long rb_stride, long nblk, const int2* __restrict__ IJ,
+    const typename vec2_of<T>::type* a, typename vec2_of<T>::type* y, int nb, int nv, int nvh,
+    long nr, int nv8, int accumulate, const T* __restrict__ V,
+    const typename vec2_of<T>::type* __restrict__ vdrho,
+    const typename vec2_of<T>::type* __restrict__ phir, T s, int with_v) {
+  using V2 = typename vec2_of<T>::type;
   constexpr int NT = NSLOT * R * BL;
   constexpr int NBL = NBT / BL;
-  extern __shared__ double lds[];
-  double* as = lds;
-  double* ys = lds + (long)nv8 * NBT * R;
+  constexpr int RS = NBT * R + SPAD;
+  // rows of a tau block loaded ahead of their use: the whole block in FP32
+  // (64 registers), two rows in FP64
+  constexpr int JU = sizeof(T) == 4 ? 8 : 2;
+  extern __shared__ char lds_raw[];
+  T* as = reinterpret_cast<T*>(lds_raw);
+  double* ys = reinterpret_cast<double*>(as + (long)nv8 * RS);
   const long rb = blockIdx.x;
   const long r0 = rb * R;
   const int n_el = nv8 * NBT * R;
@@ -277,24 +312,26 @@ __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
     const int ri = e % R;
     const int b = (e / R) % NBT;
     const int v = e / (R * NBT);
-    double av = 0.0, yv = 0.0;
+    T av = 0;
+    double yv = 0;
     if (v < nv && b < nb) {
       const long gi = ((long)b * nvh + (v >> 1)) * nr + r0 + ri;
-      av = reinterpret_cast<const double*>(a + gi)[v & 1];
-      if (accumulate) yv = reinterpret_cast<const double*>(y + gi)[v & 1];
+      av = reinterpret_cast<const T*>(a + gi)[v & 1];
+      if (accumulate) yv = reinterpret_cast<const T*>(y + gi)[v & 1];
     }
-    as[e] = av;
-    ys[e] = yv;
+    const int li = v * RS + b * R + ri;
+    as[li] = av;
+    ys[li] = yv;
   }
   __syncthreads();
   const int bl = threadIdx.x % BL;
   const int ri = (threadIdx.x / BL) % R;
   const int slot = threadIdx.x / (BL * R);
   const long b0 = nblk * slot / NSLOT, b1 = nblk * (slot + 1) / NSLOT;
-  const double* tb = tau + rb * rb_stride + ri * 8;
-  const int bo = bl * NBL;
+  const T* tb = tau + rb * rb_stride + ri * 8;
+  const int lo = bl * NBL * R + ri;  // lane offset inside an LDS row
   int curI = -1;
-  double aI[8][NBL], acc[8][NBL];
+  T aI[8][NBL], acc[8][NBL];
   for (long blk = b0; blk < b1; ++blk) {
     const int2 bij = IJ[blk];
     if (bij.x != curI) {
@@ -303,39 +340,44 @@ __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
         for (int i = 0; i < 8; ++i)
 #pragma unroll
           for (int b = 0; b < NBL; ++b)
-            atomicAdd(&ys[((curI * 8 + i) * NBT + bo + b) * R + ri], acc[i][b]);
+            atomicAdd(&ys[(curI * 8 + i) * RS + lo + b * R], (double)acc[i][b]);
       }
       curI = bij.x;
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int b = 0; b < NBL; ++b) {
-          aI[i][b] = as[((curI * 8 + i) * NBT + bo + b) * R + ri];
-          acc[i][b] = 0.0;
+          aI[i][b] = as[(curI * 8 + i) * RS + lo + b * R];
+          acc[i][b] = 0;
         }
     }
-    const double* tp = tb + blk * 64 * R;
-#pragma unroll 2
-    for (int j = 0; j < 8; ++j) {
-      double t[8];
+    const T* tp = tb + blk * 64 * R;
+#pragma unroll 1
+    for (int j0 = 0; j0 < 8; j0 += JU) {
+      T t[JU][8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) t[i] = tp[j * 8 * R + i];
-      const int wv = bij.y * 8 + j;
-      double aj[NBL], tr[NBL];
+      for (int jj = 0; jj < JU; ++jj)
 #pragma unroll
-      for (int b = 0; b < NBL; ++b) {
-        aj[b] = as[(wv * NBT + bo + b) * R + ri];
-        tr[b] = 0.0;
-      }
+        for (int i = 0; i < 8; ++i) t[jj][i] = tp[(j0 + jj) * 8 * R + i];
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int jj = 0; jj < JU; ++jj) {
+        const int wv = bij.y * 8 + j0 + jj;
+        T aj[NBL], tr[NBL];
 #pragma unroll
         for (int b = 0; b < NBL; ++b) {
-          acc[i][b] = fma(t[i], aj[b], acc[i][b]);
-          tr[b] = fma(t[i], aI[i][b], tr[b]);
+          aj[b] = as[wv * RS + lo + b * R];
+          tr[b] = 0;
         }
 #pragma unroll
-      for (int b = 0; b < NBL; ++b) atomicAdd(&ys[(wv * NBT + bo + b) * R + ri], tr[b]);
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int b = 0; b < NBL; ++b) {
+            acc[i][b] = fma(t[jj][i], aj[b], acc[i][b]);
+            tr[b] = fma(t[jj][i], aI[i][b], tr[b]);
+          }
+#pragma unroll
+        for (int b = 0; b < NBL; ++b) atomicAdd(&ys[wv * RS + lo + b * R], (double)tr[b]);
+      }
     }
   }
   if (curI >= 0) {
@@ -343,7 +385,7 @@ __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
     for (int i = 0; i < 8; ++i)
 #pragma unroll
       for (int b = 0; b < NBL; ++b)
-        atomicAdd(&ys[((curI * 8 + i) * NBT + bo + b) * R + ri], acc[i][b]);
+        atomicAdd(&ys[(curI * 8 + i) * RS + lo + b * R], (double)acc[i][b]);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < n_el; e += NT) {
@@ -352,19 +394,20 @@ __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
     const int v = e / (R * NBT);
     if (v < nv && b < nb) {
       const long gi = ((long)b * nvh + (v >> 1)) * nr + r0 + rr;
-      double out = ys[e];
+      const int li = v * RS + b * R + rr;
+      T out = (T)ys[li];
       if (FUSE) {
         const long r = r0 + rr;
-        double z = -out;
-        if (with_v) z += V[r] * as[e];
+        T z = -out;
+        if (with_v) z += V[r] * as[li];
         if (vdrho) {
-          const double d = reinterpret_cast<const double*>(vdrho + (long)(b >> 1) * nr + r)[b & 1];
-          const double f = reinterpret_cast<const double*>(phir + (long)(v >> 1) * nr + r)[v & 1];
+          const T d = reinterpret_cast<const T*>(vdrho + (long)(b >> 1) * nr + r)[b & 1];
+          const T f = reinterpret_cast<const T*>(phir + (long)(v >> 1) * nr + r)[v & 1];
           z += s * d * f;
         }
         out = z;
       }
-      reinterpret_cast<double*>(y + gi)[v & 1] = out;
+      reinterpret_cast<T*>(y + gi)[v & 1] = out;
     }
   }
 }
@@ -579,25 +622,49 @@ int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, double2*
   return BSE_OK;
 }
 
-int gather_sets(const SphereMap& m, const double2* grid, int nv, int nset, double scale,
-                const double* A, const double* T, const double* eps, double shift, double beta,
-                double* Y, hipStream_t st) {
+template <typename V2>
+static int gather_impl(const SphereMap& m, const V2* grid, int nv, int nset, double scale,
+                       const double* A, const double* T, const double* eps, double shift,
+                       double beta, double* Y, hipStream_t st) {
   const int nvh = (nv + 1) / 2;
   const long ngrid = (long)nset * nvh;
   if (ngrid <= 0) return BSE_OK;
   const dim3 g((unsigned)((m.nhalf + 1 + TPB - 1) / TPB), (unsigned)std::min(ngrid, 65535L));
-  hipLaunchKernelGGL(k_gather, g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr,
+  hipLaunchKernelGGL(k_gather<V2>, g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr,
                      m.zero, grid, nv, nvh, ngrid, scale * std::sqrt(m.omega), scale * std::sqrt(2.0 * m.omega),
                      A, T, eps, shift, beta, Y);
   CHECK_LAUNCH();
   return BSE_OK;
 }
 
+int gather_sets(const SphereMap& m, const double2* grid, int nv, int nset, double scale,
+                const double* A, const double* T, const double* eps, double shift, double beta,
+                double* Y, hipStream_t st) {
+  return gather_impl(m, grid, nv, nset, scale, A, T, eps, shift, beta, Y, st);
+}
+
+int gather_sets(const SphereMap& m, const float2* grid, int nv, int nset, double scale,
+                const double* A, const double* T, const double* eps, double shift, double beta,
+                double* Y, hipStream_t st) {
+  return gather_impl(m, grid, nv, nset, scale, A, T, eps, shift, beta, Y, st);
+}
+
 int mul_real_field(double2* grid, long ngrid, long nr, const double* f, double scale,
                    hipStream_t st) {
   const long n = ngrid * nr;
   if (n <= 0) return BSE_OK;
-  hipLaunchKernelGGL(k_mul_real, dim3(nblocks(n)), dim3(TPB), 0, st, grid, n, nr, f, scale);
+  hipLaunchKernelGGL((k_mul_real<double2, double>), dim3(nblocks(n)), dim3(TPB), 0, st, grid, n,
+                     nr, f, scale);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int mul_real_field(float2* grid, long ngrid, long nr, const float* f, float scale,
+                   hipStream_t st) {
+  const long n = ngrid * nr;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL((k_mul_real<float2, float>), dim3(nblocks(n)), dim3(TPB), 0, st, grid, n, nr,
+                     f, scale);
   CHECK_LAUNCH();
   return BSE_OK;
 }
@@ -612,8 +679,29 @@ int transition_density(const double2* phir, const double2* a, int nv, int nb, lo
                        double2* drho, hipStream_t st) {
   const long n = (long)((nb + 1) / 2) * nr;
   if (n <= 0) return BSE_OK;
-  hipLaunchKernelGGL(k_transition_density, dim3(nblocks(n)), dim3(TPB), 0, st, phir, a,
-                     (nv + 1) / 2, nb, nr, drho);
+  hipLaunchKernelGGL((k_transition_density<double2, double>), dim3(nblocks(n)), dim3(TPB), 0, st,
+                     phir, a, (nv + 1) / 2, nb, nr, drho);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int transition_density(const float2* phir, const float2* a, int nv, int nb, long nr, float2* drho,
+                       hipStream_t st) {
+  const long n = (long)((nb + 1) / 2) * nr;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL((k_transition_density<float2, float>), dim3(nblocks(n)), dim3(TPB), 0, st,
+                     phir, a, (nv + 1) / 2, nb, nr, drho);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+__global__ void k_to_f32(const double* __restrict__ x, float* __restrict__ y, long n) {
+  for (long e = gtid(); e < n; e += gstride()) y[e] = (float)x[e];
+}
+
+int to_f32(const double* x, float* y, long n, hipStream_t st) {
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_to_f32, dim3(nblocks(n)), dim3(TPB), 0, st, x, y, n);
   CHECK_LAUNCH();
   return BSE_OK;
 }
@@ -623,8 +711,19 @@ int combine(const double2* a, const double2* phir, const double* V, const double
             hipStream_t st) {
   const long n = (long)nb * ((nv + 1) / 2) * nr;
   if (n <= 0) return BSE_OK;
-  hipLaunchKernelGGL(k_combine, dim3(nblocks(n)), dim3(TPB), 0, st, a, phir, V, vdrho, y, out,
-                     (nv + 1) / 2, nb, nr, s, with_v);
+  hipLaunchKernelGGL((k_combine<double2, double>), dim3(nblocks(n)), dim3(TPB), 0, st, a, phir, V,
+                     vdrho, y, out, (nv + 1) / 2, nb, nr, s, with_v);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int combine(const float2* a, const float2* phir, const float* V, const float2* vdrho,
+            const float2* y, float2* out, int nv, int nb, long nr, double s, int with_v,
+            hipStream_t st) {
+  const long n = (long)nb * ((nv + 1) / 2) * nr;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL((k_combine<float2, float>), dim3(nblocks(n)), dim3(TPB), 0, st, a, phir, V,
+                     vdrho, y, out, (nv + 1) / 2, nb, nr, (float)s, with_v);
   CHECK_LAUNCH();
   return BSE_OK;
 }
@@ -639,59 +738,73 @@ int pair_density(const double2* phir, int nv, const int2* blkIJ, long nblk, long
   return BSE_OK;
 }
 
-int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R, double* dst,
-              long dst_nblk, long dst_blk0, hipStream_t st) {
+template <typename TD>
+static int tau_store_impl(const double2* grids, const int2* blkIJ, long nblk, long nr, int R,
+                          TD* dst, long dst_nblk, long dst_blk0, hipStream_t st) {
   const long n = (nr / R) * nblk * 64 * R;
   if (n <= 0) return BSE_OK;
-  hipLaunchKernelGGL(k_tau_store, dim3(nblocks(n)), dim3(TPB), 0, st, grids, blkIJ, nblk, nr, R,
+  hipLaunchKernelGGL(k_tau_store<TD>, dim3(nblocks(n)), dim3(TPB), 0, st, grids, blkIJ, nblk, nr, R,
                      dst, dst_nblk, dst_blk0);
   CHECK_LAUNCH();
   return BSE_OK;
 }
 
-size_t tau_stream_lds(int nv, int R) {
+int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R, double* dst,
+              long dst_nblk, long dst_blk0, hipStream_t st) {
+  return tau_store_impl(grids, blkIJ, nblk, nr, R, dst, dst_nblk, dst_blk0, st);
+}
+
+int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R, float* dst,
+              long dst_nblk, long dst_blk0, hipStream_t st) {
+  return tau_store_impl(grids, blkIJ, nblk, nr, R, dst, dst_nblk, dst_blk0, st);
+}
+
+size_t tau_stream_lds(int nv, int R, size_t elem) {
   const int nv8 = (nv + 7) / 8 * 8;
-  return 2 * sizeof(double) * (size_t)nv8 * NBT * R;
+  return (elem + sizeof(double)) * (size_t)nv8 * (NBT * R + SPAD);
 }
 
 static int g_tau_bl = 4;  // trial vectors split over this many lanes (2 or 4)
 
 void tau_stream_set_variant(int bl) { g_tau_bl = (bl == 2) ? 2 : 4; }
 
-template <int R, int BL, bool F>
-static void launch_stream(long nrb, size_t shm, hipStream_t st, const double* tau, long stride,
-                          long nblk, const int2* blkIJ, const double2* a, double2* y, int nb, int nv,
-                          long nr, int nv8, int accumulate, const double* V,
-                          const double2* vdrho, const double2* phir, double s, int with_v) {
-  hipLaunchKernelGGL((k_tau_stream<R, BL, F>), dim3((unsigned)nrb), dim3(NSLOT * R * BL), shm, st,
-                     tau, stride, nblk, blkIJ, a, y, nb, nv, (nv + 1) / 2, nr, nv8, accumulate, V,
-                     vdrho, phir, s, with_v);
+template <int R, int BL, bool F, typename T>
+static void launch_stream(long nrb, size_t shm, hipStream_t st, const T* tau, long stride,
+                          long nblk, const int2* blkIJ, const typename vec2_of<T>::type* a,
+                          typename vec2_of<T>::type* y, int nb, int nv, long nr, int nv8,
+                          int accumulate, const T* V, const typename vec2_of<T>::type* vdrho,
+                          const typename vec2_of<T>::type* phir, T s, int with_v) {
+  hipLaunchKernelGGL((k_tau_stream<R, BL, F, T>), dim3((unsigned)nrb), dim3(NSLOT * R * BL), shm,
+                     st, tau, stride, nblk, blkIJ, a, y, nb, nv, (nv + 1) / 2, nr, nv8, accumulate,
+                     V, vdrho, phir, s, with_v);
 }
 
-int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
-               const double2* a, double2* y, int nb, int nv, long nr, int accumulate,
-               size_t max_lds, hipStream_t st, const FuseArgs* fuse) {
+template <typename T, typename FA>
+static int tau_stream_impl(const T* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
+                           const typename vec2_of<T>::type* a, typename vec2_of<T>::type* y,
+                           int nb, int nv, long nr, int accumulate, size_t max_lds,
+                           hipStream_t st, const FA* fuse) {
   if (nb > NBT) return fail(BSE_EINVAL, "tau_stream: at most %d vectors per call", NBT);
   if (nr % R) return fail(BSE_EINVAL, "tau_stream: grid size not a multiple of %d", R);
-  const size_t shm = tau_stream_lds(nv, R);
+  const size_t shm = tau_stream_lds(nv, R, sizeof(T));
   if (shm > max_lds) return fail(BSE_EINVAL, "tau_stream: %zu bytes of LDS exceed %zu", shm, max_lds);
   const int nv8 = (nv + 7) / 8 * 8;
   const long nrb = nr / R;
   if (nrb > 0x7fffffffL) return fail(BSE_EINVAL, "tau_stream: grid too large");
   const long stride = buf_nblk * 64 * R;
-  const double* V = fuse ? fuse->V : nullptr;
-  const double2* vd = fuse ? fuse->vdrho : nullptr;
-  const double2* ph = fuse ? fuse->phir : nullptr;
-  const double sf = fuse ? fuse->s : 0.0;
+  const T* V = fuse ? fuse->V : nullptr;
+  const typename vec2_of<T>::type* vd = fuse ? fuse->vdrho : nullptr;
+  const typename vec2_of<T>::type* ph = fuse ? fuse->phir : nullptr;
+  const T sf = fuse ? (T)fuse->s : (T)0;
   const int wv = fuse ? fuse->with_v : 0;
-#define GO(R_, BL_)                                                                            \
-  do {                                                                                         \
-    if (fuse)                                                                                  \
-      launch_stream<R_, BL_, true>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,    \
-                                   nv8, accumulate, V, vd, ph, sf, wv);                        \
-    else                                                                                       \
-      launch_stream<R_, BL_, false>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,   \
-                                    nv8, accumulate, V, vd, ph, sf, wv);                       \
+#define GO(R_, BL_)                                                                              \
+  do {                                                                                           \
+    if (fuse)                                                                                    \
+      launch_stream<R_, BL_, true, T>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,   \
+                                      nv8, accumulate, V, vd, ph, sf, wv);                       \
+    else                                                                                         \
+      launch_stream<R_, BL_, false, T>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,  \
+                                       nv8, accumulate, V, vd, ph, sf, wv);                      \
   } while (0)
   if (R == 2 && g_tau_bl == 4)
     GO(2, 4);
@@ -708,11 +821,30 @@ int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, i
   return BSE_OK;
 }
 
+int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
+               const double2* a, double2* y, int nb, int nv, long nr, int accumulate,
+               size_t max_lds, hipStream_t st, const FuseArgs* fuse) {
+  return tau_stream_impl(tau, buf_nblk, nblk, blkIJ, R, a, y, nb, nv, nr, accumulate, max_lds, st,
+                         fuse);
+}
+
+int tau_stream(const float* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
+               const float2* a, float2* y, int nb, int nv, long nr, int accumulate,
+               size_t max_lds, hipStream_t st, const FuseArgsF* fuse) {
+  return tau_stream_impl(tau, buf_nblk, nblk, blkIJ, R, a, y, nb, nv, nr, accumulate, max_lds, st,
+                         fuse);
+}
+
 int tau_stream_set_lds_limit(size_t bytes) {
-  const void* fns[] = {(const void*)k_tau_stream<2, 4, false>, (const void*)k_tau_stream<2, 2, false>,
-                       (const void*)k_tau_stream<1, 4, false>, (const void*)k_tau_stream<1, 2, false>,
-                       (const void*)k_tau_stream<2, 4, true>,  (const void*)k_tau_stream<2, 2, true>,
-                       (const void*)k_tau_stream<1, 4, true>,  (const void*)k_tau_stream<1, 2, true>};
+  const void* fns[] = {
+      (const void*)k_tau_stream<2, 4, false, double>, (const void*)k_tau_stream<2, 2, false, double>,
+      (const void*)k_tau_stream<1, 4, false, double>, (const void*)k_tau_stream<1, 2, false, double>,
+      (const void*)k_tau_stream<2, 4, true, double>,  (const void*)k_tau_stream<2, 2, true, double>,
+      (const void*)k_tau_stream<1, 4, true, double>,  (const void*)k_tau_stream<1, 2, true, double>,
+      (const void*)k_tau_stream<2, 4, false, float>,  (const void*)k_tau_stream<2, 2, false, float>,
+      (const void*)k_tau_stream<1, 4, false, float>,  (const void*)k_tau_stream<1, 2, false, float>,
+      (const void*)k_tau_stream<2, 4, true, float>,   (const void*)k_tau_stream<2, 2, true, float>,
+      (const void*)k_tau_stream<1, 4, true, float>,   (const void*)k_tau_stream<1, 2, true, float>};
   for (const void* f : fns)
     BSE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   return BSE_OK;

@@ -163,7 +163,7 @@ int apply_H(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double2* 
 //   sum_j e_j [V^1/2 P C P^T V^1/2 rho_S]_j  via two GEMMs per tile.
 // ---------------------------------------------------------------------------
 int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double* dst,
-                    long dst_nblk, long dst_blk0, int mask) {
+                    long dst_nblk, long dst_blk0, int mask, float* dstf) {
   if (nblk <= 0) return BSE_OK;
   if (nblk > c->tile_blk) return fail(BSE_EINVAL, "tau build: tile of %ld blocks too large", nblk);
   const long nr = c->basis.nr, npw = c->basis.npw;
@@ -187,7 +187,11 @@ int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double
     BSE_HIP(hipMemsetAsync(c->tile_grids, 0, sizeof(double2) * ng * nr, c->st));
   if (pdep) BSE_TRY(scatter_sets(m64, c->tile_F, 64, (int)nblk, c->tile_grids, 1, c->st));
   BSE_TRY(fft3d(c->fft, c->tile_grids, ng, +1, c->st));
-  BSE_TRY(tau_store(c->tile_grids, c->blkIJ + gb0, nblk, nr, c->R, dst, dst_nblk, dst_blk0, c->st));
+  if (dstf)
+    BSE_TRY(tau_store(c->tile_grids, c->blkIJ + gb0, nblk, nr, c->Rf, dstf, c->nblk, gb0, c->st));
+  if (dst)
+    BSE_TRY(tau_store(c->tile_grids, c->blkIJ + gb0, nblk, nr, c->R, dst, dst_nblk, dst_blk0,
+                      c->st));
   return BSE_OK;
 }
 
@@ -317,6 +321,99 @@ int kernel_part(bse_ctx* c, const double2* agrid, double* Kt) {
 // contracted with phi), tiles rebuilt for every block.
 int sigma_phi(bse_ctx* c, const double2* agrid, double2* y) {
   return tau_contract(c, agrid, c->phir, y, 1, c->kmask, false);
+}
+
+// ---------------------------------------------------------------------------
+// mixed precision: FP32 grids, transforms, K1e and tau contraction; the
+// projector, the diagonal (T - eps + Delta) A and everything in G space stay
+// FP64
+// ---------------------------------------------------------------------------
+int ensure_mixed_work(bse_ctx* c, int nbc) {
+  if (c->nbc_f >= nbc) return BSE_OK;
+  ctx_release(c, c->agrid_f);
+  ctx_release(c, c->drho_f);
+  c->agrid_f = c->drho_f = nullptr;
+  c->nbc_f = 0;
+  const size_t nr = c->basis.nr;
+  BSE_TRY(ctx_alloc_t(c, &c->agrid_f, (size_t)nbc * c->nvh * nr));
+  BSE_TRY(ctx_alloc_t(c, &c->drho_f, (size_t)((nbc + 1) / 2) * nr));
+  c->nbc_f = nbc;
+  return BSE_OK;
+}
+
+static int ensure_compact_f(bse_ctx* c, long ngrids) {
+  if (c->compact_f_grids >= ngrids) return BSE_OK;
+  ctx_release(c, c->compact_f);
+  c->compact_f = nullptr;
+  c->compact_f_grids = 0;
+  BSE_TRY(ctx_alloc_t(c, &c->compact_f, (size_t)ngrids * c->basis.npw));
+  c->compact_f_grids = ngrids;
+  return BSE_OK;
+}
+
+static int from_grid_f(bse_ctx* c, float2* grids, int nvs, int nset, const double* A,
+                       const double* eps, double shift, double* Y) {
+  PhaseScope ps(c, PH_FFT_FWD);
+  const long ng = (long)nset * ((nvs + 1) / 2);
+  BSE_TRY(ensure_compact_f(c, ng));
+  BSE_TRY(grid_to_compact(c->fft, c->sp, grids, ng, c->compact_f, c->st));
+  return gather_sets(c->cmap, c->compact_f, nvs, nset, 1.0 / (double)c->basis.nr, A, c->T, eps,
+                     shift, 0.0, Y, c->st);
+}
+
+int apply_chunk_mixed(bse_ctx* c, int nb, const double* X, double* Y) {
+  const long nr = c->basis.nr;
+  BSE_TRY(ensure_mixed_work(c, c->nbc));
+  BSE_TRY(proj_c(c, X, c->A_s, nb));
+  {
+    PhaseScope ps(c, PH_FFT_INV);
+    BSE_TRY(sphere_to_grid(c->fft, c->sp, c->basis.omega, c->A_s, c->nv, nb, c->agrid_f, c->st));
+  }
+  const float2* vdrho = nullptr;
+  if (c->kmask & BSE_K_1E) {
+    PhaseScope ps(c, PH_K1E);
+    const long nbh = (nb + 1) / 2;
+    BSE_TRY(transition_density(c->phir_f, c->agrid_f, c->nv, nb, nr, c->drho_f, c->st));
+    BSE_TRY(fft3d(c->fft, c->drho_f, nbh, -1, c->st));
+    BSE_TRY(mul_real_field(c->drho_f, nbh, nr, c->vc_f, 1.0f / (float)nr, c->st));
+    BSE_TRY(fft3d(c->fft, c->drho_f, nbh, +1, c->st));
+    vdrho = c->drho_f;
+  }
+  const int with_v = (c->kmask & BSE_K_D) ? 1 : 0;
+  if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
+    PhaseScope ps(c, PH_TAU_STREAM);
+    FuseArgsF f{c->Vr_f, vdrho, c->phir_f, c->spin, with_v};
+    BSE_TRY(tau_stream(c->tau_f, c->nblk, c->nblk, c->blkIJ, c->Rf, c->agrid_f, c->agrid_f, nb,
+                       c->nv, nr, 0, c->max_lds, c->st, &f));
+  } else {
+    PhaseScope ps(c, PH_COMBINE);
+    BSE_TRY(combine(c->agrid_f, c->phir_f, c->Vr_f, vdrho, nullptr, c->agrid_f, c->nv, nb, nr,
+                    c->spin, with_v, c->st));
+  }
+  BSE_TRY(from_grid_f(c, c->agrid_f, c->nv, nb, with_v ? c->A_s : nullptr, c->eps_d, c->scissor,
+                      c->Zs));
+  BSE_TRY(proj_c(c, c->Zs, Y, nb));
+  return BSE_OK;
+}
+
+int apply_any(bse_ctx* c, int nb, const double* X, double* Y) {
+  if (c->active == BSE_MIXED) return apply_chunk_mixed(c, nb, X, Y);
+  return apply_chunk(c, nb, X, Y);
+}
+
+// (T + shift - eps_v) X + <e| V(r) x(r)> with the grid part in FP32
+int apply_H_f(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double shift,
+              const double* eps, int project) {
+  const long ng = (long)nset * ((nvs + 1) / 2);
+  if (ng > (long)c->nbc_f * c->nvh) return fail(BSE_EINVAL, "FP32 grid work too small");
+  {
+    PhaseScope ps(c, PH_FFT_INV);
+    BSE_TRY(sphere_to_grid(c->fft, c->sp, c->basis.omega, X, nvs, nset, c->agrid_f, c->st));
+  }
+  BSE_TRY(mul_real_field(c->agrid_f, ng, c->basis.nr, c->Vr_f, 1.0f, c->st));
+  BSE_TRY(from_grid_f(c, c->agrid_f, nvs, nset, X, eps, shift, Y));
+  if (project) BSE_TRY(proj_c(c, Y, Y, nset));
+  return BSE_OK;
 }
 
 }  // namespace bsex

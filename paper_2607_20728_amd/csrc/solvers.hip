@@ -17,6 +17,13 @@
 namespace bsex {
 
 constexpr double kPrecondShift = 0.25;  // Ha, kinetic preconditioner shift
+// The FP32-kernel Davidson stops at half the requested residual, but not below
+// kMixedFloor: the FP32 apply differs from the FP64 one by ~1e-8 of |Y|, a few
+// 1e-7 in the residual of a normalised vector, so the FP64 check then passes
+// without FP64 iterations unless tol is below that floor.
+constexpr double kMixedFloor = 3e-7;
+// relative residual of each inner FP32 PCG solve of the Z-vector refinement
+constexpr double kMixedInnerTol = 1e-4;
 
 int gram_tall(bse_ctx* c, const double* A, long m, const double* B, long n, long len, double* C) {
   const long need = dgemm_tall_work(m, n, len);
@@ -78,7 +85,7 @@ int apply_n(bse_ctx* c, long n, const double* X, double* Y) {
   const long L = (long)c->nv * c->basis.npw;
   for (long i = 0; i < n; i += c->nbc) {
     const int k = (int)std::min<long>(c->nbc, n - i);
-    BSE_TRY(apply_chunk(c, k, X + i * L, Y + i * L));
+    BSE_TRY(apply_any(c, k, X + i * L, Y + i * L));
   }
   return BSE_OK;
 }
@@ -141,8 +148,8 @@ int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len,
 // Davidson (the paper names no eigensolver; its target is the lowest
 // eigenpairs of P_c M P_c)
 // ---------------------------------------------------------------------------
-int davidson(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double* Xout,
-             bse_solver_stats* stats) {
+static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega,
+                         double* Xout, bse_solver_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
   const int maxit = (o && o->max_iter > 0) ? o->max_iter : 300;
@@ -301,10 +308,80 @@ int davidson(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double
   if (stats) {
     stats->iters = it;
     stats->applies = applies;
+    stats->applies_fp64 = c->active == BSE_MIXED ? 0 : applies;
     for (int i = 0; i < 16; ++i) stats->resid[i] = i < nb ? rn[i] : 0.0;
     stats->t_ms = elapsed_ms(t0);
   }
   if (!conv) return fail(BSE_ENOCONV, "Davidson: no convergence in %d iterations", it);
+  return BSE_OK;
+}
+
+// Davidson on the operator of the context's precision.  In mixed precision
+// the FP32-kernel operator drives the iteration; the Ritz vectors are then
+// checked with the FP64 operator (tau rebuilt in FP64) and, if the FP64
+// residual is above tol, the FP64 Davidson continues from them.
+int davidson(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double* Xout,
+             bse_solver_stats* stats) {
+  if (c->active != BSE_MIXED) return davidson_core(c, ns, o, omega, Xout, stats);
+  const auto t0 = std::chrono::steady_clock::now();
+  const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
+  const long L = (long)c->nv * c->basis.npw;
+  DVec X(c), Y(c), sv(c);
+  BSE_TRY(X.alloc((size_t)ns * L));
+  BSE_TRY(Y.alloc((size_t)ns * L));
+  BSE_TRY(sv.alloc(64));
+  bse_solver_stats s1{}, s2{};
+  bse_solver_opts o1{};
+  if (o) o1 = *o;
+  o1.tol = std::max(0.5 * tol, kMixedFloor);
+  int rc = davidson_core(c, ns, &o1, omega, X.p, &s1);
+  if (rc != BSE_OK && rc != BSE_ENOCONV) return rc;
+  c->active = BSE_FP64;
+  struct Back {
+    bse_ctx* c;
+    ~Back() { c->active = BSE_MIXED; }
+  } back{c};
+  BSE_TRY(apply_n(c, ns, X.p, Y.p));
+  std::vector<double> th, r2, xx;
+  BSE_TRY(dots_host(c, X.p, Y.p, ns, L, sv.p, th));
+  BSE_TRY(dots_host(c, X.p, X.p, ns, L, sv.p, xx));
+  std::vector<double> nt(ns);
+  for (int i = 0; i < ns; ++i) {
+    th[i] /= xx[i];
+    nt[i] = -th[i];
+  }
+  BSE_TRY(to_dev(c, nt.data(), sv.p + 32, ns));
+  BSE_TRY(row_axpby(sv.p + 32, X.p, nullptr, Y.p, ns, L, c->st));
+  BSE_TRY(dots_host(c, Y.p, Y.p, ns, L, sv.p, r2));
+  double worst = 0;
+  for (int i = 0; i < ns; ++i) worst = std::max(worst, std::sqrt(r2[i] / xx[i]));
+  int applies = s1.applies + ns, applies64 = ns;
+  int iters = s1.iters;
+  if (worst <= tol) {
+    for (int i = 0; i < ns; ++i) {
+      omega[i] = th[i];
+      s2.resid[i] = std::sqrt(r2[i] / xx[i]);
+    }
+    if (Xout) BSE_TRY(copy_dev(c, X.p, Xout, (size_t)ns * L));
+  } else {
+    bse_solver_opts o2{};
+    if (o) o2 = *o;
+    o2.x0_dev = X.p;
+    o2.n_x0 = ns;
+    rc = davidson_core(c, ns, &o2, omega, Xout ? Xout : X.p, &s2);
+    applies += s2.applies;
+    applies64 += s2.applies;
+    iters += s2.iters;
+    if (rc != BSE_OK) return rc;
+  }
+  BSE_HIP(hipStreamSynchronize(c->st));
+  if (stats) {
+    stats->iters = iters;
+    stats->applies = applies;
+    stats->applies_fp64 = applies64;
+    for (int i = 0; i < 16; ++i) stats->resid[i] = i < ns ? s2.resid[i] : 0.0;
+    stats->t_ms = elapsed_ms(t0);
+  }
   return BSE_OK;
 }
 
@@ -342,36 +419,28 @@ int u_vector(bse_ctx* c, const double* Xs, double* U) {
 // ---------------------------------------------------------------------------
 // Z-vector:  P_c (H - eps_v) P_c Z_v = -u_v, block PCG with per-band steps
 // ---------------------------------------------------------------------------
-int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
-            bse_solver_stats* stats) {
-  const auto t0 = std::chrono::steady_clock::now();
-  const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
-  const int maxit = (o && o->max_iter > 0) ? o->max_iter : 5000;
+// Solve P_c (H - eps_v) P_c Z = rhs from the current Z (projected first)
+// until ||rhs - D Z||_F <= tol ||rhs||_F; fp32 selects the FP32-grid H.
+static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, bool fp32,
+               int* iters, double* rel_out) {
   const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
-  BSE_TRY(ensure_apply_work(c, 1));
-  DVec U(c), R(c), P(c), AP(c), Zr(c), sv(c);
-  BSE_TRY(U.alloc(L));
+  DVec R(c), P(c), AP(c), Zr(c), sv(c);
   BSE_TRY(R.alloc(L));
   BSE_TRY(P.alloc(L));
   BSE_TRY(AP.alloc(L));
   BSE_TRY(Zr.alloc(L));
   BSE_TRY(sv.alloc(4 * (size_t)nv + 16));
-  BSE_TRY(u_vector(c, Xs, U.p));
-  BSE_TRY(proj_c(c, U.p, U.p, 1));
   std::vector<double> d;
-  BSE_TRY(dots_host(c, U.p, U.p, nv, npw, sv.p, d));
-  const double nu = std::sqrt(std::accumulate(d.begin(), d.end(), 0.0));
+  BSE_TRY(dots_host(c, rhs, rhs, nv, npw, sv.p, d));
+  const double nb_ = std::sqrt(std::accumulate(d.begin(), d.end(), 0.0));
   auto applyD = [&](const double* in, double* out) -> int {
     BSE_TRY(proj_c(c, in, Zr.p, 1));
+    if (fp32) return apply_H_f(c, (int)nv, 1, Zr.p, out, 0.0, c->eps_d, 1);
     return apply_H(c, (int)nv, 1, Zr.p, out, c->agrid, 0.0, c->eps_d, 1);
   };
-  if (o && o->z0_dev) {
-    BSE_TRY(proj_c(c, o->z0_dev, Z, 1));
-  } else {
-    BSE_HIP(hipMemsetAsync(Z, 0, sizeof(double) * L, c->st));
-  }
+  BSE_TRY(proj_c(c, Z, Z, 1));
   BSE_TRY(applyD(Z, AP.p));
-  BSE_TRY(axpby(-1.0, U.p, 0.0, R.p, L, c->st));
+  BSE_TRY(axpby(1.0, rhs, 0.0, R.p, L, c->st));
   BSE_TRY(axpby(-1.0, AP.p, 1.0, R.p, L, c->st));
   BSE_TRY(precond_cg(R.p, Zr.p, c->T, c->eps_d, kPrecondShift, (int)nv, (int)npw, c->st));
   BSE_TRY(proj_c(c, Zr.p, P.p, 1));
@@ -382,7 +451,7 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
   bool conv = false;
   for (it = 0; it < maxit; ++it) {
     BSE_TRY(dots_host(c, R.p, R.p, nv, npw, sv.p, rr));
-    rel = nu > 0 ? std::sqrt(std::accumulate(rr.begin(), rr.end(), 0.0)) / nu : 0.0;
+    rel = nb_ > 0 ? std::sqrt(std::accumulate(rr.begin(), rr.end(), 0.0)) / nb_ : 0.0;
     if (rel <= tol) {
       conv = true;
       break;
@@ -407,15 +476,74 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
     BSE_TRY(row_axpby(nullptr, Zr.p, sv.p + 3 * nv, P.p, nv, npw, c->st));
     rz = rzn;
   }
+  *iters = it;
+  *rel_out = rel;
+  return conv ? BSE_OK : BSE_ENOCONV;
+}
+
+int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
+            bse_solver_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
+  const int maxit = (o && o->max_iter > 0) ? o->max_iter : 5000;
+  const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
+  BSE_TRY(ensure_apply_work(c, 2));
+  DVec U(c), R(c), D(c), sv(c);
+  BSE_TRY(U.alloc(L));
+  BSE_TRY(sv.alloc(16 + (size_t)nv));
+  BSE_TRY(u_vector(c, Xs, U.p));
+  BSE_TRY(proj_c(c, U.p, U.p, 1));
+  BSE_HIP(hipStreamSynchronize(c->st));
+  if (o && o->z0_dev) {
+    BSE_TRY(proj_c(c, o->z0_dev, Z, 1));
+  } else {
+    BSE_HIP(hipMemsetAsync(Z, 0, sizeof(double) * L, c->st));
+  }
+  BSE_TRY(axpby(-1.0, U.p, 0.0, U.p, L, c->st));  // U <- -U: the right-hand side
+  int iters = 0, it = 0, rc = BSE_OK, applies64 = 0;
+  double rel = 0.0;
+  if (c->active != BSE_MIXED) {
+    rc = pcg(c, U.p, Z, tol, maxit, false, &iters, &rel);
+    applies64 = iters + 1;
+  } else {
+    // iterative refinement: FP64 residual outside, FP32-grid PCG inside
+    BSE_TRY(R.alloc(L));
+    BSE_TRY(D.alloc(L));
+    BSE_TRY(ensure_mixed_work(c, 1));
+    std::vector<double> un, rn;
+    BSE_TRY(dots_host(c, U.p, U.p, nv, npw, sv.p, un));
+    const double nu = std::sqrt(std::accumulate(un.begin(), un.end(), 0.0));
+    rc = BSE_ENOCONV;
+    for (int outer = 0; outer < 30 && iters < maxit; ++outer) {
+      BSE_TRY(proj_c(c, Z, D.p, 1));
+      BSE_TRY(apply_H(c, (int)nv, 1, D.p, R.p, c->agrid, 0.0, c->eps_d, 1));
+      ++applies64;
+      BSE_TRY(axpby(1.0, U.p, -1.0, R.p, L, c->st));  // R = rhs - D Z
+      BSE_TRY(dots_host(c, R.p, R.p, nv, npw, sv.p, rn));
+      rel = nu > 0 ? std::sqrt(std::accumulate(rn.begin(), rn.end(), 0.0)) / nu : 0.0;
+      if (rel <= tol) {
+        rc = BSE_OK;
+        break;
+      }
+      BSE_HIP(hipMemsetAsync(D.p, 0, sizeof(double) * L, c->st));
+      double irel = 0;
+      const int irc = pcg(c, R.p, D.p, kMixedInnerTol, maxit - iters, true, &it, &irel);
+      iters += it;
+      if (irc != BSE_OK && irc != BSE_ENOCONV) return irc;
+      BSE_TRY(axpby(1.0, D.p, 1.0, Z, L, c->st));
+    }
+  }
   BSE_HIP(hipStreamSynchronize(c->st));
   if (stats) {
-    stats->iters = it;
-    stats->applies = it + 1;
+    stats->iters = iters;
+    stats->applies = c->active == BSE_MIXED ? iters + applies64 : iters + 1;
+    stats->applies_fp64 = applies64;
     stats->resid[0] = rel;
     stats->t_ms = elapsed_ms(t0);
   }
-  if (!conv) return fail(BSE_ENOCONV, "Z-vector CG: no convergence in %d iterations", it);
-  return BSE_OK;
+  if (rc == BSE_ENOCONV)
+    return fail(BSE_ENOCONV, "Z-vector CG: residual %.3e after %d iterations", rel, iters);
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
