@@ -11,7 +11,8 @@ G-space basis with prescribed eigenvalues replaces the PDEP eigenpotentials of
 the screened interaction W (Eq. 3).
 
 Draw order from one ``numpy.random.Generator(PCG64(seed))`` stream:
-site positions -> depths -> widths -> PDEP Gaussian matrix -> trial block.
+site positions -> displacements (if any) -> depths -> widths (random site
+model only) -> PDEP Gaussian matrix -> trial block.
 """
 from __future__ import annotations
 
@@ -21,7 +22,7 @@ import math
 import numpy as np
 
 __all__ = ["Config", "CONFIGS", "get_config", "make_system", "diamond_sites",
-           "honeycomb_sites"]
+           "honeycomb_sites", "c5_geometry", "c4_systems", "C4_GRIDS"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -40,6 +41,11 @@ class Config:
     seed: int = 0
     n_states: int = 1      # excitons requested
     n_block: int = 8       # trial vectors per apply block in throughput runs
+    # "random": depth ~ U(depth), width ~ U(width); "dimer": honeycomb
+    # sublattices A / B with depths depth[0] / depth[1], width width[0], and one
+    # nearest-neighbour A-B pair (the substitution) with depth 2.0, width 1.1
+    site_model: str = "random"
+    displace: float = 0.0  # sigma (bohr) of N(0, sigma) site displacements
 
 
 CONFIGS = {
@@ -49,14 +55,49 @@ CONFIGS = {
     # tiny plain FP64 system: 8 random Gaussian sites, N_v = 16, N_pdep = 64
     "c1": Config("c1", (10.0, 10.0, 10.0), (24, 24, 24), 10.0, 16, 64, -0.8, 16.0,
                  "uniform:8", seed=1000),
-    # defect supercell: 3x3x3 diamond cells (216 sites) with one removed
+    # 2-D slab: 10 x 5 rectangular honeycomb cells (200 sites, nearest
+    # neighbours 2.733 bohr) in a 110-bohr cell along z
+    "c5": Config("c5", (47.34, 40.99, 110.0), (48, 48, 120), 3.26, 400, 768, -0.85, 144.0,
+                 "honeycomb", depth=(1.5, 2.5), width=(1.0, 1.0), seed=5000,
+                 site_model="dimer"),
+    # defect supercell: 3x3x3 diamond cells (216 sites) with one removed; the
+    # seed is the first from 2000 whose Kohn-Sham gap at N_v is >= 1e-3 Ha
+    # (2000: 4.7e-4, 2001: 6.5e-4, 2002: 2.1e-3)
     "c2": Config("c2", (20.2, 20.2, 20.2), (72, 72, 72), 14.2, 432, 512, -0.85, 96.0,
-                 "diamond:3", seed=2000, n_states=4, n_block=8),
+                 "diamond:3", seed=2002, n_states=4, n_block=8),
 }
 
 
 def get_config(name: str) -> Config:
     return CONFIGS[name]
+
+
+def c5_geometry(g: int) -> Config:
+    """Geometry g of the slab family: the sites of c5 displaced by N(0, 0.05
+    bohr), seed 5000 + g (g = 0 is the undisplaced slab)."""
+    base = CONFIGS["c5"]
+    return dataclasses.replace(base, name=f"c5g{g}", seed=5000 + g,
+                               displace=0.05 if g > 0 else 0.0)
+
+
+C4_GRIDS = (32, 40, 48, 64)
+
+
+def c4_systems(n: int = 32, seed: int = 4000) -> list:
+    """The uneven batch: n cubic systems with the spacing of c1 (L = 10 N / 24
+    bohr, E_cut 10 Ha, 8 random sites), N drawn from C4_GRIDS, N_v from
+    U{32..256}, N_pdep from U{128..384}, lambda_i = -0.8 exp(-i / (N_pdep / 4)).
+    System k has seed seed + 1 + k."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n):
+        N = int(rng.choice(C4_GRIDS))
+        nv = int(rng.integers(32, 257))
+        npdep = int(rng.integers(128, 385))
+        L = 10.0 * N / 24.0
+        out.append(Config(f"c4s{k}", (L, L, L), (N, N, N), 10.0, nv, npdep, -0.8, npdep / 4.0,
+                          "uniform:8", seed=seed + 1 + k))
+    return out
 
 
 def diamond_sites(cells: int, a: float, drop_origin: bool = True) -> np.ndarray:
@@ -119,8 +160,21 @@ def make_system(cfg: Config | str, n_pw: int, *, seed: int | None = None,
     else:
         raise ValueError(cfg.sites)
     n_sites = xyz.shape[0]
-    depth = rng.uniform(cfg.depth[0], cfg.depth[1], n_sites)
-    width = rng.uniform(cfg.width[0], cfg.width[1], n_sites)
+    if cfg.displace > 0:
+        xyz = xyz + rng.normal(0.0, cfg.displace, xyz.shape)
+    if cfg.site_model == "dimer":
+        # base sites 0 and 2 of each honeycomb cell are sublattice A, 1 and 3 B;
+        # the substitution pair is sites 0 and 1 (nearest neighbours) of the
+        # cell nearest the slab centre
+        sub = np.arange(n_sites) % 2
+        depth = np.where(sub == 0, cfg.depth[0], cfg.depth[1]).astype(np.float64)
+        width = np.full(n_sites, cfg.width[0])
+        c = (5 * 5 + 2) * 4
+        depth[c:c + 2] = 2.0
+        width[c:c + 2] = 1.1
+    else:
+        depth = rng.uniform(cfg.depth[0], cfg.depth[1], n_sites)
+        width = rng.uniform(cfg.width[0], cfg.width[1], n_sites)
     lam = cfg.lam_scale * np.exp(-np.arange(cfg.n_pdep) / cfg.lam_decay)
     if cfg.n_pdep > n_pw - 1:
         raise ValueError("n_pdep must be below n_pw - 1")
