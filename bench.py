@@ -24,6 +24,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 METRIC = "A·X applies/s at N_v=432"
 
@@ -98,10 +99,51 @@ def cpu_baseline(cfg_name, n_b, n_pairs_sample=32):
                         f"block of {n_b} extrapolated to {t_block:.0f} s"))
 
 
+def stream_kernel_sha():
+    """Hash of the tau-stream kernel's source: traffic counters taken on an
+    older kernel are not reported."""
+    import hashlib
+    src = open(os.path.join(HERE, "paper_2607_20728_amd", "csrc", "kernels.hip")).read()
+    a = src.index("// LDS rows (one per orbital v)")
+    b = src.index("// potential, Coulomb kernel, forces")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def stream_traffic(mixed):
+    """HBM bytes per k_tau_stream launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, scaled by the same counters on a plain
+    copy of known size), or None when absent or taken on another kernel."""
+    f = os.path.join(HERE, "profiles", f"traffic_tau_stream_{'f32' if mixed else 'f64'}.json")
+    if not os.path.exists(f):
+        return None
+    d = json.load(open(f))
+    if d.get("source_sha") != stream_kernel_sha():
+        return None
+    return (d["fetch_kib_per_launch"] * d["copy_fetch_factor"] +
+            d["write_kib_per_launch"] * d["copy_write_factor"]) * 1024.0
+
+
+def copy_calibration(args):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters: each launch reads and writes 2 GiB."""
+    import torch
+    torch.cuda.set_device(0)
+    n = 2 ** 28  # 2 GiB of float64
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(args.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes_read=8 * n, copy_bytes_written=8 * n,
+                          launches=args.steps)), flush=True)
+
+
 def time_to_force(args):
-    """FP64 time-to-force at C2: device ground state, tau cache (partial, the
-    rest rebuilt per apply), Davidson for the lowest n_states excitons to a
-    residual of 1e-6, U and the Z-vector CG to 1e-6, forces for exciton 1."""
+    """Time to force on one system (default the defect supercell): device
+    ground state and tau cache (init), Davidson for the lowest n_states
+    excitons to --tol, U and the Z-vector solve to --tol, forces for exciton 1.
+    --precision mixed runs the mixed-precision operator (residuals still judged
+    by the FP64 operator); --learned attaches a trained preconditioner."""
     import torch
 
     import synth
@@ -114,23 +156,30 @@ def time_to_force(args):
     t0 = time.perf_counter()
     prec = bsex.MIXED if args.precision == "mixed" else bsex.FP64
     ctx = bsex.init_from_synth(d, n_extra=8, gs_tol=1e-10, gap_min=args.gap_min, precision=prec)
+    net = None
+    if args.learned:
+        from paper_2607_20728_amd import learned
+        net, _ = learned.load(args.learned)
+        bsex.set_learned(ctx, net)
+    use = net is not None
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
     info = bsex.get_info(ctx)
     log(f"[ttf] init {t_init:.1f} s, gap {info['ks_gap']:.3e}, cached "
         f"{info['tau_blocks_cached']}/{info['tau_blocks']}")
     t1 = time.perf_counter()
-    w, X, ds = bsex.davidson(ctx, cfg.n_states, tol=args.tol, check=False)
+    w, X, ds = bsex.davidson(ctx, cfg.n_states, tol=args.tol, use_learned=use, check=False)
     t2 = time.perf_counter()
     log(f"[ttf] davidson {t2 - t1:.1f} s, {ds['iters']} iters, {ds['applies']} applies "
         f"({ds['applies_fp64']} FP64), "
         f"omega {w}, resid {ds['resid'][:cfg.n_states]}")
-    Z, zs = bsex.zvector_solve(ctx, X[0], tol=args.tol, check=False)
+    Z, zs = bsex.zvector_solve(ctx, X[0], tol=args.tol, use_learned=use, check=False)
     t3 = time.perf_counter()
     log(f"[ttf] U + Z {t3 - t2:.1f} s, {zs['iters']} iters, resid {zs['resid'][0]:.2e}")
     F = bsex.forces(ctx, X[0], Z, len(d["site_depth"]))
     t4 = time.perf_counter()
-    out = dict(metric=f"time-to-force @{args.tol:g} resid ({args.precision})",
+    mode = args.precision + ("+learned" if use else "")
+    out = dict(metric=f"time-to-force @{args.tol:g} resid ({mode})",
                value=round(t4 - t0, 2), unit="s", higher_is_better=False,
                dtype="f32+f64" if prec == bsex.MIXED else "f64", data="synthetic",
                seed=d["seed"],
@@ -141,11 +190,15 @@ def time_to_force(args):
                             u_z=round(t3 - t2, 2), forces=round(t4 - t3, 3)),
                davidson=dict(iters=ds["iters"], applies=ds["applies"],
                              applies_fp64=ds["applies_fp64"], rc=ds["rc"],
+                             learned=ds["learned"], fallback=ds["fallback"],
                              omega=list(map(float, w)), resid=ds["resid"][:cfg.n_states]),
                zvector=dict(iters=zs["iters"], applies_fp64=zs["applies_fp64"],
+                            learned=zs["learned"], fallback=zs["fallback"],
                             resid=zs["resid"][0], rc=zs["rc"]),
                max_abs_dwdR=float(np.abs(F).max()), sum_dwdR=list(map(float, F.sum(0))))
     ctx.free()
+    if net is not None:
+        net.free()
     print(json.dumps(out), flush=True)
 
 
@@ -165,6 +218,10 @@ def main():
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--gap-min", type=float, default=0.0)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="plain 2 GiB device copies, for scaling HBM counters")
+    ap.add_argument("--learned", default=None,
+                    help="trained preconditioner weights (.npz) for the --ttf run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -173,6 +230,9 @@ def main():
 
     if args.ttf:
         time_to_force(args)
+        return
+    if args.copy_calibration:
+        copy_calibration(args)
         return
 
     import torch
@@ -233,8 +293,10 @@ def main():
     if n_stream:
         dur = ms_stream / n_stream / 1e3
         ach = (tau_bytes + av_bytes) / dur / 1e9
+        tr = stream_traffic(mixed)
         roofline = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
+                        frac=round(ach / HBM_PEAK_GBS, 4),
+                        traffic=None if tr is None else round(tr),
                         kernel=f"k_tau_stream ({'FP32' if mixed else 'FP64'} cached blocks)",
                         bytes_per_launch=tau_bytes + av_bytes,
                         avg_launch_ms=round(1e3 * dur, 3))

@@ -179,6 +179,15 @@ typedef struct {
   const double *x0_dev;       /* optional initial guess, [k][n_val][n_pw]         */
   int32_t n_x0;               /* vectors in x0_dev                                 */
   const double *z0_dev;       /* optional Z-vector initial guess [n_val][n_pw]    */
+  int32_t use_learned;        /* 1: take the per-band preconditioner shifts and the
+                                 Z initial guess from the network attached with
+                                 bse_set_learned (ignored when none is attached)  */
+  const double *precond_shift_host; /* optional [n_val] per-band shift sigma_v of the
+                                 kinetic preconditioner (default 0.25 Ha); overrides
+                                 the network's shifts                              */
+  int32_t *band_iters_host;   /* optional out [n_val] (Z-vector): iteration at which
+                                 band v's own relative residual first reached tol;
+                                 when given, the solve runs until every band has  */
 } bse_solver_opts;
 
 typedef struct {
@@ -187,6 +196,10 @@ typedef struct {
   double resid[16];           /* final residual norms (first 16 states)           */
   double t_ms;                /* wall time of the call                            */
   int32_t applies_fp64;       /* of `applies`, those made with the FP64 operator  */
+  int32_t learned;            /* 1 when the network's outputs were used           */
+  int32_t fallback;           /* 1 when the solve dropped them for the diagonal
+                                 preconditioner (residual grew twice in a row, or
+                                 a non-finite output)                             */
 } bse_solver_stats;
 
 /* Lowest n_states eigenpairs of P_c M P_c (Eq. 1) by block Davidson with a
@@ -229,8 +242,112 @@ typedef struct {
  * (BSE_FP64 or BSE_MIXED).  ESTATE on an FP64 context asked for BSE_MIXED. */
 int bse_set_precision(bse_ctx *ctx, int32_t precision);
 
+/* Route the block applies of bse_apply and bse_davidson through HIP graphs
+ * (on = 1): the first call for each block size (and precision) runs eagerly,
+ * then captures the apply on fixed staging buffers; later calls copy the block
+ * in, replay the graph and copy the result out.  Results are those of the
+ * eager path up to the order of the LDS atomic sums in the tau stream.  Graphs are dropped when a buffer they use is released, when
+ * turned off, and by bse_free.  Ignored while profiling is on. */
+int bse_set_graphs(bse_ctx *ctx, int32_t on);
+
 int bse_set_profiling(bse_ctx *ctx, int32_t on);
 int bse_get_phase_times(bse_ctx *ctx, bse_phase_times *out, int32_t reset);
+
+/*
+ * Learned preconditioner (no counterpart in the paper; this project's form).
+ * A network maps 8 per-band features to (o_0, o_1):
+ *   sigma_v = 0.25 Ha * exp(clamp(o_0, -3, 3))   shift of the kinetic
+ *             preconditioner 1/max(|G|^2/2 - eps_v + sigma_v, 0.1) of the
+ *             Z-vector PCG and (with the scissor and the Ritz value) of Davidson;
+ *   gamma_v = clamp(o_1, -1, 3)                  Z initial guess
+ *             Z_v^0 = gamma_v P_c Prec_v(-u_v) with the default shift 0.25 Ha.
+ * Features of band v (BSE_LEARN_NFEAT = 8):
+ *   0 eps_v - eps_{N_v}          1 eps_{N_v+1} - eps_v   (Ha; eps ascending, 1-based)
+ *   2 <phi_v|T|phi_v>            3 <phi_v|V|phi_v> = eps_v - feature 2
+ *   4 log(Omega int phi_v^4)     5 log ||u_v||           6 <Prec u_v, u_v>/||u_v||^2
+ *   7 1 when features 5 and 6 are present (Z-vector), 0 for Davidson (5, 6 = 0).
+ * Every solve that uses it is still judged by the plain operator's residual.
+ */
+#define BSE_LEARN_NFEAT 8
+#define BSE_LEARN_NOUT 2
+
+typedef struct bse_mlp bse_mlp;
+
+/* Three dense layers n_in -> 128 -> 128 -> n_out with SiLU between them, BF16
+ * operands on the matrix cores with FP32 accumulation, FP32 master weights,
+ * Adam (0.9, 0.999, 1e-8).  Inputs are standardised and outputs de-standardised
+ * inside with the statistics of bse_mlp_set_norm (default 0 and 1).  Weights
+ * W ~ U(+-1/sqrt(fan_in)) from a splitmix64 stream of `seed`, biases 0.
+ * n_in 1..64, n_out 1..16.  Calls are ordered on `stream` and synchronous. */
+int bse_mlp_create(int32_t n_in, int32_t n_out, uint64_t seed, void *stream, bse_mlp **out);
+/* Flat FP32 parameter vector: W1 [128][n_in], b1 [128], W2 [128][128], b2 [128],
+ * W3 [n_out][128], b3 [n_out] (row-major).  set resets the Adam state. */
+int bse_mlp_n_params(const bse_mlp *mlp, int64_t *n);
+int bse_mlp_set_params(bse_mlp *mlp, const float *params_host);
+int bse_mlp_get_params(bse_mlp *mlp, float *params_host);
+int bse_mlp_set_norm(bse_mlp *mlp, const float *mu_x, const float *s_x, const float *mu_y,
+                     const float *s_y);
+/* y_dev [n][n_out] from x_dev [n][n_in] (FP32, device). */
+int bse_mlp_forward(bse_mlp *mlp, int32_t n, const float *x_dev, float *y_dev);
+/* One Adam step on L = sum w (yh - (t - mu_y)/s_y)^2 / max(sum w, 1), yh the
+ * normalised output.  t_dev [n][n_out]; w_dev [n][n_out] or NULL (all 1);
+ * loss_host (before the step) and grad_dev (flat dL/dparams, FP32) optional. */
+int bse_mlp_train_step(bse_mlp *mlp, int32_t n, const float *x_dev, const float *t_dev,
+                       const float *w_dev, float lr, float *loss_host, float *grad_dev);
+int bse_mlp_free(bse_mlp *mlp);
+
+/* Attach a network (n_in = BSE_LEARN_NFEAT, n_out = BSE_LEARN_NOUT) to a
+ * context; NULL detaches.  The context does not own it: keep it alive while
+ * attached. */
+int bse_set_learned(bse_ctx *ctx, bse_mlp *mlp);
+
+/* Features [n_val][BSE_LEARN_NFEAT] of the Z-vector solve for exciton Xs_dev
+ * (feature 7 = 1), and, when Zref_dev (a converged Z) is given, the
+ * least-squares initial-guess coefficient per band,
+ *   gamma_v* = <p_v, Z_v> / <p_v, p_v>,  p_v = P_c Prec_v(-u_v), shift 0.25 Ha.
+ * Needs the first conduction eigenvalue (n_orb > n_val): ESTATE otherwise. */
+int bse_learned_features(bse_ctx *ctx, const double *Xs_dev, const double *Zref_dev,
+                         float *feat_host, double *gamma_host);
+
+/*
+ * Uneven batches of independent systems (each solved as by bse_init_system,
+ * bse_davidson for the lowest exciton, bse_zvector_solve and bse_forces).
+ * Up to n_streams systems run at once, each on its own HIP stream (default
+ * priority) and host thread, largest first, a system being admitted while its
+ * device-memory estimate fits mem_budget (a system that fits nothing runs
+ * alone).  Each system's tau cache is capped at its own size.  With autotune,
+ * the Davidson block apply of every new shape (grid, N_v, precision) is timed
+ * under each kernel variant (compile-time or runtime FFT kernels; 4 or 2 lanes
+ * per grid point in the tau stream) and the fastest is cached for the process.
+ * desc.stream and desc.precision are ignored (the batch's are used).
+ */
+typedef struct {
+  double tol;                 /* Davidson and Z-vector residual target (0: 1e-6)   */
+  int32_t precision;          /* BSE_FP64 or BSE_MIXED                             */
+  int32_t n_streams;          /* systems in flight, 1..8 (0: 4)                    */
+  int64_t mem_budget;         /* device bytes the batch may hold (0: 85% of free)  */
+  int32_t autotune;           /* 1: tune kernel variants per shape                 */
+  int32_t use_graph;          /* 1: Davidson applies replay captured HIP graphs    */
+} bse_batch_opts;
+
+typedef struct {
+  int32_t status;             /* BSE_* of this system                              */
+  double omega;               /* lowest excitation energy (Ha)                     */
+  double *dwdR_host;          /* caller's [n_sites][3] output, or NULL             */
+  int32_t davidson_iters, z_iters;
+  double t_init_ms, t_davidson_ms, t_z_ms, t_force_ms;
+  int32_t variant;            /* autotuned variant (bit 0: runtime FFT kernels,
+                                 bit 1: 2 lanes per point), -1 when not tuned     */
+  int32_t stream_slot;        /* stream (worker) that ran it                       */
+  char message[160];          /* error text when status != BSE_OK                  */
+} bse_batch_result;
+
+/* Returns BSE_OK when every system succeeded, else the first failing status
+ * (every result holds its own status and message). */
+int bse_batch_run(const bse_system_desc *descs, int32_t n, const bse_batch_opts *opts,
+                  bse_batch_result *results);
+/* Forget the autotuner's cached choices. */
+int bse_tune_cache_clear(void);
 
 int bse_free(bse_ctx *ctx);
 

@@ -25,7 +25,12 @@ TAU_AUTO, TAU_CACHE, TAU_REBUILD = 0, 1, 2
 SYMBOLS = ("bse_abi_version", "bse_last_error", "bse_basis_size", "bse_basis_gvectors",
            "bse_init_system", "bse_get_info", "bse_get_orbitals", "bse_apply",
            "bse_davidson", "bse_u_vector", "bse_zvector_solve", "bse_forces",
-           "bse_set_precision", "bse_set_profiling", "bse_get_phase_times", "bse_free")
+           "bse_set_precision", "bse_set_profiling", "bse_get_phase_times",
+           "bse_mlp_create", "bse_mlp_n_params", "bse_mlp_set_params", "bse_mlp_get_params",
+           "bse_mlp_set_norm", "bse_mlp_forward", "bse_mlp_train_step", "bse_mlp_free",
+           "bse_set_learned", "bse_learned_features", "bse_set_graphs", "bse_batch_run",
+           "bse_tune_cache_clear", "bse_free")
+LEARN_NFEAT, LEARN_NOUT = 8, 2
 
 
 class BseError(RuntimeError):
@@ -57,15 +62,31 @@ class Info(C.Structure):
                 ("tau_bytes_f32", C.c_int64)]
 
 
+class BatchOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("precision", C.c_int32), ("n_streams", C.c_int32),
+                ("mem_budget", C.c_int64), ("autotune", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class BatchResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("omega", C.c_double),
+                ("dwdR_host", C.POINTER(C.c_double)), ("davidson_iters", C.c_int32),
+                ("z_iters", C.c_int32), ("t_init_ms", C.c_double), ("t_davidson_ms", C.c_double),
+                ("t_z_ms", C.c_double), ("t_force_ms", C.c_double), ("variant", C.c_int32),
+                ("stream_slot", C.c_int32), ("message", C.c_char * 160)]
+
+
 class SolverOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("block", C.c_int32),
                 ("max_subspace", C.c_int32), ("x0_dev", C.c_void_p), ("n_x0", C.c_int32),
-                ("z0_dev", C.c_void_p)]
+                ("z0_dev", C.c_void_p), ("use_learned", C.c_int32),
+                ("precond_shift_host", C.POINTER(C.c_double)),
+                ("band_iters_host", C.POINTER(C.c_int32))]
 
 
 class SolverStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("applies", C.c_int32), ("resid", C.c_double * 16),
-                ("t_ms", C.c_double), ("applies_fp64", C.c_int32)]
+                ("t_ms", C.c_double), ("applies_fp64", C.c_int32), ("learned", C.c_int32),
+                ("fallback", C.c_int32)]
 
 
 class PhaseTimes(C.Structure):
@@ -102,6 +123,22 @@ def lib():
                                     C.POINTER(SolverStats)]
     L.bse_forces.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp]
     L.bse_set_precision.argtypes = [C.c_void_p, C.c_int32]
+    fp = C.POINTER(C.c_float)
+    L.bse_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
+                                 C.POINTER(C.c_void_p)]
+    L.bse_mlp_n_params.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+    L.bse_mlp_set_params.argtypes = [C.c_void_p, fp]
+    L.bse_mlp_get_params.argtypes = [C.c_void_p, fp]
+    L.bse_mlp_set_norm.argtypes = [C.c_void_p, fp, fp, fp, fp]
+    L.bse_mlp_forward.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+    L.bse_mlp_train_step.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_float, fp, C.c_void_p]
+    L.bse_mlp_free.argtypes = [C.c_void_p]
+    L.bse_set_learned.argtypes = [C.c_void_p, C.c_void_p]
+    L.bse_set_graphs.argtypes = [C.c_void_p, C.c_int32]
+    L.bse_batch_run.argtypes = [C.POINTER(SystemDesc), C.c_int32, C.POINTER(BatchOpts),
+                                C.POINTER(BatchResult)]
+    L.bse_learned_features.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, fp, dp]
     L.bse_set_profiling.argtypes = [C.c_void_p, C.c_int32]
     L.bse_get_phase_times.argtypes = [C.c_void_p, C.POINTER(PhaseTimes), C.c_int32]
     L.bse_free.argtypes = [C.c_void_p]
@@ -173,7 +210,7 @@ class Context:
 def init_system(cell, grid, ecut, site_xyz, site_depth, site_width, n_val, pdep, lam, *,
                 scissor=0.0, spin_factor=2.0, tau_policy=TAU_AUTO, tau_budget_bytes=0,
                 gap_min=0.0, kernel_mask=K_ALL, orbitals=None, eps=None, n_extra=8,
-                gs_tol=1e-10, precision=FP64, stream=None):
+                gs_tol=1e-10, precision=FP64, stream=None, desc_only=False):
     """bse_init_system.  orbitals [n_orb][n_pw] / eps [n_orb] (host) or None to
     let the library solve the ground state."""
     import torch
@@ -207,6 +244,8 @@ def init_system(cell, grid, ecut, site_xyz, site_depth, site_width, n_val, pdep,
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     d.stream = C.c_void_p(stream)
+    if desc_only:
+        return d, keep
     h = C.c_void_p()
     _check(lib().bse_init_system(C.byref(d), C.byref(h)))
     ctx = Context(h.value)
@@ -218,6 +257,44 @@ def init_from_synth(sysd, **kw):
     return init_system(sysd["cell"], sysd["grid"], sysd["ecut"], sysd["site_xyz"],
                        sysd["site_depth"], sysd["site_width"], sysd["n_val"], sysd["pdep"],
                        sysd["lam"], **kw)
+
+
+def batch_run(systems, *, tol=1e-6, precision=FP64, n_streams=4, mem_budget=0, autotune=True,
+              use_graph=True, check=True):
+    """bse_batch_run over synth.make_system dicts (library ground states).
+    Returns a list of per-system dicts (omega, dwdR, iterations, times)."""
+    n = len(systems)
+    descs = (SystemDesc * n)()
+    keep = []
+    res = (BatchResult * n)()
+    outs = []
+    for i, sd in enumerate(systems):
+        d, k = init_system(sd["cell"], sd["grid"], sd["ecut"], sd["site_xyz"], sd["site_depth"],
+                           sd["site_width"], sd["n_val"], sd["pdep"], sd["lam"], n_extra=8,
+                           desc_only=True, stream=0)
+        descs[i] = d
+        keep.append(k)
+        f = np.zeros((max(len(sd["site_depth"]), 1), 3))
+        outs.append(f)
+        res[i].dwdR_host = _dptr(f)
+    o = BatchOpts(float(tol), int(precision), int(n_streams), int(mem_budget),
+                  1 if autotune else 0, 1 if use_graph else 0)
+    rc = lib().bse_batch_run(descs, n, C.byref(o), res)
+    if check:
+        _check(rc)
+    out = []
+    for i in range(n):
+        r = res[i]
+        out.append(dict(status=r.status, omega=r.omega, dwdR=outs[i][:len(systems[i]["site_depth"])],
+                        davidson_iters=r.davidson_iters, z_iters=r.z_iters,
+                        t_init_ms=r.t_init_ms, t_davidson_ms=r.t_davidson_ms, t_z_ms=r.t_z_ms,
+                        t_force_ms=r.t_force_ms, variant=r.variant, stream=r.stream_slot,
+                        message=r.message.decode()))
+    return out
+
+
+def tune_cache_clear():
+    _check(lib().bse_tune_cache_clear())
 
 
 def get_info(ctx):
@@ -250,9 +327,15 @@ def apply(ctx, X, Y=None):
     return Y
 
 
-def _opts(tol=0.0, max_iter=0, block=0, max_subspace=0, x0=None, z0=None):
+def _opts(tol=0.0, max_iter=0, block=0, max_subspace=0, x0=None, z0=None, use_learned=False,
+          shifts=None, band_iters=None):
     o = SolverOpts()
     o.tol, o.max_iter, o.block, o.max_subspace = float(tol), int(max_iter), int(block), int(max_subspace)
+    o.use_learned = 1 if use_learned else 0
+    if shifts is not None:
+        o.precond_shift_host = _dptr(shifts)
+    if band_iters is not None:
+        o.band_iters_host = band_iters.ctypes.data_as(C.POINTER(C.c_int32))
     if x0 is not None:
         o.x0_dev = _dev(x0, "x0").value
         o.n_x0 = x0.shape[0]
@@ -263,16 +346,17 @@ def _opts(tol=0.0, max_iter=0, block=0, max_subspace=0, x0=None, z0=None):
 
 def _stats(s):
     return dict(iters=s.iters, applies=s.applies, resid=list(s.resid), t_ms=s.t_ms,
-                applies_fp64=s.applies_fp64)
+                applies_fp64=s.applies_fp64, learned=s.learned, fallback=s.fallback)
 
 
 def davidson(ctx, n_states=1, *, tol=1e-8, max_iter=0, block=0, max_subspace=0, x0=None,
-             check=True):
+             use_learned=False, shifts=None, check=True):
     import torch
     info = get_info(ctx)
     X = torch.empty((n_states, info["n_val"], info["n_pw"]), dtype=torch.float64, device="cuda")
     w = np.zeros(n_states)
-    o = _opts(tol, max_iter, block, max_subspace, x0=x0)
+    sh = None if shifts is None else _f64(shifts)
+    o = _opts(tol, max_iter, block, max_subspace, x0=x0, use_learned=use_learned, shifts=sh)
     s = SolverStats()
     rc = lib().bse_davidson(ctx.h, n_states, C.byref(o), _dptr(w), _dev(X, "X"), C.byref(s))
     if check:
@@ -287,21 +371,114 @@ def u_vector(ctx, Xs):
     return U
 
 
-def zvector_solve(ctx, Xs, *, tol=1e-8, max_iter=0, z0=None, check=True):
+def zvector_solve(ctx, Xs, *, tol=1e-8, max_iter=0, z0=None, use_learned=False, shifts=None,
+                  band_iters=False, check=True):
+    """bse_zvector_solve.  shifts: per-band preconditioner shifts (host);
+    band_iters=True adds the per-band iteration counts to the stats."""
     import torch
     Z = torch.empty_like(Xs)
-    o = _opts(tol, max_iter, z0=z0)
+    sh = None if shifts is None else _f64(shifts)
+    bi = np.zeros(Xs.shape[0], dtype=np.int32) if band_iters else None
+    o = _opts(tol, max_iter, z0=z0, use_learned=use_learned, shifts=sh, band_iters=bi)
     s = SolverStats()
     rc = lib().bse_zvector_solve(ctx.h, _dev(Xs, "Xs"), C.byref(o), _dev(Z, "Z"), C.byref(s))
     if check:
         _check(rc)
-    return Z, dict(_stats(s), rc=rc)
+    st = dict(_stats(s), rc=rc)
+    if bi is not None:
+        st["band_iters"] = bi
+    return Z, st
 
 
 def forces(ctx, Xs, Z, n_sites):
     out = np.zeros((max(n_sites, 1), 3))
     _check(lib().bse_forces(ctx.h, _dev(Xs, "Xs"), _dev(Z, "Z"), _dptr(out)))
     return out[:n_sites]
+
+
+class Mlp:
+    """The learned preconditioner's network (bse_mlp_*): owns the handle."""
+
+    def __init__(self, n_in=LEARN_NFEAT, n_out=LEARN_NOUT, seed=0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        _check(lib().bse_mlp_create(int(n_in), int(n_out), int(seed), C.c_void_p(stream),
+                                    C.byref(h)))
+        self.h, self.n_in, self.n_out = h, int(n_in), int(n_out)
+        n = C.c_int64()
+        _check(lib().bse_mlp_n_params(self.h, C.byref(n)))
+        self.n_params = int(n.value)
+
+    def free(self):
+        if self.h is not None and self.h.value and _lib is not None:
+            _lib.bse_mlp_free(self.h)
+            self.h = C.c_void_p(None)
+
+    def __del__(self):
+        self.free()
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        assert a.size == self.n_params
+        _check(lib().bse_mlp_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def get_params(self):
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().bse_mlp_get_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float))))
+        return a
+
+    def set_norm(self, mu_x, s_x, mu_y, s_y):
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (mu_x, s_x, mu_y, s_y)]
+        _check(lib().bse_mlp_set_norm(self.h, *[a.ctypes.data_as(C.POINTER(C.c_float))
+                                                for a in arrs]))
+
+    def forward(self, x):
+        import torch
+        y = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device="cuda")
+        _check(lib().bse_mlp_forward(self.h, x.shape[0], _fdev(x, "x"), _fdev(y, "y")))
+        return y
+
+    def train_step(self, x, t, w=None, lr=1e-3, want_grad=False):
+        import torch
+        loss = C.c_float()
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda") if want_grad else None
+        _check(lib().bse_mlp_train_step(self.h, x.shape[0], _fdev(x, "x"), _fdev(t, "t"),
+                                        None if w is None else _fdev(w, "w"), float(lr),
+                                        C.byref(loss), None if g is None else _fdev(g, "g")))
+        return (float(loss.value), g) if want_grad else float(loss.value)
+
+
+def _fdev(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def set_graphs(ctx, on=True):
+    """bse_set_graphs: replay captured HIP graphs for the block applies."""
+    _check(lib().bse_set_graphs(ctx.h, 1 if on else 0))
+
+
+def set_learned(ctx, mlp):
+    """bse_set_learned: attach (or, with None, detach) a network."""
+    _check(lib().bse_set_learned(ctx.h, None if mlp is None else mlp.h))
+    ctx._learned = mlp  # keep it alive while attached
+
+
+def learned_features(ctx, Xs, Zref=None):
+    """bse_learned_features: features [n_val][8] and, with Zref, gamma* [n_val]."""
+    nv = Xs.shape[0]
+    f = np.zeros((nv, LEARN_NFEAT), dtype=np.float32)
+    g = np.zeros(nv) if Zref is not None else None
+    _check(lib().bse_learned_features(ctx.h, _dev(Xs, "Xs"),
+                                      None if Zref is None else _dev(Zref, "Zref"),
+                                      f.ctypes.data_as(C.POINTER(C.c_float)),
+                                      None if g is None else _dptr(g)))
+    return (f, g) if Zref is not None else f
 
 
 def set_precision(ctx, precision):

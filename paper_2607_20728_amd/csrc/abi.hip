@@ -31,6 +31,8 @@ bool finite_all(const double* p, long n) {
 void ctx_destroy(bse_ctx* c) {
   if (!c) return;
   if (c->st) (void)hipStreamSynchronize(c->st);
+  graphs_destroy(c);
+  if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
   for (auto& b : c->allocs) (void)hipFree(b.p);
   c->allocs.clear();
   fft_plan_free(&c->fft);
@@ -102,7 +104,7 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   c->R = (tau_stream_lds(c->nv, 2) <= c->max_lds) ? 2 : 1;
   // tuning knobs of the stream kernel (points per workgroup, lanes per point)
   if (const char* e = getenv("BSEX_TAU_R")) c->R = (atoi(e) == 1) ? 1 : c->R;
-  if (const char* e = getenv("BSEX_TAU_BL")) tau_stream_set_variant(atoi(e));
+  if (const char* e = getenv("BSEX_TAU_BL")) c->tau_bl = (atoi(e) == 2) ? 2 : 4;
   if (tau_stream_lds(c->nv, c->R) > c->max_lds)
     return fail(BSE_EINVAL, "n_val %d too large for the device LDS (%zu bytes)", c->nv, c->max_lds);
   const bool mixed = c->precision == BSE_MIXED;
@@ -130,7 +132,8 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   if (mixed) {
     // the whole FP32 cache first; the FP64 cache gets what is left
     const double fbytes = 4.0 * 64 * nr * c->nblk;
-    double cap = (double)freeb - reserve - std::max(1.0e9, 0.06 * (double)totalb);
+    double cap = (double)freeb - reserve -
+                 (has_budget ? 0.25 * (double)d->tau_budget_bytes : std::max(1.0e9, 0.06 * (double)totalb));
     if (has_budget) cap = std::min(cap, budget_left);
     if (fbytes > cap)
       return fail(BSE_ENOMEM, "FP32 tau cache needs %.1f GB, %.1f GB free", fbytes / 1e9,
@@ -152,7 +155,9 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
     c->tile_blk = small_tile;
   } else {
     BSE_TRY(ensure_ygrid(c));  // accumulation across launches
-    const double tile_target = std::max(1.0e9, 0.06 * (double)totalb);
+    double tile_target = std::max(1.0e9, 0.06 * (double)totalb);
+    if (has_budget)  // a budgeted context (batches) keeps its tiles near its cache size
+      tile_target = std::min(tile_target, std::max(blk_tile_bytes, 0.25 * (double)d->tau_budget_bytes));
     c->tile_blk = std::max(1L, std::min(c->nblk, (long)(tile_target / blk_tile_bytes)));
   }
   const long te = c->tile_blk * 64;
@@ -432,7 +437,10 @@ int bse_apply(bse_ctx* c, int32_t n_b, const double* X, double* Y) {
     const long L = (long)c->nv * c->basis.npw;
     for (long i = 0; i < n_b; i += c->nbc) {
       const int k = (int)std::min<long>(c->nbc, n_b - i);
-      BSE_TRY(apply_any(c, k, X + i * L, Y + i * L));
+      if (c->use_graph && !c->prof)
+        BSE_TRY(graph_apply(c, k, X + i * L, Y + i * L));
+      else
+        BSE_TRY(apply_any(c, k, X + i * L, Y + i * L));
     }
     BSE_HIP(hipStreamSynchronize(c->st));
     return BSE_OK;
@@ -447,6 +455,29 @@ int bse_set_precision(bse_ctx* c, int32_t precision) {
     return fail(BSE_ESTATE, "context was built without BSE_MIXED");
   c->active = precision;
   return BSE_OK;
+}
+
+int bse_set_graphs(bse_ctx* c, int32_t on) {
+  if (!c) return fail(BSE_EINVAL, "ctx is NULL");
+  if (!on) graphs_destroy(c);
+  c->use_graph = on != 0;
+  return BSE_OK;
+}
+
+int bse_set_learned(bse_ctx* c, bse_mlp* mlp) {
+  if (!c) return fail(BSE_EINVAL, "ctx is NULL");
+  if (mlp && (mlp_n_in(mlp) != BSE_LEARN_NFEAT || mlp_n_out(mlp) != BSE_LEARN_NOUT))
+    return fail(BSE_EINVAL, "network must map %d features to %d outputs", BSE_LEARN_NFEAT,
+                BSE_LEARN_NOUT);
+  c->learned = mlp;
+  return BSE_OK;
+}
+
+int bse_learned_features(bse_ctx* c, const double* Xs, const double* Zref, float* feat,
+                         double* gamma) {
+  if (!c || !Xs || !feat) return fail(BSE_EINVAL, "NULL argument");
+  if (Zref && !gamma) return fail(BSE_EINVAL, "gamma_host needed with Zref_dev");
+  return guarded(c, [&] { return learned_targets(c, Xs, Zref, feat, gamma); });
 }
 
 int bse_davidson(bse_ctx* c, int32_t n_states, const bse_solver_opts* opts, double* omega_host,

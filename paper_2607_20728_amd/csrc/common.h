@@ -54,10 +54,13 @@ struct FftPlan {
   int N[3] = {0, 0, 0};
   long nr = 0;
   size_t max_lds = 65536;
-  bool ct_plane[2] = {false, false}, ct_axis[2] = {false, false};  // [FP64, FP32]
+  bool ct_plane[2] = {false, false}, ct_axis[2] = {false, false};  // [FP64, FP32], in use
+  bool ct_plane_ok[2] = {false, false}, ct_axis_ok[2] = {false, false};  // available
   FftAxis ax[3];
 };
 int fft_plan_init(FftPlan* p, const int grid[3]);
+// runtime = true: use the runtime-length kernels even where compile-time ones exist
+void fft_plan_set_runtime(FftPlan* p, bool runtime);
 void fft_plan_free(FftPlan* p);
 // In-place batched 3-D complex transform of [batch][N1][N2][N3] (N3 fastest).
 // dir = -1: sum_r f(r) exp(-i G.r); dir = +1: sum_G f(G) exp(+i G.r).  No scaling.

@@ -70,10 +70,13 @@ struct bse_ctx {
   double2 *agrid = nullptr, *ygrid = nullptr, *drho = nullptr;
   double* gw = nullptr;
   long gw_len = 0;
+  double* rdw = nullptr;  // row_dots partial sums
+  long rdw_len = 0;
   // mixed precision (FP32 grids, FFTs and tau; FP64 projector, diagonal, solvers)
   int precision = BSE_FP64;   // capability the context was built with
   int active = BSE_FP64;      // precision of the operator applies
   int Rf = 2;                 // grid points per stream workgroup, FP32 layout
+  int tau_bl = 4;             // lanes per grid point in the stream kernel (2 or 4)
   float2* phir_f = nullptr;   // [nvh][nr]
   float* Vr_f = nullptr;      // [nr]
   float* vc_f = nullptr;      // [nr]
@@ -81,6 +84,16 @@ struct bse_ctx {
   float2 *agrid_f = nullptr, *drho_f = nullptr, *compact_f = nullptr;
   int nbc_f = 0;
   long compact_f_grids = 0;
+  // learned preconditioner (not owned)
+  bse_mlp* learned = nullptr;
+  // HIP graphs of the block apply, one per (block size, precision), replayed
+  // on the staging buffers gX -> gY; graph_bufs are the context buffers the
+  // graphs reference: releasing any of them destroys every graph first
+  bool use_graph = false;
+  hipStream_t cap_st = nullptr;  // private stream the graphs are captured on
+  double *gX = nullptr, *gY = nullptr;
+  std::vector<std::pair<int, hipGraphExec_t>> graphs;
+  std::vector<void*> graph_bufs;
   // profiling
   bool prof = false;
   double ph_ms[bsex::PH_COUNT] = {0};
@@ -131,7 +144,15 @@ int ensure_ygrid(bse_ctx* c);
 // cache, Rf points per row, at block gb0); either may be null
 int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double* dst,
                     long dst_nblk, long dst_blk0, int mask, float* dstf = nullptr);
+// learned preconditioner network (mlp.hip): y [n][n_out] from x [n][n_in]
+int mlp_eval(bse_mlp* q, long n, const float* x, float* y, hipStream_t st);
+int mlp_n_in(const bse_mlp* q);
+int mlp_n_out(const bse_mlp* q);
+int learned_targets(bse_ctx* c, const double* Xs, const double* Zref, float* feat, double* gamma);
 int apply_chunk_mixed(bse_ctx* c, int nb, const double* X, double* Y);
+// block apply through a captured HIP graph (captured on first use per block size)
+int graph_apply(bse_ctx* c, int nb, const double* X, double* Y);
+void graphs_destroy(bse_ctx* c);
 int apply_any(bse_ctx* c, int nb, const double* X, double* Y);
 int apply_H_f(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double shift,
               const double* eps, int project);

@@ -84,6 +84,13 @@ int fft_plan_init(FftPlan* p, const int grid[3]) {
   return BSE_OK;
 }
 
+void fft_plan_set_runtime(FftPlan* p, bool runtime) {
+  for (int q = 0; q < 2; ++q) {
+    p->ct_plane[q] = p->ct_plane_ok[q] && !runtime;
+    p->ct_axis[q] = p->ct_axis_ok[q] && !runtime;
+  }
+}
+
 void fft_plan_free(FftPlan* p) {
   for (int a = 0; a < 3; ++a) {
     if (p->ax[a].tw) (void)hipFree(p->ax[a].tw);

@@ -695,8 +695,8 @@ int init_kernels(FftPlan* p) {
   if (const char* e = getenv("BSEX_FFT_RUNTIME")) {
     if (atoi(e)) ctp = cta = false;
   }
-  p->ct_plane[BSEX_FFT_PREC] = ctp;
-  p->ct_axis[BSEX_FFT_PREC] = cta;
+  p->ct_plane[BSEX_FFT_PREC] = p->ct_plane_ok[BSEX_FFT_PREC] = ctp;
+  p->ct_axis[BSEX_FFT_PREC] = p->ct_axis_ok[BSEX_FFT_PREC] = cta;
   return set_ct_lds_limits(ctp ? p->N[1] : -1, ctp ? p->N[2] : -1, cta ? p->N[0] : -1);
 }
 

@@ -77,19 +77,19 @@ struct FuseArgsF {
   int with_v;
 };
 // y[b][v] (+)= sum_v' tau_{vv'} a[b][v'] over the blocks of one buffer; with
-// fuse != NULL, y receives z instead and may alias a.
+// fuse != NULL, y receives z instead and may alias a.  R grid points per
+// workgroup (1 or 2, the layout tau was stored in); bl lanes share one grid
+// point's 8 trial vectors (2 or 4).
 int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                const double2* a, double2* y, int nb, int nv, long nr, int accumulate,
-               size_t max_lds, hipStream_t st, const FuseArgs* fuse = nullptr);
-// FP32 variant (tau, a, y and accumulation in FP32)
+               size_t max_lds, hipStream_t st, const FuseArgs* fuse = nullptr, int bl = 4);
+// FP32 variant (tau, a, y in FP32; products in FP32, sums in FP64 LDS)
 int tau_stream(const float* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                const float2* a, float2* y, int nb, int nv, long nr, int accumulate,
-               size_t max_lds, hipStream_t st, const FuseArgsF* fuse = nullptr);
+               size_t max_lds, hipStream_t st, const FuseArgsF* fuse = nullptr, int bl = 4);
 size_t tau_stream_lds(int nv, int R, size_t elem = sizeof(double));
 // raise the dynamic-LDS limit of the stream kernels (bytes <= device maximum)
 int tau_stream_set_lds_limit(size_t bytes);
-// lanes sharing one grid point's 8 trial vectors in the stream kernel (2 or 4)
-void tau_stream_set_variant(int bl);
 
 // potential V(G) of Gaussian sites on the full grid (Nyquist zero), complex
 int site_potential(const double* xyz, const double* depth, const double* width, int nsites,
@@ -106,19 +106,34 @@ int force_reduce(const double2* rhoG, const double* xyz, const double* depth,
 long force_reduce_work(int nsites, long nr);
 
 // ---- vector helpers for the solvers (deterministic reductions) --------------------------
-// out[i] = sum_j A[i*ld + j] * B[i*ld + j], i < rows
-int row_dots(const double* A, const double* B, long rows, long len, double* out, hipStream_t st);
+// out[i] = sum_j A[i*len + j] * B[i*len + j], i < rows (fixed-order split
+// reduction through `work`, which must hold row_dots_work(rows, len) doubles)
+int row_dots(const double* A, const double* B, long rows, long len, double* out, double* work,
+             long work_len, hipStream_t st);
+long row_dots_work(long rows, long len);
 // Y[i][j] = a[i] * X[i][j] + b[i] * Y[i][j]  (a or b NULL means 1)
 int row_axpby(const double* a, const double* X, const double* b, double* Y, long rows, long len,
               hipStream_t st);
 // Y[i][j] *= s[i]
 int row_scale(const double* s, double* Y, long rows, long len, hipStream_t st);
+// p[0..n) = 0 by a kernel (safe inside captured graphs, unlike a memset node)
+int zero_fill(double* p, long n, hipStream_t st);
 // Y = alpha X + beta Y over n elements
 int axpby(double alpha, const double* X, double beta, double* Y, long n, hipStream_t st);
-// Davidson preconditioner: T[k][v][j] = R[k][v][j] / clamp(Tk_j - eps_v + shift - theta_k)
+// Davidson preconditioner: T[k][v][j] = R[k][v][j] / clamp(Tk_j - eps_v + shift_v - theta_k),
+// shift_v = shift + (vshift ? vshift[v] : 0)
 int precond_davidson(const double* R, double* T, const double* Tk, const double* eps,
-                     const double* theta, double shift, int nk, int nv, int npw, hipStream_t st);
-// CG preconditioner: T[v][j] = R[v][j] / max(Tk_j - eps_v + shift, 0.1)
+                     const double* theta, double shift, int nk, int nv, int npw, hipStream_t st,
+                     const double* vshift = nullptr);
+// CG preconditioner: T[v][j] = R[v][j] / max(Tk_j - eps_v + shift_v, 0.1),
+// shift_v = vshift ? vshift[v] : shift
 int precond_cg(const double* R, double* T, const double* Tk, const double* eps, double shift,
-               int nv, int npw, hipStream_t st);
+               int nv, int npw, hipStream_t st, const double* vshift = nullptr);
+// Per-band sums for the learned preconditioner's features: out[v][0] =
+// sum_j Tk_j Phi_vj^2, [1] = sum_j U_vj^2, [2] = sum_j U_vj^2 / max(Tk_j - eps_v
+// + shift, 0.1), [3] = sum_r phi_v(r)^4 (phir packs two bands per complex grid).
+// U may be NULL (then [1] = [2] = 0).
+int band_features(const double* Phi, const double* Tk, const double* eps, const double* U,
+                  const double2* phir, double shift, int nv, int npw, long nr, double* out,
+                  hipStream_t st);
 }  // namespace bsex

@@ -536,22 +536,40 @@ __global__ void k_force_final(const double* __restrict__ part, int nsites, int n
 // ---------------------------------------------------------------------------
 // solver vector helpers
 // ---------------------------------------------------------------------------
+// partial dot products of rows: grid (nsplit, rows); block s of row r sums the
+// s-th of nsplit equal chunks
 __global__ __launch_bounds__(256) void k_row_dots(const double* __restrict__ A,
                                                   const double* __restrict__ B, long len,
-                                                  double* __restrict__ out) {
+                                                  int nsplit, double* __restrict__ part) {
   __shared__ double red[256];
-  const long row = blockIdx.x;
+  const long row = blockIdx.y;
+  const long chunk = (len + nsplit - 1) / nsplit;
+  const long j0 = blockIdx.x * chunk;
+  const long j1 = j0 + chunk < len ? j0 + chunk : len;
   const double* a = A + row * len;
   const double* b = B + row * len;
   double s = 0.0;
-  for (long j = threadIdx.x; j < len; j += 256) s += a[j] * b[j];
+  for (long j = j0 + threadIdx.x; j < j1; j += 256) s += a[j] * b[j];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[row] = red[0];
+  if (threadIdx.x == 0) part[row * nsplit + blockIdx.x] = red[0];
+}
+
+__global__ void k_row_dots_final(const double* __restrict__ part, long rows, int nsplit,
+                                 double* __restrict__ out) {
+  const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  double s = 0.0;
+  for (int q = 0; q < nsplit; ++q) s += part[r * nsplit + q];
+  out[r] = s;
+}
+
+__global__ void k_zero(double* __restrict__ p, long n) {
+  for (long e = gtid(); e < n; e += gstride()) p[e] = 0.0;
 }
 
 __global__ void k_row_axpby(const double* __restrict__ a, const double* __restrict__ X,
@@ -578,13 +596,13 @@ __global__ void k_axpby(double alpha, const double* __restrict__ X, double beta,
 __global__ void k_precond_davidson(const double* __restrict__ R, double* __restrict__ T,
                                    const double* __restrict__ Tk, const double* __restrict__ eps,
                                    const double* __restrict__ theta, double shift, int nk, int nv,
-                                   int npw) {
+                                   int npw, const double* __restrict__ vshift) {
   const long n = (long)nk * nv * npw;
   for (long e = gtid(); e < n; e += gstride()) {
     const int j = (int)(e % npw);
     const int v = (int)((e / npw) % nv);
     const int k = (int)(e / ((long)npw * nv));
-    double den = Tk[j] - eps[v] + shift - theta[k];
+    double den = Tk[j] - eps[v] + shift + (vshift ? vshift[v] : 0.0) - theta[k];
     if (fabs(den) < 0.1) den = (den < 0.0) ? -0.1 : 0.1;
     T[e] = R[e] / den;
   }
@@ -592,14 +610,50 @@ __global__ void k_precond_davidson(const double* __restrict__ R, double* __restr
 
 __global__ void k_precond_cg(const double* __restrict__ R, double* __restrict__ T,
                              const double* __restrict__ Tk, const double* __restrict__ eps,
-                             double shift, int nv, int npw) {
+                             double shift, int nv, int npw, const double* __restrict__ vshift) {
   const long n = (long)nv * npw;
   for (long e = gtid(); e < n; e += gstride()) {
     const int j = (int)(e % npw);
     const int v = (int)(e / npw);
-    const double den = fmax(Tk[j] - eps[v] + shift, 0.1);
+    const double den = fmax(Tk[j] - eps[v] + (vshift ? vshift[v] : shift), 0.1);
     T[e] = R[e] / den;
   }
+}
+
+// one workgroup per band, fixed-order tree reductions
+__global__ __launch_bounds__(256) void k_band_features(
+    const double* __restrict__ Phi, const double* __restrict__ Tk, const double* __restrict__ eps,
+    const double* __restrict__ U, const double2* __restrict__ phir, double shift, int npw, long nr,
+    double* __restrict__ out) {
+  __shared__ double sh[4][256];
+  const int v = blockIdx.x;
+  const double* ph = Phi + (long)v * npw;
+  const double* u = U ? U + (long)v * npw : nullptr;
+  double a = 0, b = 0, c = 0, d = 0;
+  for (int j = threadIdx.x; j < npw; j += 256) {
+    a += Tk[j] * ph[j] * ph[j];
+    if (u) {
+      const double uu = u[j] * u[j];
+      b += uu;
+      c += uu / fmax(Tk[j] - eps[v] + shift, 0.1);
+    }
+  }
+  const double* pr = reinterpret_cast<const double*>(phir + (long)(v >> 1) * nr) + (v & 1);
+  for (long r = threadIdx.x; r < nr; r += 256) {
+    const double f = pr[2 * r];
+    d += f * f * f * f;
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  sh[2][threadIdx.x] = c;
+  sh[3][threadIdx.x] = d;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[(long)v * 4 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 }  // namespace
@@ -764,9 +818,6 @@ size_t tau_stream_lds(int nv, int R, size_t elem) {
   return (elem + sizeof(double)) * (size_t)nv8 * (NBT * R + SPAD);
 }
 
-static int g_tau_bl = 4;  // trial vectors split over this many lanes (2 or 4)
-
-void tau_stream_set_variant(int bl) { g_tau_bl = (bl == 2) ? 2 : 4; }
 
 template <int R, int BL, bool F, typename T>
 static void launch_stream(long nrb, size_t shm, hipStream_t st, const T* tau, long stride,
@@ -783,7 +834,7 @@ template <typename T, typename FA>
 static int tau_stream_impl(const T* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                            const typename vec2_of<T>::type* a, typename vec2_of<T>::type* y,
                            int nb, int nv, long nr, int accumulate, size_t max_lds,
-                           hipStream_t st, const FA* fuse) {
+                           hipStream_t st, const FA* fuse, int bl) {
   if (nb > NBT) return fail(BSE_EINVAL, "tau_stream: at most %d vectors per call", NBT);
   if (nr % R) return fail(BSE_EINVAL, "tau_stream: grid size not a multiple of %d", R);
   const size_t shm = tau_stream_lds(nv, R, sizeof(T));
@@ -806,16 +857,16 @@ static int tau_stream_impl(const T* tau, long buf_nblk, long nblk, const int2* b
       launch_stream<R_, BL_, false, T>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,  \
                                        nv8, accumulate, V, vd, ph, sf, wv);                      \
   } while (0)
-  if (R == 2 && g_tau_bl == 4)
+  if (R == 2 && bl == 4)
     GO(2, 4);
-  else if (R == 2)
+  else if (R == 2 && bl == 2)
     GO(2, 2);
-  else if (R == 1 && g_tau_bl == 4)
+  else if (R == 1 && bl == 4)
     GO(1, 4);
-  else if (R == 1)
+  else if (R == 1 && bl == 2)
     GO(1, 2);
   else
-    return fail(BSE_EINVAL, "tau_stream: R = %d unsupported", R);
+    return fail(BSE_EINVAL, "tau_stream: R = %d, BL = %d unsupported", R, bl);
 #undef GO
   CHECK_LAUNCH();
   return BSE_OK;
@@ -823,16 +874,16 @@ static int tau_stream_impl(const T* tau, long buf_nblk, long nblk, const int2* b
 
 int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                const double2* a, double2* y, int nb, int nv, long nr, int accumulate,
-               size_t max_lds, hipStream_t st, const FuseArgs* fuse) {
+               size_t max_lds, hipStream_t st, const FuseArgs* fuse, int bl) {
   return tau_stream_impl(tau, buf_nblk, nblk, blkIJ, R, a, y, nb, nv, nr, accumulate, max_lds, st,
-                         fuse);
+                         fuse, bl);
 }
 
 int tau_stream(const float* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                const float2* a, float2* y, int nb, int nv, long nr, int accumulate,
-               size_t max_lds, hipStream_t st, const FuseArgsF* fuse) {
+               size_t max_lds, hipStream_t st, const FuseArgsF* fuse, int bl) {
   return tau_stream_impl(tau, buf_nblk, nblk, blkIJ, R, a, y, nb, nv, nr, accumulate, max_lds, st,
-                         fuse);
+                         fuse, bl);
 }
 
 int tau_stream_set_lds_limit(size_t bytes) {
@@ -904,9 +955,25 @@ int force_reduce(const double2* rhoG, const double* xyz, const double* depth, co
   return BSE_OK;
 }
 
-int row_dots(const double* A, const double* B, long rows, long len, double* out, hipStream_t st) {
+static int row_dots_split(long rows, long len) {
+  // ~64k elements per block, at most 512 blocks per row and 64k blocks in all
+  long ns = std::max(1L, std::min(512L, len / 65536));
+  while (ns > 1 && rows * ns > 65536) ns /= 2;
+  return (int)ns;
+}
+
+long row_dots_work(long rows, long len) { return rows * row_dots_split(rows, len); }
+
+int row_dots(const double* A, const double* B, long rows, long len, double* out, double* work,
+             long work_len, hipStream_t st) {
   if (rows <= 0) return BSE_OK;
-  hipLaunchKernelGGL(k_row_dots, dim3((unsigned)rows), dim3(256), 0, st, A, B, len, out);
+  if (rows > 65535) return fail(BSE_EINVAL, "row_dots: too many rows");
+  const int ns = row_dots_split(rows, len);
+  if (work_len < rows * ns) return fail(BSE_EINVAL, "row_dots: work buffer too small");
+  hipLaunchKernelGGL(k_row_dots, dim3((unsigned)ns, (unsigned)rows), dim3(256), 0, st, A, B, len,
+                     ns, work);
+  hipLaunchKernelGGL(k_row_dots_final, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, work,
+                     rows, ns, out);
   CHECK_LAUNCH();
   return BSE_OK;
 }
@@ -928,6 +995,13 @@ int row_scale(const double* s, double* Y, long rows, long len, hipStream_t st) {
   return BSE_OK;
 }
 
+int zero_fill(double* p, long n, hipStream_t st) {
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_zero, dim3(nblocks(n)), dim3(TPB), 0, st, p, n);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
 int axpby(double alpha, const double* X, double beta, double* Y, long n, hipStream_t st) {
   if (n <= 0) return BSE_OK;
   hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(TPB), 0, st, alpha, X, beta, Y, n);
@@ -936,21 +1010,32 @@ int axpby(double alpha, const double* X, double beta, double* Y, long n, hipStre
 }
 
 int precond_davidson(const double* R, double* T, const double* Tk, const double* eps,
-                     const double* theta, double shift, int nk, int nv, int npw, hipStream_t st) {
+                     const double* theta, double shift, int nk, int nv, int npw, hipStream_t st,
+                     const double* vshift) {
   const long n = (long)nk * nv * npw;
   if (n <= 0) return BSE_OK;
   hipLaunchKernelGGL(k_precond_davidson, dim3(nblocks(n)), dim3(TPB), 0, st, R, T, Tk, eps, theta,
-                     shift, nk, nv, npw);
+                     shift, nk, nv, npw, vshift);
   CHECK_LAUNCH();
   return BSE_OK;
 }
 
 int precond_cg(const double* R, double* T, const double* Tk, const double* eps, double shift,
-               int nv, int npw, hipStream_t st) {
+               int nv, int npw, hipStream_t st, const double* vshift) {
   const long n = (long)nv * npw;
   if (n <= 0) return BSE_OK;
   hipLaunchKernelGGL(k_precond_cg, dim3(nblocks(n)), dim3(TPB), 0, st, R, T, Tk, eps, shift, nv,
-                     npw);
+                     npw, vshift);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int band_features(const double* Phi, const double* Tk, const double* eps, const double* U,
+                  const double2* phir, double shift, int nv, int npw, long nr, double* out,
+                  hipStream_t st) {
+  if (nv <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_band_features, dim3(nv), dim3(256), 0, st, Phi, Tk, eps, U, phir, shift, npw,
+                     nr, out);
   CHECK_LAUNCH();
   return BSE_OK;
 }

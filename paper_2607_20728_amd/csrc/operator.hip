@@ -1,5 +1,6 @@
 // The DMPT BSE operator on the device: projector, transforms, K1e, tau
 // build and stream, combine, diagonal term (Eqs. 1-3).
+#include <algorithm>
 #include <cmath>
 
 #include "context.h"
@@ -26,6 +27,9 @@ int ctx_alloc(bse_ctx* c, void** p, size_t bytes) {
 
 void ctx_release(bse_ctx* c, void* p) {
   if (!p) return;
+  if (!c->graphs.empty() &&
+      std::find(c->graph_bufs.begin(), c->graph_bufs.end(), p) != c->graph_bufs.end())
+    graphs_destroy(c);
   for (size_t i = 0; i < c->allocs.size(); ++i)
     if (c->allocs[i].p == p) {
       (void)hipFree(p);
@@ -183,8 +187,8 @@ int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double
   }
   if (mask & BSE_K_1D_BARE)
     BSE_TRY(mul_real_field(c->tile_grids, ng, nr, c->vc, 1.0 / (double)nr, c->st));
-  else
-    BSE_HIP(hipMemsetAsync(c->tile_grids, 0, sizeof(double2) * ng * nr, c->st));
+  else  // a fill kernel, not a memset: this may run inside a captured graph
+    BSE_TRY(zero_fill(reinterpret_cast<double*>(c->tile_grids), 2 * ng * nr, c->st));
   if (pdep) BSE_TRY(scatter_sets(m64, c->tile_F, 64, (int)nblk, c->tile_grids, 1, c->st));
   BSE_TRY(fft3d(c->fft, c->tile_grids, ng, +1, c->st));
   if (dstf)
@@ -207,7 +211,7 @@ static int tau_contract(bse_ctx* c, const double2* orbr, const double2* a, doubl
   if (use_cache && c->nblk_cached > 0) {
     PhaseScope ps(c, PH_TAU_STREAM);
     BSE_TRY(tau_stream(c->tau_cache, c->nblk_cached, c->nblk_cached, c->blkIJ, c->R, a, y, nb,
-                       c->nv, nr, 0, c->max_lds, c->st, fuse));
+                       c->nv, nr, 0, c->max_lds, c->st, fuse, c->tau_bl));
     first = 0;
     start = c->nblk_cached;
   }
@@ -219,7 +223,7 @@ static int tau_contract(bse_ctx* c, const double2* orbr, const double2* a, doubl
     }
     PhaseScope ps(c, PH_TAU_TILE);
     BSE_TRY(tau_stream(c->rebuild_buf, nt, nt, c->blkIJ + gb0, c->R, a, y, nb, c->nv, nr,
-                       first ? 0 : 1, c->max_lds, c->st));
+                       first ? 0 : 1, c->max_lds, c->st, nullptr, c->tau_bl));
     first = 0;
   }
   return BSE_OK;
@@ -384,7 +388,7 @@ int apply_chunk_mixed(bse_ctx* c, int nb, const double* X, double* Y) {
     PhaseScope ps(c, PH_TAU_STREAM);
     FuseArgsF f{c->Vr_f, vdrho, c->phir_f, c->spin, with_v};
     BSE_TRY(tau_stream(c->tau_f, c->nblk, c->nblk, c->blkIJ, c->Rf, c->agrid_f, c->agrid_f, nb,
-                       c->nv, nr, 0, c->max_lds, c->st, &f));
+                       c->nv, nr, 0, c->max_lds, c->st, &f, c->tau_bl));
   } else {
     PhaseScope ps(c, PH_COMBINE);
     BSE_TRY(combine(c->agrid_f, c->phir_f, c->Vr_f, vdrho, nullptr, c->agrid_f, c->nv, nb, nr,
@@ -413,6 +417,73 @@ int apply_H_f(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double 
   BSE_TRY(mul_real_field(c->agrid_f, ng, c->basis.nr, c->Vr_f, 1.0f, c->st));
   BSE_TRY(from_grid_f(c, c->agrid_f, nvs, nset, X, eps, shift, Y));
   if (project) BSE_TRY(proj_c(c, Y, Y, nset));
+  return BSE_OK;
+}
+
+}  // namespace bsex
+
+namespace bsex {
+
+// ---------------------------------------------------------------------------
+// HIP graphs of the block apply
+// ---------------------------------------------------------------------------
+void graphs_destroy(bse_ctx* c) {
+  if (c->graphs.empty()) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+  c->graphs.clear();
+  c->graph_bufs.clear();
+}
+
+int graph_apply(bse_ctx* c, int nb, const double* X, double* Y) {
+  const long L = (long)c->nv * c->basis.npw;
+  if (nb < 1 || nb > c->nbc) return fail(BSE_EINVAL, "graph apply: block of %d", nb);
+  const int key = nb * 4 + c->active;
+  for (auto& g : c->graphs)
+    if (g.first == key) {
+      BSE_HIP(hipMemcpyAsync(c->gX, X, sizeof(double) * nb * L, hipMemcpyDeviceToDevice, c->st));
+      BSE_HIP(hipGraphLaunch(g.second, c->st));
+      BSE_HIP(hipMemcpyAsync(Y, c->gY, sizeof(double) * nb * L, hipMemcpyDeviceToDevice, c->st));
+      return BSE_OK;
+    }
+  if (!c->gX) {
+    BSE_TRY(ctx_alloc_t(c, &c->gX, (size_t)c->nbc * L));
+    BSE_TRY(ctx_alloc_t(c, &c->gY, (size_t)c->nbc * L));
+  }
+  // eager run first: it sizes every lazily allocated buffer and gives Y
+  BSE_HIP(hipMemcpyAsync(c->gX, X, sizeof(double) * nb * L, hipMemcpyDeviceToDevice, c->st));
+  BSE_TRY(apply_any(c, nb, c->gX, c->gY));
+  BSE_HIP(hipMemcpyAsync(Y, c->gY, sizeof(double) * nb * L, hipMemcpyDeviceToDevice, c->st));
+  BSE_HIP(hipStreamSynchronize(c->st));
+  const size_t n_alloc = c->allocs.size();
+  // capture on a private stream (the context's may be the legacy null stream,
+  // which cannot be captured); nothing runs during capture
+  if (!c->cap_st) BSE_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  BSE_HIP(hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal));
+  hipStream_t keep = c->st;
+  c->st = c->cap_st;
+  const int rc = apply_any(c, nb, c->gX, c->gY);
+  c->st = keep;
+  const hipError_t e = hipStreamEndCapture(c->cap_st, &graph);
+  if (rc != BSE_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess || !graph)
+    return fail(BSE_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  if (c->allocs.size() != n_alloc) {  // cannot happen after the eager run
+    (void)hipGraphDestroy(graph);
+    return fail(BSE_ESTATE, "graph capture allocated");
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return fail(BSE_EHIP, "graph instantiate: %s", hipGetErrorString(e2));
+  c->graphs.push_back({key, exec});
+  // every buffer of the context may be referenced by the graph
+  c->graph_bufs.clear();
+  for (auto& b : c->allocs) c->graph_bufs.push_back(b.p);
   return BSE_OK;
 }
 

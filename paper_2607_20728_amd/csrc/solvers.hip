@@ -25,6 +25,10 @@ constexpr double kMixedFloor = 3e-7;
 // relative residual of each inner FP32 PCG solve of the Z-vector refinement
 constexpr double kMixedInnerTol = 1e-4;
 
+int learned_features(bse_ctx* c, const double* U, std::vector<float>& F);
+int learned_eval(bse_ctx* c, const std::vector<float>& F, std::vector<double>& sigma,
+                 std::vector<double>& gamma, bool* ok);
+
 int gram_tall(bse_ctx* c, const double* A, long m, const double* B, long n, long len, double* C) {
   const long need = dgemm_tall_work(m, n, len);
   if (need > c->gw_len) {
@@ -71,7 +75,15 @@ int copy_dev(bse_ctx* c, const double* s, double* d, size_t n) {
 
 int dots_host(bse_ctx* c, const double* A, const double* B, long rows, long len, double* scratch,
               std::vector<double>& out) {
-  BSE_TRY(row_dots(A, B, rows, len, scratch, c->st));
+  const long need = row_dots_work(rows, len);
+  if (need > c->rdw_len) {
+    ctx_release(c, c->rdw);
+    c->rdw = nullptr;
+    c->rdw_len = 0;
+    BSE_TRY(ctx_alloc_t(c, &c->rdw, (size_t)need));
+    c->rdw_len = need;
+  }
+  BSE_TRY(row_dots(A, B, rows, len, scratch, c->rdw, c->rdw_len, c->st));
   out.resize(rows);
   return to_host(c, scratch, out.data(), rows);
 }
@@ -85,7 +97,10 @@ int apply_n(bse_ctx* c, long n, const double* X, double* Y) {
   const long L = (long)c->nv * c->basis.npw;
   for (long i = 0; i < n; i += c->nbc) {
     const int k = (int)std::min<long>(c->nbc, n - i);
-    BSE_TRY(apply_any(c, k, X + i * L, Y + i * L));
+    if (c->use_graph && !c->prof)
+      BSE_TRY(graph_apply(c, k, X + i * L, Y + i * L));
+    else
+      BSE_TRY(apply_any(c, k, X + i * L, Y + i * L));
   }
   return BSE_OK;
 }
@@ -170,6 +185,34 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
   double* Cd = sm.p;                              // [m][k] coefficients
   double* vecd = sm.p + (size_t)maxsub * maxsub;  // small vectors
   int applies = 0;
+  // preconditioner shifts: the default, the caller's per-band values, or the
+  // network's (dropped for the default if the residual grows twice in a row)
+  DVec vs(c);
+  BSE_TRY(vs.alloc((size_t)nv));
+  const double* vshift = nullptr;
+  double pshift = c->scissor + kPrecondShift;
+  bool learned = false, fallback = false;
+  if (o && o->precond_shift_host) {
+    BSE_TRY(to_dev(c, o->precond_shift_host, vs.p, nv));
+    vshift = vs.p;
+    pshift = c->scissor;
+  } else if (o && o->use_learned && c->learned) {
+    std::vector<float> F;
+    std::vector<double> sig, gam;
+    bool ok = false;
+    BSE_TRY(learned_features(c, nullptr, F));
+    BSE_TRY(learned_eval(c, F, sig, gam, &ok));
+    if (ok) {
+      BSE_TRY(to_dev(c, sig.data(), vs.p, nv));
+      vshift = vs.p;
+      pshift = c->scissor;
+      learned = true;
+    } else {
+      fallback = true;
+    }
+  }
+  double prev_res = 1e300;
+  int grew = 0;
 
   // ---- initial block: user vectors, then lowest bare transitions ----------
   BSE_HIP(hipMemsetAsync(W.p, 0, sizeof(double) * (size_t)nb * L, c->st));
@@ -258,11 +301,24 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
     for (int i = 0; i < kr; ++i) rn[i] = std::sqrt(std::max(0.0, r2[i]));
     theta.assign(w.begin(), w.begin() + std::min(ns, m));
     bool all = (m >= ns);
-    for (int i = 0; i < ns && i < kr; ++i) all = all && (rn[i] <= tol);
+    double rmax = 0.0;
+    for (int i = 0; i < ns && i < kr; ++i) {
+      all = all && (rn[i] <= tol);
+      rmax = std::max(rmax, rn[i]);
+    }
     if (all) {
       conv = true;
       break;
     }
+    if (learned && vshift) {
+      grew = rmax > prev_res ? grew + 1 : 0;
+      if (grew >= 2 || !std::isfinite(rmax)) {
+        vshift = nullptr;
+        pshift = c->scissor + kPrecondShift;
+        fallback = true;
+      }
+    }
+    prev_res = rmax;
     // preconditioned residuals of the unconverged Ritz vectors
     std::vector<int> todo;
     for (int i = 0; i < kr; ++i)
@@ -273,8 +329,8 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
     std::vector<double> th(nt);
     for (int q = 0; q < nt; ++q) th[q] = w[todo[q]];
     BSE_TRY(to_dev(c, th.data(), vecd, nt));
-    BSE_TRY(precond_davidson(W.p, W.p, c->T, c->eps_d, vecd, c->scissor + kPrecondShift, nt,
-                             (int)nv, (int)npw, c->st));
+    BSE_TRY(precond_davidson(W.p, W.p, c->T, c->eps_d, vecd, pshift, nt, (int)nv, (int)npw, c->st,
+                             vshift));
     BSE_TRY(proj_c(c, W.p, W.p, nt));
     if (m + nt > maxsub) {  // thick restart on the lowest 2 nb Ritz vectors
       const int keep = std::min(2 * nb, m);
@@ -309,6 +365,8 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
     stats->iters = it;
     stats->applies = applies;
     stats->applies_fp64 = c->active == BSE_MIXED ? 0 : applies;
+    stats->learned = learned ? 1 : 0;
+    stats->fallback = fallback ? 1 : 0;
     for (int i = 0; i < 16; ++i) stats->resid[i] = i < nb ? rn[i] : 0.0;
     stats->t_ms = elapsed_ms(t0);
   }
@@ -379,6 +437,8 @@ int davidson(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double
     stats->iters = iters;
     stats->applies = applies;
     stats->applies_fp64 = applies64;
+    stats->learned = s1.learned;
+    stats->fallback = (s1.fallback || s2.fallback) ? 1 : 0;
     for (int i = 0; i < 16; ++i) stats->resid[i] = i < ns ? s2.resid[i] : 0.0;
     stats->t_ms = elapsed_ms(t0);
   }
@@ -417,12 +477,94 @@ int u_vector(bse_ctx* c, const double* Xs, double* U) {
 }
 
 // ---------------------------------------------------------------------------
+// Learned preconditioner: per-band features -> (shift sigma_v, gamma_v)
+// ---------------------------------------------------------------------------
+// Features of every band (layout in the ABI header); U = NULL leaves the
+// u-dependent ones at 0 (Davidson).
+int learned_features(bse_ctx* c, const double* U, std::vector<float>& F) {
+  const int nv = c->nv;
+  if (c->norb <= nv || (int)c->eps_h.size() <= nv)
+    return fail(BSE_ESTATE, "learned features need eps_{N_v+1} (n_orb > n_val)");
+  DVec o(c);
+  BSE_TRY(o.alloc(4 * (size_t)nv));
+  BSE_TRY(band_features(c->Phi, c->T, c->eps_d, U, c->phir, kPrecondShift, nv, c->basis.npw,
+                        c->basis.nr, o.p, c->st));
+  std::vector<double> h(4 * (size_t)nv);
+  BSE_TRY(to_host(c, o.p, h.data(), h.size()));
+  const double eh = c->eps_h[nv - 1], el = c->eps_h[nv], om = c->basis.omega;
+  F.assign((size_t)nv * BSE_LEARN_NFEAT, 0.0f);
+  for (int v = 0; v < nv; ++v) {
+    float* f = F.data() + (size_t)v * BSE_LEARN_NFEAT;
+    const double e = c->eps_h[v], t = h[4 * v], u2 = h[4 * v + 1], upu = h[4 * v + 2];
+    const double ipr = om * om * h[4 * v + 3] / (double)c->basis.nr;
+    f[0] = (float)(e - eh);
+    f[1] = (float)(el - e);
+    f[2] = (float)t;
+    f[3] = (float)(e - t);
+    f[4] = (float)std::log(std::max(ipr, 1e-300));
+    if (U) {
+      f[5] = (float)(0.5 * std::log(std::max(u2, 1e-300)));
+      f[6] = (float)(u2 > 0 ? upu / u2 : 0.0);
+      f[7] = 1.0f;
+    }
+  }
+  return BSE_OK;
+}
+
+// Network outputs -> sigma_v (Ha) and gamma_v; returns false when an output
+// is not finite (the caller falls back to the diagonal preconditioner).
+int learned_eval(bse_ctx* c, const std::vector<float>& F, std::vector<double>& sigma,
+                 std::vector<double>& gamma, bool* ok) {
+  const int nv = c->nv;
+  float *xd = nullptr, *yd = nullptr;
+  BSE_TRY(ctx_alloc_t(c, &xd, F.size()));
+  int rc = ctx_alloc_t(c, &yd, (size_t)nv * BSE_LEARN_NOUT);
+  std::vector<float> y((size_t)nv * BSE_LEARN_NOUT);
+  if (rc == BSE_OK) {
+    auto run = [&]() -> int {
+      BSE_HIP(hipMemcpyAsync(xd, F.data(), sizeof(float) * F.size(), hipMemcpyHostToDevice, c->st));
+      BSE_TRY(mlp_eval(c->learned, nv, xd, yd, c->st));
+      BSE_HIP(hipMemcpyAsync(y.data(), yd, sizeof(float) * y.size(), hipMemcpyDeviceToHost, c->st));
+      BSE_HIP(hipStreamSynchronize(c->st));
+      return BSE_OK;
+    };
+    rc = run();
+  }
+  ctx_release(c, xd);
+  ctx_release(c, yd);
+  BSE_TRY(rc);
+  sigma.assign(nv, kPrecondShift);
+  gamma.assign(nv, 0.0);
+  *ok = true;
+  for (int v = 0; v < nv; ++v) {
+    const double o0 = y[(size_t)v * 2], o1 = y[(size_t)v * 2 + 1];
+    if (!std::isfinite(o0) || !std::isfinite(o1)) {
+      *ok = false;
+      return BSE_OK;
+    }
+    sigma[v] = kPrecondShift * std::exp(std::min(3.0, std::max(-3.0, o0)));
+    gamma[v] = std::min(3.0, std::max(-1.0, o1));
+  }
+  return BSE_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Z-vector:  P_c (H - eps_v) P_c Z_v = -u_v, block PCG with per-band steps
 // ---------------------------------------------------------------------------
+struct PcgOut {
+  int iters = 0;
+  double rel = 0.0;
+  bool fallback = false;
+};
+
 // Solve P_c (H - eps_v) P_c Z = rhs from the current Z (projected first)
-// until ||rhs - D Z||_F <= tol ||rhs||_F; fp32 selects the FP32-grid H.
+// until ||rhs - D Z||_F <= tol ||rhs||_F (or, with band_iters, until every
+// band's own relative residual is <= tol, recording when each got there);
+// fp32 selects the FP32-grid H.  vshift: per-band preconditioner shifts
+// (NULL: kPrecondShift); dropped for the default if the residual grows in two
+// consecutive iterations.
 static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, bool fp32,
-               int* iters, double* rel_out) {
+               const double* vshift, int* band_iters, PcgOut* out) {
   const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
   DVec R(c), P(c), AP(c), Zr(c), sv(c);
   BSE_TRY(R.alloc(L));
@@ -433,29 +575,56 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
   std::vector<double> d;
   BSE_TRY(dots_host(c, rhs, rhs, nv, npw, sv.p, d));
   const double nb_ = std::sqrt(std::accumulate(d.begin(), d.end(), 0.0));
-  auto applyD = [&](const double* in, double* out) -> int {
+  auto applyD = [&](const double* in, double* o_) -> int {
     BSE_TRY(proj_c(c, in, Zr.p, 1));
-    if (fp32) return apply_H_f(c, (int)nv, 1, Zr.p, out, 0.0, c->eps_d, 1);
-    return apply_H(c, (int)nv, 1, Zr.p, out, c->agrid, 0.0, c->eps_d, 1);
+    if (fp32) return apply_H_f(c, (int)nv, 1, Zr.p, o_, 0.0, c->eps_d, 1);
+    return apply_H(c, (int)nv, 1, Zr.p, o_, c->agrid, 0.0, c->eps_d, 1);
+  };
+  std::vector<double> rz, pap, rzn, rr;
+  // P = P_c Prec(R), rz = <R, P> per band
+  auto restart = [&]() -> int {
+    BSE_TRY(precond_cg(R.p, Zr.p, c->T, c->eps_d, kPrecondShift, (int)nv, (int)npw, c->st, vshift));
+    BSE_TRY(proj_c(c, Zr.p, P.p, 1));
+    return dots_host(c, R.p, P.p, nv, npw, sv.p, rz);
   };
   BSE_TRY(proj_c(c, Z, Z, 1));
   BSE_TRY(applyD(Z, AP.p));
   BSE_TRY(axpby(1.0, rhs, 0.0, R.p, L, c->st));
   BSE_TRY(axpby(-1.0, AP.p, 1.0, R.p, L, c->st));
-  BSE_TRY(precond_cg(R.p, Zr.p, c->T, c->eps_d, kPrecondShift, (int)nv, (int)npw, c->st));
-  BSE_TRY(proj_c(c, Zr.p, P.p, 1));
-  std::vector<double> rz, pap, rzn, rr;
-  BSE_TRY(dots_host(c, R.p, P.p, nv, npw, sv.p, rz));
-  double rel = 0.0;
+  BSE_TRY(restart());
+  if (band_iters)
+    for (long v = 0; v < nv; ++v) band_iters[v] = -1;
+  double rel = 0.0, prev = 1e300;
+  int grew = 0;
   int it = 0;
   bool conv = false;
   for (it = 0; it < maxit; ++it) {
     BSE_TRY(dots_host(c, R.p, R.p, nv, npw, sv.p, rr));
     rel = nb_ > 0 ? std::sqrt(std::accumulate(rr.begin(), rr.end(), 0.0)) / nb_ : 0.0;
-    if (rel <= tol) {
+    if (band_iters) {
+      bool all = true;
+      for (long v = 0; v < nv; ++v) {
+        if (band_iters[v] < 0 && (d[v] <= 0 || std::sqrt(rr[v] / d[v]) <= tol)) band_iters[v] = it;
+        all = all && band_iters[v] >= 0;
+      }
+      if (all) {
+        conv = true;
+        break;
+      }
+    } else if (rel <= tol) {
       conv = true;
       break;
     }
+    if (vshift) {  // fallback rule of the learned preconditioner
+      grew = rel > prev ? grew + 1 : 0;
+      if (grew >= 2 || !std::isfinite(rel)) {
+        vshift = nullptr;
+        out->fallback = true;
+        BSE_TRY(restart());
+        grew = 0;
+      }
+    }
+    prev = rel;
     BSE_TRY(applyD(P.p, AP.p));
     BSE_TRY(dots_host(c, P.p, AP.p, nv, npw, sv.p, pap));
     std::vector<double> al(nv), nal(nv);
@@ -467,7 +636,7 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
     BSE_TRY(to_dev(c, nal.data(), sv.p + 2 * nv, nv));
     BSE_TRY(row_axpby(sv.p + nv, P.p, nullptr, Z, nv, npw, c->st));
     BSE_TRY(row_axpby(sv.p + 2 * nv, AP.p, nullptr, R.p, nv, npw, c->st));
-    BSE_TRY(precond_cg(R.p, AP.p, c->T, c->eps_d, kPrecondShift, (int)nv, (int)npw, c->st));
+    BSE_TRY(precond_cg(R.p, AP.p, c->T, c->eps_d, kPrecondShift, (int)nv, (int)npw, c->st, vshift));
     BSE_TRY(proj_c(c, AP.p, Zr.p, 1));
     BSE_TRY(dots_host(c, R.p, Zr.p, nv, npw, sv.p, rzn));
     std::vector<double> be(nv);
@@ -476,9 +645,15 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
     BSE_TRY(row_axpby(nullptr, Zr.p, sv.p + 3 * nv, P.p, nv, npw, c->st));
     rz = rzn;
   }
-  *iters = it;
-  *rel_out = rel;
+  out->iters = it;
+  out->rel = rel;
   return conv ? BSE_OK : BSE_ENOCONV;
+}
+
+// p_v = P_c Prec_v(rhs_v) with the default shift, into P
+static int precond_rhs(bse_ctx* c, const double* rhs, double* P) {
+  BSE_TRY(precond_cg(rhs, P, c->T, c->eps_d, kPrecondShift, c->nv, c->basis.npw, c->st));
+  return proj_c(c, P, P, 1);
 }
 
 int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
@@ -488,22 +663,52 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
   const int maxit = (o && o->max_iter > 0) ? o->max_iter : 5000;
   const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
   BSE_TRY(ensure_apply_work(c, 2));
-  DVec U(c), R(c), D(c), sv(c);
+  DVec U(c), R(c), D(c), sv(c), vs(c);
   BSE_TRY(U.alloc(L));
-  BSE_TRY(sv.alloc(16 + (size_t)nv));
+  BSE_TRY(sv.alloc(16 + 2 * (size_t)nv));
+  BSE_TRY(vs.alloc((size_t)nv));
   BSE_TRY(u_vector(c, Xs, U.p));
   BSE_TRY(proj_c(c, U.p, U.p, 1));
-  BSE_HIP(hipStreamSynchronize(c->st));
+  BSE_TRY(axpby(-1.0, U.p, 0.0, U.p, L, c->st));  // U <- -U: the right-hand side
+  // per-band preconditioner shifts and initial guess
+  const double* vshift = nullptr;
+  bool learned = false, fallback = false;
+  std::vector<double> gam;
+  if (o && o->precond_shift_host) {
+    BSE_TRY(to_dev(c, o->precond_shift_host, vs.p, nv));
+    vshift = vs.p;
+  } else if (o && o->use_learned && c->learned) {
+    std::vector<float> F;
+    std::vector<double> sig;
+    BSE_TRY(learned_features(c, U.p, F));  // U holds -u: features use |u| only
+    bool ok = false;
+    BSE_TRY(learned_eval(c, F, sig, gam, &ok));
+    if (ok) {
+      BSE_TRY(to_dev(c, sig.data(), vs.p, nv));
+      vshift = vs.p;
+      learned = true;
+    } else {
+      fallback = true;
+    }
+  }
   if (o && o->z0_dev) {
     BSE_TRY(proj_c(c, o->z0_dev, Z, 1));
+  } else if (learned) {  // Z0_v = gamma_v P_c Prec_v(-u_v)
+    BSE_TRY(precond_rhs(c, U.p, Z));
+    BSE_TRY(to_dev(c, gam.data(), sv.p + 16, nv));
+    BSE_TRY(row_scale(sv.p + 16, Z, nv, npw, c->st));
   } else {
     BSE_HIP(hipMemsetAsync(Z, 0, sizeof(double) * L, c->st));
   }
-  BSE_TRY(axpby(-1.0, U.p, 0.0, U.p, L, c->st));  // U <- -U: the right-hand side
-  int iters = 0, it = 0, rc = BSE_OK, applies64 = 0;
+  int* band_iters = o ? o->band_iters_host : nullptr;
+  int iters = 0, rc = BSE_OK, applies64 = 0;
   double rel = 0.0;
-  if (c->active != BSE_MIXED) {
-    rc = pcg(c, U.p, Z, tol, maxit, false, &iters, &rel);
+  PcgOut po;
+  if (c->active != BSE_MIXED || band_iters) {
+    rc = pcg(c, U.p, Z, tol, maxit, false, vshift, band_iters, &po);
+    iters = po.iters;
+    rel = po.rel;
+    fallback = fallback || po.fallback;
     applies64 = iters + 1;
   } else {
     // iterative refinement: FP64 residual outside, FP32-grid PCG inside
@@ -525,10 +730,13 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
         rc = BSE_OK;
         break;
       }
+      // inner target: the FP32 limit, or just past what the outer step needs
+      const double itol = std::max(kMixedInnerTol, 0.5 * tol / rel);
       BSE_HIP(hipMemsetAsync(D.p, 0, sizeof(double) * L, c->st));
-      double irel = 0;
-      const int irc = pcg(c, R.p, D.p, kMixedInnerTol, maxit - iters, true, &it, &irel);
-      iters += it;
+      const int irc = pcg(c, R.p, D.p, itol, maxit - iters, true, vshift, nullptr, &po);
+      iters += po.iters;
+      fallback = fallback || po.fallback;
+      if (po.fallback) vshift = nullptr;
       if (irc != BSE_OK && irc != BSE_ENOCONV) return irc;
       BSE_TRY(axpby(1.0, D.p, 1.0, Z, L, c->st));
     }
@@ -536,14 +744,42 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
   BSE_HIP(hipStreamSynchronize(c->st));
   if (stats) {
     stats->iters = iters;
-    stats->applies = c->active == BSE_MIXED ? iters + applies64 : iters + 1;
+    stats->applies = c->active == BSE_MIXED && !band_iters ? iters + applies64 : iters + 1;
     stats->applies_fp64 = applies64;
     stats->resid[0] = rel;
     stats->t_ms = elapsed_ms(t0);
+    stats->learned = learned ? 1 : 0;
+    stats->fallback = fallback ? 1 : 0;
   }
   if (rc == BSE_ENOCONV)
     return fail(BSE_ENOCONV, "Z-vector CG: residual %.3e after %d iterations", rel, iters);
   return rc;
+}
+
+// features of the Z-vector solve and, with Zref, the least-squares
+// initial-guess coefficients gamma_v* = <p_v, Z_v> / <p_v, p_v>
+int learned_targets(bse_ctx* c, const double* Xs, const double* Zref, float* feat,
+                    double* gamma) {
+  const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
+  BSE_TRY(ensure_apply_work(c, 2));
+  DVec U(c), P(c), sv(c);
+  BSE_TRY(U.alloc(L));
+  BSE_TRY(sv.alloc(2 * (size_t)nv + 16));
+  BSE_TRY(u_vector(c, Xs, U.p));
+  BSE_TRY(proj_c(c, U.p, U.p, 1));
+  BSE_TRY(axpby(-1.0, U.p, 0.0, U.p, L, c->st));
+  std::vector<float> F;
+  BSE_TRY(learned_features(c, U.p, F));
+  if (feat) std::copy(F.begin(), F.end(), feat);
+  if (Zref && gamma) {
+    BSE_TRY(P.alloc(L));
+    BSE_TRY(precond_rhs(c, U.p, P.p));
+    std::vector<double> pz, pp;
+    BSE_TRY(dots_host(c, P.p, Zref, nv, npw, sv.p, pz));
+    BSE_TRY(dots_host(c, P.p, P.p, nv, npw, sv.p, pp));
+    for (long v = 0; v < nv; ++v) gamma[v] = pp[v] > 0 ? pz[v] / pp[v] : 0.0;
+  }
+  return BSE_OK;
 }
 
 // ---------------------------------------------------------------------------

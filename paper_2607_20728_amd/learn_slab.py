@@ -1,0 +1,149 @@
+"""Train and evaluate the learned preconditioner on the slab family.
+
+    python -m paper_2607_20728_amd.learn_slab collect --first 1 --count 8 --out DIR
+    python -m paper_2607_20728_amd.learn_slab train --records DIR [DIR ...] --out W.npz
+    python -m paper_2607_20728_amd.learn_slab gain --weights W.npz --first 17 --count 4
+
+Geometry g is the 48x48x120 honeycomb slab (200 sites, N_v = 400, N_pdep =
+768) with its sites displaced by N(0, 0.05 bohr), seed 5000 + g.  Every
+geometry is solved by the library (ground state, lowest exciton by the mixed
+Davidson to 1e-6, Z-vector histories by the plain FP64 PCG); training runs on
+the library's BF16 kernels.  Each step prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def _log(**kw):
+    print(json.dumps(kw), flush=True)
+
+
+def _context(g, precision):
+    import synth
+    from . import bsex
+    cfg = synth.c5_geometry(g)
+    n_pw = bsex.basis_size(cfg.cell, cfg.grid, cfg.ecut)
+    d = synth.make_system(cfg, n_pw)
+    t0 = time.perf_counter()
+    ctx = bsex.init_from_synth(d, n_extra=8, gs_tol=1e-10, precision=precision)
+    return ctx, cfg, d, time.perf_counter() - t0
+
+
+def collect(args):
+    from . import bsex, learned
+    os.makedirs(args.out, exist_ok=True)
+    for g in range(args.first, args.first + args.count):
+        ctx, cfg, d, t_init = _context(g, bsex.MIXED)
+        info = bsex.get_info(ctx)
+        t0 = time.perf_counter()
+        w, X, ds = bsex.davidson(ctx, 1, tol=args.tol)
+        t1 = time.perf_counter()
+        rec = learned.collect(ctx, X[0], tol=args.tol)
+        t2 = time.perf_counter()
+        np.savez(os.path.join(args.out, f"slab_g{g}.npz"), **rec)
+        _log(step="collect", geometry=g, init_s=round(t_init, 1), ks_gap=info["ks_gap"],
+             omega=float(w[0]), davidson_iters=ds["iters"], davidson_s=round(t1 - t0, 1),
+             collect_s=round(t2 - t1, 1),
+             iters_by_shift={f"{s:g}": int(np.max(np.where(np.isfinite(b), b, -1)))
+                             for s, b in zip(rec["shifts"], rec["band_iters"])})
+        ctx.free()
+
+
+def _records(dirs):
+    out = []
+    for dd in dirs:
+        for f in sorted(glob.glob(os.path.join(dd, "slab_g*.npz"))):
+            with np.load(f) as z:
+                out.append({k: z[k] for k in z.files})
+    return out
+
+
+def train(args):
+    from . import learned
+    recs = _records(args.records)
+    if not recs:
+        sys.exit("no records found")
+    t0 = time.perf_counter()
+    net, norm, losses = learned.train(recs, steps=args.steps, lr=args.lr, seed=args.seed)
+    learned.save(args.out, net, norm)
+    _log(step="train", geometries=len(recs), samples=2 * sum(len(r["gamma"]) for r in recs),
+         loss_first=losses[0], loss_last=losses[-1], train_s=round(time.perf_counter() - t0, 2))
+
+
+def gain(args):
+    """Held-out geometries: Davidson and Z-vector with and without the network,
+    each judged by the plain FP64 residual (both at the same tolerance)."""
+    from . import bsex, learned
+    net, _ = learned.load(args.weights)
+    rows = []
+    for g in range(args.first, args.first + args.count):
+        ctx, cfg, d, t_init = _context(g, bsex.MIXED)
+        res = {}
+        for mode in ("plain", "learned"):
+            use = mode == "learned"
+            bsex.set_learned(ctx, net if use else None)
+            t0 = time.perf_counter()
+            w, X, ds = bsex.davidson(ctx, 1, tol=args.tol, use_learned=use)
+            t1 = time.perf_counter()
+            Z, zs = bsex.zvector_solve(ctx, X[0], tol=args.tol, use_learned=use)
+            t2 = time.perf_counter()
+            res[mode] = dict(omega=float(w[0]), davidson_iters=ds["iters"],
+                             davidson_applies=ds["applies"], davidson_s=round(t1 - t0, 2),
+                             z_iters=zs["iters"], z_s=round(t2 - t1, 2),
+                             z_resid=zs["resid"][0], learned=int(ds["learned"] and zs["learned"]),
+                             fallback=int(ds["fallback"] or zs["fallback"]))
+        bsex.set_learned(ctx, None)
+        ctx.free()
+        rows.append(dict(geometry=g, **res))
+        _log(step="gain", **rows[-1])
+    if rows:
+        def mean(mode, key):
+            return float(np.mean([r[mode][key] for r in rows]))
+
+        def worst(key):
+            return float(max(r["learned"][key] / r["plain"][key] for r in rows))
+        _log(step="gain_summary", geometries=len(rows),
+             davidson_iters=dict(plain=mean("plain", "davidson_iters"),
+                                 learned=mean("learned", "davidson_iters"),
+                                 worst_ratio=worst("davidson_iters")),
+             z_iters=dict(plain=mean("plain", "z_iters"), learned=mean("learned", "z_iters"),
+                          worst_ratio=worst("z_iters")),
+             seconds=dict(plain=mean("plain", "davidson_s") + mean("plain", "z_s"),
+                          learned=mean("learned", "davidson_s") + mean("learned", "z_s")))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect")
+    c.add_argument("--first", type=int, default=1)
+    c.add_argument("--count", type=int, default=8)
+    c.add_argument("--out", required=True)
+    c.add_argument("--tol", type=float, default=1e-6)
+    t = sub.add_parser("train")
+    t.add_argument("--records", nargs="+", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--steps", type=int, default=1500)
+    t.add_argument("--lr", type=float, default=2e-3)
+    t.add_argument("--seed", type=int, default=0)
+    e = sub.add_parser("gain")
+    e.add_argument("--weights", required=True)
+    e.add_argument("--first", type=int, default=17)
+    e.add_argument("--count", type=int, default=4)
+    e.add_argument("--tol", type=float, default=1e-6)
+    args = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    {"collect": collect, "train": train, "gain": gain}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main()

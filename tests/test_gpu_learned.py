@@ -1,0 +1,165 @@
+"""The learned preconditioner on the GPU: the BF16 network's forward pass,
+gradients and Adam step against the FP64 reference network, training, the
+per-band features against the oracle, and the solver hooks (per-band shifts,
+learned initial guess, fallback) against the plain solves.
+
+Bounds.  BF16 operands carry 8 significant bits (relative rounding 2^-9), and
+a layer sums at most 128 such products in FP32, so forward outputs and
+gradients agree with FP64 to ~1e-2 relative in norm (asserted: 3e-2);
+losses to 1e-2.  The Adam kernel is checked exactly (FP32, 1e-6) on the GPU's
+own gradient.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import basis, mlp as omlp, model, solvers
+from oracle.model import K_ALL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2607_20728_amd import bsex  # noqa: E402
+
+
+def _cuda32(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+
+
+def _cuda(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _nrel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _batch(n=300, n_in=8, n_out=2, seed=5):
+    rng = np.random.default_rng(seed)
+    x = (rng.normal(0, 1, (n, n_in)) * np.linspace(0.5, 3, n_in) + 1.0).astype(np.float32)
+    t = np.stack([np.sin(x[:, 0]) + 0.1 * x[:, 1] ** 2, x[:, 2] * x[:, 3] / 3],
+                 axis=1)[:, :n_out].astype(np.float32)
+    w = rng.uniform(0.5, 1.0, (n, n_out)).astype(np.float32)
+    norm = (x.mean(0), x.std(0), t.mean(0), t.std(0))
+    return x, t, w, [np.asarray(a, np.float32) for a in norm]
+
+
+def test_mlp_forward_gradient_adam_vs_reference():
+    print("[gpu] mlp forward/grad/adam", flush=True)
+    x, t, w, norm = _batch()
+    net = bsex.Mlp(8, 2, seed=11)
+    net.set_norm(*norm)
+    p0 = net.get_params().astype(np.float64)
+    nrm64 = [a.astype(np.float64) for a in norm]
+    y = net.forward(_cuda32(x)).cpu().numpy()
+    yo = omlp.forward(p0, x, 8, 2, nrm64)
+    assert _nrel(y, yo) < 3e-2, _nrel(y, yo)
+    loss, g = net.train_step(_cuda32(x), _cuda32(t), _cuda32(w), lr=1e-3, want_grad=True)
+    Lo, go = omlp.loss_and_grad(p0, x, t, w, 8, 2, nrm64)
+    g = g.cpu().numpy()
+    print(f"  forward {_nrel(y, yo):.2e}  grad {_nrel(g, go):.2e}  loss {loss:.4e} vs {Lo:.4e}")
+    assert abs(loss - Lo) < 1e-2 * Lo
+    assert _nrel(g, go) < 3e-2
+    # per layer too: no layer may hide behind a larger one
+    offs = np.cumsum([0, 128 * 8, 128, 128 * 128, 128, 2 * 128, 2])
+    for k in range(6):
+        sl = slice(offs[k], offs[k + 1])
+        assert _nrel(g[sl], go[sl]) < 5e-2, (k, _nrel(g[sl], go[sl]))
+    # the Adam step on the GPU's own gradient, exactly
+    p1 = net.get_params().astype(np.float64)
+    pw, _, _ = omlp.adam_step(p0, g.astype(np.float64), 0.0, 0.0, 1, 1e-3)
+    assert np.abs(p1 - pw).max() < 1e-6
+    net.free()
+
+
+def test_mlp_training_reduces_loss():
+    print("[gpu] mlp training", flush=True)
+    x, t, _, norm = _batch(n=2000, seed=6)
+    net = bsex.Mlp(8, 2, seed=3)
+    net.set_norm(*norm)
+    xd, td = _cuda32(x), _cuda32(t)
+    l0 = net.train_step(xd, td, lr=3e-3)
+    for _ in range(400):
+        loss = net.train_step(xd, td, lr=3e-3)
+    print(f"  loss {l0:.3e} -> {loss:.3e}")
+    assert loss < 0.05 * l0
+    # the trained network's forward agrees with the reference on its weights
+    p = net.get_params().astype(np.float64)
+    y = net.forward(xd).cpu().numpy()
+    yo = omlp.forward(p, x, 8, 2, [a.astype(np.float64) for a in norm])
+    assert _nrel(y, yo) < 3e-2
+    net.free()
+
+
+def _c1():
+    cfg = synth.get_config("c1")
+    b = basis.Basis(cfg.cell, cfg.grid, cfg.ecut)
+    d = synth.make_system(cfg, b.n_pw)
+    S = model.System(b, d["site_xyz"], d["site_depth"], d["site_width"], d["pdep"], d["lam"],
+                     cfg.n_val, kmask=K_ALL)
+    S.ground_state(n_extra=8)
+    orbs = np.vstack([S.phi, S.psi_c])
+    eps = np.concatenate([S.eps, S.eps_c])
+    ctx = bsex.init_from_synth(d, orbitals=orbs, eps=eps)
+    return S, ctx
+
+
+def test_learned_features_and_gamma_vs_oracle():
+    print("[gpu] learned features c1", flush=True)
+    S, ctx = _c1()
+    wo, Xo, _ = solvers.davidson(S, 1, tol=1e-10)
+    X = Xo[0]
+    Zo, _ = solvers.zvector_cg(S, solvers.u_vector(S, X), tol=1e-12)
+    F, gam = bsex.learned_features(ctx, _cuda(X), _cuda(Zo))
+    b = S.b
+    nv = S.n_val
+    phr = b.to_grid(S.phi)
+    u = S.proj_c(solvers.u_vector(S, X))
+    pre = np.maximum(S.T[None, :] - S.eps[:, None] + 0.25, 0.1)
+    Fo = np.zeros((nv, 8))
+    Fo[:, 0] = S.eps - S.eps[-1]
+    Fo[:, 1] = S.eps_c[0] - S.eps
+    Fo[:, 2] = (S.T[None, :] * S.phi ** 2).sum(1)
+    Fo[:, 3] = S.eps - Fo[:, 2]
+    Fo[:, 4] = np.log(b.omega ** 2 * (phr ** 4).reshape(nv, -1).sum(1) / b.n_r)
+    Fo[:, 5] = 0.5 * np.log((u ** 2).sum(1))
+    Fo[:, 6] = (u ** 2 / pre).sum(1) / (u ** 2).sum(1)
+    Fo[:, 7] = 1.0
+    assert np.abs(F - Fo).max() < 1e-5 * max(1.0, np.abs(Fo).max())
+    p = S.proj_c(-u / pre)
+    go = (p * Zo).sum(1) / (p * p).sum(1)
+    assert np.abs(gam - go).max() < 1e-8 * max(1.0, np.abs(go).max())
+    ctx.free()
+
+
+def test_solver_hooks_reach_the_plain_solution():
+    print("[gpu] learned hooks c1", flush=True)
+    S, ctx = _c1()
+    w, X, _ = bsex.davidson(ctx, 1, tol=1e-10)
+    Zp, sp = bsex.zvector_solve(ctx, X[0], tol=1e-10)
+    nv = S.n_val
+    rng = np.random.default_rng(1)
+    sh = rng.uniform(0.1, 1.0, nv)
+    Zs, ss = bsex.zvector_solve(ctx, X[0], tol=1e-10, shifts=sh, band_iters=True)
+    assert np.abs((Zs - Zp).cpu().numpy()).max() < 1e-7 * float(Zp.abs().max())
+    assert (ss["band_iters"] >= 0).all() and ss["band_iters"].max() == ss["iters"]
+    # an (untrained) network: used, and the solve still reaches the same Z
+    net = bsex.Mlp(8, 2, seed=7)
+    bsex.set_learned(ctx, net)
+    Zl, sl = bsex.zvector_solve(ctx, X[0], tol=1e-10, use_learned=True)
+    assert sl["learned"] == 1 and sl["rc"] == 0
+    assert np.abs((Zl - Zp).cpu().numpy()).max() < 1e-7 * float(Zp.abs().max())
+    wl, Xl, dl = bsex.davidson(ctx, 1, tol=1e-10, use_learned=True)
+    assert dl["learned"] == 1 and abs(wl[0] - w[0]) < 1e-10
+    # a network with non-finite outputs is dropped for the diagonal one
+    p = net.get_params()
+    p[:] = 3e38
+    net.set_params(p)
+    Zf, sf = bsex.zvector_solve(ctx, X[0], tol=1e-10, use_learned=True)
+    assert sf["fallback"] == 1 and sf["learned"] == 0
+    assert np.abs((Zf - Zp).cpu().numpy()).max() < 1e-7 * float(Zp.abs().max())
+    print(f"  iters plain {sp['iters']} shifted {ss['iters']} learned {sl['iters']}")
+    bsex.set_learned(ctx, None)
+    net.free()
+    ctx.free()
