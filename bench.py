@@ -138,6 +138,52 @@ def copy_calibration(args):
                           launches=args.steps)), flush=True)
 
 
+def batch(args):
+    """The uneven batch: the 32 systems of synth.c4_systems, lowest exciton and
+    forces each, once one system at a time (one stream, no graphs, default
+    kernels) and once batched (4 streams, HIP graphs, autotuned kernels)."""
+    import torch
+
+    import synth
+    from paper_2607_20728_amd import bsex
+    torch.cuda.set_device(0)
+    cfgs = synth.c4_systems(args.batch_n)
+    systems = []
+    for cfg in cfgs:
+        n_pw = bsex.basis_size(cfg.cell, cfg.grid, cfg.ecut)
+        systems.append(synth.make_system(cfg, n_pw))
+    prec = bsex.MIXED if args.precision == "mixed" else bsex.FP64
+    runs = {}
+    for name, kw in (("sequential", dict(n_streams=1, autotune=False, use_graph=False)),
+                     ("batched", dict(n_streams=4, autotune=True, use_graph=True))):
+        bsex.tune_cache_clear()
+        t0 = time.perf_counter()
+        res = bsex.batch_run(systems, tol=args.tol, precision=prec, check=False, **kw)
+        dt = time.perf_counter() - t0
+        bad = [r["message"] for r in res if r["status"] != 0]
+        runs[name] = dict(seconds=round(dt, 2), systems_per_s=round(len(res) / dt, 4),
+                          failed=len(bad), first_error=bad[0] if bad else None,
+                          davidson_iters=sum(r["davidson_iters"] for r in res),
+                          z_iters=sum(r["z_iters"] for r in res),
+                          variants=[r["variant"] for r in res], res=res)
+        log(f"[batch] {name}: {dt:.1f} s, {len(bad)} failed")
+    a, b = runs["sequential"]["res"], runs["batched"]["res"]
+    dw = max(abs(x["omega"] - y["omega"]) for x, y in zip(a, b))
+    dF = max(float(np.abs(x["dwdR"] - y["dwdR"]).max()) for x, y in zip(a, b))
+    for r in runs.values():
+        r.pop("res")
+    out = dict(metric="uneven batch: systems/s (lowest exciton + forces each)",
+               value=runs["batched"]["systems_per_s"], unit="systems/s", higher_is_better=True,
+               dtype="f32+f64" if prec == bsex.MIXED else "f64", data="synthetic",
+               config=dict(workload="32 cubic systems, grids {32,40,48,64}^3, N_v U{32..256}, "
+                                    "N_pdep U{128..384}, 8 Gaussian sites (seed 4000)",
+                           tol=args.tol, grids=[c.grid[0] for c in cfgs],
+                           n_val=[c.n_val for c in cfgs]),
+               runs=runs, max_abs_domega=dw, max_abs_ddwdR=dF,
+               speedup=round(runs["sequential"]["seconds"] / runs["batched"]["seconds"], 3))
+    print(json.dumps(out), flush=True)
+
+
 def time_to_force(args):
     """Time to force on one system (default the defect supercell): device
     ground state and tau cache (init), Davidson for the lowest n_states
@@ -155,7 +201,8 @@ def time_to_force(args):
     d = synth.make_system(cfg, n_pw, seed=args.seed)
     t0 = time.perf_counter()
     prec = bsex.MIXED if args.precision == "mixed" else bsex.FP64
-    ctx = bsex.init_from_synth(d, n_extra=8, gs_tol=1e-10, gap_min=args.gap_min, precision=prec)
+    ctx = bsex.init_from_synth(d, n_extra=args.n_extra, gs_tol=1e-10, gap_min=args.gap_min,
+                               precision=prec)
     net = None
     if args.learned:
         from paper_2607_20728_amd import learned
@@ -168,22 +215,25 @@ def time_to_force(args):
     log(f"[ttf] init {t_init:.1f} s, gap {info['ks_gap']:.3e}, cached "
         f"{info['tau_blocks_cached']}/{info['tau_blocks']}")
     t1 = time.perf_counter()
-    w, X, ds = bsex.davidson(ctx, cfg.n_states, tol=args.tol, use_learned=use, check=False)
+    tl = args.two_level
+    w, X, ds = bsex.davidson(ctx, cfg.n_states, tol=args.tol, use_learned=use, two_level=tl,
+                             check=False)
     t2 = time.perf_counter()
     log(f"[ttf] davidson {t2 - t1:.1f} s, {ds['iters']} iters, {ds['applies']} applies "
         f"({ds['applies_fp64']} FP64), "
         f"omega {w}, resid {ds['resid'][:cfg.n_states]}")
-    Z, zs = bsex.zvector_solve(ctx, X[0], tol=args.tol, use_learned=use, check=False)
+    Z, zs = bsex.zvector_solve(ctx, X[0], tol=args.tol, use_learned=use, two_level=tl,
+                               check=False)
     t3 = time.perf_counter()
     log(f"[ttf] U + Z {t3 - t2:.1f} s, {zs['iters']} iters, resid {zs['resid'][0]:.2e}")
     F = bsex.forces(ctx, X[0], Z, len(d["site_depth"]))
     t4 = time.perf_counter()
-    mode = args.precision + ("+learned" if use else "")
+    mode = args.precision + ("+learned" if use else "") + ("+two-level" if tl else "")
     out = dict(metric=f"time-to-force @{args.tol:g} resid ({mode})",
                value=round(t4 - t0, 2), unit="s", higher_is_better=False,
                dtype="f32+f64" if prec == bsex.MIXED else "f64", data="synthetic",
                seed=d["seed"],
-               config=dict(workload=cfg.name, n_states=cfg.n_states,
+               config=dict(workload=cfg.name, n_states=cfg.n_states, n_extra=args.n_extra,
                            tau_blocks_cached=info["tau_blocks_cached"],
                            tau_blocks=info["tau_blocks"], ks_gap_ha=info["ks_gap"]),
                split_s=dict(init=round(t_init, 2), davidson=round(t2 - t1, 2),
@@ -218,6 +268,12 @@ def main():
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--gap-min", type=float, default=0.0)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--two-level", action="store_true",
+                    help="two-level preconditioner on the conduction states held (--ttf)")
+    ap.add_argument("--n-extra", type=int, default=8,
+                    help="conduction states the ground-state solve computes (--ttf)")
+    ap.add_argument("--batch", action="store_true", help="uneven batch run instead")
+    ap.add_argument("--batch-n", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="plain 2 GiB device copies, for scaling HBM counters")
     ap.add_argument("--learned", default=None,
@@ -233,6 +289,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration(args)
+        return
+    if args.batch:
+        batch(args)
         return
 
     import torch

@@ -188,6 +188,12 @@ typedef struct {
   int32_t *band_iters_host;   /* optional out [n_val] (Z-vector): iteration at which
                                  band v's own relative residual first reached tol;
                                  when given, the solve runs until every band has  */
+  int32_t two_level;          /* 1: correct the kinetic preconditioner on the span
+                                 of the conduction states the context holds (n_orb
+                                 > n_val): there it is 1/(eps_c - eps_v + Delta -
+                                 theta) (Davidson; |.| >= 1e-3 Ha) or
+                                 1/(eps_c - eps_v) (Z-vector), applied as
+                                 Q K^-1 Q + Psi D^-1 Psi^T, Q = 1 - Psi Psi^T      */
 } bse_solver_opts;
 
 typedef struct {
@@ -259,8 +265,9 @@ int bse_get_phase_times(bse_ctx *ctx, bse_phase_times *out, int32_t reset);
  *   sigma_v = 0.25 Ha * exp(clamp(o_0, -3, 3))   shift of the kinetic
  *             preconditioner 1/max(|G|^2/2 - eps_v + sigma_v, 0.1) of the
  *             Z-vector PCG and (with the scissor and the Ritz value) of Davidson;
- *   gamma_v = clamp(o_1, -1, 3)                  Z initial guess
- *             Z_v^0 = gamma_v P_c Prec_v(-u_v) with the default shift 0.25 Ha.
+ *   gamma_v = exp(clamp(o_1, -6, 8))             Z initial guess
+ *             Z_v^0 = gamma_v P_c Prec_v(-u_v) with the default shift 0.25 Ha
+ *             (Prec in its two-level form when the solve uses it).
  * Features of band v (BSE_LEARN_NFEAT = 8):
  *   0 eps_v - eps_{N_v}          1 eps_{N_v+1} - eps_v   (Ha; eps ascending, 1-based)
  *   2 <phi_v|T|phi_v>            3 <phi_v|V|phi_v> = eps_v - feature 2
@@ -304,10 +311,13 @@ int bse_set_learned(bse_ctx *ctx, bse_mlp *mlp);
 /* Features [n_val][BSE_LEARN_NFEAT] of the Z-vector solve for exciton Xs_dev
  * (feature 7 = 1), and, when Zref_dev (a converged Z) is given, the
  * least-squares initial-guess coefficient per band,
- *   gamma_v* = <p_v, Z_v> / <p_v, p_v>,  p_v = P_c Prec_v(-u_v), shift 0.25 Ha.
- * Needs the first conduction eigenvalue (n_orb > n_val): ESTATE otherwise. */
+ *   gamma_v* = <p_v, Z_v> / <p_v, p_v>,  p_v = P_c Prec_v(-u_v), shift 0.25 Ha,
+ * Prec the kinetic diagonal, or its two-level form when two_level = 1 (the
+ * Z-vector solve builds its learned initial guess with the preconditioner it
+ * runs with).  Needs the first conduction eigenvalue (n_orb > n_val):
+ * ESTATE otherwise. */
 int bse_learned_features(bse_ctx *ctx, const double *Xs_dev, const double *Zref_dev,
-                         float *feat_host, double *gamma_host);
+                         int32_t two_level, float *feat_host, double *gamma_host);
 
 /*
  * Uneven batches of independent systems (each solved as by bse_init_system,

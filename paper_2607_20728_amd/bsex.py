@@ -80,7 +80,7 @@ class SolverOpts(C.Structure):
                 ("max_subspace", C.c_int32), ("x0_dev", C.c_void_p), ("n_x0", C.c_int32),
                 ("z0_dev", C.c_void_p), ("use_learned", C.c_int32),
                 ("precond_shift_host", C.POINTER(C.c_double)),
-                ("band_iters_host", C.POINTER(C.c_int32))]
+                ("band_iters_host", C.POINTER(C.c_int32)), ("two_level", C.c_int32)]
 
 
 class SolverStats(C.Structure):
@@ -138,7 +138,7 @@ def lib():
     L.bse_set_graphs.argtypes = [C.c_void_p, C.c_int32]
     L.bse_batch_run.argtypes = [C.POINTER(SystemDesc), C.c_int32, C.POINTER(BatchOpts),
                                 C.POINTER(BatchResult)]
-    L.bse_learned_features.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, fp, dp]
+    L.bse_learned_features.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, fp, dp]
     L.bse_set_profiling.argtypes = [C.c_void_p, C.c_int32]
     L.bse_get_phase_times.argtypes = [C.c_void_p, C.POINTER(PhaseTimes), C.c_int32]
     L.bse_free.argtypes = [C.c_void_p]
@@ -328,8 +328,9 @@ def apply(ctx, X, Y=None):
 
 
 def _opts(tol=0.0, max_iter=0, block=0, max_subspace=0, x0=None, z0=None, use_learned=False,
-          shifts=None, band_iters=None):
+          shifts=None, band_iters=None, two_level=False):
     o = SolverOpts()
+    o.two_level = 1 if two_level else 0
     o.tol, o.max_iter, o.block, o.max_subspace = float(tol), int(max_iter), int(block), int(max_subspace)
     o.use_learned = 1 if use_learned else 0
     if shifts is not None:
@@ -350,13 +351,14 @@ def _stats(s):
 
 
 def davidson(ctx, n_states=1, *, tol=1e-8, max_iter=0, block=0, max_subspace=0, x0=None,
-             use_learned=False, shifts=None, check=True):
+             use_learned=False, shifts=None, two_level=False, check=True):
     import torch
     info = get_info(ctx)
     X = torch.empty((n_states, info["n_val"], info["n_pw"]), dtype=torch.float64, device="cuda")
     w = np.zeros(n_states)
     sh = None if shifts is None else _f64(shifts)
-    o = _opts(tol, max_iter, block, max_subspace, x0=x0, use_learned=use_learned, shifts=sh)
+    o = _opts(tol, max_iter, block, max_subspace, x0=x0, use_learned=use_learned, shifts=sh,
+              two_level=two_level)
     s = SolverStats()
     rc = lib().bse_davidson(ctx.h, n_states, C.byref(o), _dptr(w), _dev(X, "X"), C.byref(s))
     if check:
@@ -372,14 +374,15 @@ def u_vector(ctx, Xs):
 
 
 def zvector_solve(ctx, Xs, *, tol=1e-8, max_iter=0, z0=None, use_learned=False, shifts=None,
-                  band_iters=False, check=True):
+                  band_iters=False, two_level=False, check=True):
     """bse_zvector_solve.  shifts: per-band preconditioner shifts (host);
     band_iters=True adds the per-band iteration counts to the stats."""
     import torch
     Z = torch.empty_like(Xs)
     sh = None if shifts is None else _f64(shifts)
     bi = np.zeros(Xs.shape[0], dtype=np.int32) if band_iters else None
-    o = _opts(tol, max_iter, z0=z0, use_learned=use_learned, shifts=sh, band_iters=bi)
+    o = _opts(tol, max_iter, z0=z0, use_learned=use_learned, shifts=sh, band_iters=bi,
+              two_level=two_level)
     s = SolverStats()
     rc = lib().bse_zvector_solve(ctx.h, _dev(Xs, "Xs"), C.byref(o), _dev(Z, "Z"), C.byref(s))
     if check:
@@ -469,13 +472,14 @@ def set_learned(ctx, mlp):
     ctx._learned = mlp  # keep it alive while attached
 
 
-def learned_features(ctx, Xs, Zref=None):
+def learned_features(ctx, Xs, Zref=None, two_level=False):
     """bse_learned_features: features [n_val][8] and, with Zref, gamma* [n_val]."""
     nv = Xs.shape[0]
     f = np.zeros((nv, LEARN_NFEAT), dtype=np.float32)
     g = np.zeros(nv) if Zref is not None else None
     _check(lib().bse_learned_features(ctx.h, _dev(Xs, "Xs"),
                                       None if Zref is None else _dev(Zref, "Zref"),
+                                      1 if two_level else 0,
                                       f.ctypes.data_as(C.POINTER(C.c_float)),
                                       None if g is None else _dptr(g)))
     return (f, g) if Zref is not None else f

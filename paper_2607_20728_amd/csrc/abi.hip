@@ -473,11 +473,11 @@ int bse_set_learned(bse_ctx* c, bse_mlp* mlp) {
   return BSE_OK;
 }
 
-int bse_learned_features(bse_ctx* c, const double* Xs, const double* Zref, float* feat,
-                         double* gamma) {
+int bse_learned_features(bse_ctx* c, const double* Xs, const double* Zref, int32_t two_level,
+                         float* feat, double* gamma) {
   if (!c || !Xs || !feat) return fail(BSE_EINVAL, "NULL argument");
   if (Zref && !gamma) return fail(BSE_EINVAL, "gamma_host needed with Zref_dev");
-  return guarded(c, [&] { return learned_targets(c, Xs, Zref, feat, gamma); });
+  return guarded(c, [&] { return learned_targets(c, Xs, Zref, two_level != 0, feat, gamma); });
 }
 
 int bse_davidson(bse_ctx* c, int32_t n_states, const bse_solver_opts* opts, double* omega_host,

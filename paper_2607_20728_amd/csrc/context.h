@@ -148,7 +148,8 @@ int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double
 int mlp_eval(bse_mlp* q, long n, const float* x, float* y, hipStream_t st);
 int mlp_n_in(const bse_mlp* q);
 int mlp_n_out(const bse_mlp* q);
-int learned_targets(bse_ctx* c, const double* Xs, const double* Zref, float* feat, double* gamma);
+int learned_targets(bse_ctx* c, const double* Xs, const double* Zref, bool two_level, float* feat,
+                    double* gamma);
 int apply_chunk_mixed(bse_ctx* c, int nb, const double* X, double* Y);
 // block apply through a captured HIP graph (captured on first use per block size)
 int graph_apply(bse_ctx* c, int nb, const double* X, double* Y);

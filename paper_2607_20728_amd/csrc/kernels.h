@@ -129,6 +129,9 @@ int precond_davidson(const double* R, double* T, const double* Tk, const double*
 // shift_v = vshift ? vshift[v] : shift
 int precond_cg(const double* R, double* T, const double* Tk, const double* eps, double shift,
                int nv, int npw, hipStream_t st, const double* vshift = nullptr);
+// C[k][v][c] /= clamp(eps[nv + c] - eps[v] + shift - (theta ? theta[k] : 0)), |den| >= dmin
+int coarse_scale(double* C, int nk, int nv, int nc, const double* eps, const double* theta,
+                 double shift, double dmin, hipStream_t st);
 // Per-band sums for the learned preconditioner's features: out[v][0] =
 // sum_j Tk_j Phi_vj^2, [1] = sum_j U_vj^2, [2] = sum_j U_vj^2 / max(Tk_j - eps_v
 // + shift, 0.1), [3] = sum_r phi_v(r)^4 (phir packs two bands per complex grid).

@@ -620,6 +620,20 @@ __global__ void k_precond_cg(const double* __restrict__ R, double* __restrict__ 
   }
 }
 
+__global__ void k_coarse_scale(double* __restrict__ C, int nk, int nv, int nc,
+                               const double* __restrict__ eps, const double* __restrict__ theta,
+                               double shift, double dmin) {
+  const long n = (long)nk * nv * nc;
+  for (long e = gtid(); e < n; e += gstride()) {
+    const int cc = (int)(e % nc);
+    const int v = (int)((e / nc) % nv);
+    const int k = (int)(e / ((long)nc * nv));
+    double den = eps[nv + cc] - eps[v] + shift - (theta ? theta[k] : 0.0);
+    if (fabs(den) < dmin) den = den < 0.0 ? -dmin : dmin;
+    C[e] /= den;
+  }
+}
+
 // one workgroup per band, fixed-order tree reductions
 __global__ __launch_bounds__(256) void k_band_features(
     const double* __restrict__ Phi, const double* __restrict__ Tk, const double* __restrict__ eps,
@@ -1026,6 +1040,16 @@ int precond_cg(const double* R, double* T, const double* Tk, const double* eps, 
   if (n <= 0) return BSE_OK;
   hipLaunchKernelGGL(k_precond_cg, dim3(nblocks(n)), dim3(TPB), 0, st, R, T, Tk, eps, shift, nv,
                      npw, vshift);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int coarse_scale(double* C, int nk, int nv, int nc, const double* eps, const double* theta,
+                 double shift, double dmin, hipStream_t st) {
+  const long n = (long)nk * nv * nc;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_coarse_scale, dim3(nblocks(n)), dim3(TPB), 0, st, C, nk, nv, nc, eps, theta,
+                     shift, dmin);
   CHECK_LAUNCH();
   return BSE_OK;
 }

@@ -22,6 +22,9 @@ constexpr double kPrecondShift = 0.25;  // Ha, kinetic preconditioner shift
 // 1e-7 in the residual of a normalised vector, so the FP64 check then passes
 // without FP64 iterations unless tol is below that floor.
 constexpr double kMixedFloor = 3e-7;
+// smallest |eps_c - eps_v + Delta - theta| the two-level Davidson
+// preconditioner divides by on the conduction states it holds
+constexpr double kDavidsonMinDen = 1e-3;
 // relative residual of each inner FP32 PCG solve of the Z-vector refinement
 constexpr double kMixedInnerTol = 1e-4;
 
@@ -103,6 +106,37 @@ int apply_n(bse_ctx* c, long n, const double* X, double* Y) {
       BSE_TRY(apply_any(c, k, X + i * L, Y + i * L));
   }
   return BSE_OK;
+}
+
+// Two-level preconditioner on the rows W[k][v][:] (in place):
+//   W <- Q K^-1 Q W + Psi diag(1/(eps_c - eps_v + shift - theta_k)) Psi^T W,
+// Psi the conduction states the context holds, Q = 1 - Psi Psi^T, K^-1 the
+// kinetic diagonal (kin: the caller's kernel applied in place).  Symmetric
+// positive definite when K^-1 is and the denominators are positive (Z-vector);
+// in Davidson it is the transition-space diagonal of M on span(Psi).
+template <typename Kin>
+int precond_two_level(bse_ctx* c, double* W, int nk, const double* theta, double shift,
+                      double dmin, Kin kin) {
+  const int nv = c->nv, npw = c->basis.npw, nc = c->norb - c->nv;
+  if (nc <= 0) return kin(W);
+  const long M = (long)nk * nv;
+  const double* Psi = c->Phi + (long)nv * npw;
+  double *C1 = nullptr, *C2 = nullptr;
+  BSE_TRY(ctx_alloc_t(c, &C1, (size_t)M * nc));
+  int rc = ctx_alloc_t(c, &C2, (size_t)M * nc);
+  auto run = [&]() -> int {
+    BSE_TRY(gemm(c, 0, 1, M, nc, npw, 1.0, W, npw, Psi, npw, 0.0, C1, nc));    // Psi^T R
+    BSE_TRY(dgemm(0, 0, M, npw, nc, -1.0, C1, nc, Psi, npw, 1.0, W, npw, c->st));  // Q R
+    BSE_TRY(kin(W));                                                            // K^-1 Q R
+    BSE_TRY(gemm(c, 0, 1, M, nc, npw, 1.0, W, npw, Psi, npw, 0.0, C2, nc));
+    BSE_TRY(dgemm(0, 0, M, npw, nc, -1.0, C2, nc, Psi, npw, 1.0, W, npw, c->st));  // Q K^-1 Q R
+    BSE_TRY(coarse_scale(C1, nk, nv, nc, c->eps_d, theta, shift, dmin, c->st));
+    return dgemm(0, 0, M, npw, nc, 1.0, C1, nc, Psi, npw, 1.0, W, npw, c->st);
+  };
+  if (rc == BSE_OK) rc = run();
+  ctx_release(c, C1);
+  ctx_release(c, C2);
+  return rc;
 }
 
 }  // namespace
@@ -213,6 +247,7 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
   }
   double prev_res = 1e300;
   int grew = 0;
+  const bool two_level = o && o->two_level && c->norb > c->nv;
 
   // ---- initial block: user vectors, then lowest bare transitions ----------
   BSE_HIP(hipMemsetAsync(W.p, 0, sizeof(double) * (size_t)nb * L, c->st));
@@ -329,8 +364,14 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
     std::vector<double> th(nt);
     for (int q = 0; q < nt; ++q) th[q] = w[todo[q]];
     BSE_TRY(to_dev(c, th.data(), vecd, nt));
-    BSE_TRY(precond_davidson(W.p, W.p, c->T, c->eps_d, vecd, pshift, nt, (int)nv, (int)npw, c->st,
-                             vshift));
+    auto kin = [&](double* w) {
+      return precond_davidson(w, w, c->T, c->eps_d, vecd, pshift, nt, (int)nv, (int)npw, c->st,
+                              vshift);
+    };
+    if (two_level)
+      BSE_TRY(precond_two_level(c, W.p, nt, vecd, c->scissor, kDavidsonMinDen, kin));
+    else
+      BSE_TRY(kin(W.p));
     BSE_TRY(proj_c(c, W.p, W.p, nt));
     if (m + nt > maxsub) {  // thick restart on the lowest 2 nb Ritz vectors
       const int keep = std::min(2 * nb, m);
@@ -543,7 +584,7 @@ int learned_eval(bse_ctx* c, const std::vector<float>& F, std::vector<double>& s
       return BSE_OK;
     }
     sigma[v] = kPrecondShift * std::exp(std::min(3.0, std::max(-3.0, o0)));
-    gamma[v] = std::min(3.0, std::max(-1.0, o1));
+    gamma[v] = std::exp(std::min(8.0, std::max(-6.0, o1)));
   }
   return BSE_OK;
 }
@@ -564,7 +605,7 @@ struct PcgOut {
 // (NULL: kPrecondShift); dropped for the default if the residual grows in two
 // consecutive iterations.
 static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, bool fp32,
-               const double* vshift, int* band_iters, PcgOut* out) {
+               const double* vshift, int* band_iters, PcgOut* out, bool two_level) {
   const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
   DVec R(c), P(c), AP(c), Zr(c), sv(c);
   BSE_TRY(R.alloc(L));
@@ -582,8 +623,17 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
   };
   std::vector<double> rz, pap, rzn, rr;
   // P = P_c Prec(R), rz = <R, P> per band
+  // Zr = M^-1 R (kinetic diagonal, or two-level on the conduction states held)
+  auto prec = [&](const double* r, double* t) -> int {
+    auto kin = [&](double* w) {
+      return precond_cg(w, w, c->T, c->eps_d, kPrecondShift, (int)nv, (int)npw, c->st, vshift);
+    };
+    if (t != r) BSE_HIP(hipMemcpyAsync(t, r, sizeof(double) * L, hipMemcpyDeviceToDevice, c->st));
+    if (two_level) return precond_two_level(c, t, 1, nullptr, 0.0, 1e-12, kin);
+    return kin(t);
+  };
   auto restart = [&]() -> int {
-    BSE_TRY(precond_cg(R.p, Zr.p, c->T, c->eps_d, kPrecondShift, (int)nv, (int)npw, c->st, vshift));
+    BSE_TRY(prec(R.p, Zr.p));
     BSE_TRY(proj_c(c, Zr.p, P.p, 1));
     return dots_host(c, R.p, P.p, nv, npw, sv.p, rz);
   };
@@ -636,7 +686,7 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
     BSE_TRY(to_dev(c, nal.data(), sv.p + 2 * nv, nv));
     BSE_TRY(row_axpby(sv.p + nv, P.p, nullptr, Z, nv, npw, c->st));
     BSE_TRY(row_axpby(sv.p + 2 * nv, AP.p, nullptr, R.p, nv, npw, c->st));
-    BSE_TRY(precond_cg(R.p, AP.p, c->T, c->eps_d, kPrecondShift, (int)nv, (int)npw, c->st, vshift));
+    BSE_TRY(prec(R.p, AP.p));
     BSE_TRY(proj_c(c, AP.p, Zr.p, 1));
     BSE_TRY(dots_host(c, R.p, Zr.p, nv, npw, sv.p, rzn));
     std::vector<double> be(nv);
@@ -650,9 +700,17 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
   return conv ? BSE_OK : BSE_ENOCONV;
 }
 
-// p_v = P_c Prec_v(rhs_v) with the default shift, into P
-static int precond_rhs(bse_ctx* c, const double* rhs, double* P) {
-  BSE_TRY(precond_cg(rhs, P, c->T, c->eps_d, kPrecondShift, c->nv, c->basis.npw, c->st));
+// p_v = P_c Prec_v(rhs_v) with the default shift (two-level form if asked), into P
+static int precond_rhs(bse_ctx* c, const double* rhs, double* P, bool two_level) {
+  const long L = (long)c->nv * c->basis.npw;
+  BSE_HIP(hipMemcpyAsync(P, rhs, sizeof(double) * L, hipMemcpyDeviceToDevice, c->st));
+  auto kin = [&](double* w) {
+    return precond_cg(w, w, c->T, c->eps_d, kPrecondShift, c->nv, c->basis.npw, c->st);
+  };
+  if (two_level && c->norb > c->nv)
+    BSE_TRY(precond_two_level(c, P, 1, nullptr, 0.0, 1e-12, kin));
+  else
+    BSE_TRY(kin(P));
   return proj_c(c, P, P, 1);
 }
 
@@ -694,18 +752,19 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
   if (o && o->z0_dev) {
     BSE_TRY(proj_c(c, o->z0_dev, Z, 1));
   } else if (learned) {  // Z0_v = gamma_v P_c Prec_v(-u_v)
-    BSE_TRY(precond_rhs(c, U.p, Z));
+    BSE_TRY(precond_rhs(c, U.p, Z, o->two_level && c->norb > c->nv));
     BSE_TRY(to_dev(c, gam.data(), sv.p + 16, nv));
     BSE_TRY(row_scale(sv.p + 16, Z, nv, npw, c->st));
   } else {
     BSE_HIP(hipMemsetAsync(Z, 0, sizeof(double) * L, c->st));
   }
   int* band_iters = o ? o->band_iters_host : nullptr;
+  const bool two_level = o && o->two_level && c->norb > c->nv;
   int iters = 0, rc = BSE_OK, applies64 = 0;
   double rel = 0.0;
   PcgOut po;
   if (c->active != BSE_MIXED || band_iters) {
-    rc = pcg(c, U.p, Z, tol, maxit, false, vshift, band_iters, &po);
+    rc = pcg(c, U.p, Z, tol, maxit, false, vshift, band_iters, &po, two_level);
     iters = po.iters;
     rel = po.rel;
     fallback = fallback || po.fallback;
@@ -733,7 +792,7 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
       // inner target: the FP32 limit, or just past what the outer step needs
       const double itol = std::max(kMixedInnerTol, 0.5 * tol / rel);
       BSE_HIP(hipMemsetAsync(D.p, 0, sizeof(double) * L, c->st));
-      const int irc = pcg(c, R.p, D.p, itol, maxit - iters, true, vshift, nullptr, &po);
+      const int irc = pcg(c, R.p, D.p, itol, maxit - iters, true, vshift, nullptr, &po, two_level);
       iters += po.iters;
       fallback = fallback || po.fallback;
       if (po.fallback) vshift = nullptr;
@@ -758,7 +817,7 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
 
 // features of the Z-vector solve and, with Zref, the least-squares
 // initial-guess coefficients gamma_v* = <p_v, Z_v> / <p_v, p_v>
-int learned_targets(bse_ctx* c, const double* Xs, const double* Zref, float* feat,
+int learned_targets(bse_ctx* c, const double* Xs, const double* Zref, bool two_level, float* feat,
                     double* gamma) {
   const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
   BSE_TRY(ensure_apply_work(c, 2));
@@ -773,7 +832,7 @@ int learned_targets(bse_ctx* c, const double* Xs, const double* Zref, float* fea
   if (feat) std::copy(F.begin(), F.end(), feat);
   if (Zref && gamma) {
     BSE_TRY(P.alloc(L));
-    BSE_TRY(precond_rhs(c, U.p, P.p));
+    BSE_TRY(precond_rhs(c, U.p, P.p, two_level));
     std::vector<double> pz, pp;
     BSE_TRY(dots_host(c, P.p, Zref, nv, npw, sv.p, pz));
     BSE_TRY(dots_host(c, P.p, P.p, nv, npw, sv.p, pp));

@@ -7,7 +7,8 @@
 Geometry g is the 48x48x120 honeycomb slab (200 sites, N_v = 400, N_pdep =
 768) with its sites displaced by N(0, 0.05 bohr), seed 5000 + g.  Every
 geometry is solved by the library (ground state, lowest exciton by the mixed
-Davidson to 1e-6, Z-vector histories by the plain FP64 PCG); training runs on
+Davidson to 1e-6, Z-vector histories by the FP64 PCG, both with the two-level
+preconditioner on 32 conduction states); training runs on
 the library's BF16 kernels.  Each step prints one JSON line.
 """
 from __future__ import annotations
@@ -26,6 +27,9 @@ def _log(**kw):
     print(json.dumps(kw), flush=True)
 
 
+N_EXTRA = 32  # conduction states held for the two-level preconditioner
+
+
 def _context(g, precision):
     import synth
     from . import bsex
@@ -33,7 +37,7 @@ def _context(g, precision):
     n_pw = bsex.basis_size(cfg.cell, cfg.grid, cfg.ecut)
     d = synth.make_system(cfg, n_pw)
     t0 = time.perf_counter()
-    ctx = bsex.init_from_synth(d, n_extra=8, gs_tol=1e-10, precision=precision)
+    ctx = bsex.init_from_synth(d, n_extra=N_EXTRA, gs_tol=1e-10, precision=precision)
     return ctx, cfg, d, time.perf_counter() - t0
 
 
@@ -44,9 +48,9 @@ def collect(args):
         ctx, cfg, d, t_init = _context(g, bsex.MIXED)
         info = bsex.get_info(ctx)
         t0 = time.perf_counter()
-        w, X, ds = bsex.davidson(ctx, 1, tol=args.tol)
+        w, X, ds = bsex.davidson(ctx, 1, tol=args.tol, two_level=True)
         t1 = time.perf_counter()
-        rec = learned.collect(ctx, X[0], tol=args.tol)
+        rec = learned.collect(ctx, X[0], tol=args.tol, two_level=True)
         t2 = time.perf_counter()
         np.savez(os.path.join(args.out, f"slab_g{g}.npz"), **rec)
         _log(step="collect", geometry=g, init_s=round(t_init, 1), ks_gap=info["ks_gap"],
@@ -78,28 +82,34 @@ def train(args):
          loss_first=losses[0], loss_last=losses[-1], train_s=round(time.perf_counter() - t0, 2))
 
 
+MODES = {"diagonal": (False, False), "two-level": (True, False),
+         "two-level+learned": (True, True)}
+
+
 def gain(args):
-    """Held-out geometries: Davidson and Z-vector with and without the network,
-    each judged by the plain FP64 residual (both at the same tolerance)."""
+    """Held-out geometries: Davidson and Z-vector with the kinetic diagonal
+    preconditioner, its two-level form, and the two-level form with the
+    network, each judged by the plain FP64 residual at the same tolerance."""
     from . import bsex, learned
     net, _ = learned.load(args.weights)
     rows = []
     for g in range(args.first, args.first + args.count):
         ctx, cfg, d, t_init = _context(g, bsex.MIXED)
         res = {}
-        for mode in ("plain", "learned"):
-            use = mode == "learned"
+        for mode, (tl, use) in MODES.items():
             bsex.set_learned(ctx, net if use else None)
             t0 = time.perf_counter()
-            w, X, ds = bsex.davidson(ctx, 1, tol=args.tol, use_learned=use)
+            w, X, ds = bsex.davidson(ctx, 1, tol=args.tol, use_learned=use, two_level=tl)
             t1 = time.perf_counter()
-            Z, zs = bsex.zvector_solve(ctx, X[0], tol=args.tol, use_learned=use)
+            Z, zs = bsex.zvector_solve(ctx, X[0], tol=args.tol, use_learned=use, two_level=tl)
             t2 = time.perf_counter()
             res[mode] = dict(omega=float(w[0]), davidson_iters=ds["iters"],
                              davidson_applies=ds["applies"], davidson_s=round(t1 - t0, 2),
                              z_iters=zs["iters"], z_s=round(t2 - t1, 2),
                              z_resid=zs["resid"][0], learned=int(ds["learned"] and zs["learned"]),
                              fallback=int(ds["fallback"] or zs["fallback"]))
+        res["omega_spread"] = max(r["omega"] for r in res.values()) - min(
+            r["omega"] for r in res.values())
         bsex.set_learned(ctx, None)
         ctx.free()
         rows.append(dict(geometry=g, **res))
@@ -108,16 +118,14 @@ def gain(args):
         def mean(mode, key):
             return float(np.mean([r[mode][key] for r in rows]))
 
-        def worst(key):
-            return float(max(r["learned"][key] / r["plain"][key] for r in rows))
-        _log(step="gain_summary", geometries=len(rows),
-             davidson_iters=dict(plain=mean("plain", "davidson_iters"),
-                                 learned=mean("learned", "davidson_iters"),
-                                 worst_ratio=worst("davidson_iters")),
-             z_iters=dict(plain=mean("plain", "z_iters"), learned=mean("learned", "z_iters"),
-                          worst_ratio=worst("z_iters")),
-             seconds=dict(plain=mean("plain", "davidson_s") + mean("plain", "z_s"),
-                          learned=mean("learned", "davidson_s") + mean("learned", "z_s")))
+        def worst(key, ref):
+            return float(max(r["two-level+learned"][key] / max(r[ref][key], 1) for r in rows))
+        summ = {}
+        for key in ("davidson_iters", "z_iters", "davidson_s", "z_s"):
+            summ[key] = {m: mean(m, key) for m in MODES}
+            summ[key]["worst_ratio_learned_vs_two_level"] = worst(key, "two-level")
+            summ[key]["worst_ratio_learned_vs_diagonal"] = worst(key, "diagonal")
+        _log(step="gain_summary", geometries=len(rows), **summ)
 
 
 def main():

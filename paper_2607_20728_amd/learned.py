@@ -11,7 +11,7 @@ through the C ABI:
   0.25 Ha), regressed as log(sigma_v*/0.25);
 * initial-guess coefficient gamma_v*: the least-squares scalar along the
   preconditioned right-hand side, from a Z converged 1000x below the
-  tolerance (bse_learned_features).
+  tolerance (bse_learned_features), regressed as log(max(gamma_v*, 1e-3)).
 
 Each band gives two samples: the Z-vector one (all features) and a Davidson
 one (the u-dependent features 5 and 6 and the flag 7 set to zero, gamma
@@ -27,20 +27,22 @@ SHIFTS = (0.0625, 0.125, 0.25, 0.5, 1.0, 2.0)
 DEFAULT_SHIFT = 0.25
 
 
-def collect(ctx, Xs, *, tol=1e-6, shifts=SHIFTS, max_iter=0):
+def collect(ctx, Xs, *, tol=1e-6, shifts=SHIFTS, max_iter=0, two_level=False):
     """One geometry's training record from the plain solver on context ctx
-    for the normalised exciton Xs [n_val][n_pw] (CUDA float64)."""
+    for the normalised exciton Xs [n_val][n_pw] (CUDA float64), under the
+    preconditioner form the solves will use (two_level)."""
     nv = Xs.shape[0]
     its = []
     for s in shifts:
         _, st = bsex.zvector_solve(ctx, Xs, tol=tol, shifts=np.full(nv, float(s)),
-                                   band_iters=True, max_iter=max_iter, check=False)
+                                   band_iters=True, max_iter=max_iter, two_level=two_level,
+                                   check=False)
         bi = st["band_iters"].astype(np.float64)
         bi[bi < 0] = np.inf  # band not converged within max_iter
         its.append(bi)
     its = np.array(its)                                   # [n_shift][n_val]
-    Zref, _ = bsex.zvector_solve(ctx, Xs, tol=min(tol * 1e-3, 1e-9))
-    feat, gamma = bsex.learned_features(ctx, Xs, Zref)
+    Zref, _ = bsex.zvector_solve(ctx, Xs, tol=min(tol * 1e-3, 1e-9), two_level=two_level)
+    feat, gamma = bsex.learned_features(ctx, Xs, Zref, two_level=two_level)
     sh = np.asarray(shifts, dtype=np.float64)
     dist = np.abs(np.log(sh / DEFAULT_SHIFT))
     best = np.empty(nv)
@@ -52,11 +54,16 @@ def collect(ctx, Xs, *, tol=1e-6, shifts=SHIFTS, max_iter=0):
                 gamma=np.asarray(gamma, dtype=np.float64), band_iters=its, shifts=sh)
 
 
+def log_gamma(g):
+    return np.log(np.maximum(np.asarray(g, dtype=np.float64), 1e-3))
+
+
 def training_arrays(records):
     """x [2N][8], t [2N][2], w [2N][2] (float32) from collect() records."""
     F = np.concatenate([r["features"] for r in records]).astype(np.float32)
     T = np.stack([np.concatenate([r["log_sigma"] for r in records]),
-                  np.concatenate([r["gamma"] for r in records])], axis=1).astype(np.float32)
+                  np.concatenate([log_gamma(r["gamma"]) for r in records])],
+                 axis=1).astype(np.float32)
     Fd = F.copy()
     Fd[:, 5:8] = 0.0
     Wz = np.ones_like(T)
@@ -113,4 +120,4 @@ def predict(net, features):
     import torch
     y = net.forward(torch.tensor(np.ascontiguousarray(features, np.float32),
                                  device="cuda")).cpu().numpy().astype(np.float64)
-    return (DEFAULT_SHIFT * np.exp(np.clip(y[:, 0], -3, 3)), np.clip(y[:, 1], -1, 3))
+    return (DEFAULT_SHIFT * np.exp(np.clip(y[:, 0], -3, 3)), np.exp(np.clip(y[:, 1], -6, 8)))

@@ -56,9 +56,11 @@ CONFIGS = {
     "c1": Config("c1", (10.0, 10.0, 10.0), (24, 24, 24), 10.0, 16, 64, -0.8, 16.0,
                  "uniform:8", seed=1000),
     # 2-D slab: 10 x 5 rectangular honeycomb cells (200 sites, nearest
-    # neighbours 2.733 bohr) in a 110-bohr cell along z
+    # neighbours 2.733 bohr) in a 110-bohr cell along z; sublattice depths
+    # 1.0 / 4.0 Ha give a Kohn-Sham gap of 0.034 Ha at N_v = 400 (1.5 / 2.5
+    # leaves the layer semi-metallic: gap 1.3e-6 Ha)
     "c5": Config("c5", (47.34, 40.99, 110.0), (48, 48, 120), 3.26, 400, 768, -0.85, 144.0,
-                 "honeycomb", depth=(1.5, 2.5), width=(1.0, 1.0), seed=5000,
+                 "honeycomb", depth=(1.0, 4.0), width=(1.0, 1.0), seed=5000,
                  site_model="dimer"),
     # defect supercell: 3x3x3 diamond cells (216 sites) with one removed; the
     # seed is the first from 2000 whose Kohn-Sham gap at N_v is >= 1e-3 Ha

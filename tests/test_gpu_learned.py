@@ -159,7 +159,13 @@ def test_solver_hooks_reach_the_plain_solution():
     Zf, sf = bsex.zvector_solve(ctx, X[0], tol=1e-10, use_learned=True)
     assert sf["fallback"] == 1 and sf["learned"] == 0
     assert np.abs((Zf - Zp).cpu().numpy()).max() < 1e-7 * float(Zp.abs().max())
-    print(f"  iters plain {sp['iters']} shifted {ss['iters']} learned {sl['iters']}")
+    # the two-level preconditioner (conduction states held by the context)
+    Zt, stl = bsex.zvector_solve(ctx, X[0], tol=1e-10, two_level=True)
+    assert np.abs((Zt - Zp).cpu().numpy()).max() < 1e-7 * float(Zp.abs().max())
+    wt, Xt, dt = bsex.davidson(ctx, 1, tol=1e-10, two_level=True)
+    assert abs(wt[0] - w[0]) < 1e-10
+    print(f"  iters plain {sp['iters']} shifted {ss['iters']} learned {sl['iters']} "
+          f"two-level {stl['iters']}; davidson two-level {dt['iters']}")
     bsex.set_learned(ctx, None)
     net.free()
     ctx.free()
