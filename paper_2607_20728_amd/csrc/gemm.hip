@@ -144,11 +144,13 @@ int dgemm(int ta, int tb, long M, long N, long K, double alpha, const double* A,
   return BSE_OK;
 }
 
-// split-K factor for an op(A) op(B) product whose tile grid is small
+// split-K factor for an op(A) op(B) product whose tile grid is small: aim at
+// ~4096 workgroups (16 per CU, so global-load latency is hidden by occupancy)
+// with K chunks of at least 1024
 static long k_splits(long M, long N, long K) {
   const long tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  if (tiles >= 512 || K < 2048) return 1;
-  long s = std::min((K + 1023) / 1024, std::max(1L, 1024 / tiles));
+  if (tiles >= 2048 || K < 2048) return 1;
+  long s = std::min((K + 1023) / 1024, std::max(1L, 4096 / tiles));
   return std::max(s, 1L);
 }
 
