@@ -129,11 +129,15 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   const double reserve = has_budget ? 1.0e9 : 4.0e9 + 2.0 * 72 * 8.0 * c->nv * npw;
   const long small_tile = std::min(c->nblk, 4L);
   double budget_left = has_budget ? (double)d->tau_budget_bytes : 0.0;
+  // rebuild tiles: ~6% of the device, or, for a budgeted context (batches),
+  // at most a quarter of its budget
+  double tile_target = std::max(1.0e9, 0.06 * (double)totalb);
+  if (has_budget)
+    tile_target = std::min(tile_target, std::max(blk_tile_bytes, 0.25 * (double)d->tau_budget_bytes));
   if (mixed) {
     // the whole FP32 cache first; the FP64 cache gets what is left
     const double fbytes = 4.0 * 64 * nr * c->nblk;
-    double cap = (double)freeb - reserve -
-                 (has_budget ? 0.25 * (double)d->tau_budget_bytes : std::max(1.0e9, 0.06 * (double)totalb));
+    double cap = (double)freeb - reserve - tile_target;
     if (has_budget) cap = std::min(cap, budget_left);
     if (fbytes > cap)
       return fail(BSE_ENOMEM, "FP32 tau cache needs %.1f GB, %.1f GB free", fbytes / 1e9,
@@ -155,9 +159,6 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
     c->tile_blk = small_tile;
   } else {
     BSE_TRY(ensure_ygrid(c));  // accumulation across launches
-    double tile_target = std::max(1.0e9, 0.06 * (double)totalb);
-    if (has_budget)  // a budgeted context (batches) keeps its tiles near its cache size
-      tile_target = std::min(tile_target, std::max(blk_tile_bytes, 0.25 * (double)d->tau_budget_bytes));
     c->tile_blk = std::max(1L, std::min(c->nblk, (long)(tile_target / blk_tile_bytes)));
   }
   const long te = c->tile_blk * 64;

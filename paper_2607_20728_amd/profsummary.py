@@ -1,16 +1,105 @@
-"""Summarise a rocprofv3 rocpd database by kernel and launch shape.
+"""Summaries of rocprofv3 output.
 
-usage: python -m paper_2607_20728_amd.profsummary <results.db> [rows]
+    python -m paper_2607_20728_amd.profsummary kernels <results.db> [rows]
+        per-kernel time from a --kernel-trace run (rocpd database), grouped
+        by kernel and launch shape;
+
+    python -m paper_2607_20728_amd.profsummary traffic --fetch DIR --write DIR
+            --copy-fetch DIR --copy-write DIR --match k_tau_stream --out FILE
+            [--command TEXT]
+        HBM bytes per launch of the kernels whose name contains --match, from
+        the FETCH_SIZE and WRITE_SIZE counter runs (--output-format csv),
+        each scaled by the same counter on a plain 2 GiB copy
+        (bench.py --copy-calibration); writes the JSON bench.py reads.
 """
-import sqlite3, collections, sys, re
-db=sys.argv[1]
-con=sqlite3.connect(db); cur=con.cursor()
-rows=cur.execute("select name, grid_x, workgroup_x, lds_size, vgpr_count, accum_vgpr_count, duration from kernels").fetchall()
-g=collections.defaultdict(list)
-for n,gx,wx,lds,vg,ag,du in rows:
-    m=re.search(r'(k_[a-z_0-9]+(<[^>]*>)?|__amd_rocclr_\w+)', n); short=m.group(1) if m else n[:40]
-    g[(short,gx,lds,vg,ag)].append(du)
-tot=sum(sum(v) for v in g.values())
-print(f"{'kernel':28s} {'grid_x':>10s} {'lds':>6s} {'vgpr':>4s} {'agpr':>4s} {'calls':>6s} {'avg_us':>10s} {'tot_ms':>9s} {'%':>5s}")
-for k,v in sorted(g.items(), key=lambda kv:-sum(kv[1]))[:int(sys.argv[2]) if len(sys.argv)>2 else 30]:
-    print(f"{k[0]:28s} {k[1]:10d} {k[2]:6d} {k[3]:4d} {k[4]:4d} {len(v):6d} {sum(v)/len(v)/1e3:10.1f} {sum(v)/1e6:9.1f} {100*sum(v)/tot:5.1f}")
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import json
+import os
+import re
+import sqlite3
+import statistics
+import sys
+
+
+def kernels(db, rows=30):
+    con = sqlite3.connect(db)
+    cur = con.cursor()
+    q = ("select name, grid_x, workgroup_x, lds_size, vgpr_count, accum_vgpr_count, duration "
+         "from kernels")
+    g = collections.defaultdict(list)
+    for n, gx, wx, lds, vg, ag, du in cur.execute(q).fetchall():
+        m = re.search(r'(k_[a-z_0-9]+(<[^>]*>)?|__amd_rocclr_\w+)', n)
+        short = m.group(1) if m else n[:40]
+        g[(short, gx, lds, vg, ag)].append(du)
+    tot = sum(sum(v) for v in g.values())
+    print(f"{'kernel':34s} {'grid_x':>10s} {'lds':>6s} {'calls':>6s} {'avg_us':>10s} "
+          f"{'tot_ms':>9s} {'%':>5s}")
+    for k, v in sorted(g.items(), key=lambda kv: -sum(kv[1]))[:rows]:
+        print(f"{k[0]:34s} {k[1]:10d} {k[2]:6d} {len(v):6d} {sum(v) / len(v) / 1e3:10.1f} "
+              f"{sum(v) / 1e6:9.1f} {100 * sum(v) / tot:5.1f}")
+
+
+def _counter_rows(d, counter):
+    """(kernel name, value) per dispatch of one counter, from rocprofv3 CSVs."""
+    out = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    out.append((r.get("Kernel_Name", ""), float(r["Counter_Value"])))
+    if not out:
+        sys.exit(f"no {counter} rows under {d}")
+    return out
+
+
+def _copy_factor(d, counter, expected_kib):
+    # the 2 GiB copy (and, for WRITE_SIZE, the 2 GiB fill before it) are the
+    # only dispatches of that size in the calibration run
+    vals = [v for _, v in _counter_rows(d, counter) if v > 0.5 * expected_kib]
+    if not vals:
+        sys.exit(f"no 2 GiB dispatch in {d}")
+    return expected_kib / statistics.median(vals), vals
+
+
+def traffic(a):
+    gib_kib = 2.0 * 1024 * 1024
+    ff, fvals = _copy_factor(a.copy_fetch, "FETCH_SIZE", gib_kib)
+    wf, wvals = _copy_factor(a.copy_write, "WRITE_SIZE", gib_kib)
+    fk = [(n, v) for n, v in _counter_rows(a.fetch, "FETCH_SIZE") if a.match in n]
+    wk = [(n, v) for n, v in _counter_rows(a.write, "WRITE_SIZE") if a.match in n]
+    if not fk or not wk:
+        sys.exit(f"no dispatch of {a.match}")
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    out = dict(kernel=sorted({n for n, _ in fk})[0][:120], source_sha=bench.stream_kernel_sha(),
+               launches=len(fk), fetch_kib_per_launch=statistics.mean(v for _, v in fk),
+               write_kib_per_launch=statistics.mean(v for _, v in wk),
+               copy_fetch_factor=ff, copy_write_factor=wf,
+               copy_fetch_kib=fvals, copy_write_kib=wvals, command=a.command)
+    with open(a.out, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "kernels":
+        kernels(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 30)
+        return
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "out"):
+        t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    t.add_argument("--match", default="k_tau_stream")
+    t.add_argument("--command", default="")
+    a = ap.parse_args()
+    traffic(a)
+
+
+if __name__ == "__main__":
+    main()

@@ -116,3 +116,17 @@ def test_mixed_davidson_z_forces(name):
     print(f"  force diff {np.abs(F - Fo).max():.2e}")
     assert np.abs(F - Fo).max() < 1e-7
     ctx.free()
+
+
+def test_mixed_with_explicit_budget():
+    """A budget larger than the device (the throughput bench passes one) still
+    gives the whole FP32 cache."""
+    print("[gpu] mixed budget c1", flush=True)
+    S, d = _oracle("c1")
+    ctx = _lib_ctx(S, d, precision=bsex.MIXED, tau_budget_bytes=10 ** 12)
+    info = bsex.get_info(ctx)
+    assert info["tau_bytes_f32"] == info["tau_blocks"] * 64 * int(np.prod(d["grid"])) * 4
+    X = d["trial"][:3]
+    Y = bsex.apply(ctx, _cuda(X)).cpu().numpy()
+    assert _frel(Y, S.apply(X)) < 2e-6
+    ctx.free()
