@@ -68,8 +68,10 @@ void householder_tridiag(Mat& A, Mat& Q, std::vector<double>& d, std::vector<dou
 }
 
 // One implicit Wilkinson-shifted QR step on the unreduced block [lo, hi].
-void qr_step(int lo, int hi, std::vector<double>& d, std::vector<double>& e, Mat& Q) {
-  const int n = Q.n;
+// Qt holds the eigenvector estimates as rows (Q transposed), so each plane
+// rotation combines two contiguous rows.
+void qr_step(int lo, int hi, std::vector<double>& d, std::vector<double>& e, Mat& Qt) {
+  const int n = Qt.n;
   const double a = d[hi - 1], b = e[hi - 1], c = d[hi];
   const double delta = 0.5 * (a - c);
   const double rad = std::hypot(delta, b);
@@ -92,10 +94,12 @@ void qr_step(int lo, int hi, std::vector<double>& d, std::vector<double>& e, Mat
       e[k + 1] = cs * e[k + 1];
       x = e[k];
     }
+    double* rk = &Qt(k, 0);
+    double* r1 = &Qt(k + 1, 0);
     for (int i = 0; i < n; ++i) {
-      const double qk = Q(i, k), q1 = Q(i, k + 1);
-      Q(i, k) = cs * qk + sn * q1;
-      Q(i, k + 1) = -sn * qk + cs * q1;
+      const double qk = rk[i], q1 = r1[i];
+      rk[i] = cs * qk + sn * q1;
+      r1[i] = -sn * qk + cs * q1;
     }
   }
 }
@@ -112,6 +116,9 @@ int host_syev(int n, double* Ain, double* w) {
   }
   std::vector<double> d(n), e(n);
   householder_tridiag(A, Q, d, e);
+  Mat& Qt = A;  // A is no longer needed: it receives Q transposed
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Qt(j, i) = Q(i, j);
   int hi = n - 1, guard = 0;
   const double eps = 2.220446049250313e-16;
   while (hi > 0) {
@@ -123,7 +130,7 @@ int host_syev(int n, double* Ain, double* w) {
     int lo = hi - 1;
     while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
     if (lo > 0) e[lo - 1] = 0.0;
-    qr_step(lo, hi, d, e, Q);
+    qr_step(lo, hi, d, e, Qt);
     if (++guard > 60 * n + 100) return 1;
   }
   std::vector<int> idx(n);
@@ -131,7 +138,7 @@ int host_syev(int n, double* Ain, double* w) {
   std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
   for (int j = 0; j < n; ++j) {
     w[j] = d[idx[j]];
-    for (int i = 0; i < n; ++i) Ain[(size_t)i * n + j] = Q(i, idx[j]);
+    for (int i = 0; i < n; ++i) Ain[(size_t)i * n + j] = Qt(idx[j], i);
   }
   return 0;
 }
