@@ -34,7 +34,9 @@ void ctx_destroy(bse_ctx* c) {
   graphs_destroy(c);
   if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
   for (auto& b : c->allocs) (void)hipFree(b.p);
+  for (auto& b : c->pool) (void)hipFree(b.p);
   c->allocs.clear();
+  c->pool.clear();
   fft_plan_free(&c->fft);
   sphere_plan_free(&c->sp);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
@@ -123,6 +125,7 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   const double blk_bytes = 8.0 * 64 * nr;
   const double blk_tile_bytes = 8.0 * 64 * (2.0 * nr + 2.0 * npw + std::max(c->npdep, 1));
   size_t freeb = 0, totalb = 0;
+  ctx_pool_flush(c);  // scratch of the ground-state solve goes back first
   BSE_HIP(hipMemGetInfo(&freeb, &totalb));
   const bool has_budget = d->tau_budget_bytes > 0;
   // without an explicit budget, keep room for a 64-vector Davidson subspace

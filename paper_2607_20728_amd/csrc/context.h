@@ -41,6 +41,7 @@ struct bse_ctx {
   double2* compact = nullptr;
   long compact_grids = 0;
   std::vector<bsex::DevBuf> allocs;
+  std::vector<bsex::DevBuf> pool;  // released blocks kept for reuse
   // device system data
   int *idx_p = nullptr, *idx_m = nullptr;
   double* T = nullptr;        // [npw] |G|^2/2
@@ -110,6 +111,8 @@ int ctx_alloc_t(bse_ctx* c, T** p, size_t count) {
   return ctx_alloc(c, reinterpret_cast<void**>(p), sizeof(T) * count);
 }
 void ctx_release(bse_ctx* c, void* p);
+// return the cached released blocks to the device (before sizing caches)
+void ctx_pool_flush(bse_ctx* c);
 
 // profiling
 struct PhaseScope {

@@ -10,11 +10,39 @@ namespace bsex {
 // ---------------------------------------------------------------------------
 // allocation and profiling helpers
 // ---------------------------------------------------------------------------
+// Device memory of a context.  Released blocks go to a per-context cache and
+// are handed out again (smallest block that fits, at most twice the request),
+// so the solvers' scratch does not call hipMalloc/hipFree in steady state:
+// hipFree waits for the whole device, which would serialise the streams of a
+// batch.  Blocks are reused on the context's own stream only, so stream order
+// keeps every earlier use of a block ahead of its next one.  The cache is
+// returned to the device when an allocation fails, and at bse_free.
 int ctx_alloc(bse_ctx* c, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
+  long best = -1;
+  for (size_t i = 0; i < c->pool.size(); ++i) {
+    const size_t b = c->pool[i].bytes;
+    if (b >= bytes && b <= 2 * bytes + (1u << 20) &&
+        (best < 0 || b < c->pool[(size_t)best].bytes))
+      best = (long)i;
+  }
+  if (best >= 0) {
+    const DevBuf d = c->pool[(size_t)best];
+    c->pool.erase(c->pool.begin() + best);
+    c->allocs.push_back(d);
+    *p = d.p;
+    return BSE_OK;
+  }
   void* q = nullptr;
   hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess && !c->pool.empty()) {
+    (void)hipGetLastError();
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    for (auto& b : c->pool) (void)hipFree(b.p);
+    c->pool.clear();
+    e = hipMalloc(&q, bytes);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(BSE_ENOMEM, "device allocation of %zu bytes failed (%s)", bytes,
@@ -25,6 +53,13 @@ int ctx_alloc(bse_ctx* c, void** p, size_t bytes) {
   return BSE_OK;
 }
 
+void ctx_pool_flush(bse_ctx* c) {
+  if (c->pool.empty()) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  for (auto& b : c->pool) (void)hipFree(b.p);
+  c->pool.clear();
+}
+
 void ctx_release(bse_ctx* c, void* p) {
   if (!p) return;
   if (!c->graphs.empty() &&
@@ -32,7 +67,7 @@ void ctx_release(bse_ctx* c, void* p) {
     graphs_destroy(c);
   for (size_t i = 0; i < c->allocs.size(); ++i)
     if (c->allocs[i].p == p) {
-      (void)hipFree(p);
+      c->pool.push_back(c->allocs[i]);
       c->allocs.erase(c->allocs.begin() + i);
       return;
     }
