@@ -175,3 +175,33 @@ def test_end_to_end_c1_library_ground_state():
     assert np.abs(F - Fo).max() < 1e-5
     print(f"omega diff {abs(w[0]-wo[0]):.2e}  force diff {np.abs(F - Fo).max():.2e}")
     ctx.free()
+
+
+def test_full_size_c2_properties():
+    """At the benchmark's own size (N_v = 432, 72^3, 21,079 plane waves, in the
+    launch configuration bench.py times: whole FP32 cache, FP64 cache beside
+    it, 8-vector blocks), where the oracle cannot build the ground state:
+    the operator is symmetric, maps occupied directions to zero, and the FP32
+    and FP64 applies agree to the FP32 bound."""
+    print("[gpu] full-size C2 properties", flush=True)
+    cfg = synth.get_config("c2")
+    n_pw = bsex.basis_size(cfg.cell, cfg.grid, cfg.ecut)
+    d = synth.make_system(cfg, n_pw, n_trial=8)
+    ctx = bsex.init_from_synth(d, n_extra=8, precision=bsex.MIXED)
+    X = _cuda(d["trial"])
+    Ym = bsex.apply(ctx, X)
+    bsex.set_precision(ctx, bsex.FP64)
+    Yd = bsex.apply(ctx, X)
+    rel = float((Ym - Yd).norm() / Yd.norm())
+    print(f"  mixed vs FP64 rel {rel:.2e}")
+    assert rel < 2e-6
+    # symmetry <x_i, A x_j> = <x_j, A x_i> (FP64)
+    G = torch.einsum("ivp,jvp->ij", X, Yd)
+    asym = float((G - G.T).abs().max() / G.abs().max())
+    print(f"  asymmetry {asym:.2e}")
+    assert asym < 1e-12
+    # occupied directions map to zero: X = Phi (one trial vector per band set)
+    phi, _ = bsex.get_orbitals(ctx)
+    Yp = bsex.apply(ctx, phi.unsqueeze(0).contiguous())
+    assert float(Yp.abs().max()) < 1e-12 * float(Yd.abs().max())
+    ctx.free()
