@@ -103,7 +103,9 @@ typedef struct {
   int32_t precision;          /* BSE_FP64 or BSE_MIXED                            */
   int32_t tau_policy;         /* BSE_TAU_*: cache W(phi_v phi_v') or rebuild it   */
   int64_t tau_budget_bytes;   /* cap on tau cache bytes (FP32 and FP64 caches together);
-                                 0 = auto, keeping ~14 GB for solver work; > 0 also drops
+                                 0 = auto, keeping 4 GB + 200 trial vectors of device
+                                 memory for solver work (18.6 GB at N_v 432,
+                                 N_pw 21,079); > 0 also drops
                                  that reserve to 1 GB (apply-only use).  BSE_MIXED needs
                                  the whole FP32 cache (ENOMEM otherwise) and gives the
                                  FP64 cache what is left. */
@@ -122,6 +124,12 @@ int32_t bse_abi_version(void);
 
 /* Thread-local message of the last failing call ("" when none). */
 const char *bse_last_error(void);
+
+/* Optional: start the HIP runtime on the current device and load the
+ * library's device code there (one tiny kernel launch, 256 bytes allocated
+ * and freed), so that this one-time cost stays out of later timed calls.
+ * EHIP on a runtime error. */
+int bse_warm_up(void);
 
 /* Host-only basis queries (no device needed).  n_pw of the sphere; EINVAL if
  * the sphere does not fit the grid. */
@@ -151,6 +159,10 @@ typedef struct {
   int32_t precision;          /* precision the context was built with            */
   int32_t active_precision;   /* precision bse_apply uses now                    */
   int64_t tau_bytes_f32;      /* bytes of the FP32 tau cache (BSE_MIXED), else 0 */
+  int32_t gs_sweeps;          /* filter sweeps of the ground-state solve (0: orbitals supplied) */
+  double t_ground_state_ms;   /* wall time of bse_init_system: ground-state solve */
+  double t_tau_ms;            /*   sizing, allocation and build of the tau caches */
+  double t_init_ms;           /*   the whole call                                 */
 } bse_info;
 
 int bse_get_info(bse_ctx *ctx, bse_info *info);

@@ -22,7 +22,7 @@ K_D, K_1E, K_1D_BARE, K_1D_PDEP, K_ALL = 1, 2, 4, 8, 15
 FP64, MIXED = 0, 1
 TAU_AUTO, TAU_CACHE, TAU_REBUILD = 0, 1, 2
 
-SYMBOLS = ("bse_abi_version", "bse_last_error", "bse_basis_size", "bse_basis_gvectors",
+SYMBOLS = ("bse_abi_version", "bse_last_error", "bse_warm_up", "bse_basis_size", "bse_basis_gvectors",
            "bse_init_system", "bse_get_info", "bse_get_orbitals", "bse_apply",
            "bse_davidson", "bse_u_vector", "bse_zvector_solve", "bse_forces",
            "bse_set_precision", "bse_set_profiling", "bse_get_phase_times",
@@ -59,7 +59,9 @@ class Info(C.Structure):
                 ("tau_blocks", C.c_int64), ("tau_blocks_cached", C.c_int64),
                 ("tau_bytes", C.c_int64), ("gs_resid", C.c_double), ("ks_gap", C.c_double),
                 ("precision", C.c_int32), ("active_precision", C.c_int32),
-                ("tau_bytes_f32", C.c_int64)]
+                ("tau_bytes_f32", C.c_int64), ("gs_sweeps", C.c_int32),
+                ("t_ground_state_ms", C.c_double), ("t_tau_ms", C.c_double),
+                ("t_init_ms", C.c_double)]
 
 
 class BatchOpts(C.Structure):
@@ -304,7 +306,9 @@ def get_info(ctx):
                 tau_policy=i.tau_policy, tau_blocks=i.tau_blocks,
                 tau_blocks_cached=i.tau_blocks_cached, tau_bytes=i.tau_bytes,
                 gs_resid=i.gs_resid, ks_gap=i.ks_gap, precision=i.precision,
-                active_precision=i.active_precision, tau_bytes_f32=i.tau_bytes_f32)
+                active_precision=i.active_precision, tau_bytes_f32=i.tau_bytes_f32,
+                gs_sweeps=i.gs_sweeps, t_ground_state_ms=i.t_ground_state_ms,
+                t_tau_ms=i.t_tau_ms, t_init_ms=i.t_init_ms)
 
 
 def get_orbitals(ctx, n=None):
@@ -488,6 +492,11 @@ def learned_features(ctx, Xs, Zref=None, two_level=False):
 def set_precision(ctx, precision):
     """bse_set_precision: FP64 or MIXED for the applies of a MIXED context."""
     _check(lib().bse_set_precision(ctx.h, int(precision)))
+
+
+def warm_up():
+    """bse_warm_up: HIP runtime start and device-code load, once per process."""
+    _check(lib().bse_warm_up())
 
 
 def set_profiling(ctx, on=True):

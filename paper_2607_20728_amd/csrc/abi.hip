@@ -128,8 +128,10 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   ctx_pool_flush(c);  // scratch of the ground-state solve goes back first
   BSE_HIP(hipMemGetInfo(&freeb, &totalb));
   const bool has_budget = d->tau_budget_bytes > 0;
-  // without an explicit budget, keep room for a 64-vector Davidson subspace
-  const double reserve = has_budget ? 1.0e9 : 4.0e9 + 2.0 * 72 * 8.0 * c->nv * npw;
+  // without an explicit budget, keep room for the solvers: a 64-vector
+  // Davidson subspace and its products, the blocks beside them, graph
+  // staging and the caller's own vectors, about 200 trial vectors in all
+  const double reserve = has_budget ? 1.0e9 : 4.0e9 + 200 * 8.0 * c->nv * npw;
   const long small_tile = std::min(c->nblk, 4L);
   double budget_left = has_budget ? (double)d->tau_budget_bytes : 0.0;
   // rebuild tiles: ~6% of the device, or, for a budgeted context (batches),
@@ -202,6 +204,10 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   else if (need_k1d)
     c->tau_policy = (c->nblk_cached == 0) ? BSE_TAU_REBUILD : BSE_TAU_AUTO;
   return BSE_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 int init_impl(const bse_system_desc* d, bse_ctx* c) {
@@ -295,7 +301,10 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
   } else {
     const int extra = d->n_extra > 0 ? d->n_extra : 8;
     const int want = (int)std::min<long>(npw, (long)c->nv + extra);
+    const auto t0 = std::chrono::steady_clock::now();
     BSE_TRY(ground_state(c, want, c->gs_tol));
+    BSE_HIP(hipStreamSynchronize(c->st));
+    c->t_gs_ms = ms_since(t0);
   }
   if (c->norb > c->nv) {
     c->ks_gap = c->eps_h[c->nv] - c->eps_h[c->nv - 1];
@@ -314,9 +323,12 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
     BSE_TRY(to_f32(c->Vr, c->Vr_f, nr, c->st));
     BSE_TRY(to_f32(c->vc, c->vc_f, nr, c->st));
   }
+  BSE_HIP(hipStreamSynchronize(c->st));
+  const auto t1 = std::chrono::steady_clock::now();
   BSE_TRY(plan_tau(c, d));
   c->active = c->precision;
   BSE_HIP(hipStreamSynchronize(c->st));
+  c->t_tau_ms = ms_since(t1);
   return BSE_OK;
 }
 
@@ -343,6 +355,16 @@ extern "C" {
 int32_t bse_abi_version(void) { return BSEX_ABI_VERSION; }
 
 const char* bse_last_error(void) { return last_error(); }
+
+int bse_warm_up(void) {
+  double* p = nullptr;
+  BSE_HIP(hipMalloc(&p, 256));
+  int rc = zero_fill(p, 32, nullptr);
+  if (rc == BSE_OK && hipStreamSynchronize(nullptr) != hipSuccess)
+    rc = fail(BSE_EHIP, "warm-up launch failed");
+  (void)hipFree(p);
+  return rc;
+}
 
 int bse_basis_size(const double cell[3], const int32_t grid[3], double ecut, int32_t* n_pw) {
   if (!cell || !grid || !n_pw) return fail(BSE_EINVAL, "NULL argument");
@@ -384,7 +406,9 @@ int bse_init_system(const bse_system_desc* desc, bse_ctx** out) {
   } catch (...) {
     return fail(BSE_ENOMEM, "host allocation failed");
   }
+  const auto t0 = std::chrono::steady_clock::now();
   int rc = guarded(nullptr, [&] { return init_impl(desc, c); });
+  c->t_init_ms = ms_since(t0);
   if (rc != BSE_OK) {
     std::string keep = last_error();
     ctx_destroy(c);
@@ -411,6 +435,10 @@ int bse_get_info(bse_ctx* c, bse_info* info) {
   info->tau_bytes_f32 = c->tau_f ? (int64_t)c->nblk * 64 * c->basis.nr * 4 : 0;
   info->gs_resid = c->gs_resid;
   info->ks_gap = c->ks_gap;
+  info->gs_sweeps = c->gs_sweeps;
+  info->t_ground_state_ms = c->t_gs_ms;
+  info->t_tau_ms = c->t_tau_ms;
+  info->t_init_ms = c->t_init_ms;
   return BSE_OK;
 }
 

@@ -114,4 +114,7 @@ long dgemm_tall_work(long M, long N, long K);
 int host_syev(int n, double* A, double* w);
 // Lower Cholesky in place; returns non-zero when not positive definite.
 int host_cholesky(int n, double* A);
+// in-place inverse of a lower-triangular L (row-major, upper part zero);
+// returns nonzero on a zero or non-finite diagonal
+int host_trinv_lower(int n, double* L);
 }  // namespace bsex

@@ -33,6 +33,8 @@ struct bse_ctx {
   bsex::Basis basis;
   int nv = 0, nvh = 0, npdep = 0, nsites = 0, kmask = 0, norb = 0, n_extra = 0;
   double scissor = 0, spin = 2, gap_min = 0, gs_tol = 1e-10, gs_resid = -1, ks_gap = -1;
+  int gs_sweeps = 0;
+  double t_gs_ms = 0, t_tau_ms = 0, t_init_ms = 0;  // wall time of the init stages
   hipStream_t st = nullptr;
   bsex::FftPlan fft;
   bsex::SphereMap map{};     // sphere <-> full grid

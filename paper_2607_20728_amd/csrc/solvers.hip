@@ -193,6 +193,48 @@ int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len,
   return (int)kk;
 }
 
+// Orthonormalise the k rows of W[k][len] in place by Cholesky QR, done twice:
+// rows normalised, then W <- L^{-1} W with W W^T = L L^T.  Returns k; returns
+// 0, with W still spanning the same space, when the normalised Gram matrix is
+// too ill-conditioned for it (smallest Cholesky pivot below 1e-6 of the
+// largest, the loss of orthogonality of one pass then being ~1e-4 or worse),
+// so that the caller can fall back to orth_block; negative on error.
+static int chol_orth(bse_ctx* c, double* W, long k, long len, double* tmp) {
+  if (k <= 0) return 0;
+  PhaseScope ps(c, PH_SOLVER);
+  DVec sm(c);
+  if (sm.alloc((size_t)k * k + 2 * (size_t)k + 16) != BSE_OK) return -BSE_ENOMEM;
+  double* Gd = sm.p;
+  double* vec = sm.p + (size_t)k * k;
+  std::vector<double> nrm;
+  if (dots_host(c, W, W, k, len, vec, nrm) != BSE_OK) return -BSE_EHIP;
+  std::vector<double> sc(k);
+  for (long i = 0; i < k; ++i) {
+    if (!(nrm[i] > 0.0)) return 0;
+    sc[i] = 1.0 / std::sqrt(nrm[i]);
+  }
+  if (to_dev(c, sc.data(), vec, k) != BSE_OK) return -BSE_EHIP;
+  if (row_scale(vec, W, k, len, c->st) != BSE_OK) return -BSE_EHIP;
+  std::vector<double> G((size_t)k * k);
+  for (int pass = 0; pass < 2; ++pass) {
+    if (gram_tall(c, W, k, W, k, len, Gd) != BSE_OK) return -BSE_EHIP;
+    if (to_host(c, Gd, G.data(), G.size()) != BSE_OK) return -BSE_EHIP;
+    if (host_cholesky((int)k, G.data())) return 0;
+    double lmin = G[0], lmax = G[0];
+    for (long i = 0; i < k; ++i) {
+      lmin = std::min(lmin, G[(size_t)i * k + i]);
+      lmax = std::max(lmax, G[(size_t)i * k + i]);
+    }
+    if (lmin < 1e-6 * lmax) return 0;
+    if (host_trinv_lower((int)k, G.data())) return 0;
+    if (to_dev(c, G.data(), Gd, G.size()) != BSE_OK) return -BSE_EHIP;
+    if (dgemm(0, 0, k, len, k, 1.0, Gd, k, W, len, 0.0, tmp, len, c->st) != BSE_OK)
+      return -BSE_EHIP;
+    if (copy_dev(c, tmp, W, (size_t)k * len) != BSE_OK) return -BSE_EHIP;
+  }
+  return (int)k;
+}
+
 // ---------------------------------------------------------------------------
 // Davidson (the paper names no eigensolver; its target is the lowest
 // eigenpairs of P_c M P_c)
@@ -915,7 +957,10 @@ int ground_state(bse_ctx* c, int n_want, double tol) {
   };
   std::vector<double> theta(ns);
   auto rayleigh_ritz = [&]() -> int {
-    int k = orth_block(c, nullptr, 0, X.p, nsl, npw, Z.p, 2, 1e-12);
+    // Cholesky QR once the filtered basis is well conditioned; the Gram
+    // eigen-decomposition (which can drop directions) otherwise
+    int k = chol_orth(c, X.p, nsl, npw, Z.p);
+    if (k == 0) k = orth_block(c, nullptr, 0, X.p, nsl, npw, Z.p, 2, 1e-12);
     if (k < 0) return -k;
     if (k < ns) return fail(BSE_EINVAL, "ground state: subspace collapsed (%d of %d)", k, ns);
     BSE_TRY(Happly(X.p, HX.p, 0.0));
@@ -969,6 +1014,7 @@ int ground_state(bse_ctx* c, int n_want, double tol) {
     }
     std::swap(X.p, Y.p);
     BSE_TRY(rayleigh_ritz());
+    ++c->gs_sweeps;
   }
   c->gs_resid = resid;
   if (resid > tol) return fail(BSE_ENOCONV, "ground state: residual %.3e above %.3e", resid, tol);

@@ -123,6 +123,8 @@ def test_ground_state_solver_c1():
     ctx = bsex.init_from_synth(d, n_extra=8, gs_tol=1e-10)
     info = bsex.get_info(ctx)
     assert info["gs_resid"] <= 1e-10
+    assert info["gs_sweeps"] > 0
+    assert 0 < info["t_ground_state_ms"] <= info["t_init_ms"]
     phi, eps = bsex.get_orbitals(ctx, info["n_orb"])
     n = info["n_orb"]
     assert np.abs(eps - S.eps_all[:n]).max() < 1e-10
