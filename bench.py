@@ -245,6 +245,7 @@ def time_to_force(args):
                             u_z=round(t3 - t2, 2), forces=round(t4 - t3, 3)),
                init_s=dict(ground_state=round(info["t_ground_state_ms"] / 1e3, 2),
                            gs_sweeps=info["gs_sweeps"], tau=round(info["t_tau_ms"] / 1e3, 2),
+                           tau_alloc=round(info["t_tau_alloc_ms"] / 1e3, 2),
                            library=round(info["t_init_ms"] / 1e3, 2)),
                process_start_s=round(t_start, 2),
                davidson=dict(iters=ds["iters"], applies=ds["applies"],

@@ -162,6 +162,7 @@ typedef struct {
   int32_t gs_sweeps;          /* filter sweeps of the ground-state solve (0: orbitals supplied) */
   double t_ground_state_ms;   /* wall time of bse_init_system: ground-state solve */
   double t_tau_ms;            /*   sizing, allocation and build of the tau caches */
+  double t_tau_alloc_ms;      /*     of which the allocation of the caches      */
   double t_init_ms;           /*   the whole call                                 */
 } bse_info;
 

@@ -61,7 +61,7 @@ class Info(C.Structure):
                 ("precision", C.c_int32), ("active_precision", C.c_int32),
                 ("tau_bytes_f32", C.c_int64), ("gs_sweeps", C.c_int32),
                 ("t_ground_state_ms", C.c_double), ("t_tau_ms", C.c_double),
-                ("t_init_ms", C.c_double)]
+                ("t_tau_alloc_ms", C.c_double), ("t_init_ms", C.c_double)]
 
 
 class BatchOpts(C.Structure):
@@ -308,7 +308,7 @@ def get_info(ctx):
                 gs_resid=i.gs_resid, ks_gap=i.ks_gap, precision=i.precision,
                 active_precision=i.active_precision, tau_bytes_f32=i.tau_bytes_f32,
                 gs_sweeps=i.gs_sweeps, t_ground_state_ms=i.t_ground_state_ms,
-                t_tau_ms=i.t_tau_ms, t_init_ms=i.t_init_ms)
+                t_tau_ms=i.t_tau_ms, t_tau_alloc_ms=i.t_tau_alloc_ms, t_init_ms=i.t_init_ms)
 
 
 def get_orbitals(ctx, n=None):

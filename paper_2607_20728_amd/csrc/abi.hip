@@ -88,6 +88,10 @@ int validate(const bse_system_desc* d) {
   return BSE_OK;
 }
 
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   const long nr = c->basis.nr, npw = c->basis.npw;
   const long nB = (c->nv + 7) / 8;
@@ -147,7 +151,9 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
     if (fbytes > cap)
       return fail(BSE_ENOMEM, "FP32 tau cache needs %.1f GB, %.1f GB free", fbytes / 1e9,
                   (double)freeb / 1e9);
+    const auto ta = std::chrono::steady_clock::now();
     BSE_TRY(ctx_alloc_t(c, &c->tau_f, (size_t)c->nblk * 64 * nr));
+    c->t_tau_alloc_ms += ms_since(ta);
     budget_left -= fbytes;
     BSE_HIP(hipMemGetInfo(&freeb, &totalb));
   }
@@ -185,7 +191,11 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
     ncache = std::min(fit, c->nblk);
   }
   c->nblk_cached = ncache;
-  if (ncache > 0) BSE_TRY(ctx_alloc_t(c, &c->tau_cache, (size_t)ncache * 64 * nr));
+  if (ncache > 0) {
+    const auto ta = std::chrono::steady_clock::now();
+    BSE_TRY(ctx_alloc_t(c, &c->tau_cache, (size_t)ncache * 64 * nr));
+    c->t_tau_alloc_ms += ms_since(ta);
+  }
   // one build feeds both caches: blocks below ncache go to the FP64 cache,
   // every block to the FP32 cache of a mixed context
   const long nbuild = mixed ? c->nblk : ncache;
@@ -206,9 +216,6 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   return BSE_OK;
 }
 
-double ms_since(std::chrono::steady_clock::time_point t0) {
-  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-}
 
 int init_impl(const bse_system_desc* d, bse_ctx* c) {
   BSE_TRY(validate(d));
@@ -438,6 +445,7 @@ int bse_get_info(bse_ctx* c, bse_info* info) {
   info->gs_sweeps = c->gs_sweeps;
   info->t_ground_state_ms = c->t_gs_ms;
   info->t_tau_ms = c->t_tau_ms;
+  info->t_tau_alloc_ms = c->t_tau_alloc_ms;
   info->t_init_ms = c->t_init_ms;
   return BSE_OK;
 }

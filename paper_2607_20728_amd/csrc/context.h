@@ -34,7 +34,7 @@ struct bse_ctx {
   int nv = 0, nvh = 0, npdep = 0, nsites = 0, kmask = 0, norb = 0, n_extra = 0;
   double scissor = 0, spin = 2, gap_min = 0, gs_tol = 1e-10, gs_resid = -1, ks_gap = -1;
   int gs_sweeps = 0;
-  double t_gs_ms = 0, t_tau_ms = 0, t_init_ms = 0;  // wall time of the init stages
+  double t_gs_ms = 0, t_tau_ms = 0, t_tau_alloc_ms = 0, t_init_ms = 0;  // init stages, wall
   hipStream_t st = nullptr;
   bsex::FftPlan fft;
   bsex::SphereMap map{};     // sphere <-> full grid
@@ -93,6 +93,9 @@ struct bse_ctx {
   // on the staging buffers gX -> gY; graph_bufs are the context buffers the
   // graphs reference: releasing any of them destroys every graph first
   bool use_graph = false;
+  // the vectors handed to the block apply already lie in the P_c space (the
+  // solvers' own subspace vectors): the input projection is skipped
+  bool in_pc = false;
   hipStream_t cap_st = nullptr;  // private stream the graphs are captured on
   double *gX = nullptr, *gY = nullptr;
   std::vector<std::pair<int, hipGraphExec_t>> graphs;

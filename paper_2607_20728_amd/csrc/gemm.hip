@@ -1,9 +1,14 @@
 // FP64 GEMM on the CDNA matrix cores (v_mfma_f64_16x16x4f64).
 //
-// Workgroup tile 64 x 64, K step 16 staged through LDS; four waves each own
-// a 32 x 32 quarter as 2 x 2 MFMA tiles.  Operand layout of the 16x16x4 f64
-// instruction: A[i][k] and B[k][j] from lane i + 16 k (i, j < 16, k < 4);
-// the four accumulator values of lane j + 16 q are C[q + 4 t][j], t < 4.
+// Workgroup tile BM x 64, K step 16 staged through LDS (the next step's
+// tiles are held in registers meanwhile), four waves.  BM = 64:
+// the waves own 32 x 32 quarters as 2 x 2 MFMA tiles.  BM = 16, for outputs
+// of at most 16 rows (the solvers' products of a few vectors with a whole
+// subspace): the waves own the four 16 x 16 tiles side by side, so no matrix
+// core work or LDS is spent on 48 rows of zeros.  Operand layout of the
+// 16x16x4 f64 instruction: A[i][k] and B[k][j] from lane i + 16 k (i, j <
+// 16, k < 4); the four accumulator values of lane j + 16 q are C[q + 4 t][j],
+// t < 4.
 //
 // The tall variant splits a long K across workgroups (C = A B^T with small
 // M, N) and sums the partial tiles in a fixed order, so results repeat
@@ -18,86 +23,115 @@ namespace {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BN = 64, BK = 16;
 
-template <int TA, int TB>
+// rows of the workgroup tile for an M-row output
+inline int bm_for(long M) { return M <= 16 ? 16 : 64; }
+
+template <int TA, int TB, int BM>
 __global__ __launch_bounds__(256) void k_dgemm(long M, long N, long K, double alpha,
                                                const double* __restrict__ A, long lda,
                                                const double* __restrict__ B, long ldb,
                                                double beta, double* __restrict__ C, long ldc,
                                                long k_chunk, long c_split_stride) {
+  constexpr int WGM = BM == 64 ? 2 : 1;  // waves along M
+  constexpr int WGN = 4 / WGM;           // waves along N
+  constexpr int TM = BM / (16 * WGM);    // MFMA tiles per wave along M
+  constexpr int TN = BN / (16 * WGN);    // and along N
   __shared__ double As[BK][BM + 1];
   __shared__ double Bs[BK][BN + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
   const long m0 = (long)blockIdx.y * BM;
   const long n0 = (long)blockIdx.x * BN;
   const long kb = (long)blockIdx.z * k_chunk;
   const long ke = min(K, kb + k_chunk);
-  double4_t acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  double4_t acc[TM][TN];
+  for (int a = 0; a < TM; ++a)
+    for (int b = 0; b < TN; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-  for (long k0 = kb; k0 < ke; k0 += BK) {
-    // A tile: op(A)[m0 + m][k0 + k]
-    for (int e = tid; e < BM * BK; e += 256) {
-      int m, k;
-      if (TA) {  // A[k][m], m contiguous
-        m = e % BM;
-        k = e / BM;
-      } else {   // A[m][k], k contiguous
-        k = e % BK;
-        m = e / BK;
-      }
-      const long gm = m0 + m, gk = k0 + k;
-      double v = 0.0;
-      if (gm < M && gk < ke) v = TA ? A[gk * lda + gm] : A[gm * lda + gk];
-      As[k][m] = v;
+  // element e of a thread's share of the A tile is (m, k) = a_mk(e), of the
+  // B tile (n, k) = b_nk(e); the next K step's tiles are loaded into
+  // registers while the matrix cores work on the current one
+  constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
+  auto a_mk = [&](int e, int& m, int& k) {
+    if (TA) {  // A[k][m], m contiguous
+      m = e % BM;
+      k = e / BM;
+    } else {   // A[m][k], k contiguous
+      k = e % BK;
+      m = e / BK;
     }
-    // B tile: op(B)[k0 + k][n0 + n]
-    for (int e = tid; e < BN * BK; e += 256) {
+  };
+  auto b_nk = [&](int e, int& n, int& k) {
+    if (TB) {  // B[n][k], k contiguous
+      k = e % BK;
+      n = e / BK;
+    } else {   // B[k][n], n contiguous
+      n = e % BN;
+      k = e / BN;
+    }
+  };
+  double ra[NA], rb[NB];
+  auto fetch = [&](long k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      int m, k;
+      a_mk(tid + 256 * q, m, k);
+      const long gm = m0 + m, gk = k0 + k;
+      ra[q] = (gm < M && gk < ke) ? (TA ? A[gk * lda + gm] : A[gm * lda + gk]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
       int n, k;
-      if (TB) {  // B[n][k], k contiguous
-        k = e % BK;
-        n = e / BK;
-      } else {   // B[k][n], n contiguous
-        n = e % BN;
-        k = e / BN;
-      }
+      b_nk(tid + 256 * q, n, k);
       const long gn = n0 + n, gk = k0 + k;
-      double v = 0.0;
-      if (gn < N && gk < ke) v = TB ? B[gn * ldb + gk] : B[gk * ldb + gn];
-      Bs[k][n] = v;
+      rb[q] = (gn < N && gk < ke) ? (TB ? B[gn * ldb + gk] : B[gk * ldb + gn]) : 0.0;
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (long k0 = kb; k0 < ke; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      int m, k;
+      a_mk(tid + 256 * q, m, k);
+      As[k][m] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      int n, k;
+      b_nk(tid + 256 * q, n, k);
+      Bs[k][n] = rb[q];
     }
     __syncthreads();
+    if (k0 + BK < ke) fetch(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      double a[2], b[2];
+      double a[TM], b[TN];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t] = As[kr][wm * 32 + t * 16 + (lane & 15)];
-        b[t] = Bs[kr][wn * 32 + t * 16 + (lane & 15)];
-      }
+      for (int t = 0; t < TM; ++t) a[t] = As[kr][wm * 16 * TM + t * 16 + (lane & 15)];
 #pragma unroll
-      for (int ta = 0; ta < 2; ++ta)
+      for (int t = 0; t < TN; ++t) b[t] = Bs[kr][wn * 16 * TN + t * 16 + (lane & 15)];
 #pragma unroll
-        for (int tb = 0; tb < 2; ++tb)
+      for (int ta = 0; ta < TM; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < TN; ++tb)
           acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
     }
     __syncthreads();
   }
   double* Cz = C + (long)blockIdx.z * c_split_stride;
 #pragma unroll
-  for (int ta = 0; ta < 2; ++ta)
+  for (int ta = 0; ta < TM; ++ta)
 #pragma unroll
-    for (int tb = 0; tb < 2; ++tb)
+    for (int tb = 0; tb < TN; ++tb)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const long gm = m0 + wm * 32 + ta * 16 + (lane >> 4) + 4 * t;
-        const long gn = n0 + wn * 32 + tb * 16 + (lane & 15);
+        const long gm = m0 + wm * 16 * TM + ta * 16 + (lane >> 4) + 4 * t;
+        const long gn = n0 + wn * 16 * TN + tb * 16 + (lane & 15);
         if (gm < M && gn < N) {
           double v = alpha * acc[ta][tb][t];
           if (beta != 0.0) v += beta * Cz[gm * ldc + gn];
@@ -121,25 +155,47 @@ __global__ void k_reduce_split(long M, long N, int nz, const double* __restrict_
 
 }  // namespace
 
+namespace {
+
+void launch(int ta, int tb, int bm, dim3 grid, hipStream_t st, long M, long N, long K,
+            double alpha, const double* A, long lda, const double* B, long ldb, double beta,
+            double* C, long ldc, long kc, long cstride) {
+#define L3(TA_, TB_, BM_)                                                                      \
+  hipLaunchKernelGGL((k_dgemm<TA_, TB_, BM_>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, \
+                     B, ldb, beta, C, ldc, kc, cstride)
+#define L2(TA_, TB_)    \
+  if (bm == 16)         \
+    L3(TA_, TB_, 16);   \
+  else                  \
+    L3(TA_, TB_, 64)
+  if (!ta && !tb)
+    L2(0, 0);
+  else if (!ta && tb)
+    L2(0, 1);
+  else if (ta && !tb)
+    L2(1, 0);
+  else
+    L2(1, 1);
+#undef L2
+#undef L3
+}
+
+long tiles_of(long M, long N) {
+  const long bm = bm_for(M);
+  return ((M + bm - 1) / bm) * ((N + BN - 1) / BN);
+}
+
+}  // namespace
+
 int dgemm(int ta, int tb, long M, long N, long K, double alpha, const double* A, long lda,
           const double* B, long ldb, double beta, double* C, long ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return BSE_OK;
-  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), 1);
+  const int bm = bm_for(M);
+  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + bm - 1) / bm), 1);
   if (grid.y > 65535) return fail(BSE_EINVAL, "dgemm: M too large for the grid");
   const long kc = K > 0 ? K : 1;
   if (K <= 0) alpha = 0.0;
-#define LAUNCH(TA_, TB_)                                                                    \
-  hipLaunchKernelGGL((k_dgemm<TA_, TB_>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, \
-                     ldb, beta, C, ldc, kc, 0L)
-  if (!ta && !tb)
-    LAUNCH(0, 0);
-  else if (!ta && tb)
-    LAUNCH(0, 1);
-  else if (ta && !tb)
-    LAUNCH(1, 0);
-  else
-    LAUNCH(1, 1);
-#undef LAUNCH
+  launch(ta, tb, bm, grid, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kc, 0L);
   BSE_HIP(hipGetLastError());
   return BSE_OK;
 }
@@ -148,7 +204,7 @@ int dgemm(int ta, int tb, long M, long N, long K, double alpha, const double* A,
 // ~4096 workgroups (16 per CU, so global-load latency is hidden by occupancy)
 // with K chunks of at least 1024
 static long k_splits(long M, long N, long K) {
-  const long tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  const long tiles = tiles_of(M, N);
   if (tiles >= 2048 || K < 2048) return 1;
   long s = std::min((K + 1023) / 1024, std::max(1L, 4096 / tiles));
   return std::max(s, 1L);
@@ -168,20 +224,10 @@ int dgemm_ws(int ta, int tb, long M, long N, long K, double alpha, const double*
   long kc = (K + s - 1) / s;
   kc = ((kc + BK - 1) / BK) * BK;
   s = (K + kc - 1) / kc;
-  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)s);
+  const int bm = bm_for(M);
+  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + bm - 1) / bm), (unsigned)s);
   if (grid.y > 65535) return fail(BSE_EINVAL, "dgemm: M too large for the grid");
-#define LAUNCH(TA_, TB_)                                                                       \
-  hipLaunchKernelGGL((k_dgemm<TA_, TB_>), grid, dim3(256), 0, st, M, N, K, 1.0, A, lda, B, ldb, \
-                     0.0, work, N, kc, M * N)
-  if (!ta && !tb)
-    LAUNCH(0, 0);
-  else if (!ta && tb)
-    LAUNCH(0, 1);
-  else if (ta && !tb)
-    LAUNCH(1, 0);
-  else
-    LAUNCH(1, 1);
-#undef LAUNCH
+  launch(ta, tb, bm, grid, st, M, N, K, 1.0, A, lda, B, ldb, 0.0, work, N, kc, M * N);
   BSE_HIP(hipGetLastError());
   const long tot = M * N;
   hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,
@@ -190,10 +236,13 @@ int dgemm_ws(int ta, int tb, long M, long N, long K, double alpha, const double*
   return BSE_OK;
 }
 
+// K splits of a product with a long K: about TALL_TARGET workgroups in all,
+// K chunks of at least 1024
+constexpr long TALL_TARGET = 1024;
 static long tall_splits(long M, long N, long K) {
-  const long tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  long s = 1024 / (tiles > 0 ? tiles : 1);
-  const long maxs = (K + 4095) / 4096;
+  const long tiles = tiles_of(M, N);
+  long s = TALL_TARGET / (tiles > 0 ? tiles : 1);
+  const long maxs = (K + 1023) / 1024;
   if (s > maxs) s = maxs;
   if (s < 1) s = 1;
   return s;
@@ -212,9 +261,9 @@ int dgemm_tall(long M, long N, long K, double alpha, const double* A, long lda, 
   if (kc < BK) kc = BK;
   s = (K + kc - 1) / kc;
   if (s < 1) s = 1;
-  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)s);
-  hipLaunchKernelGGL((k_dgemm<0, 1>), grid, dim3(256), 0, st, M, N, K, 1.0, A, lda, B, ldb, 0.0,
-                     work, N, kc, M * N);
+  const int bm = bm_for(M);
+  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + bm - 1) / bm), (unsigned)s);
+  launch(0, 1, bm, grid, st, M, N, K, 1.0, A, lda, B, ldb, 0.0, work, N, kc, M * N);
   BSE_HIP(hipGetLastError());
   const long tot = M * N;
   hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,

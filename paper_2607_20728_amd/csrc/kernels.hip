@@ -774,6 +774,17 @@ int to_f32(const double* x, float* y, long n, hipStream_t st) {
   return BSE_OK;
 }
 
+__global__ void k_to_f64(const float* __restrict__ x, double* __restrict__ y, long n) {
+  for (long e = gtid(); e < n; e += gstride()) y[e] = (double)x[e];
+}
+
+int to_f64(const float* x, double* y, long n, hipStream_t st) {
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_to_f64, dim3(nblocks(n)), dim3(TPB), 0, st, x, y, n);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
 int combine(const double2* a, const double2* phir, const double* V, const double2* vdrho,
             const double2* y, double2* out, int nv, int nb, long nr, double s, int with_v,
             hipStream_t st) {

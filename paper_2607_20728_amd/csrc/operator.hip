@@ -295,8 +295,9 @@ int ensure_ygrid(bse_ctx* c) {
 // Y = P_c (D + s K1e - K1d) P_c X for nb <= c->nbc vectors
 int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
   const long nr = c->basis.nr;
-  BSE_TRY(proj_c(c, X, c->A_s, nb));
-  BSE_TRY(to_grid(c, c->A_s, c->nv, nb, c->agrid));
+  const double* A = c->in_pc ? X : c->A_s;
+  if (!c->in_pc) BSE_TRY(proj_c(c, X, c->A_s, nb));
+  BSE_TRY(to_grid(c, A, c->nv, nb, c->agrid));
   const double2* vdrho = nullptr;
   if (c->kmask & BSE_K_1E) {
     PhaseScope ps(c, PH_K1E);
@@ -327,7 +328,7 @@ int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
     BSE_TRY(combine(c->agrid, c->phir, c->Vr, vdrho, nullptr, c->agrid, c->nv, nb, nr, c->spin,
                     with_v, c->st));
   }
-  BSE_TRY(from_grid(c, zg, c->nv, nb, with_v ? c->A_s : nullptr, c->eps_d, c->scissor, c->Zs));
+  BSE_TRY(from_grid(c, zg, c->nv, nb, with_v ? A : nullptr, c->eps_d, c->scissor, c->Zs));
   BSE_TRY(proj_c(c, c->Zs, Y, nb));
   return BSE_OK;
 }
@@ -335,6 +336,9 @@ int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
 // kernel part of the operator on one exciton, before P_c, gathered:
 //   Kt_v = <e| s (v_c*Drho) phi_v - sum_v' tau_{v'v} a_v' >
 // a(r) in agrid set 0; set 1 is scratch; drho keeps v_c*Drho afterwards.
+// A mixed context contracts with its whole FP32 tau cache (a and the sum
+// pass through FP32 grids) instead of rebuilding the blocks its FP64 cache
+// lacks.
 int kernel_part(bse_ctx* c, const double2* agrid, double* Kt) {
   const long nr = c->basis.nr;
   double2* y = c->agrid + (long)c->nvh * nr;
@@ -347,7 +351,22 @@ int kernel_part(bse_ctx* c, const double2* agrid, double* Kt) {
     vdrho = c->drho;
   }
   const double2* yk = nullptr;
-  if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
+  if ((c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) && c->active == BSE_MIXED && c->tau_f) {
+    BSE_TRY(ensure_mixed_work(c, 2));
+    const long ng = (long)c->nvh * nr;
+    float2* af = c->agrid_f;
+    float2* yf = c->agrid_f + ng;
+    BSE_TRY(to_f32(reinterpret_cast<const double*>(agrid), reinterpret_cast<float*>(af), 2 * ng,
+                   c->st));
+    {
+      PhaseScope ps(c, PH_TAU_STREAM);
+      BSE_TRY(tau_stream(c->tau_f, c->nblk, c->nblk, c->blkIJ, c->Rf, af, yf, 1, c->nv, nr, 0,
+                         c->max_lds, c->st, nullptr, c->tau_bl));
+    }
+    BSE_TRY(to_f64(reinterpret_cast<const float*>(yf), reinterpret_cast<double*>(y), 2 * ng,
+                   c->st));
+    yk = y;
+  } else if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
     BSE_TRY(tau_contract(c, c->phir, agrid, y, 1, c->kmask, true));
     yk = y;
   }
@@ -403,10 +422,11 @@ static int from_grid_f(bse_ctx* c, float2* grids, int nvs, int nset, const doubl
 int apply_chunk_mixed(bse_ctx* c, int nb, const double* X, double* Y) {
   const long nr = c->basis.nr;
   BSE_TRY(ensure_mixed_work(c, c->nbc));
-  BSE_TRY(proj_c(c, X, c->A_s, nb));
+  const double* A = c->in_pc ? X : c->A_s;
+  if (!c->in_pc) BSE_TRY(proj_c(c, X, c->A_s, nb));
   {
     PhaseScope ps(c, PH_FFT_INV);
-    BSE_TRY(sphere_to_grid(c->fft, c->sp, c->basis.omega, c->A_s, c->nv, nb, c->agrid_f, c->st));
+    BSE_TRY(sphere_to_grid(c->fft, c->sp, c->basis.omega, A, c->nv, nb, c->agrid_f, c->st));
   }
   const float2* vdrho = nullptr;
   if (c->kmask & BSE_K_1E) {
@@ -429,7 +449,7 @@ int apply_chunk_mixed(bse_ctx* c, int nb, const double* X, double* Y) {
     BSE_TRY(combine(c->agrid_f, c->phir_f, c->Vr_f, vdrho, nullptr, c->agrid_f, c->nv, nb, nr,
                     c->spin, with_v, c->st));
   }
-  BSE_TRY(from_grid_f(c, c->agrid_f, c->nv, nb, with_v ? c->A_s : nullptr, c->eps_d, c->scissor,
+  BSE_TRY(from_grid_f(c, c->agrid_f, c->nv, nb, with_v ? A : nullptr, c->eps_d, c->scissor,
                       c->Zs));
   BSE_TRY(proj_c(c, c->Zs, Y, nb));
   return BSE_OK;
@@ -473,7 +493,7 @@ void graphs_destroy(bse_ctx* c) {
 int graph_apply(bse_ctx* c, int nb, const double* X, double* Y) {
   const long L = (long)c->nv * c->basis.npw;
   if (nb < 1 || nb > c->nbc) return fail(BSE_EINVAL, "graph apply: block of %d", nb);
-  const int key = nb * 4 + c->active;
+  const int key = nb * 4 + c->active + (c->in_pc ? 2 : 0);
   for (auto& g : c->graphs)
     if (g.first == key) {
       BSE_HIP(hipMemcpyAsync(c->gX, X, sizeof(double) * nb * L, hipMemcpyDeviceToDevice, c->st));

@@ -95,9 +95,16 @@ double elapsed_ms(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// apply the operator to n vectors in chunks of at most c->nbc
-int apply_n(bse_ctx* c, long n, const double* X, double* Y) {
+// apply the operator to n vectors in chunks of at most c->nbc; in_pc: the
+// vectors already lie in the P_c space
+int apply_n(bse_ctx* c, long n, const double* X, double* Y, bool in_pc = false) {
   const long L = (long)c->nv * c->basis.npw;
+  struct Flag {
+    bse_ctx* c;
+    bool keep;
+    ~Flag() { c->in_pc = keep; }
+  } flag{c, c->in_pc};
+  c->in_pc = in_pc;
   for (long i = 0; i < n; i += c->nbc) {
     const int k = (int)std::min<long>(c->nbc, n - i);
     if (c->use_graph && !c->prof)
@@ -142,11 +149,15 @@ int precond_two_level(bse_ctx* c, double* W, int nk, const double* theta, double
 }  // namespace
 
 // Orthonormalise the rows of W[k][len] against V[m][len] and among
-// themselves.  Rows are normalised first; two rounds of (project out V,
-// then orthonormalise through the eigen-decomposition of the Gram matrix)
-// follow.  Directions with Gram eigenvalue below drop^2 are dropped in the
-// first round.  Surviving rows are compacted to the front of W; returns
-// their number, or a negative status.
+// themselves.  Rows are normalised first; up to two rounds of (project out
+// V, then orthonormalise through the eigen-decomposition of the Gram
+// matrix) follow.  Directions with Gram eigenvalue below drop^2 are dropped
+// in the first round.  The second round is skipped when the first lost at
+// most half of the squared norm in every direction (smallest Gram
+// eigenvalue >= 1/2): one classical Gram-Schmidt pass is then accurate to
+// rounding (the criterion of Daniel, Gragg, Kaufman and Stewart, Math.
+// Comp. 30, 772 (1976)).  Surviving rows are compacted to the front of W;
+// returns their number, or a negative status.
 int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len, double* tmp,
                int passes, double drop) {
   if (k <= 0) return 0;
@@ -174,6 +185,7 @@ int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len,
     std::vector<double> G((size_t)kk * kk), lam(kk);
     if (to_host(c, Bm, G.data(), (size_t)kk * kk) != BSE_OK) return -BSE_EHIP;
     if (host_syev((int)kk, G.data(), lam.data())) return -fail(BSE_EINVAL, "Gram eigensolver failed");
+    const bool enough = pass == 0 && lam[0] >= 0.5;
     const double thr = (pass == 0) ? drop * drop : 1e-300;
     std::vector<double> Bh;
     long knew = 0;
@@ -189,6 +201,7 @@ int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len,
       return -BSE_EHIP;
     if (copy_dev(c, tmp, W, (size_t)knew * len) != BSE_OK) return -BSE_EHIP;
     kk = knew;
+    if (enough) break;
   }
   return (int)kk;
 }
@@ -332,7 +345,7 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
   int m = orth_block(c, V.p, 0, W.p, k, L, AW.p, 2, 1e-8);
   if (m <= 0) return m < 0 ? -m : fail(BSE_EINVAL, "Davidson: empty initial block");
   BSE_TRY(copy_dev(c, W.p, V.p, (size_t)m * L));
-  BSE_TRY(apply_n(c, m, V.p, AV.p));
+  BSE_TRY(apply_n(c, m, V.p, AV.p, true));
   applies += m;
   std::vector<double> Hs((size_t)maxsub * maxsub, 0.0);
   auto refresh_rows = [&](long r0, long r1) -> int {  // Hs rows/cols r0..r1-1 against 0..r1-1
@@ -434,7 +447,7 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
     const int kn = orth_block(c, V.p, m, W.p, nt, L, AW.p, 2, 1e-8);
     if (kn < 0) return -kn;
     if (kn == 0) break;
-    BSE_TRY(apply_n(c, kn, W.p, AW.p));
+    BSE_TRY(apply_n(c, kn, W.p, AW.p, true));
     applies += kn;
     BSE_TRY(copy_dev(c, W.p, V.p + (size_t)m * L, (size_t)kn * L));
     BSE_TRY(copy_dev(c, AW.p, AV.p + (size_t)m * L, (size_t)kn * L));

@@ -10,7 +10,10 @@ its error is a few 1e-7 of the FP32 terms' scale; the FP64 diagonal term
 confirmed, and continued if needed, with the FP64 operator; the Z-vector
 solve is refined against the FP64 residual), so energies and forces obey the
 FP64 bounds: |d omega| <= 1e-9 Ha and |dF| <= 1e-7 Ha/bohr at tol 1e-10,
-against the targets 1e-6 Ha and 1e-5 Ha/bohr.
+against the targets 1e-6 Ha and 1e-5 Ha/bohr.  The right-hand side U of the
+Z-vector equation takes its sum over tau from the FP32 cache, so Z carries
+the FP32 rounding of that term (a few 1e-8 of |Z|, asserted <= 1e-6 of
+max|Z|); the forces stay within 1e-7 Ha/bohr.
 """
 import numpy as np
 import pytest
@@ -110,7 +113,7 @@ def test_mixed_davidson_z_forces(name):
     Zo, _ = solvers.zvector_cg(S, Uo, tol=1e-12)
     print(f"  Z rel err {_frel(Z.cpu().numpy(), Zo):.2e} iters {zs['iters']}")
     assert zs["resid"][0] <= 1e-10
-    assert np.abs(Z.cpu().numpy() - Zo).max() < 1e-8 * np.abs(Zo).max()
+    assert np.abs(Z.cpu().numpy() - Zo).max() < 1e-6 * np.abs(Zo).max()
     F = bsex.forces(ctx, _cuda(Xo[0]), Z, S.n_sites)
     Fo = solvers.dwdR(S, Xo[0], Zo)
     print(f"  force diff {np.abs(F - Fo).max():.2e}")
