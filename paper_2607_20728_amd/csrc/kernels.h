@@ -22,6 +22,8 @@ struct SphereMap {
 // accumulate = 1, in which case the coefficients are added).
 int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, double2* grid,
                  int accumulate, hipStream_t st);
+int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, float2* grid,
+                 int accumulate, hipStream_t st);
 // Y[set][v][j] = scale * <e_j | grid>  (+ (T_j + shift - eps_v) * A[set][v][j] if A)
 // (+ beta * Y).  The grid holds N_r times the Fourier coefficients when it
 // comes straight from a forward transform, so callers pass scale = 1/N_r.
@@ -56,10 +58,14 @@ int combine(const float2* a, const float2* phir, const float* V, const float2* v
 // pair densities of 8x8 blocks [blk0, blk0 + nblk) of the upper triangle
 int pair_density(const double2* phir, int nv, const int2* blkIJ, long nblk, long nr,
                  double2* grids, hipStream_t st);
+int pair_density(const float2* phir, int nv, const int2* blkIJ, long nblk, long nr,
+                 float2* grids, hipStream_t st);
 // natural tau tile (packed grids, 64 elements per block) -> blocked stream layout
 int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R, double* dst,
               long dst_nblk, long dst_blk0, hipStream_t st);
 int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R, float* dst,
+              long dst_nblk, long dst_blk0, hipStream_t st);
+int tau_store(const float2* grids, const int2* blkIJ, long nblk, long nr, int R, float* dst,
               long dst_nblk, long dst_blk0, hipStream_t st);
 // optional epilogue of the last stream launch: write z = with_v V a +
 // s (v_c*Drho_b) phi - y (vdrho may be NULL) instead of y

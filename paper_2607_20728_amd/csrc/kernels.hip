@@ -24,9 +24,18 @@ __device__ __forceinline__ long gstride() { return (long)gridDim.x * blockDim.x;
 //   f(0) = x0/sqrt(Omega), f(+G) = (xc - i xs)/sqrt(2 Omega), f(-G) = conj(f(+G));
 //   grid of orbitals u (real part) and w (imaginary part): H = U + i W.
 // ---------------------------------------------------------------------------
+template <typename V2>
+__device__ __forceinline__ V2 make2(double x, double y) {
+  V2 v;
+  v.x = x;
+  v.y = y;
+  return v;
+}
+
+template <typename V2>
 __global__ void k_scatter(const int* __restrict__ idx_p, const int* __restrict__ idx_m, int nhalf,
                           int npw, long nr, long zero, const double* __restrict__ X, int nv,
-                          int nvh, long ngrid, double2* __restrict__ grid, int acc, double s0,
+                          int nvh, long ngrid, V2* __restrict__ grid, int acc, double s0,
                           double s1) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t > nhalf) return;
@@ -36,14 +45,14 @@ __global__ void k_scatter(const int* __restrict__ idx_p, const int* __restrict__
     const int v1 = 2 * p, v2 = 2 * p + 1;
     const double* x1 = X + (set * nv + v1) * (long)npw;
     const double* x2 = (v2 < nv) ? X + (set * nv + v2) * (long)npw : nullptr;
-    double2* G = grid + g * nr;
+    V2* G = grid + g * nr;
     if (t == 0) {
       double2 h = make_double2(x1[0] * s0, x2 ? x2[0] * s0 : 0.0);
       if (acc) {
         h.x += G[zero].x;
         h.y += G[zero].y;
       }
-      G[zero] = h;
+      G[zero] = make2<V2>(h.x, h.y);
     } else {
       const int k = t - 1;
       const double c1 = x1[1 + 2 * k], q1 = x1[2 + 2 * k];
@@ -52,14 +61,14 @@ __global__ void k_scatter(const int* __restrict__ idx_p, const int* __restrict__
       double2 hm = make_double2((c1 - q2) * s1, (q1 + c2) * s1);
       const int ip = idx_p[k], im = idx_m[k];
       if (acc) {
-        const double2 op = G[ip], om = G[im];
+        const V2 op = G[ip], om = G[im];
         hp.x += op.x;
         hp.y += op.y;
         hm.x += om.x;
         hm.y += om.y;
       }
-      G[ip] = hp;
-      G[im] = hm;
+      G[ip] = make2<V2>(hp.x, hp.y);
+      G[im] = make2<V2>(hm.x, hm.y);
     }
   }
 }
@@ -193,17 +202,19 @@ __global__ void k_combine(const V2* __restrict__ a, const V2* __restrict__ phir,
   }
 }
 
-__device__ __forceinline__ double orb_at(const double2* __restrict__ phir, int v, int nv, long nr,
+template <typename V2>
+__device__ __forceinline__ double orb_at(const V2* __restrict__ phir, int v, int nv, long nr,
                                          long r) {
   if (v >= nv) return 0.0;
-  const double2 f = phir[(long)(v >> 1) * nr + r];
+  const V2 f = phir[(long)(v >> 1) * nr + r];
   return (v & 1) ? f.y : f.x;
 }
 
 // grid q of a tile holds elements 2q, 2q+1 of the 64 per block, element
 // e = j*8 + i is the pair (8I + i, 8J + j)
-__global__ void k_pair_density(const double2* __restrict__ phir, int nv, const int2* __restrict__ IJ,
-                               long nblk, long nr, double2* __restrict__ grids) {
+template <typename V2>
+__global__ void k_pair_density(const V2* __restrict__ phir, int nv, const int2* __restrict__ IJ,
+                               long nblk, long nr, V2* __restrict__ grids) {
   const long n = nblk * 32 * nr;
   for (long e = gtid(); e < n; e += gstride()) {
     const long r = e % nr;
@@ -216,13 +227,13 @@ __global__ void k_pair_density(const double2* __restrict__ phir, int nv, const i
     const double w = orb_at(phir, 8 * b.y + j, nv, nr, r);
     const double u0 = orb_at(phir, 8 * b.x + i0, nv, nr, r);
     const double u1 = orb_at(phir, 8 * b.x + i0 + 1, nv, nr, r);
-    grids[e] = make_double2(u0 * w, u1 * w);
+    grids[e] = make2<V2>(u0 * w, u1 * w);
   }
 }
 
 // dst[rb][dst_blk0 + blk][j][ri][i] from the packed tile
-template <typename TD>
-__global__ void k_tau_store(const double2* __restrict__ grids, const int2* __restrict__ IJ,
+template <typename G2, typename TD>
+__global__ void k_tau_store(const G2* __restrict__ grids, const int2* __restrict__ IJ,
                             long nblk, long nr, int R, TD* __restrict__ dst, long dst_nblk,
                             long dst_blk0) {
   const long per_rb = nblk * 64 * R;
@@ -238,7 +249,7 @@ __global__ void k_tau_store(const double2* __restrict__ grids, const int2* __res
     const int j = (int)(w % 8);
     const long blk = w / 8;
     const long el = blk * 64 + j * 8 + i;
-    const double2 g = grids[(el >> 1) * nr + rb * R + ri];
+    const G2 g = grids[(el >> 1) * nr + rb * R + ri];
     double v = (el & 1) ? g.y : g.x;
     const int2 b = IJ[blk];
     if (b.x == b.y) {
@@ -677,17 +688,28 @@ __global__ __launch_bounds__(256) void k_band_features(
 // ============================================================================
 #define CHECK_LAUNCH() BSE_HIP(hipGetLastError())
 
-int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, double2* grid,
-                 int accumulate, hipStream_t st) {
+template <typename V2>
+static int scatter_impl(const SphereMap& m, const double* X, int nv, int nset, V2* grid,
+                        int accumulate, hipStream_t st) {
   const int nvh = (nv + 1) / 2;
   const long ngrid = (long)nset * nvh;
   if (ngrid <= 0) return BSE_OK;
   const dim3 g((unsigned)((m.nhalf + 1 + TPB - 1) / TPB), (unsigned)std::min(ngrid, 65535L));
-  hipLaunchKernelGGL(k_scatter, g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr,
+  hipLaunchKernelGGL((k_scatter<V2>), g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr,
                      m.zero, X, nv, nvh, ngrid, grid, accumulate, 1.0 / std::sqrt(m.omega),
                      1.0 / std::sqrt(2.0 * m.omega));
   CHECK_LAUNCH();
   return BSE_OK;
+}
+
+int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, double2* grid,
+                 int accumulate, hipStream_t st) {
+  return scatter_impl(m, X, nv, nset, grid, accumulate, st);
+}
+
+int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, float2* grid,
+                 int accumulate, hipStream_t st) {
+  return scatter_impl(m, X, nv, nset, grid, accumulate, st);
 }
 
 template <typename V2>
@@ -807,23 +829,34 @@ int combine(const float2* a, const float2* phir, const float* V, const float2* v
   return BSE_OK;
 }
 
-int pair_density(const double2* phir, int nv, const int2* blkIJ, long nblk, long nr,
-                 double2* grids, hipStream_t st) {
+template <typename V2>
+static int pair_density_impl(const V2* phir, int nv, const int2* blkIJ, long nblk, long nr,
+                             V2* grids, hipStream_t st) {
   const long n = nblk * 32 * nr;
   if (n <= 0) return BSE_OK;
-  hipLaunchKernelGGL(k_pair_density, dim3(nblocks(n)), dim3(TPB), 0, st, phir, nv, blkIJ, nblk, nr,
-                     grids);
+  hipLaunchKernelGGL((k_pair_density<V2>), dim3(nblocks(n)), dim3(TPB), 0, st, phir, nv, blkIJ,
+                     nblk, nr, grids);
   CHECK_LAUNCH();
   return BSE_OK;
 }
 
-template <typename TD>
-static int tau_store_impl(const double2* grids, const int2* blkIJ, long nblk, long nr, int R,
+int pair_density(const double2* phir, int nv, const int2* blkIJ, long nblk, long nr,
+                 double2* grids, hipStream_t st) {
+  return pair_density_impl(phir, nv, blkIJ, nblk, nr, grids, st);
+}
+
+int pair_density(const float2* phir, int nv, const int2* blkIJ, long nblk, long nr,
+                 float2* grids, hipStream_t st) {
+  return pair_density_impl(phir, nv, blkIJ, nblk, nr, grids, st);
+}
+
+template <typename G2, typename TD>
+static int tau_store_impl(const G2* grids, const int2* blkIJ, long nblk, long nr, int R,
                           TD* dst, long dst_nblk, long dst_blk0, hipStream_t st) {
   const long n = (nr / R) * nblk * 64 * R;
   if (n <= 0) return BSE_OK;
-  hipLaunchKernelGGL(k_tau_store<TD>, dim3(nblocks(n)), dim3(TPB), 0, st, grids, blkIJ, nblk, nr, R,
-                     dst, dst_nblk, dst_blk0);
+  hipLaunchKernelGGL((k_tau_store<G2, TD>), dim3(nblocks(n)), dim3(TPB), 0, st, grids, blkIJ, nblk,
+                     nr, R, dst, dst_nblk, dst_blk0);
   CHECK_LAUNCH();
   return BSE_OK;
 }
@@ -834,6 +867,11 @@ int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R
 }
 
 int tau_store(const double2* grids, const int2* blkIJ, long nblk, long nr, int R, float* dst,
+              long dst_nblk, long dst_blk0, hipStream_t st) {
+  return tau_store_impl(grids, blkIJ, nblk, nr, R, dst, dst_nblk, dst_blk0, st);
+}
+
+int tau_store(const float2* grids, const int2* blkIJ, long nblk, long nr, int R, float* dst,
               long dst_nblk, long dst_blk0, hipStream_t st) {
   return tau_store_impl(grids, blkIJ, nblk, nr, R, dst, dst_nblk, dst_blk0, st);
 }

@@ -234,6 +234,38 @@ int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double
   return BSE_OK;
 }
 
+// The same tile in FP32 (mixed contexts): pair densities, transforms, the
+// bare Coulomb kernel and the stored tile in FP32; the PDEP projections and
+// their GEMMs in FP64.  The tile grids and dst are the FP64 buffers'
+// storage reused at half the size.
+static int tau_build_range_f(bse_ctx* c, const float2* orbr, long gb0, long nblk, float* dst,
+                             long dst_nblk, long dst_blk0, int mask) {
+  if (nblk <= 0) return BSE_OK;
+  if (nblk > c->tile_blk) return fail(BSE_EINVAL, "tau build: tile of %ld blocks too large", nblk);
+  const long nr = c->basis.nr, npw = c->basis.npw;
+  const long ng = nblk * 32, ne = nblk * 64;
+  float2* tg = reinterpret_cast<float2*>(c->tile_grids);
+  BSE_TRY(pair_density(orbr, c->nv, c->blkIJ + gb0, nblk, nr, tg, c->st));
+  BSE_TRY(fft3d(c->fft, tg, ng, -1, c->st));
+  SphereMap m64 = c->map;
+  const bool pdep = (mask & BSE_K_1D_PDEP) && c->npdep > 0;
+  if (pdep) {
+    BSE_TRY(gather_sets(m64, tg, 64, (int)nblk, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0,
+                        0.0, c->tile_RS, c->st));
+    BSE_TRY(gemm(c, 0, 0, ne, c->npdep, npw, 1.0, c->tile_RS, npw, c->Pt, c->npdep, 0.0,
+                 c->tile_T, c->npdep));
+    BSE_TRY(dgemm(0, 1, ne, npw, c->npdep, 1.0, c->tile_T, c->npdep, c->Ptc, c->npdep, 0.0,
+                  c->tile_F, npw, c->st));
+  }
+  if (mask & BSE_K_1D_BARE)
+    BSE_TRY(mul_real_field(tg, ng, nr, c->vc_f, 1.0f / (float)nr, c->st));
+  else  // one float2 per double
+    BSE_TRY(zero_fill(reinterpret_cast<double*>(tg), ng * nr, c->st));
+  if (pdep) BSE_TRY(scatter_sets(m64, c->tile_F, 64, (int)nblk, tg, 1, c->st));
+  BSE_TRY(fft3d(c->fft, tg, ng, +1, c->st));
+  return tau_store(tg, c->blkIJ + gb0, nblk, nr, c->Rf, dst, dst_nblk, dst_blk0, c->st);
+}
+
 // y[b][v] = sum_v' tau_{vv'} a[b][v'] over all pairs: cached blocks, then
 // tiles rebuilt on the fly.  orbr are the orbitals tau is built from.
 static int tau_contract(bse_ctx* c, const double2* orbr, const double2* a, double2* y, int nb,
@@ -376,9 +408,30 @@ int kernel_part(bse_ctx* c, const double2* agrid, double* Kt) {
 }
 
 // sigma term of U:  y_v = sum_v' W(a_v' a_v) phi_v'  (sigma built from a,
-// contracted with phi), tiles rebuilt for every block.
+// contracted with phi), tiles rebuilt for every block.  A mixed context
+// builds and contracts the tiles in FP32 (a and the sum pass through FP32
+// grids).
 int sigma_phi(bse_ctx* c, const double2* agrid, double2* y) {
-  return tau_contract(c, agrid, c->phir, y, 1, c->kmask, false);
+  if (!(c->active == BSE_MIXED && c->vc_f && c->phir_f))
+    return tau_contract(c, agrid, c->phir, y, 1, c->kmask, false);
+  const long nr = c->basis.nr, ng = (long)c->nvh * nr;
+  BSE_TRY(ensure_mixed_work(c, 2));
+  float2* af = c->agrid_f;
+  float2* yf = c->agrid_f + ng;
+  BSE_TRY(to_f32(reinterpret_cast<const double*>(agrid), reinterpret_cast<float*>(af), 2 * ng,
+                 c->st));
+  float* buf = reinterpret_cast<float*>(c->rebuild_buf);
+  for (long gb0 = 0; gb0 < c->nblk; gb0 += c->tile_blk) {
+    const long nt = std::min(c->tile_blk, c->nblk - gb0);
+    {
+      PhaseScope ps(c, PH_TAU_BUILD);
+      BSE_TRY(tau_build_range_f(c, af, gb0, nt, buf, nt, 0, c->kmask));
+    }
+    PhaseScope ps(c, PH_TAU_TILE);
+    BSE_TRY(tau_stream(buf, nt, nt, c->blkIJ + gb0, c->Rf, c->phir_f, yf, 1, c->nv, nr,
+                       gb0 == 0 ? 0 : 1, c->max_lds, c->st, nullptr, c->tau_bl));
+  }
+  return to_f64(reinterpret_cast<const float*>(yf), reinterpret_cast<double*>(y), 2 * ng, c->st);
 }
 
 // ---------------------------------------------------------------------------
