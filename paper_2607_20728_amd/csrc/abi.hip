@@ -204,8 +204,11 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
     for (long gb0 = 0; gb0 < nbuild;) {
       long nt = std::min(c->tile_blk, nbuild - gb0);
       if (gb0 < ncache) nt = std::min(nt, ncache - gb0);
-      BSE_TRY(tau_build_range(c, c->phir, gb0, nt, gb0 < ncache ? c->tau_cache : nullptr, ncache,
-                              gb0, c->kmask, c->tau_f));
+      if (gb0 < ncache)
+        BSE_TRY(tau_build_range(c, c->phir, gb0, nt, c->tau_cache, ncache, gb0, c->kmask,
+                                c->tau_f));
+      else
+        BSE_TRY(tau_build_range_f(c, c->phir_f, gb0, nt, c->tau_f, c->nblk, gb0, c->kmask));
       gb0 += nt;
     }
   }

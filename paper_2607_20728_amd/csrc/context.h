@@ -150,6 +150,8 @@ int ensure_ygrid(bse_ctx* c);
 // tau of blocks [gb0, gb0 + nblk) stored into dst (FP64, R points per row,
 // a buffer of dst_nblk blocks from dst_blk0) and/or dstf (the whole FP32
 // cache, Rf points per row, at block gb0); either may be null
+int tau_build_range_f(bse_ctx* c, const float2* orbr, long gb0, long nblk, float* dst,
+                      long dst_nblk, long dst_blk0, int mask);
 int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double* dst,
                     long dst_nblk, long dst_blk0, int mask, float* dstf = nullptr);
 // learned preconditioner network (mlp.hip): y [n][n_out] from x [n][n_in]

@@ -238,8 +238,8 @@ int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double
 // bare Coulomb kernel and the stored tile in FP32; the PDEP projections and
 // their GEMMs in FP64.  The tile grids and dst are the FP64 buffers'
 // storage reused at half the size.
-static int tau_build_range_f(bse_ctx* c, const float2* orbr, long gb0, long nblk, float* dst,
-                             long dst_nblk, long dst_blk0, int mask) {
+int tau_build_range_f(bse_ctx* c, const float2* orbr, long gb0, long nblk, float* dst,
+                      long dst_nblk, long dst_blk0, int mask) {
   if (nblk <= 0) return BSE_OK;
   if (nblk > c->tile_blk) return fail(BSE_EINVAL, "tau build: tile of %ld blocks too large", nblk);
   const long nr = c->basis.nr, npw = c->basis.npw;

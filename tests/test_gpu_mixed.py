@@ -133,3 +133,34 @@ def test_mixed_with_explicit_budget():
     Y = bsex.apply(ctx, _cuda(X)).cpu().numpy()
     assert _frel(Y, S.apply(X)) < 2e-6
     ctx.free()
+
+
+def test_mixed_partial_fp64_cache():
+    """With the FP64 cache holding only part of the blocks, the others reach
+    the FP32 cache through the FP32 tile pipeline; the apply keeps the FP32
+    bound and the solvers (whose FP64 checks rebuild the missing FP64 blocks)
+    the FP64 ones."""
+    print("[gpu] mixed partial FP64 cache c1", flush=True)
+    S, d = _oracle("c1")
+    n_r = int(np.prod(d["grid"]))
+    full = _lib_ctx(S, d)
+    nblk = bsex.get_info(full)["tau_blocks"]
+    full.free()
+    fbytes = nblk * 64 * n_r * 4
+    ctx = _lib_ctx(S, d, precision=bsex.MIXED, tau_budget_bytes=2 * fbytes)
+    info = bsex.get_info(ctx)
+    assert 0 < info["tau_blocks_cached"] < info["tau_blocks"]
+    X = d["trial"][:8]
+    err = _frel(bsex.apply(ctx, _cuda(X)).cpu().numpy(), S.apply(X))
+    print(f"  cached {info['tau_blocks_cached']}/{info['tau_blocks']} apply rel err {err:.2e}")
+    assert err < 2e-6
+    w, Xe, st = bsex.davidson(ctx, 2, tol=1e-10)
+    wo, Xo, _ = solvers.davidson(S, 2, tol=1e-10)
+    assert np.abs(w - wo).max() < 1e-9
+    Z, zs = bsex.zvector_solve(ctx, _cuda(Xo[0]), tol=1e-10)
+    Zo, _ = solvers.zvector_cg(S, solvers.u_vector(S, Xo[0]), tol=1e-12)
+    F = bsex.forces(ctx, _cuda(Xo[0]), Z, S.n_sites)
+    Fo = solvers.dwdR(S, Xo[0], Zo)
+    print(f"  omega diff {np.abs(w - wo).max():.2e} force diff {np.abs(F - Fo).max():.2e}")
+    assert np.abs(F - Fo).max() < 1e-7
+    ctx.free()
