@@ -316,41 +316,57 @@ int host_syev(int n, double* Ain, double* w) {
 }
 
 int host_cholesky(int n, double* A) {
+  // column by column; the rows below the pivot are independent
   for (int j = 0; j < n; ++j) {
-    double s = A[(size_t)j * n + j];
-    for (int k = 0; k < j; ++k) s -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+    const double* lj = A + (size_t)j * n;
+    double s = lj[j];
+    for (int k = 0; k < j; ++k) s -= lj[k] * lj[k];
     if (!(s > 0.0)) return 1;
     const double r = std::sqrt(s);
     A[(size_t)j * n + j] = r;
-    for (int i = j + 1; i < n; ++i) {
-      double t = A[(size_t)i * n + j];
-      for (int k = 0; k < j; ++k) t -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
-      A[(size_t)i * n + j] = t / r;
-    }
-    for (int k = j + 1; k < n; ++k) A[(size_t)j * n + k] = 0.0;
+    split_range(n - j - 1, 2.0 * (n - j - 1) * (double)j, [&](int lo, int hi) {
+      for (int i = j + 1 + lo; i < j + 1 + hi; ++i) {
+        const double* li = A + (size_t)i * n;
+        double t = li[j];
+        for (int k = 0; k < j; ++k) t -= li[k] * lj[k];
+        A[(size_t)i * n + j] = t / r;
+      }
+    });
   }
+  for (int j = 0; j < n; ++j)
+    for (int k = j + 1; k < n; ++k) A[(size_t)j * n + k] = 0.0;
   return 0;
 }
 
 int host_trinv_lower(int n, double* L) {
-  // row i of M = L^{-1}: (e_i - sum_{k<i} L_ik M_k) / L_ii, built in place
-  // from the top row down (row i of L is read before it is overwritten)
-  std::vector<double> row(n);
   for (int i = 0; i < n; ++i) {
-    const double* li = L + (size_t)i * n;
-    const double d = li[i];
+    const double d = L[(size_t)i * n + i];
     if (!(d != 0.0) || !std::isfinite(d)) return 1;
-    std::fill(row.begin(), row.end(), 0.0);
-    row[i] = 1.0;
-    for (int k = 0; k < i; ++k) {
-      const double f = li[k];
-      if (f == 0.0) continue;
-      const double* mk = L + (size_t)k * n;  // row k of M (columns 0..k)
-      for (int j = 0; j <= k; ++j) row[j] -= f * mk[j];
-    }
-    double* mi = L + (size_t)i * n;
-    for (int j = 0; j <= i; ++j) mi[j] = row[j] / d;
   }
+  // column j of M = L^{-1} by forward substitution, M_ij = (delta_ij -
+  // sum_{j<=k<i} L_ik M_kj) / L_ii; the columns are independent and are
+  // dealt out to the workers in turn (column j costs about (n - j)^2)
+  std::vector<double> M((size_t)n * n, 0.0);
+  auto column = [&](int j, std::vector<double>& x) {
+    for (int i = j; i < n; ++i) {
+      const double* li = L + (size_t)i * n;
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int k = j; k < i; ++k) s -= li[k] * x[k];
+      x[i] = s / li[i];
+    }
+    for (int i = j; i < n; ++i) M[(size_t)i * n + j] = x[i];
+  };
+  Workers& w = Workers::get();
+  if (w.size() == 1 || n < 64) {
+    std::vector<double> x(n);
+    for (int j = 0; j < n; ++j) column(j, x);
+  } else {
+    w.run([&](int t, int nt) {
+      std::vector<double> x(n);
+      for (int j = t; j < n; j += nt) column(j, x);
+    });
+  }
+  std::copy(M.begin(), M.end(), L);
   return 0;
 }
 
