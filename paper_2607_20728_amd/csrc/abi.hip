@@ -166,8 +166,14 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   if (d->tau_policy == BSE_TAU_CACHE && !full)
     return fail(BSE_ENOMEM, "tau cache needs %.1f GB, %.1f GB free", c->nblk * blk_bytes / 1e9,
                 (double)freeb / 1e9);
-  if (full) {
-    c->tile_blk = small_tile;
+  if (full && has_budget) {
+    c->tile_blk = small_tile;  // a budgeted context stays within its share
+  } else if (full) {
+    // device memory beyond the cache and the reserve goes to larger rebuild
+    // tiles: the U vector rebuilds every block from the exciton
+    const double spare = (double)freeb - reserve - c->nblk * blk_bytes;
+    const double tb = std::min(tile_target, std::max(small_tile * blk_tile_bytes, spare));
+    c->tile_blk = std::max(small_tile, std::min(c->nblk, (long)(tb / blk_tile_bytes)));
   } else {
     BSE_TRY(ensure_ygrid(c));  // accumulation across launches
     c->tile_blk = std::max(1L, std::min(c->nblk, (long)(tile_target / blk_tile_bytes)));
