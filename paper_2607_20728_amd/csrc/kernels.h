@@ -41,6 +41,10 @@ int mul_real_field(float2* grid, long ngrid, long nr, const float* f, float scal
 // y[i] = (float)x[i]
 int to_f32(const double* x, float* y, long n, hipStream_t st);
 int to_f64(const float* x, double* y, long n, hipStream_t st);
+// X[i][j] = g_ij / (1 + T_j), g_ij standard normal from a counter-based
+// generator of the given seed (the same for any launch shape)
+int random_smooth(double* X, long rows, long len, const double* T, unsigned long long seed,
+                  hipStream_t st);
 // out[r] = Re(grid[r]) for one grid
 int real_part(const double2* grid, long nr, double* out, hipStream_t st);
 // drho[b/2][r] packed over vectors: drho_b(r) = sum_v phi_v(r) a_{b,v}(r)

@@ -796,6 +796,38 @@ int to_f32(const double* x, float* y, long n, hipStream_t st) {
   return BSE_OK;
 }
 
+// SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014) as a counter-based
+// generator: element e of stream seed draws from mix(seed, e) only, so the
+// result does not depend on the launch shape.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+// X[i][j] = g_ij / (1 + T_j), g_ij standard normal (Box-Muller on two 32-bit
+// uniforms of one 64-bit draw)
+__global__ void k_random_smooth(double* __restrict__ X, long rows, long len,
+                                const double* __restrict__ T, unsigned long long seed) {
+  const long n = rows * len;
+  for (long e = gtid(); e < n; e += gstride()) {
+    const unsigned long long h = mix64(seed + 0x9e3779b97f4a7c15ULL * (unsigned long long)(e + 1));
+    const double u1 = ((double)(h >> 32) + 1.0) * 2.3283064365386963e-10;  // (0, 1]
+    const double u2 = (double)(h & 0xffffffffULL) * 2.3283064365386963e-10;  // [0, 1)
+    const double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2);
+    X[e] = g / (1.0 + T[e % len]);
+  }
+}
+
+int random_smooth(double* X, long rows, long len, const double* T, unsigned long long seed,
+                  hipStream_t st) {
+  const long n = rows * len;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_random_smooth, dim3(nblocks(n)), dim3(TPB), 0, st, X, rows, len, T, seed);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
 __global__ void k_to_f64(const float* __restrict__ x, double* __restrict__ y, long n) {
   for (long e = gtid(); e < n; e += gstride()) y[e] = (double)x[e];
 }

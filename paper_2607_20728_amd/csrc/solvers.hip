@@ -956,15 +956,9 @@ int ground_state(bse_ctx* c, int n_want, double tol) {
   } rel_g{c, grids};
   double* Cd = sm.p;
   double* vec = sm.p + nsl * nsl;
-  // random start (fixed seed), smooth: divided by (1 + |G|^2/2)
-  {
-    std::mt19937_64 gen(12345);
-    std::normal_distribution<double> nd;
-    std::vector<double> h(nsl * npw);
-    for (long i = 0; i < nsl; ++i)
-      for (long j = 0; j < npw; ++j) h[i * npw + j] = nd(gen) / (1.0 + 0.5 * c->basis.g2[j]);
-    BSE_TRY(to_dev(c, h.data(), X.p, h.size()));
-  }
+  // random start (fixed seed, drawn on the device), smooth: divided by
+  // (1 + |G|^2/2)
+  BSE_TRY(random_smooth(X.p, nsl, npw, c->T, 12345ULL, c->st));
   auto Happly = [&](const double* in, double* out, double shift) -> int {
     return apply_H(c, ns, 1, in, out, grids, shift, nullptr, 0);
   };
