@@ -165,6 +165,8 @@ def batch(args):
                           failed=len(bad), first_error=bad[0] if bad else None,
                           davidson_iters=sum(r["davidson_iters"] for r in res),
                           z_iters=sum(r["z_iters"] for r in res),
+                          sum_stage_s={k: round(sum(r["t_" + k + "_ms"] for r in res) / 1e3, 2)
+                                       for k in ("init", "davidson", "z", "force")},
                           variants=[r["variant"] for r in res], res=res)
         log(f"[batch] {name}: {dt:.1f} s, {len(bad)} failed")
     a, b = runs["sequential"]["res"], runs["batched"]["res"]
