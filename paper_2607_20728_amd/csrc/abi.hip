@@ -101,6 +101,7 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
     for (long J = I; J < nB; ++J) ij.push_back(make_int2((int)I, (int)J));
   BSE_TRY(ctx_alloc_t(c, &c->blkIJ, ij.size()));
   BSE_TRY(upload(c, c->blkIJ, ij.data(), sizeof(int2) * ij.size()));
+  c->blkIJ_h = ij;
   // stream kernel geometry from the device LDS size
   int dev = 0;
   BSE_HIP(hipGetDevice(&dev));

@@ -56,6 +56,7 @@ struct bse_ctx {
   double* Ptc = nullptr;      // [npw][npdep] v_c^1/2 P c
   double* sites = nullptr;    // xyz[3n] | depth[n] | width[n]
   int2* blkIJ = nullptr;      // [nblk]
+  std::vector<int2> blkIJ_h;  // the same on the host
   std::vector<double> eps_h;  // [norb]
   std::vector<double> site_h; // same layout as sites
   // tau

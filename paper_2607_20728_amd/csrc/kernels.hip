@@ -293,7 +293,9 @@ struct vec2_of<float> {
 
 // LDS rows (one per orbital v) hold NBT * R values plus SPAD of padding: the
 // slots of a wave work on unrelated rows, and an unpadded row of 16 words
-// would put the same word of every row in the same bank.
+// would put the same word of every row in the same bank.  A launch stages the
+// rows row0 .. row0 + nrows - 1 only: the bands its blocks touch (a rebuilt
+// tile late in the block order touches only the last bands).
 constexpr int SPAD = 1;
 
 // T: storage and arithmetic type of tau, a and y.  The LDS accumulators of y
@@ -303,7 +305,7 @@ template <int R, int BL, bool FUSE, typename T>
 __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
     const T* __restrict__ tau, long rb_stride, long nblk, const int2* __restrict__ IJ,
     const typename vec2_of<T>::type* a, typename vec2_of<T>::type* y, int nb, int nv, int nvh,
-    long nr, int nv8, int accumulate, const T* __restrict__ V,
+    long nr, int row0, int nrows, int accumulate, const T* __restrict__ V,
     const typename vec2_of<T>::type* __restrict__ vdrho,
     const typename vec2_of<T>::type* __restrict__ phir, T s, int with_v) {
   using V2 = typename vec2_of<T>::type;
@@ -315,14 +317,15 @@ __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
   constexpr int JU = sizeof(T) == 4 ? 8 : 2;
   extern __shared__ char lds_raw[];
   T* as = reinterpret_cast<T*>(lds_raw);
-  double* ys = reinterpret_cast<double*>(as + (long)nv8 * RS);
+  double* ys = reinterpret_cast<double*>(as + (long)nrows * RS);
   const long rb = blockIdx.x;
   const long r0 = rb * R;
-  const int n_el = nv8 * NBT * R;
+  const int n_el = nrows * NBT * R;
   for (int e = threadIdx.x; e < n_el; e += NT) {
     const int ri = e % R;
     const int b = (e / R) % NBT;
-    const int v = e / (R * NBT);
+    const int vl = e / (R * NBT);
+    const int v = row0 + vl;
     T av = 0;
     double yv = 0;
     if (v < nv && b < nb) {
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
       av = reinterpret_cast<const T*>(a + gi)[v & 1];
       if (accumulate) yv = reinterpret_cast<const T*>(y + gi)[v & 1];
     }
-    const int li = v * RS + b * R + ri;
+    const int li = vl * RS + b * R + ri;
     as[li] = av;
     ys[li] = yv;
   }
@@ -351,14 +354,14 @@ __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
         for (int i = 0; i < 8; ++i)
 #pragma unroll
           for (int b = 0; b < NBL; ++b)
-            atomicAdd(&ys[(curI * 8 + i) * RS + lo + b * R], (double)acc[i][b]);
+            atomicAdd(&ys[(curI * 8 + i - row0) * RS + lo + b * R], (double)acc[i][b]);
       }
       curI = bij.x;
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int b = 0; b < NBL; ++b) {
-          aI[i][b] = as[(curI * 8 + i) * RS + lo + b * R];
+          aI[i][b] = as[(curI * 8 + i - row0) * RS + lo + b * R];
           acc[i][b] = 0;
         }
     }
@@ -372,7 +375,7 @@ __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
         for (int i = 0; i < 8; ++i) t[jj][i] = tp[(j0 + jj) * 8 * R + i];
 #pragma unroll
       for (int jj = 0; jj < JU; ++jj) {
-        const int wv = bij.y * 8 + j0 + jj;
+        const int wv = bij.y * 8 + j0 + jj - row0;
         T aj[NBL], tr[NBL];
 #pragma unroll
         for (int b = 0; b < NBL; ++b) {
@@ -396,16 +399,17 @@ __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
     for (int i = 0; i < 8; ++i)
 #pragma unroll
       for (int b = 0; b < NBL; ++b)
-        atomicAdd(&ys[(curI * 8 + i) * RS + lo + b * R], (double)acc[i][b]);
+        atomicAdd(&ys[(curI * 8 + i - row0) * RS + lo + b * R], (double)acc[i][b]);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < n_el; e += NT) {
     const int rr = e % R;
     const int b = (e / R) % NBT;
-    const int v = e / (R * NBT);
+    const int vl = e / (R * NBT);
+    const int v = row0 + vl;
     if (v < nv && b < nb) {
       const long gi = ((long)b * nvh + (v >> 1)) * nr + r0 + rr;
-      const int li = v * RS + b * R + rr;
+      const int li = vl * RS + b * R + rr;
       T out = (T)ys[li];
       if (FUSE) {
         const long r = r0 + rr;
@@ -917,24 +921,32 @@ size_t tau_stream_lds(int nv, int R, size_t elem) {
 template <int R, int BL, bool F, typename T>
 static void launch_stream(long nrb, size_t shm, hipStream_t st, const T* tau, long stride,
                           long nblk, const int2* blkIJ, const typename vec2_of<T>::type* a,
-                          typename vec2_of<T>::type* y, int nb, int nv, long nr, int nv8,
-                          int accumulate, const T* V, const typename vec2_of<T>::type* vdrho,
+                          typename vec2_of<T>::type* y, int nb, int nv, long nr, int row0,
+                          int nrows, int accumulate, const T* V,
+                          const typename vec2_of<T>::type* vdrho,
                           const typename vec2_of<T>::type* phir, T s, int with_v) {
   hipLaunchKernelGGL((k_tau_stream<R, BL, F, T>), dim3((unsigned)nrb), dim3(NSLOT * R * BL), shm,
-                     st, tau, stride, nblk, blkIJ, a, y, nb, nv, (nv + 1) / 2, nr, nv8, accumulate,
-                     V, vdrho, phir, s, with_v);
+                     st, tau, stride, nblk, blkIJ, a, y, nb, nv, (nv + 1) / 2, nr, row0, nrows,
+                     accumulate, V, vdrho, phir, s, with_v);
 }
 
 template <typename T, typename FA>
 static int tau_stream_impl(const T* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                            const typename vec2_of<T>::type* a, typename vec2_of<T>::type* y,
                            int nb, int nv, long nr, int accumulate, size_t max_lds,
-                           hipStream_t st, const FA* fuse, int bl) {
+                           hipStream_t st, const FA* fuse, int bl, int row0, int rows) {
   if (nb > NBT) return fail(BSE_EINVAL, "tau_stream: at most %d vectors per call", NBT);
   if (nr % R) return fail(BSE_EINVAL, "tau_stream: grid size not a multiple of %d", R);
-  const size_t shm = tau_stream_lds(nv, R, sizeof(T));
-  if (shm > max_lds) return fail(BSE_EINVAL, "tau_stream: %zu bytes of LDS exceed %zu", shm, max_lds);
   const int nv8 = (nv + 7) / 8 * 8;
+  if (rows <= 0) {
+    row0 = 0;
+    rows = nv8;
+  }
+  if (row0 < 0 || row0 % 8 || rows % 8 || row0 + rows > nv8)
+    return fail(BSE_EINVAL, "tau_stream: band rows %d..%d outside 0..%d", row0, row0 + rows, nv8);
+  if (fuse && rows != nv8) return fail(BSE_EINVAL, "tau_stream: the fused epilogue needs every band");
+  const size_t shm = tau_stream_lds(rows, R, sizeof(T));
+  if (shm > max_lds) return fail(BSE_EINVAL, "tau_stream: %zu bytes of LDS exceed %zu", shm, max_lds);
   const long nrb = nr / R;
   if (nrb > 0x7fffffffL) return fail(BSE_EINVAL, "tau_stream: grid too large");
   const long stride = buf_nblk * 64 * R;
@@ -947,10 +959,10 @@ static int tau_stream_impl(const T* tau, long buf_nblk, long nblk, const int2* b
   do {                                                                                           \
     if (fuse)                                                                                    \
       launch_stream<R_, BL_, true, T>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,   \
-                                      nv8, accumulate, V, vd, ph, sf, wv);                       \
+                                      row0, rows, accumulate, V, vd, ph, sf, wv);                \
     else                                                                                         \
       launch_stream<R_, BL_, false, T>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,  \
-                                       nv8, accumulate, V, vd, ph, sf, wv);                      \
+                                       row0, rows, accumulate, V, vd, ph, sf, wv);               \
   } while (0)
   if (R == 2 && bl == 4)
     GO(2, 4);
@@ -969,16 +981,16 @@ static int tau_stream_impl(const T* tau, long buf_nblk, long nblk, const int2* b
 
 int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                const double2* a, double2* y, int nb, int nv, long nr, int accumulate,
-               size_t max_lds, hipStream_t st, const FuseArgs* fuse, int bl) {
+               size_t max_lds, hipStream_t st, const FuseArgs* fuse, int bl, int row0, int rows) {
   return tau_stream_impl(tau, buf_nblk, nblk, blkIJ, R, a, y, nb, nv, nr, accumulate, max_lds, st,
-                         fuse, bl);
+                         fuse, bl, row0, rows);
 }
 
 int tau_stream(const float* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                const float2* a, float2* y, int nb, int nv, long nr, int accumulate,
-               size_t max_lds, hipStream_t st, const FuseArgsF* fuse, int bl) {
+               size_t max_lds, hipStream_t st, const FuseArgsF* fuse, int bl, int row0, int rows) {
   return tau_stream_impl(tau, buf_nblk, nblk, blkIJ, R, a, y, nb, nv, nr, accumulate, max_lds, st,
-                         fuse, bl);
+                         fuse, bl, row0, rows);
 }
 
 int tau_stream_set_lds_limit(size_t bytes) {

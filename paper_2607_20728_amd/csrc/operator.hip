@@ -266,6 +266,18 @@ int tau_build_range_f(bse_ctx* c, const float2* orbr, long gb0, long nblk, float
   return tau_store(tg, c->blkIJ + gb0, nblk, nr, c->Rf, dst, dst_nblk, dst_blk0, c->st);
 }
 
+// band rows [row0, row0 + rows) that blocks [gb0, gb0 + nt) of the block list
+// touch: a launch that accumulates into y stages only those
+static void tile_rows(const bse_ctx* c, long gb0, long nt, int* row0, int* rows) {
+  int imin = c->blkIJ_h[gb0].x, jmax = 0;
+  for (long k = gb0; k < gb0 + nt; ++k) {
+    imin = std::min(imin, c->blkIJ_h[k].x);
+    jmax = std::max(jmax, c->blkIJ_h[k].y);
+  }
+  *row0 = 8 * imin;
+  *rows = 8 * (jmax + 1) - *row0;
+}
+
 // y[b][v] = sum_v' tau_{vv'} a[b][v'] over all pairs: cached blocks, then
 // tiles rebuilt on the fly.  orbr are the orbitals tau is built from.
 static int tau_contract(bse_ctx* c, const double2* orbr, const double2* a, double2* y, int nb,
@@ -289,8 +301,10 @@ static int tau_contract(bse_ctx* c, const double2* orbr, const double2* a, doubl
       BSE_TRY(tau_build_range(c, orbr, gb0, nt, c->rebuild_buf, nt, 0, mask));
     }
     PhaseScope ps(c, PH_TAU_TILE);
+    int row0 = 0, rows = 0;  // the first launch writes every band of y
+    if (!first) tile_rows(c, gb0, nt, &row0, &rows);
     BSE_TRY(tau_stream(c->rebuild_buf, nt, nt, c->blkIJ + gb0, c->R, a, y, nb, c->nv, nr,
-                       first ? 0 : 1, c->max_lds, c->st, nullptr, c->tau_bl));
+                       first ? 0 : 1, c->max_lds, c->st, nullptr, c->tau_bl, row0, rows));
     first = 0;
   }
   return BSE_OK;
@@ -428,8 +442,10 @@ int sigma_phi(bse_ctx* c, const double2* agrid, double2* y) {
       BSE_TRY(tau_build_range_f(c, af, gb0, nt, buf, nt, 0, c->kmask));
     }
     PhaseScope ps(c, PH_TAU_TILE);
+    int row0 = 0, rows = 0;  // the first launch writes every band of y
+    if (gb0 > 0) tile_rows(c, gb0, nt, &row0, &rows);
     BSE_TRY(tau_stream(buf, nt, nt, c->blkIJ + gb0, c->Rf, c->phir_f, yf, 1, c->nv, nr,
-                       gb0 == 0 ? 0 : 1, c->max_lds, c->st, nullptr, c->tau_bl));
+                       gb0 == 0 ? 0 : 1, c->max_lds, c->st, nullptr, c->tau_bl, row0, rows));
   }
   return to_f64(reinterpret_cast<const float*>(yf), reinterpret_cast<double*>(y), 2 * ng, c->st);
 }

@@ -79,6 +79,36 @@ def test_apply_c1_tau_policies(policy, budget):
     ctx.free()
 
 
+def test_rebuild_tiles_stage_band_ranges():
+    """Five band blocks (15 pair blocks) with one block cached and the rest
+    rebuilt one block per tile: every accumulating tile launch stages only
+    the band rows its blocks touch (down to the last 8 bands), in the FP64
+    apply, the FP64 U vector, and the FP32 tiles of a mixed U vector."""
+    print("[gpu] rebuild tiles c4s27", flush=True)
+    cfg = [x for x in synth.c4_systems() if x.name == "c4s27"][0]
+    b = basis.Basis(cfg.cell, cfg.grid, cfg.ecut)
+    d = synth.make_system(cfg, b.n_pw, n_trial=8)
+    S = model.System(b, d["site_xyz"], d["site_depth"], d["site_width"], d["pdep"], d["lam"],
+                     cfg.n_val, kmask=K_ALL)
+    S.ground_state(n_extra=8)
+    n_r = int(np.prod(d["grid"]))
+    blk = 64 * n_r * 8
+    ctx = _lib_ctx(S, d, tau_budget_bytes=blk)
+    info = bsex.get_info(ctx)
+    assert info["tau_blocks"] == 15 and info["tau_blocks_cached"] == 1
+    X = d["trial"]
+    assert _rel(bsex.apply(ctx, _cuda(X)).cpu().numpy(), S.apply(X)) < 1e-11
+    Uo = solvers.u_vector(S, X[0])
+    assert _rel(bsex.u_vector(ctx, _cuda(X[0])).cpu().numpy(), Uo) < 1e-10
+    ctx.free()
+    ctx = _lib_ctx(S, d, precision=bsex.MIXED, tau_budget_bytes=15 * blk // 2 + blk)
+    assert bsex.get_info(ctx)["tau_blocks_cached"] < 15
+    U = bsex.u_vector(ctx, _cuda(X[0])).cpu().numpy()
+    print(f"  mixed U rel err {_rel(U, Uo):.2e}")
+    assert _rel(U, Uo) < 1e-5
+    ctx.free()
+
+
 def test_free_electron_closed_form_full_grid():
     """V = 0, one occupied orbital, on the 72^3 / 21,079-plane-wave grid: every
     plane wave is an eigenvector with |G|^2/2 + s 4 pi/(Omega |G|^2)."""
