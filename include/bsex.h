@@ -115,7 +115,9 @@ typedef struct {
   const double *orbitals;     /* host [n_orb][n_pw] orthonormal eigenvectors      */
   const double *eps;          /* host [n_orb] eigenvalues, ascending              */
   int32_t n_extra;            /* extra (conduction) states the solver computes    */
-  double gs_tol;              /* eigen-residual target of the solver (0: 1e-10)   */
+  double gs_tol;              /* eigen-residual target of the solver for the n_val
+                                 occupied states (0: 1e-10); the n_extra states
+                                 above them stop at max(gs_tol, 1e-6)           */
   void *stream;               /* hipStream_t, NULL for the null stream            */
 } bse_system_desc;
 
@@ -154,7 +156,7 @@ typedef struct {
   int64_t tau_blocks;         /* 8x8 pair blocks of the upper triangle            */
   int64_t tau_blocks_cached;  /* blocks held in the FP64 cache                   */
   int64_t tau_bytes;          /* bytes of the FP64 cache                         */
-  double gs_resid;            /* max eigen-residual of the supplied/solved orbitals */
+  double gs_resid;            /* max eigen-residual of the solved occupied orbitals (-1 if supplied) */
   double ks_gap;              /* eps_{n_val+1} - eps_{n_val} when known, else -1  */
   int32_t precision;          /* precision the context was built with            */
   int32_t active_precision;   /* precision bse_apply uses now                    */

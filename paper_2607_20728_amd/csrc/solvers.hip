@@ -27,6 +27,10 @@ constexpr double kMixedFloor = 3e-7;
 constexpr double kDavidsonMinDen = 1e-3;
 // relative residual of each inner FP32 PCG solve of the Z-vector refinement
 constexpr double kMixedInnerTol = 1e-4;
+// eigen-residual the ground state asks of the states above the occupied ones
+// (they serve the preconditioners and the gap check only), unless gs_tol is
+// looser
+constexpr double kExtraStateTol = 1e-6;
 
 int learned_features(bse_ctx* c, const double* U, std::vector<float>& F);
 int learned_eval(bse_ctx* c, const std::vector<float>& F, std::vector<double>& sigma,
@@ -1000,8 +1004,15 @@ int ground_state(bse_ctx* c, int n_want, double tol) {
     std::vector<double> r2;
     BSE_TRY(dots_host(c, Z.p, Z.p, n_want, npw, vec, r2));
     resid = 0;
-    for (double x : r2) resid = std::max(resid, std::sqrt(std::max(0.0, x)));
-    if (resid <= tol) break;
+    double resid_x = 0;  // the states above the occupied ones
+    for (int i = 0; i < n_want; ++i) {
+      const double r = std::sqrt(std::max(0.0, r2[i]));
+      if (i < c->nv)
+        resid = std::max(resid, r);
+      else
+        resid_x = std::max(resid_x, r);
+    }
+    if (resid <= tol && resid_x <= std::max(tol, kExtraStateTol)) break;
     // filter [a, bup] out, amplify below a
     const double a = theta[ns - 1], a0 = theta[0];
     const double e = 0.5 * (bup - a), cc = 0.5 * (bup + a);
