@@ -103,8 +103,8 @@ typedef struct {
   int32_t precision;          /* BSE_FP64 or BSE_MIXED                            */
   int32_t tau_policy;         /* BSE_TAU_*: cache W(phi_v phi_v') or rebuild it   */
   int64_t tau_budget_bytes;   /* cap on tau cache bytes (FP32 and FP64 caches together);
-                                 0 = auto, keeping 4 GB + 200 trial vectors of device
-                                 memory for solver work (18.6 GB at N_v 432,
+                                 0 = auto, keeping 4 GB + 330 trial vectors of device
+                                 memory for solver work (28 GB at N_v 432,
                                  N_pw 21,079); > 0 also drops
                                  that reserve to 1 GB (apply-only use).  BSE_MIXED needs
                                  the whole FP32 cache (ENOMEM otherwise) and gives the
@@ -190,7 +190,7 @@ typedef struct {
   double tol;                 /* residual target; 0 -> 1e-8                        */
   int32_t max_iter;           /* 0 -> 300 (Davidson) / 5000 (CG)                   */
   int32_t block;              /* Davidson block; 0 -> n_states + 4                 */
-  int32_t max_subspace;       /* 0 -> 8 * block                                    */
+  int32_t max_subspace;       /* 0 -> 16 * block, or less if device memory is short */
   const double *x0_dev;       /* optional initial guess, [k][n_val][n_pw]         */
   int32_t n_x0;               /* vectors in x0_dev                                 */
   const double *z0_dev;       /* optional Z-vector initial guess [n_val][n_pw]    */

@@ -114,7 +114,7 @@ double estimate_bytes(const bse_system_desc& d, int prec, long npw, double* tau_
   const double L = nv * npw * 8.0;
   const double grids = 8 * nvh * nr * 16.0 * (prec == BSE_MIXED ? 2.5 : 2.0);
   const double tiles = 4 * 64 * (2.0 * nr + 2.0 * npw + std::max(d.n_pdep, 1)) * 8.0;
-  const double solver = (2 * 40 + 4 * 5 + 8) * L;
+  const double solver = (2 * 16 * 5 + 4 * 5 + 8) * L;  // Davidson of one state: 5-vector blocks
   const double gs = (d.n_val + 56) * npw * 8.0 * 8;
   return *tau_bytes + grids + tiles + solver + gs + 0.5e9;
 }

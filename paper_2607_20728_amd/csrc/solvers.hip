@@ -263,17 +263,29 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
   const int maxit = (o && o->max_iter > 0) ? o->max_iter : 300;
   int nb = (o && o->block > 0) ? o->block : ns + 4;
   if (nb < ns) nb = ns;
-  int maxsub = (o && o->max_subspace > 0) ? o->max_subspace : 8 * nb;
+  // default subspace: 16 blocks (at the defect-supercell size it needs about
+  // 60% of the iterations of an 8-block one), smaller if memory runs short
+  const bool fixed_sub = o && o->max_subspace > 0;
+  int maxsub = fixed_sub ? o->max_subspace : 16 * nb;
   if (maxsub < 3 * nb) maxsub = 3 * nb;
   const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
   BSE_TRY(ensure_apply_work(c, std::min(nb, 8)));
   DVec V(c), AV(c), W(c), AW(c), X(c), AX(c), sm(c);
-  BSE_TRY(V.alloc((size_t)maxsub * L));
-  BSE_TRY(AV.alloc((size_t)maxsub * L));
   BSE_TRY(W.alloc((size_t)2 * nb * L));
   BSE_TRY(AW.alloc((size_t)2 * nb * L));
   BSE_TRY(X.alloc((size_t)nb * L));
   BSE_TRY(AX.alloc((size_t)nb * L));
+  for (;;) {
+    int rc = V.alloc((size_t)maxsub * L);
+    if (rc == BSE_OK) rc = AV.alloc((size_t)maxsub * L);
+    if (rc == BSE_OK) break;
+    ctx_release(c, V.p);
+    ctx_release(c, AV.p);
+    V.p = AV.p = nullptr;
+    if (fixed_sub || maxsub <= 3 * nb) return rc;
+    maxsub = std::max(3 * nb, maxsub * 3 / 4);
+    set_error("%s", "");
+  }
   BSE_TRY(sm.alloc((size_t)maxsub * maxsub + 4 * (size_t)maxsub + 64));
   double* Cd = sm.p;                              // [m][k] coefficients
   double* vecd = sm.p + (size_t)maxsub * maxsub;  // small vectors
