@@ -103,9 +103,9 @@ typedef struct {
   int32_t precision;          /* BSE_FP64 or BSE_MIXED                            */
   int32_t tau_policy;         /* BSE_TAU_*: cache W(phi_v phi_v') or rebuild it   */
   int64_t tau_budget_bytes;   /* cap on tau cache bytes (FP32 and FP64 caches together);
-                                 0 = auto, keeping 4 GB + 330 trial vectors of device
-                                 memory for solver work (28 GB at N_v 432,
-                                 N_pw 21,079); > 0 also drops
+                                 0 = auto, keeping 4 GB + 330 trial vectors (at most
+                                 12% of the device) for solver work (28 GB at
+                                 N_v 432, N_pw 21,079); > 0 also drops
                                  that reserve to 1 GB (apply-only use).  BSE_MIXED needs
                                  the whole FP32 cache (ENOMEM otherwise) and gives the
                                  FP64 cache what is left. */
@@ -341,9 +341,11 @@ int bse_learned_features(bse_ctx *ctx, const double *Xs_dev, const double *Zref_
  * priority) and host thread, largest first, a system being admitted while its
  * device-memory estimate fits mem_budget (a system that fits nothing runs
  * alone).  Each system's tau cache is capped at its own size.  With autotune,
- * the Davidson block apply of every new shape (grid, N_v, precision) is timed
- * under each kernel variant (compile-time or runtime FFT kernels; 4 or 2 lanes
- * per grid point in the tau stream) and the fastest is cached for the process.
+ * the Davidson block apply of each shape class (grid, N_v in buckets of 64,
+ * precision) that occurs more than once in the batch is timed under each
+ * kernel variant (compile-time or runtime FFT kernels; 4 or 2 lanes per grid
+ * point in the tau stream; one warm-up, two timed applies each) and the
+ * fastest is cached for the process; a class met once keeps the defaults.
  * desc.stream and desc.precision are ignored (the batch's are used).
  */
 typedef struct {

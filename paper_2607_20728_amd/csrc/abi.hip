@@ -135,8 +135,11 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   const bool has_budget = d->tau_budget_bytes > 0;
   // without an explicit budget, keep room for the solvers: a 128-vector
   // Davidson subspace and its products, the blocks beside them, graph
-  // staging and the caller's own vectors, about 330 trial vectors in all
-  const double reserve = has_budget ? 1.0e9 : 4.0e9 + 330 * 8.0 * c->nv * npw;
+  // staging and the caller's own vectors, about 330 trial vectors in all,
+  // but at most 12% of the device (the subspace shrinks to what is left)
+  const double reserve =
+      has_budget ? 1.0e9
+                 : 4.0e9 + std::min(330 * 8.0 * c->nv * npw, 0.12 * (double)totalb);
   const long small_tile = std::min(c->nblk, 4L);
   double budget_left = has_budget ? (double)d->tau_budget_bytes : 0.0;
   // rebuild tiles: ~6% of the device, or, for a budgeted context (batches),

@@ -37,7 +37,6 @@ std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune;
 
 int time_variant(bse_ctx* c, int nb, double* X, double* Y, int reps, double* ms) {
-  BSE_TRY(apply_any(c, nb, X, Y));  // warm-up (and lazy buffers)
   hipEvent_t e0 = nullptr, e1 = nullptr;
   BSE_HIP(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -58,9 +57,16 @@ int time_variant(bse_ctx* c, int nb, double* X, double* Y, int reps, double* ms)
   return rc;
 }
 
-// pick (and cache) the fastest variant for this context's shape
+// shape class of a system: grid, band count in buckets of 64, precision and
+// Davidson block (the variants' ranking follows the grid and the band scale)
+TuneKey tune_key(const int grid[3], int nv, int precision, int nb) {
+  return TuneKey{grid[0], grid[1], grid[2], (nv + 63) / 64, precision, nb};
+}
+
+// pick (and cache) the fastest variant for this context's shape class: one
+// warm-up apply, then two timed applies per variant
 int autotune(bse_ctx* c, int nb, int* chosen, double* best_ms) {
-  const TuneKey key{c->basis.grid[0], c->basis.grid[1], c->basis.grid[2], c->nv, c->active, nb};
+  const TuneKey key = tune_key(c->basis.grid, c->nv, c->active, nb);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
@@ -80,11 +86,12 @@ int autotune(bse_ctx* c, int nb, int* chosen, double* best_ms) {
                   c->fft.ct_axis_ok[1];
   int best = 0;
   double bms = 1e300;
+  if (rc == BSE_OK) rc = apply_any(c, nb, X, Y);  // warm-up (and lazy buffers)
   for (int v = 0; v < 4 && rc == BSE_OK; ++v) {
     if ((v & 1) && !ct) continue;  // no compile-time FFT to switch off
     set_variant(c, v);
     double ms = 0.0;
-    rc = time_variant(c, nb, X, Y, 3, &ms);
+    rc = time_variant(c, nb, X, Y, 2, &ms);
     if (rc == BSE_OK && ms < bms) {
       bms = ms;
       best = v;
@@ -120,7 +127,7 @@ double estimate_bytes(const bse_system_desc& d, int prec, long npw, double* tau_
 }
 
 int run_one(const bse_system_desc& d0, const bse_batch_opts& o, hipStream_t st, double tau_bytes,
-            bse_batch_result* r) {
+            bool tune, bse_batch_result* r) {
   using clk = std::chrono::steady_clock;
   auto ms_since = [](clk::time_point t) {
     return std::chrono::duration<double, std::milli>(clk::now() - t).count();
@@ -140,7 +147,7 @@ int run_one(const bse_system_desc& d0, const bse_batch_opts& o, hipStream_t st, 
   bse_solver_opts so{};
   so.tol = o.tol > 0 ? o.tol : 1e-6;
   const int block = 5;  // Davidson block for one state
-  if (rc == BSE_OK && o.autotune) {
+  if (rc == BSE_OK && tune) {
     double ms = 0;
     rc = autotune(c, block, &r->variant, &ms);
   }
@@ -206,6 +213,10 @@ extern "C" int bse_batch_run(const bse_system_desc* descs, int32_t n, const bse_
     results[i].stream_slot = -1;
     results[i].message[0] = 0;
   }
+  // tuning pays only for shape classes that recur in the batch
+  std::map<TuneKey, int> classes;
+  for (int i = 0; i < n; ++i)
+    ++classes[tune_key(descs[i].grid, descs[i].n_val, o.precision, 5)];
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return est[a] > est[b]; });
@@ -246,7 +257,9 @@ extern "C" int bse_batch_run(const bse_system_desc* descs, int32_t n, const bse_
       int rc = st ? BSE_OK : fail(BSE_EHIP, "stream creation failed");
       if (rc == BSE_OK) {
         try {
-          rc = run_one(descs[pick], o, st, taub[pick], r);
+          const bool tune =
+              o.autotune && classes.at(tune_key(descs[pick].grid, descs[pick].n_val, o.precision, 5)) > 1;
+          rc = run_one(descs[pick], o, st, taub[pick], tune, r);
         } catch (...) {
           rc = fail(BSE_ENOMEM, "host allocation failed");
         }
