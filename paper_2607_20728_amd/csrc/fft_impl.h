@@ -651,11 +651,13 @@ static int launch_axis(const FftAxis& a, cplx* data, int dir, int es, int n_inne
   return BSE_OK;
 }
 
-// axis-1 pass over [batch][N1][N2][N3]
+// axis-1 pass over [batch][N1][N2][N3]: the N2 * N3 lines of one grid start
+// at consecutive addresses, so they are tiled as a single range and no tile
+// is left partly empty at the end of each row of N3 lines
 static int x_pass(const FftPlan& p, cplx* data, long batch, int dir, int ld_lim, int st_lim,
                   hipStream_t st) {
-  const int N2 = p.N[1], N3 = p.N[2];
-  return launch_axis(p.ax[0], data, dir, N2 * N3, N3, 1, N2, N3, batch, p.nr, ld_lim, st_lim, st,
+  const int np2 = p.N[1] * p.N[2];
+  return launch_axis(p.ax[0], data, dir, np2, np2, 1, 1, 0, batch, p.nr, ld_lim, st_lim, st,
                      p.ct_axis[BSEX_FFT_PREC]);
 }
 

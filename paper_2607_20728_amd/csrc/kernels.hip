@@ -140,30 +140,40 @@ __global__ void k_real_part(const double2* __restrict__ g, long nr, double* __re
   for (long e = gtid(); e < nr; e += gstride()) out[e] = g[e].x;
 }
 
+// A thread owns one grid point and a group of up to TD_B vectors, so each
+// phi_v(r) is read once per group rather than once per pair of vectors.
+constexpr int TD_B = 8;
+
 template <typename V2, typename R>
 __global__ void k_transition_density(const V2* __restrict__ phir, const V2* __restrict__ a,
                                      int nvh, int nb, long nr, V2* __restrict__ drho) {
-  const long nbh = (nb + 1) / 2;
-  for (long e = gtid(); e < nbh * nr; e += gstride()) {
+  const long ngroups = (nb + TD_B - 1) / TD_B;
+  for (long e = gtid(); e < ngroups * nr; e += gstride()) {
     const long r = e % nr;
-    const int bp = (int)(e / nr);
-    R s[2] = {0, 0};
-    for (int o = 0; o < 2; ++o) {
-      const int b = 2 * bp + o;
-      if (b >= nb) break;
-      const V2* ab = a + (long)b * nvh * nr + r;
-      R acc = 0;
-      for (int p = 0; p < nvh; ++p) {
-        const V2 f = phir[(long)p * nr + r];
-        const V2 x = ab[(long)p * nr];
-        acc += f.x * x.x + f.y * x.y;
+    const int b0 = (int)(e / nr) * TD_B;
+    const int nbg = min(TD_B, nb - b0);
+    R s[TD_B];
+#pragma unroll
+    for (int o = 0; o < TD_B; ++o) s[o] = 0;
+    for (int p = 0; p < nvh; ++p) {
+      const V2 f = phir[(long)p * nr + r];
+#pragma unroll
+      for (int o = 0; o < TD_B; ++o) {
+        if (o < nbg) {
+          const V2 x = a[((long)(b0 + o) * nvh + p) * nr + r];
+          s[o] += f.x * x.x + f.y * x.y;
+        }
       }
-      s[o] = acc;
     }
-    V2 out;
-    out.x = s[0];
-    out.y = s[1];
-    drho[e] = out;
+#pragma unroll
+    for (int o = 0; o < TD_B; o += 2) {
+      if (o < nbg) {
+        V2 out;
+        out.x = s[o];
+        out.y = (o + 1 < nbg) ? s[o + 1] : (R)0;
+        drho[(long)((b0 + o) / 2) * nr + r] = out;
+      }
+    }
   }
 }
 
@@ -771,7 +781,7 @@ int real_part(const double2* grid, long nr, double* out, hipStream_t st) {
 
 int transition_density(const double2* phir, const double2* a, int nv, int nb, long nr,
                        double2* drho, hipStream_t st) {
-  const long n = (long)((nb + 1) / 2) * nr;
+  const long n = (long)((nb + TD_B - 1) / TD_B) * nr;
   if (n <= 0) return BSE_OK;
   hipLaunchKernelGGL((k_transition_density<double2, double>), dim3(nblocks(n)), dim3(TPB), 0, st,
                      phir, a, (nv + 1) / 2, nb, nr, drho);
@@ -781,7 +791,7 @@ int transition_density(const double2* phir, const double2* a, int nv, int nb, lo
 
 int transition_density(const float2* phir, const float2* a, int nv, int nb, long nr, float2* drho,
                        hipStream_t st) {
-  const long n = (long)((nb + 1) / 2) * nr;
+  const long n = (long)((nb + TD_B - 1) / TD_B) * nr;
   if (n <= 0) return BSE_OK;
   hipLaunchKernelGGL((k_transition_density<float2, float>), dim3(nblocks(n)), dim3(TPB), 0, st,
                      phir, a, (nv + 1) / 2, nb, nr, drho);

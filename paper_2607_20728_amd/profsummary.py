@@ -4,6 +4,10 @@
         per-kernel time from a --kernel-trace run (rocpd database), grouped
         by kernel and launch shape;
 
+    python -m paper_2607_20728_amd.profsummary apply <results.db>
+        the kernels of the last apply in a bench trace (those launched after
+        the next-to-last k_tau_stream, up to the last one), in launch order;
+
     python -m paper_2607_20728_amd.profsummary traffic --fetch DIR --write DIR
             --copy-fetch DIR --copy-write DIR --match k_tau_stream --out FILE
             [--command TEXT]
@@ -42,6 +46,18 @@ def kernels(db, rows=30):
     for k, v in sorted(g.items(), key=lambda kv: -sum(kv[1]))[:rows]:
         print(f"{k[0]:34s} {k[1]:10d} {k[2]:6d} {len(v):6d} {sum(v) / len(v) / 1e3:10.1f} "
               f"{sum(v) / 1e6:9.1f} {100 * sum(v) / tot:5.1f}")
+
+
+def last_apply(db):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, grid_x, duration from kernels order by start").fetchall()
+    idx = [i for i, r in enumerate(rows) if "k_tau_stream" in r[0]]
+    if len(idx) < 2:
+        sys.exit("fewer than two k_tau_stream launches in the trace")
+    print(f"{'kernel':48s} {'grid_x':>10s} {'us':>9s}")
+    for n, gx, du in rows[idx[-2] + 1:idx[-1] + 1]:
+        m = re.search(r'(k_[a-z_0-9]+(<[^>]*>)?|__amd_rocclr_\w+)', n)
+        print(f"{(m.group(1) if m else n[:40]):48s} {gx:10d} {du / 1e3:9.1f}")
 
 
 def _counter_rows(d, counter):
@@ -87,6 +103,9 @@ def traffic(a):
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "apply":
+        last_apply(sys.argv[2])
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "kernels":
         kernels(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 30)
         return
