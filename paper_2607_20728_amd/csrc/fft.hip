@@ -4,11 +4,14 @@
 //  * a plane kernel holds one N2 x N3 plane (fixed i1) in LDS (83 KB at
 //    72 x 72) and transforms both in-plane axes, lines going through small
 //    ping-pong scratch buffers in LDS;
-//  * an axis kernel transforms along N1, L neighbouring lines along N3 per
-//    workgroup so every global access touches L consecutive values.
-// Both run mixed-radix (2, 3, 4, 5) Stockham passes (autosort, no bit
-// reversal) with twiddles from a per-axis table exp(-2 pi i k/n) computed on
-// the host in long double.
+//  * an axis kernel transforms along N1, L neighbouring lines per workgroup
+//    (the N2 * N3 lines of a grid taken as one range) so every global access
+//    touches L consecutive values.
+// Both run mixed-radix Stockham passes (autosort, no bit reversal) with
+// twiddles from a per-axis table exp(-2 pi i k/n) computed on the host in
+// long double: radices 2, 3, 4, 5 in the kernels for any length, and 8 and 9
+// first (then 4, 2, 3, 5) in the compile-time kernels for the grid lengths
+// in use, so 72 = 8 x 9 and 64 = 8 x 8 take two passes.
 //
 // Transforms between the wavefunction sphere and the grid are pruned: only
 // the planes |n1| <= n1max that meet the sphere are built (the sphere scatter

@@ -73,6 +73,64 @@ __device__ __forceinline__ void dft5(cplx* v) {
   v[3] = csub(a2, b2);
 }
 
+// v times exp(DIR i theta), given cos(theta) = c and sin(theta) = s
+template <int DIR>
+__device__ __forceinline__ cplx rot(cplx v, real c, real s) {
+  const real ds = DIR > 0 ? s : -s;
+  return mk(c * v.x - ds * v.y, c * v.y + ds * v.x);
+}
+// Length 8 as 2 x 4: with r = 4a + b and m = c + 2d the kernel
+// exp(DIR 2 pi i r m / 8) splits into a length-2 DFT over a, the twiddle
+// exp(DIR 2 pi i b c / 8), and a length-4 DFT over b.
+template <int DIR>
+__device__ __forceinline__ void dft8(cplx* v) {
+  const real h = (real)0.70710678118654752440;  // cos(pi/4) = sin(pi/4)
+  cplx y0[4], y1[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    y0[b] = cadd(v[b], v[b + 4]);
+    y1[b] = csub(v[b], v[b + 4]);
+  }
+  y1[1] = rot<DIR>(y1[1], h, h);
+  y1[2] = mul_i<DIR>(y1[2]);
+  y1[3] = rot<DIR>(y1[3], -h, h);
+  dft4<DIR>(y0);
+  dft4<DIR>(y1);
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    v[2 * d] = y0[d];
+    v[2 * d + 1] = y1[d];
+  }
+}
+// Length 9 as 3 x 3: with r = 3a + b and m = c + 3d, a length-3 DFT over a,
+// the twiddle exp(DIR 2 pi i b c / 9), and a length-3 DFT over b.
+template <int DIR>
+__device__ __forceinline__ void dft9(cplx* v) {
+  const real c1 = (real)0.76604444311897803520, s1 = (real)0.64278760968653932632;   // 2 pi/9
+  const real c2 = (real)0.17364817766693034885, s2 = (real)0.98480775301220805937;   // 4 pi/9
+  const real c4 = (real)-0.93969262078590838405, s4 = (real)0.34202014332566873304;  // 8 pi/9
+  cplx y[3][3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    y[b][0] = v[b];
+    y[b][1] = v[b + 3];
+    y[b][2] = v[b + 6];
+    dft3<DIR>(y[b]);
+  }
+  y[1][1] = rot<DIR>(y[1][1], c1, s1);
+  y[1][2] = rot<DIR>(y[1][2], c2, s2);
+  y[2][1] = rot<DIR>(y[2][1], c2, s2);
+  y[2][2] = rot<DIR>(y[2][2], c4, s4);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cplx t[3] = {y[0][c], y[1][c], y[2][c]};
+    dft3<DIR>(t);
+    v[c] = t[0];
+    v[c + 3] = t[1];
+    v[c + 6] = t[2];
+  }
+}
+
 // One Stockham pass of radix R over L lines: element k of line l is read
 // at in[k*iks + l*ils] and written at out[k*oks + l*ols].  Lines l >= nl
 // are skipped.
@@ -311,8 +369,9 @@ struct Fac {
 constexpr Fac factor(int N) {
   Fac f{0, {0, 0, 0, 0, 0, 0, 0, 0}};
   int m = N;
-  const int rs[4] = {4, 2, 3, 5};
-  for (int q = 0; q < 4; ++q)
+  // radix 8 and 9 first: fewer passes through LDS (72 = 8 x 9, 64 = 8 x 8)
+  const int rs[6] = {8, 4, 2, 9, 3, 5};
+  for (int q = 0; q < 6; ++q)
     while (m % rs[q] == 0) {
       f.r[f.n++] = rs[q];
       m /= rs[q];
@@ -346,6 +405,8 @@ __device__ __forceinline__ void spass_ct(const cplx* __restrict__ in, cplx* __re
     if (R == 3) dft3<DIR>(v);
     if (R == 4) dft4<DIR>(v);
     if (R == 5) dft5<DIR>(v);
+    if (R == 8) dft8<DIR>(v);
+    if (R == 9) dft9<DIR>(v);
     const int base = (j / NS) * NS * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) out[(base + r * NS) * OKS + l * OLS] = v[r];
