@@ -432,13 +432,35 @@ __device__ __forceinline__ void ct_passes(const cplx* src, cplx* S0, cplx* S1,
   }
 }
 
+// Scratch buffers of a plane: line transforms of at most two passes go
+// P -> S0 -> P, longer ones also use S1.
+template <int N2, int N3>
+constexpr int plane_nscratch() {
+  return (factor(N2).n <= 2 && factor(N3).n <= 2) ? 1 : 2;
+}
+
 template <int N2, int N3>
 constexpr int plane_lb() {
+  const int nmax = N2 > N3 ? N2 : N3;
+  const int ns = plane_nscratch<N2, N3>();
+  if (N2 == N3 && ns == 1) {
+    // one scratch buffer: the largest divisor of N (at most 64) whose batch
+    // fits 160 KB in FP64 and 80 KB in FP32 (two workgroups per CU), so a
+    // plane takes few equal batches (72: 2 x 36)
+    const int budget = sizeof(cplx) == 16 ? 163840 : 81920;
+    for (int d = 64; d >= 4; --d)
+      if (N2 % d == 0 && (int)sizeof(cplx) * (N2 * N3 + d * nmax) <= budget) return d;
+  }
   // lines per scratch batch: largest power of two (<= 32) fitting 160 KB
   int lb = 32;
-  const int nmax = N2 > N3 ? N2 : N3;
-  while (lb > 4 && (int)sizeof(cplx) * (N2 * N3 + 2 * lb * nmax) > 163840) lb /= 2;
+  while (lb > 4 && (int)sizeof(cplx) * (N2 * N3 + ns * lb * nmax) > 163840) lb /= 2;
   return lb;
+}
+
+template <int N2, int N3>
+constexpr int plane_lds_bytes() {
+  const int nmax = N2 > N3 ? N2 : N3;
+  return (int)sizeof(cplx) * (N2 * N3 + plane_nscratch<N2, N3>() * plane_lb<N2, N3>() * nmax);
 }
 
 template <int N2, int N3, int DIR, int IN, int OUT>
@@ -452,7 +474,8 @@ __global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_ct(cplx* data, Plan
   extern __shared__ cplx lds[];
   cplx* P = lds;
   cplx* S0 = P + NP2;
-  cplx* S1 = S0 + LB * NM;
+  // with one scratch buffer S1 is never used: alias it to S0
+  cplx* S1 = plane_nscratch<N2, N3>() == 2 ? S0 + LB * NM : S0;
   const long g = blockIdx.x / pa.nplanes;
   const int pl = (int)(blockIdx.x % pa.nplanes);
   const int i1 = pa.plane_i1 ? pa.plane_i1[pl] : pl;
@@ -592,7 +615,7 @@ bool plane_ct_supported(int n2, int n3) {
 
 size_t plane_ct_lds(int n2, int n3) {
 #define C(A, B) \
-  if (n2 == A && n3 == B) return sizeof(cplx) * (size_t)(A * B + 2 * plane_lb<A, B>() * (A > B ? A : B));
+  if (n2 == A && n3 == B) return (size_t)plane_lds_bytes<A, B>();
   BSEX_PLANE_SIZES(C)
 #undef C
   return 0;
