@@ -234,8 +234,9 @@ def dwdR(sys: System, A, Z):
 
 
 def hf_ground_forces(sys: System):
-    """d(sum of occupied eps)/dR = sum_v <phi_v|dV/dR|phi_v>  (parity unpinned;
-    reported only as a convenience, the method's output is d omega/d R)."""
+    """d(sum of occupied eps)/dR = sum_v <phi_v|dV/dR|phi_v> (Hellmann-Feynman;
+    a convenience beside the method's output d omega/d R, pinned against
+    central differences of the occupied eigenvalue sum)."""
     b = sys.b
     rho = (sys.phir ** 2).sum(0)
     rg = np.fft.fftn(rho) / b.n_r

@@ -16,7 +16,9 @@
 * Z-vector CG against the dense sum over states (Eq. 7 with the KS kernels
   zero for the synthetic Hamiltonian);
 * analytic d omega/d R against central finite differences with W frozen
-  (SM Sec. II protocol), translational invariance, zero-trace densities.
+  (SM Sec. II protocol), translational invariance, zero-trace densities;
+* the ground-state Hellmann-Feynman derivative of the occupied eigenvalue
+  sum against central finite differences.
 """
 import numpy as np
 import pytest
@@ -179,6 +181,27 @@ def test_forces_match_finite_difference_c1(c1_solved):
     for site, ax in ((0, 0), (3, 2)):
         fd = solvers.fd_force(S, site, ax, h, method="davidson")
         assert abs(F[site, ax] - fd) < 1e-5
+
+
+def test_hellmann_feynman_ground_forces_m0(m0_solved):
+    """d(sum_v eps_v)/dR = sum_v <phi_v|dV/dR|phi_v> (Hellmann-Feynman for the
+    occupied eigenvalues of H(R)) against central differences of the
+    occupied eigenvalue sum, Richardson-extrapolated."""
+    S = m0_solved["S"]
+    F = solvers.hf_ground_forces(S)
+
+    def eps_sum(site, ax, d):
+        T = solvers.displaced(S, site, ax, d)
+        T.ground_state()
+        return T.eps.sum()
+
+    h = 0.006742
+    for site, ax in ((0, 0), (2, 1), (S.n_sites - 1, 2)):
+        f1 = (eps_sum(site, ax, h) - eps_sum(site, ax, -h)) / (2 * h)
+        f2 = (eps_sum(site, ax, h / 2) - eps_sum(site, ax, -h / 2)) / h
+        rich = (4 * f2 - f1) / 3
+        assert abs(F[site, ax]) > 1e-3
+        assert abs(F[site, ax] - rich) < 1e-7, (site, ax, F[site, ax], rich)
 
 
 @pytest.mark.parametrize("diag_pdep", [False, True])
