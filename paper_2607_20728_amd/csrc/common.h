@@ -95,6 +95,12 @@ int grid_to_compact(const FftPlan& p, const SpherePlan& sp, float2* grid, long b
 // op(A) = A[M][K] (ta = 0) or A^T with A[K][M] (ta = 1); op(B) likewise.
 int dgemm(int ta, int tb, long M, long N, long K, double alpha, const double* A, long lda,
           const double* B, long ldb, double beta, double* C, long ldc, hipStream_t st);
+// the same with the beta term read from Cin (same layout and ldc) instead of
+// C: C = alpha op(A) op(B) + beta Cin.  Cin = NULL reads C; otherwise Cin
+// must not overlap C.
+int dgemm_from(int ta, int tb, long M, long N, long K, double alpha, const double* A, long lda,
+               const double* B, long ldb, double beta, const double* Cin, double* C, long ldc,
+               hipStream_t st);
 // dgemm with K split across workgroups when the output tiles are too few to
 // fill the device (partials in `work`, summed in a fixed order)
 int dgemm_ws(int ta, int tb, long M, long N, long K, double alpha, const double* A, long lda,

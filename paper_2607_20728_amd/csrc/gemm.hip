@@ -32,8 +32,9 @@ template <int TA, int TB, int BM>
 __global__ __launch_bounds__(256) void k_dgemm(long M, long N, long K, double alpha,
                                                const double* __restrict__ A, long lda,
                                                const double* __restrict__ B, long ldb,
-                                               double beta, double* __restrict__ C, long ldc,
-                                               long k_chunk, long c_split_stride) {
+                                               double beta, const double* Cin,
+                                               double* __restrict__ C, long ldc, long k_chunk,
+                                               long c_split_stride) {
   constexpr int WGM = BM == 64 ? 2 : 1;  // waves along M
   constexpr int WGN = 4 / WGM;           // waves along N
   constexpr int TM = BM / (16 * WGM);    // MFMA tiles per wave along M
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(256) void k_dgemm(long M, long N, long K, double al
         const long gn = n0 + wn * 16 * TN + tb * 16 + (lane & 15);
         if (gm < M && gn < N) {
           double v = alpha * acc[ta][tb][t];
-          if (beta != 0.0) v += beta * Cz[gm * ldc + gn];
+          if (beta != 0.0) v += beta * (Cin ? Cin[gm * ldc + gn] : Cz[gm * ldc + gn]);
           Cz[gm * ldc + gn] = v;
         }
       }
@@ -159,10 +160,10 @@ namespace {
 
 void launch(int ta, int tb, int bm, dim3 grid, hipStream_t st, long M, long N, long K,
             double alpha, const double* A, long lda, const double* B, long ldb, double beta,
-            double* C, long ldc, long kc, long cstride) {
+            const double* Cin, double* C, long ldc, long kc, long cstride) {
 #define L3(TA_, TB_, BM_)                                                                      \
   hipLaunchKernelGGL((k_dgemm<TA_, TB_, BM_>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, \
-                     B, ldb, beta, C, ldc, kc, cstride)
+                     B, ldb, beta, Cin, C, ldc, kc, cstride)
 #define L2(TA_, TB_)    \
   if (bm == 16)         \
     L3(TA_, TB_, 16);   \
@@ -189,13 +190,19 @@ long tiles_of(long M, long N) {
 
 int dgemm(int ta, int tb, long M, long N, long K, double alpha, const double* A, long lda,
           const double* B, long ldb, double beta, double* C, long ldc, hipStream_t st) {
+  return dgemm_from(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, nullptr, C, ldc, st);
+}
+
+int dgemm_from(int ta, int tb, long M, long N, long K, double alpha, const double* A, long lda,
+               const double* B, long ldb, double beta, const double* Cin, double* C, long ldc,
+               hipStream_t st) {
   if (M <= 0 || N <= 0) return BSE_OK;
   const int bm = bm_for(M);
   const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + bm - 1) / bm), 1);
   if (grid.y > 65535) return fail(BSE_EINVAL, "dgemm: M too large for the grid");
   const long kc = K > 0 ? K : 1;
   if (K <= 0) alpha = 0.0;
-  launch(ta, tb, bm, grid, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kc, 0L);
+  launch(ta, tb, bm, grid, st, M, N, K, alpha, A, lda, B, ldb, beta, Cin, C, ldc, kc, 0L);
   BSE_HIP(hipGetLastError());
   return BSE_OK;
 }
@@ -227,7 +234,7 @@ int dgemm_ws(int ta, int tb, long M, long N, long K, double alpha, const double*
   const int bm = bm_for(M);
   const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + bm - 1) / bm), (unsigned)s);
   if (grid.y > 65535) return fail(BSE_EINVAL, "dgemm: M too large for the grid");
-  launch(ta, tb, bm, grid, st, M, N, K, 1.0, A, lda, B, ldb, 0.0, work, N, kc, M * N);
+  launch(ta, tb, bm, grid, st, M, N, K, 1.0, A, lda, B, ldb, 0.0, nullptr, work, N, kc, M * N);
   BSE_HIP(hipGetLastError());
   const long tot = M * N;
   hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,
@@ -263,7 +270,7 @@ int dgemm_tall(long M, long N, long K, double alpha, const double* A, long lda, 
   if (s < 1) s = 1;
   const int bm = bm_for(M);
   const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + bm - 1) / bm), (unsigned)s);
-  launch(0, 1, bm, grid, st, M, N, K, 1.0, A, lda, B, ldb, 0.0, work, N, kc, M * N);
+  launch(0, 1, bm, grid, st, M, N, K, 1.0, A, lda, B, ldb, 0.0, nullptr, work, N, kc, M * N);
   BSE_HIP(hipGetLastError());
   const long tot = M * N;
   hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,

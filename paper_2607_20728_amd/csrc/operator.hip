@@ -148,9 +148,9 @@ int proj_c(bse_ctx* c, const double* X, double* Y, int nset) {
   const long npw = c->basis.npw, nv = c->nv, n = (long)nset * nv;
   // Ov[w][(s,v)] = <phi_w | x_{s,v}>
   BSE_TRY(gemm(c, 0, 1, nv, n, npw, 1.0, c->Phi, npw, X, npw, 0.0, c->Ov, n));
-  if (Y != X) BSE_HIP(hipMemcpyAsync(Y, X, sizeof(double) * n * npw, hipMemcpyDeviceToDevice, c->st));
-  // Y -= Ov^T Phi
-  BSE_TRY(dgemm(1, 0, n, npw, nv, -1.0, c->Ov, n, c->Phi, npw, 1.0, Y, npw, c->st));
+  // Y = X - Ov^T Phi (the GEMM reads X as its C input: no copy when Y != X)
+  BSE_TRY(dgemm_from(1, 0, n, npw, nv, -1.0, c->Ov, n, c->Phi, npw, 1.0, Y != X ? X : nullptr, Y,
+                     npw, c->st));
   return BSE_OK;
 }
 
