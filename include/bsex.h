@@ -250,6 +250,19 @@ int bse_zvector_solve(bse_ctx *ctx, const double *Xs_dev, const bse_solver_opts 
  * dwdR_host [n_sites][3].  The excitation-energy force is -dwdR. */
 int bse_forces(bse_ctx *ctx, const double *Xs_dev, const double *Z_dev, double *dwdR_host);
 
+/* The ground-state part of the excited-state force: the paper writes the
+ * excited-state force as the ground-state force minus d omega / d R (the
+ * sentence introducing Eq. 4).  For the synthetic Hamiltonian H = T + V,
+ * whose ground-state energy is the occupied eigenvalue sum, that part is the
+ * Hellmann-Feynman derivative
+ *   dE/dR_{I,a} = sum_v <phi_v| dV/dR_{I,a} |phi_v>
+ *              = Omega sum_G Re[ conj(-i G_a V_I(G)) rho(G) ],  rho = sum_v phi_v^2,
+ * per unit occupation (multiply by the spin factor for a spin-degenerate
+ * ground state).  Uses the context's occupied orbitals; no other input.
+ * dEdR_host [n_sites][3] (may be NULL when n_sites = 0).  The excited-state
+ * force on the surface E + omega is -(dEdR + dwdR). */
+int bse_ground_state_forces(bse_ctx *ctx, double *dEdR_host);
+
 /* Per-phase device time of the calls since the last reset, measured with HIP
  * events on the context's stream while enabled (off by default). */
 typedef struct {

@@ -25,6 +25,7 @@ TAU_AUTO, TAU_CACHE, TAU_REBUILD = 0, 1, 2
 SYMBOLS = ("bse_abi_version", "bse_last_error", "bse_warm_up", "bse_basis_size", "bse_basis_gvectors",
            "bse_init_system", "bse_get_info", "bse_get_orbitals", "bse_apply",
            "bse_davidson", "bse_u_vector", "bse_zvector_solve", "bse_forces",
+           "bse_ground_state_forces",
            "bse_set_precision", "bse_set_profiling", "bse_get_phase_times",
            "bse_mlp_create", "bse_mlp_n_params", "bse_mlp_set_params", "bse_mlp_get_params",
            "bse_mlp_set_norm", "bse_mlp_forward", "bse_mlp_train_step", "bse_mlp_free",
@@ -124,6 +125,7 @@ def lib():
     L.bse_zvector_solve.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(SolverOpts), C.c_void_p,
                                     C.POINTER(SolverStats)]
     L.bse_forces.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp]
+    L.bse_ground_state_forces.argtypes = [C.c_void_p, dp]
     L.bse_set_precision.argtypes = [C.c_void_p, C.c_int32]
     fp = C.POINTER(C.c_float)
     L.bse_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
@@ -400,6 +402,13 @@ def zvector_solve(ctx, Xs, *, tol=1e-8, max_iter=0, z0=None, use_learned=False, 
 def forces(ctx, Xs, Z, n_sites):
     out = np.zeros((max(n_sites, 1), 3))
     _check(lib().bse_forces(ctx.h, _dev(Xs, "Xs"), _dev(Z, "Z"), _dptr(out)))
+    return out[:n_sites]
+
+
+def ground_state_forces(ctx, n_sites):
+    """bse_ground_state_forces: d(sum_v eps_v)/dR [n_sites][3] (Hellmann-Feynman)."""
+    out = np.zeros((max(n_sites, 1), 3))
+    _check(lib().bse_ground_state_forces(ctx.h, _dptr(out)))
     return out[:n_sites]
 
 

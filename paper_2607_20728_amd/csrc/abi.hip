@@ -16,6 +16,7 @@ int u_vector(bse_ctx* c, const double* Xs, double* U);
 int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
             bse_solver_stats* stats);
 int forces(bse_ctx* c, const double* Xs, const double* Zin, double* dwdR_host);
+int ground_state_forces(bse_ctx* c, double* dEdR_host);
 }  // namespace bsex
 
 using namespace bsex;
@@ -556,6 +557,11 @@ int bse_zvector_solve(bse_ctx* c, const double* Xs, const bse_solver_opts* opts,
 int bse_forces(bse_ctx* c, const double* Xs, const double* Z, double* dwdR_host) {
   if (!c || !Xs || !Z || (!dwdR_host && c->nsites > 0)) return fail(BSE_EINVAL, "NULL argument");
   return guarded(c, [&] { return forces(c, Xs, Z, dwdR_host); });
+}
+
+int bse_ground_state_forces(bse_ctx* c, double* dEdR_host) {
+  if (!c || (!dEdR_host && c->nsites > 0)) return fail(BSE_EINVAL, "NULL argument");
+  return guarded(c, [&] { return ground_state_forces(c, dEdR_host); });
 }
 
 int bse_set_profiling(bse_ctx* c, int32_t on) {

@@ -115,6 +115,8 @@ int coulomb_kernel(const int grid[3], const double cell[3], double* out, hipStre
 int force_density(const double2* a, const double2* phit, const double2* z, const double2* phir,
                   int nv, long nr, double2* rho, hipStream_t st);
 // partial sums for dw/dR: out[site][3] (host) from the forward transform of rho
+// rho[r] = (sum_v phi_v(r)^2, 0) over the nv orbitals of phir
+int occupied_density(const double2* phir, int nv, long nr, double2* rho, hipStream_t st);
 int force_reduce(const double2* rhoG, const double* xyz, const double* depth,
                  const double* width, int nsites, const int grid[3], const double cell[3],
                  double* part, long part_len, double* out_dev, hipStream_t st);

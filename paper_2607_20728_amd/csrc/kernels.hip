@@ -502,6 +502,19 @@ __global__ void k_force_density(const double2* __restrict__ a, const double2* __
   }
 }
 
+// occupied density sum_v phi_v(r)^2 (two orbitals per complex grid)
+__global__ void k_occupied_density(const double2* __restrict__ phir, int nvh, long nr,
+                                   double2* __restrict__ rho) {
+  for (long r = gtid(); r < nr; r += gstride()) {
+    double s = 0.0;
+    for (int p = 0; p < nvh; ++p) {
+      const double2 f = phir[(long)p * nr + r];
+      s += f.x * f.x + f.y * f.y;
+    }
+    rho[r] = make_double2(s, 0.0);
+  }
+}
+
 // part[site][chunk][3]; G over chunk ranges; fixed-order tree reduction
 __global__ __launch_bounds__(256) void k_force_partial(
     const double2* __restrict__ rhoG, const double* __restrict__ xyz,
@@ -1040,6 +1053,13 @@ int force_density(const double2* a, const double2* phit, const double2* z, const
                   int nv, long nr, double2* rho, hipStream_t st) {
   hipLaunchKernelGGL(k_force_density, dim3(nblocks(nr)), dim3(TPB), 0, st, a, phit, z, phir,
                      (nv + 1) / 2, nr, rho);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int occupied_density(const double2* phir, int nv, long nr, double2* rho, hipStream_t st) {
+  hipLaunchKernelGGL(k_occupied_density, dim3(nblocks(nr)), dim3(TPB), 0, st, phir, (nv + 1) / 2,
+                     nr, rho);
   CHECK_LAUNCH();
   return BSE_OK;
 }

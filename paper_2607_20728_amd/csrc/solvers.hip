@@ -945,6 +945,27 @@ int forces(bse_ctx* c, const double* Xs, const double* Zin, double* dwdR_host) {
   return BSE_OK;
 }
 
+// d(sum_v eps_v)/dR = sum_v <phi_v| dV/dR |phi_v> (Hellmann-Feynman): the
+// occupied density contracted with each site's potential derivative, the
+// same reduction as d omega/d R with rho_t replaced by sum_v phi_v^2.
+int ground_state_forces(bse_ctx* c, double* dEdR_host) {
+  const long nr = c->basis.nr;
+  if (c->nsites <= 0) return BSE_OK;
+  DVec rho(c), part(c), outd(c);
+  const long pl = force_reduce_work(c->nsites, nr);
+  BSE_TRY(rho.alloc((size_t)2 * nr));  // one complex grid
+  BSE_TRY(part.alloc((size_t)std::max(pl, 1L)));
+  BSE_TRY(outd.alloc((size_t)3 * c->nsites));
+  double2* rg = reinterpret_cast<double2*>(rho.p);
+  BSE_TRY(occupied_density(c->phir, c->nv, nr, rg, c->st));
+  BSE_TRY(fft3d(c->fft, rg, 1, -1, c->st));
+  BSE_TRY(force_reduce(rg, c->sites, c->sites + 3 * c->nsites, c->sites + 4 * c->nsites,
+                       c->nsites, c->basis.grid, c->basis.cell, part.p, pl, outd.p, c->st));
+  BSE_TRY(to_host(c, outd.p, dEdR_host, (size_t)3 * c->nsites));
+  BSE_HIP(hipStreamSynchronize(c->st));
+  return BSE_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Ground state: lowest n_want eigenpairs of H = T + V by Chebyshev-filtered
 // subspace iteration (the scaled three-term filter of Zhou, Saad, Tiago and

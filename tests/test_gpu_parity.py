@@ -209,6 +209,28 @@ def test_end_to_end_c1_library_ground_state():
     ctx.free()
 
 
+@pytest.mark.parametrize("name", ["m0", "c1"])
+def test_ground_state_forces(name):
+    """d(sum_v eps_v)/dR (Hellmann-Feynman, the ground-state part of the
+    excited-state force) against the oracle with the same orbitals, in an FP64
+    and a mixed context, and from the library's own ground state."""
+    print(f"[gpu] ground-state forces {name}", flush=True)
+    S, d = _oracle(name)
+    Fo = solvers.hf_ground_forces(S)
+    assert np.abs(Fo).max() > 1e-3
+    for prec in (bsex.FP64, bsex.MIXED):
+        ctx = _lib_ctx(S, d, precision=prec)
+        F = bsex.ground_state_forces(ctx, S.n_sites)
+        assert F.shape == Fo.shape
+        assert np.abs(F - Fo).max() < 1e-9 * np.abs(Fo).max(), prec
+        ctx.free()
+    ctx = bsex.init_from_synth(d, n_extra=8)
+    F = bsex.ground_state_forces(ctx, S.n_sites)
+    print(f"  library ground state: max diff {np.abs(F - Fo).max():.2e}")
+    assert np.abs(F - Fo).max() < 1e-6
+    ctx.free()
+
+
 def test_full_size_c2_properties():
     """At the benchmark's own size (N_v = 432, 72^3, 21,079 plane waves, in the
     launch configuration bench.py times: whole FP32 cache, FP64 cache beside
