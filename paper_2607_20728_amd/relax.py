@@ -29,6 +29,8 @@ def evaluate(sysd, xyz, *, surface="es", spring=5.0, f_occ=2.0, tol=1e-9, n_extr
              precision=bsex.FP64):
     """(E, dE/dR [n_sites][3]) of the ground- ("gs") or excited-state ("es")
     surface at site positions xyz, from a fresh context."""
+    if surface not in ("gs", "es"):
+        raise ValueError(f"surface {surface!r}: 'gs' or 'es'")
     d = dict(sysd)
     d["site_xyz"] = np.ascontiguousarray(xyz, dtype=float)
     x0 = np.asarray(sysd["site_xyz"], dtype=float)
@@ -43,8 +45,6 @@ def evaluate(sysd, xyz, *, surface="es", spring=5.0, f_occ=2.0, tol=1e-9, n_extr
             Z, _ = bsex.zvector_solve(ctx, X[0], tol=tol)
             E += float(w[0])
             G = G + bsex.forces(ctx, X[0], Z, n)
-        elif surface != "gs":
-            raise ValueError(f"surface {surface!r}: 'gs' or 'es'")
     finally:
         ctx.free()
     return E, G
@@ -53,10 +53,15 @@ def evaluate(sysd, xyz, *, surface="es", spring=5.0, f_occ=2.0, tol=1e-9, n_extr
 def bfgs(fun, x0, *, gtol=1e-5, max_steps=50, max_step=0.2):
     """Minimise fun(x) -> (f, grad) by BFGS on the inverse Hessian with an
     Armijo backtracking line search; steps are capped at max_step (bohr) per
-    coordinate.  Returns (x, f, grad, history of (f, |grad|_max))."""
+    coordinate.  A line search that finds no decrease resets the Hessian to
+    the identity and tries again from the same point; if that fails too the
+    minimisation stops there (the energies carry no more information), so
+    the accepted energies never increase.  Returns (x, f, grad, history of
+    (f, |grad|_max))."""
     x = np.asarray(x0, dtype=float).copy()
     f, g = fun(x)
     H = np.eye(x.size)
+    reset = True
     hist = [(f, float(np.abs(g).max()))]
     for _ in range(max_steps):
         if np.abs(g).max() < gtol:
@@ -74,9 +79,19 @@ def bfgs(fun, x0, *, gtol=1e-5, max_steps=50, max_step=0.2):
         while True:
             xn = x + t * p
             fn, gn = fun(xn)
-            if fn <= f + 1e-4 * t * slope or t < 1e-4:
+            if fn <= f + 1e-4 * t * slope:
                 break
             t *= 0.5
+            if t < 1e-4:
+                xn = None
+                break
+        if xn is None:
+            if reset:
+                break
+            H = np.eye(x.size)
+            reset = True
+            continue
+        reset = False
         s, y = xn - x, gn - g
         sy = float(s @ y)
         if sy > 1e-12:

@@ -38,13 +38,17 @@ def test_delta_q():
 
 def _oracle_evaluator(cfg, b):
     def ev(sysd, xyz, *, surface="gs", spring=5.0, f_occ=2.0):
-        assert surface == "gs"
         S = model.System(b, np.asarray(xyz), sysd["site_depth"], sysd["site_width"],
                          sysd["pdep"], sysd["lam"], cfg.n_val)
-        S.ground_state()
+        S.ground_state(n_extra=8)
         x0 = np.asarray(sysd["site_xyz"])
         E = f_occ * S.eps.sum() + 0.5 * spring * np.sum((xyz - x0) ** 2)
         G = f_occ * solvers.hf_ground_forces(S) + spring * (xyz - x0)
+        if surface == "es":
+            w, X, _ = solvers.davidson(S, 1, tol=1e-10)
+            Z, _ = solvers.zvector_cg(S, solvers.u_vector(S, X[0]), tol=1e-10)
+            E += w[0]
+            G = G + solvers.dwdR(S, X[0], Z)
         return E, G
     return ev
 
@@ -66,3 +70,19 @@ def test_ground_state_relaxation_with_the_oracle():
     for h in (0.02, -0.02):
         assert ev(d, xyz + h * u)[0] > E
     assert relax.delta_q(xyz, d["site_xyz"]) > 1e-3
+
+
+def test_excited_state_relaxation_with_the_oracle():
+    """Both minima of the tiny system with the oracle as the evaluator: the
+    excited-state minimum differs from the ground-state one (Delta Q > 0)
+    and each is a stationary point of its own surface only."""
+    cfg = synth.get_config("m0")
+    b = basis.Basis(cfg.cell, cfg.grid, cfg.ecut)
+    d = synth.make_system(cfg, b.n_pw, n_trial=1)
+    ev = _oracle_evaluator(cfg, b)
+    xg, _, hg = relax.relax(d, surface="gs", evaluator=ev, gtol=1e-6, max_steps=60)
+    xe, _, he = relax.relax(d, surface="es", evaluator=ev, gtol=1e-6, max_steps=60)
+    assert hg[-1][1] < 1e-6 and he[-1][1] < 1e-6
+    assert all(h1[0] <= h0[0] + 1e-12 for h0, h1 in zip(he, he[1:]))
+    assert relax.delta_q(xg, xe) > 1e-3
+    assert np.abs(ev(d, xg, surface="es")[1]).max() > 1e-4   # not a minimum of E_ES
