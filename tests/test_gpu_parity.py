@@ -53,6 +53,8 @@ def test_apply_m0_every_kernel(kmask):
         X = d["trial"][:nb]
         Y = bsex.apply(ctx, _cuda(X)).cpu().numpy()
         assert _rel(Y, S.apply(X)) < 1e-11, (kmask, nb)
+    # an empty block is a no-op (n_b = 0)
+    assert bsex.apply(ctx, _cuda(d["trial"][:0])).shape[0] == 0
     ctx.free()
 
 
