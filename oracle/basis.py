@@ -18,6 +18,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import fft as _fft
+
 
 class Basis:
     def __init__(self, cell, grid, ecut):
@@ -92,12 +94,12 @@ class Basis:
     def to_grid(self, x):
         """Real-space values f(r_j) of x[..., n_pw] on the grid."""
         F = self.coeffs(x)
-        f = np.fft.ifftn(F, axes=(-3, -2, -1)) * self.n_r
+        f = _fft.ifftn(F, axes=(-3, -2, -1)) * self.n_r
         return f.real.copy()
 
     def from_grid(self, g):
         """Projection <e_k|g> (grid quadrature) of real grid values g."""
-        G = np.fft.fftn(np.asarray(g, dtype=np.float64), axes=(-3, -2, -1)) / self.n_r
+        G = _fft.fftn(np.asarray(g, dtype=np.float64), axes=(-3, -2, -1)) / self.n_r
         return self.from_coeffs(G)
 
     def from_coeffs(self, G):

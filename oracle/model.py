@@ -27,6 +27,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import fft as _fft
+
 from .basis import Basis
 
 # kernel mask bits (same meaning on both sides; a test hook)
@@ -55,7 +57,7 @@ class System:
         b = basis
         self.T = 0.5 * b.g2
         self.VG = self.potential_G()
-        self.Vr = (np.fft.ifftn(self.VG) * b.n_r).real
+        self.Vr = (_fft.ifftn(self.VG) * b.n_r).real
         self.V0 = self.VG[0, 0, 0].real
         g2 = b.grid_g2
         vc = np.zeros_like(g2)
@@ -122,8 +124,8 @@ class System:
     # ---- Coulomb and W ----------------------------------------------------
     def poisson(self, rho):
         """v_c * rho on the grid (v_c(G) = 4 pi/|G|^2, v_c(0) = 0)."""
-        G = np.fft.fftn(rho, axes=(-3, -2, -1))
-        return np.fft.ifftn(G * self.vc, axes=(-3, -2, -1)).real
+        G = _fft.fftn(rho, axes=(-3, -2, -1))
+        return _fft.ifftn(G * self.vc, axes=(-3, -2, -1)).real
 
     def pdep_term(self, rho):
         """Low-rank part of Eq. 3 acting on a grid density:
@@ -192,6 +194,40 @@ class System:
                 Z = self.b.from_grid(z)
             Y[i] = self.proj_c(Z)
         return Y[0] if one else Y
+
+    def apply_bands(self, X, bands):
+        """Rows `bands` of Y = P_c M P_c X for X[n_b][N_v][N_pw], without the
+        whole tau: tau_{v'v} = W(phi_v' phi_v) is built for every v' and the
+        requested output bands v only (Eq. 2c).  Each output row needs every
+        input row (P_c on the input, Drho of Eq. 2b and the sum over v'), but
+        the output projector acts on each row alone, so the rows returned are
+        those of the full apply.  Returns [n_b][len(bands)][N_pw]."""
+        X = np.asarray(X, dtype=np.float64)
+        bands = np.asarray(bands, dtype=np.int64)
+        mask = self.kmask
+        taus = None
+        if mask & (K_1D_BARE | K_1D_PDEP):
+            taus = [self.apply_W(self.phir * self.phir[v]) for v in bands]
+        Y = np.empty((X.shape[0], len(bands), X.shape[2]))
+        for i in range(X.shape[0]):
+            A = self.proj_c(X[i])
+            ar = self.b.to_grid(A)
+            z = np.zeros((len(bands),) + self.b.grid)
+            if mask & K_1E:
+                drho = (self.phir * ar).sum(0)
+                z += self.spin * self.poisson(drho) * self.phir[bands]
+            if taus is not None:
+                for k in range(len(bands)):
+                    z[k] -= np.einsum("uxyz,uxyz->xyz", taus[k], ar)
+            Ab = A[bands]
+            if mask & K_D:
+                z += self.Vr * ar[bands]
+                Z = self.b.from_grid(z) + (self.T[None, :] - self.eps[bands][:, None]
+                                           + self.scissor) * Ab
+            else:
+                Z = self.b.from_grid(z)
+            Y[i] = Z - (Z @ self.phi.T) @ self.phi
+        return Y
 
     def diag_precond(self):
         """Kinetic diagonal model of D used to precondition Davidson:

@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import fft as _fft
 from .model import K_1D_BARE, K_1D_PDEP, K_1E, PRECOND_SHIFT, System
 
 
@@ -223,7 +224,7 @@ def dwdR(sys: System, A, Z):
     over the full grid, rho_t = Drho_x + Drho_z.  Returns [n_sites][3]."""
     b = sys.b
     rx, rz = densities(sys, A, Z)
-    rg = np.fft.fftn(rx + rz) / b.n_r
+    rg = _fft.fftn(rx + rz) / b.n_r
     out = np.zeros((sys.n_sites, 3))
     for i in range(sys.n_sites):
         vi = sys.site_potential_G(i)
@@ -239,7 +240,7 @@ def hf_ground_forces(sys: System):
     central differences of the occupied eigenvalue sum)."""
     b = sys.b
     rho = (sys.phir ** 2).sum(0)
-    rg = np.fft.fftn(rho) / b.n_r
+    rg = _fft.fftn(rho) / b.n_r
     out = np.zeros((sys.n_sites, 3))
     for i in range(sys.n_sites):
         vi = sys.site_potential_G(i)

@@ -22,7 +22,7 @@ import math
 import numpy as np
 
 __all__ = ["Config", "CONFIGS", "get_config", "make_system", "diamond_sites",
-           "honeycomb_sites", "c5_geometry", "c4_systems", "C4_GRIDS"]
+           "honeycomb_sites", "c5_geometry", "c4_systems", "C4_GRIDS", "random_orbitals"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -193,3 +193,18 @@ def make_system(cfg: Config | str, n_pw: int, *, seed: int | None = None,
     if n_trial:
         out["trial"] = rng.standard_normal((n_trial, cfg.n_val, n_pw))
     return out
+
+
+def random_orbitals(n_pw: int, n_val: int, n_extra: int = 0, seed: int = 0):
+    """A made-up orbital set for operator parity at sizes where no dense
+    ground state is affordable: n_val + n_extra orthonormal rows [n][n_pw]
+    (Householder QR of an N(0,1) matrix, diag(R) > 0) and ascending made-up
+    energies, occupied in [-1, -0.3] Ha and the extra states in [0.1, 0.5] Ha.
+    They are not eigenpairs of any Hamiltonian: the operator apply takes
+    orbitals and energies as inputs and does not assume that."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = n_val + n_extra
+    q, r = np.linalg.qr(rng.standard_normal((n_pw, n)))
+    q = q * np.sign(np.diag(r))[None, :]
+    eps = np.concatenate([np.linspace(-1.0, -0.3, n_val), np.linspace(0.1, 0.5, n_extra)])
+    return np.ascontiguousarray(q.T), eps

@@ -229,3 +229,25 @@ def test_translational_invariance(diag_pdep):
     F = solvers.dwdR(S, X[0], Z)
     assert np.abs(F).max() > 1e-3
     assert np.abs(F.sum(0)).max() < 1e-9
+
+
+# --------------------------------------------------------------------------
+# the band-subset apply used for parity at full size
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kmask", [K_D, K_D | K_1E, K_D | K_1D_BARE | K_1D_PDEP, K_ALL])
+def test_band_subset_apply_equals_rows_of_full_apply(kmask):
+    """apply_bands builds tau only for the requested output bands; its rows
+    equal the full apply's, with ground-state and with made-up orbitals."""
+    for name in ("m0", "c1"):
+        S, d = _oracle_system(name, kmask=kmask, scissor=0.05)
+        rng = np.random.default_rng(5)
+        X = rng.standard_normal((3, S.n_val, S.b.n_pw))
+        bands = [0, S.n_val // 2, S.n_val - 1]
+        Yf = S.apply(X)[:, bands]
+        Yb = S.apply_bands(X, bands)
+        assert np.abs(Yb - Yf).max() < 1e-13 * np.abs(Yf).max(), name
+    phi, eps = synth.random_orbitals(S.b.n_pw, S.n_val, 4, seed=9)
+    S.set_orbitals(phi[:S.n_val], eps[:S.n_val])
+    assert np.abs(phi @ phi.T - np.eye(len(phi))).max() < 1e-13
+    Yf = S.apply(X)[:, bands]
+    assert np.abs(S.apply_bands(X, bands) - Yf).max() < 1e-13 * np.abs(Yf).max()
