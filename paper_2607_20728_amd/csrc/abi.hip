@@ -41,13 +41,12 @@ void ctx_destroy(bse_ctx* c) {
   fft_plan_free(&c->fft);
   sphere_plan_free(&c->sp);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  stage_free(&c->hstage);
   delete c;
 }
 
 int upload(bse_ctx* c, void* dst, const void* src, size_t bytes) {
-  BSE_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->st));
-  BSE_HIP(hipStreamSynchronize(c->st));
-  return BSE_OK;
+  return stage_h2d(&c->hstage, src, dst, bytes, c->st);
 }
 
 int validate(const bse_system_desc* d) {

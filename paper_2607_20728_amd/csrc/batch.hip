@@ -1,5 +1,5 @@
-// Uneven batches of independent systems: a host scheduler keeps up to
-// n_streams systems in flight, each on its own HIP stream and host thread,
+// Uneven batches of independent systems: a host scheduler (batch_sched.h) keeps up
+// to n_streams systems in flight, each on its own HIP stream and host thread,
 // largest first, admitting a system only while its device-memory estimate
 // fits the batch budget.  Per shape (grid, N_v, precision, block) an
 // autotuner times the Davidson block apply under each kernel variant and
@@ -19,11 +19,15 @@
 #include <vector>
 
 #include "context.h"
+#include "batch_sched.h"
 
 namespace bsex {
 const char* last_error();
 
 namespace {
+
+// stack of each slot thread (solver host code, HIP runtime, profiler callbacks)
+constexpr size_t kSlotStack = (size_t)64 << 20;
 
 // variant bits: 1 = runtime-length FFT kernels, 2 = two lanes per grid point
 // in the tau stream (instead of four)
@@ -217,73 +221,42 @@ extern "C" int bse_batch_run(const bse_system_desc* descs, int32_t n, const bse_
   std::map<TuneKey, int> classes;
   for (int i = 0; i < n; ++i)
     ++classes[tune_key(descs[i].grid, descs[i].n_val, o.precision, 5)];
-  std::vector<int> order(n);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return est[a] > est[b]; });
-  std::mutex mu;
-  std::condition_variable cv;
-  std::vector<char> started(n, 0);
-  double reserved = 0.0;
-  int running = 0, left = n;
-  auto worker = [&](int slot) {
+  // one stream per slot thread, created and destroyed on that thread
+  std::vector<hipStream_t> streams(ns, nullptr);
+  BatchHooks hooks;
+  hooks.slot_begin = [&](int slot) {
     (void)hipSetDevice(dev);
-    hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
-    for (;;) {
-      int pick = -1;
-      {
-        std::unique_lock<std::mutex> lk(mu);
-        for (;;) {
-          if (left == 0) break;
-          for (int i : order)
-            if (!started[i] && (reserved + est[i] <= budget || running == 0)) {
-              pick = i;
-              break;
-            }
-          if (pick >= 0) break;
-          bool any = false;
-          for (int i : order) any = any || !started[i];
-          if (!any) break;
-          cv.wait(lk);
-        }
-        if (pick < 0) break;
-        started[pick] = 1;
-        reserved += est[pick];
-        ++running;
-        --left;
+    if (hipStreamCreateWithFlags(&streams[slot], hipStreamNonBlocking) != hipSuccess)
+      streams[slot] = nullptr;
+  };
+  hooks.run = [&](int slot, int pick) {
+    bse_batch_result* r = &results[pick];
+    r->stream_slot = slot;
+    hipStream_t st = streams[slot];
+    int rc = st ? BSE_OK : fail(BSE_EHIP, "stream creation failed");
+    if (rc == BSE_OK) {
+      try {
+        const bool tune =
+            o.autotune && classes.at(tune_key(descs[pick].grid, descs[pick].n_val, o.precision, 5)) > 1;
+        rc = run_one(descs[pick], o, st, taub[pick], tune, r);
+      } catch (...) {
+        rc = fail(BSE_ENOMEM, "host allocation failed");
       }
-      bse_batch_result* r = &results[pick];
-      r->stream_slot = slot;
-      int rc = st ? BSE_OK : fail(BSE_EHIP, "stream creation failed");
-      if (rc == BSE_OK) {
-        try {
-          const bool tune =
-              o.autotune && classes.at(tune_key(descs[pick].grid, descs[pick].n_val, o.precision, 5)) > 1;
-          rc = run_one(descs[pick], o, st, taub[pick], tune, r);
-        } catch (...) {
-          rc = fail(BSE_ENOMEM, "host allocation failed");
-        }
-      }
-      r->status = rc;
-      if (rc != BSE_OK) {
-        std::strncpy(r->message, bse_last_error(), sizeof(r->message) - 1);
-        r->message[sizeof(r->message) - 1] = 0;
-      }
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        reserved -= est[pick];
-        --running;
-      }
-      cv.notify_all();
     }
-    if (st) {
-      (void)hipStreamSynchronize(st);
-      (void)hipStreamDestroy(st);
+    r->status = rc;
+    if (rc != BSE_OK) {
+      std::strncpy(r->message, bse_last_error(), sizeof(r->message) - 1);
+      r->message[sizeof(r->message) - 1] = 0;
     }
   };
-  std::vector<std::thread> th;
-  for (int s = 0; s < ns; ++s) th.emplace_back(worker, s);
-  for (auto& t : th) t.join();
+  hooks.slot_end = [&](int slot) {
+    if (streams[slot]) {
+      (void)hipStreamSynchronize(streams[slot]);
+      (void)hipStreamDestroy(streams[slot]);
+    }
+  };
+  if (schedule_batch(n, est, budget, ns, kSlotStack, hooks) != 0)
+    return fail(BSE_EINVAL, "no batch worker thread could be started");
   for (int i = 0; i < n; ++i)
     if (results[i].status != BSE_OK)
       return fail(results[i].status, "system %d: %s", i, results[i].message);

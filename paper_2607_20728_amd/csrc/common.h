@@ -29,6 +29,17 @@ int fail(int code, const char* fmt, ...);
     if (rc_ != BSE_OK) return rc_;    \
   } while (0)
 
+// ---- host <-> device copies ------------------------------------------------------
+// A pinned host buffer through which every copy between device memory and a
+// caller's (pageable) host buffer goes; synchronous on `st` when it returns.
+struct HostStage {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+int stage_d2h(HostStage* s, const void* dev, void* host, size_t bytes, hipStream_t st);
+int stage_h2d(HostStage* s, const void* host, void* dev, size_t bytes, hipStream_t st);
+void stage_free(HostStage* s);
+
 // ---- basis (host) -------------------------------------------------------------
 struct Basis {
   double cell[3];

@@ -36,6 +36,7 @@ struct bse_ctx {
   int gs_sweeps = 0;
   double t_gs_ms = 0, t_tau_ms = 0, t_tau_alloc_ms = 0, t_init_ms = 0;  // init stages, wall
   hipStream_t st = nullptr;
+  bsex::HostStage hstage;     // pinned staging of every host <-> device copy
   bsex::FftPlan fft;
   bsex::SphereMap map{};     // sphere <-> full grid
   bsex::SpherePlan sp;        // pruned transforms

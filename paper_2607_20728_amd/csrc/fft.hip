@@ -71,9 +71,12 @@ int fft_plan_init(FftPlan* p, const int grid[3]) {
       twf[k] = make_float2((float)cosl(ang), (float)sinl(ang));
     }
     BSE_HIP(hipMalloc(&ax.tw, sizeof(double2) * n));
-    BSE_HIP(hipMemcpy(ax.tw, tw.data(), sizeof(double2) * n, hipMemcpyHostToDevice));
     BSE_HIP(hipMalloc(&ax.twf, sizeof(float2) * n));
-    BSE_HIP(hipMemcpy(ax.twf, twf.data(), sizeof(float2) * n, hipMemcpyHostToDevice));
+    HostStage hs;
+    int rc = stage_h2d(&hs, tw.data(), ax.tw, sizeof(double2) * n, nullptr);
+    if (rc == BSE_OK) rc = stage_h2d(&hs, twf.data(), ax.twf, sizeof(float2) * n, nullptr);
+    stage_free(&hs);
+    BSE_TRY(rc);
     p->N[a] = n;
     p->nr *= n;
   }
@@ -141,8 +144,10 @@ int sphere_plan_build(const FftPlan& p, const Basis& b, SpherePlan* sp) {
   sp->nmax1 = nmax1;
   auto up = [](int** d, const std::vector<int>& h) -> int {
     BSE_HIP(hipMalloc(d, sizeof(int) * std::max<size_t>(h.size(), 1)));
-    BSE_HIP(hipMemcpy(*d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice));
-    return BSE_OK;
+    HostStage hs;
+    const int rc = stage_h2d(&hs, h.data(), *d, sizeof(int) * h.size(), nullptr);
+    stage_free(&hs);
+    return rc;
   };
   BSE_TRY(up(&sp->plane_i1, planes));
   BSE_TRY(up(&sp->plane_off, off));

@@ -34,6 +34,7 @@ struct bse_mlp {
         *dz1 = nullptr;
   double* red = nullptr;
   std::vector<void*> allocs;
+  bsex::HostStage hs;  // pinned staging of host <-> device copies
 };
 
 namespace bsex {
@@ -314,9 +315,8 @@ int create_impl(int n_in, int n_out, uint64_t seed, hipStream_t st, bse_mlp* q) 
   std::vector<float> nrm(2 * (n_in + n_out), 0.0f);
   for (int c = 0; c < n_in; ++c) nrm[n_in + c] = 1.0f;
   for (int o = 0; o < n_out; ++o) nrm[2 * n_in + n_out + o] = 1.0f;
-  BSE_HIP(hipMemcpyAsync(q->p, h.data(), sizeof(float) * q->np, hipMemcpyHostToDevice, st));
-  BSE_HIP(hipMemcpyAsync(q->norm, nrm.data(), sizeof(float) * nrm.size(), hipMemcpyHostToDevice,
-                         st));
+  BSE_TRY(stage_h2d(&q->hs, h.data(), q->p, sizeof(float) * q->np, st));
+  BSE_TRY(stage_h2d(&q->hs, nrm.data(), q->norm, sizeof(float) * nrm.size(), st));
   BSE_HIP(hipMemsetAsync(q->m, 0, sizeof(float) * q->np, st));
   BSE_HIP(hipMemsetAsync(q->v, 0, sizeof(float) * q->np, st));
   BSE_TRY(refresh_bf16(q));
@@ -328,6 +328,7 @@ void destroy(bse_mlp* q) {
   if (!q) return;
   if (q->st) (void)hipStreamSynchronize(q->st);
   for (void* p : q->allocs) (void)hipFree(p);
+  stage_free(&q->hs);
   delete q;
 }
 
@@ -368,8 +369,7 @@ int train_impl(bse_mlp* q, long n, const float* x, const float* t, const float* 
   BSE_HIP(hipGetLastError());
   BSE_TRY(refresh_bf16(q));
   double L = 0.0;
-  BSE_HIP(hipMemcpyAsync(&L, q->red, sizeof(double), hipMemcpyDeviceToHost, q->st));
-  BSE_HIP(hipStreamSynchronize(q->st));
+  BSE_TRY(stage_d2h(&q->hs, q->red, &L, sizeof(double), q->st));
   if (loss_host) *loss_host = (float)L;
   return BSE_OK;
 }
@@ -423,7 +423,7 @@ int bse_mlp_set_params(bse_mlp* q, const float* params_host) {
   if (!q || !params_host) return fail(BSE_EINVAL, "NULL argument");
   for (long e = 0; e < q->np; ++e)
     if (!std::isfinite(params_host[e])) return fail(BSE_EINVAL, "non-finite parameter %ld", e);
-  BSE_HIP(hipMemcpyAsync(q->p, params_host, sizeof(float) * q->np, hipMemcpyHostToDevice, q->st));
+  BSE_TRY(stage_h2d(&q->hs, params_host, q->p, sizeof(float) * q->np, q->st));
   BSE_HIP(hipMemsetAsync(q->m, 0, sizeof(float) * q->np, q->st));
   BSE_HIP(hipMemsetAsync(q->v, 0, sizeof(float) * q->np, q->st));
   q->step = 0;
@@ -434,9 +434,7 @@ int bse_mlp_set_params(bse_mlp* q, const float* params_host) {
 
 int bse_mlp_get_params(bse_mlp* q, float* params_host) {
   if (!q || !params_host) return fail(BSE_EINVAL, "NULL argument");
-  BSE_HIP(hipMemcpyAsync(params_host, q->p, sizeof(float) * q->np, hipMemcpyDeviceToHost, q->st));
-  BSE_HIP(hipStreamSynchronize(q->st));
-  return BSE_OK;
+  return stage_d2h(&q->hs, q->p, params_host, sizeof(float) * q->np, q->st);
 }
 
 int bse_mlp_set_norm(bse_mlp* q, const float* mu_x, const float* s_x, const float* mu_y,
@@ -453,9 +451,7 @@ int bse_mlp_set_norm(bse_mlp* q, const float* mu_x, const float* s_x, const floa
     if (!(s_x[c] > 0)) return fail(BSE_EINVAL, "s_x[%d] must be positive", c);
   for (int o = 0; o < q->n_out; ++o)
     if (!(s_y[o] > 0)) return fail(BSE_EINVAL, "s_y[%d] must be positive", o);
-  BSE_HIP(hipMemcpyAsync(q->norm, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, q->st));
-  BSE_HIP(hipStreamSynchronize(q->st));
-  return BSE_OK;
+  return stage_h2d(&q->hs, h.data(), q->norm, sizeof(float) * h.size(), q->st);
 }
 
 int bse_mlp_forward(bse_mlp* q, int32_t n, const float* x_dev, float* y_dev) {

@@ -60,18 +60,24 @@ struct DVec {  // scoped device scratch owned by the context
   DVec& operator=(const DVec&) = delete;
 };
 
+// host copies go through the context's pinned staging buffer; the vector
+// forms check that the host buffer holds the n elements copied
 int to_host(bse_ctx* c, const double* d, double* h, size_t n) {
-  if (n == 0) return BSE_OK;
-  BSE_HIP(hipMemcpyAsync(h, d, sizeof(double) * n, hipMemcpyDeviceToHost, c->st));
-  BSE_HIP(hipStreamSynchronize(c->st));
-  return BSE_OK;
+  return stage_d2h(&c->hstage, d, h, sizeof(double) * n, c->st);
 }
 
 int to_dev(bse_ctx* c, const double* h, double* d, size_t n) {
-  if (n == 0) return BSE_OK;
-  BSE_HIP(hipMemcpyAsync(d, h, sizeof(double) * n, hipMemcpyHostToDevice, c->st));
-  BSE_HIP(hipStreamSynchronize(c->st));
-  return BSE_OK;
+  return stage_h2d(&c->hstage, h, d, sizeof(double) * n, c->st);
+}
+
+int to_host(bse_ctx* c, const double* d, std::vector<double>& h, size_t n) {
+  if (n > h.size()) return fail(BSE_EINVAL, "copy of %zu values into a host buffer of %zu", n, h.size());
+  return to_host(c, d, h.data(), n);
+}
+
+int to_dev(bse_ctx* c, const std::vector<double>& h, double* d, size_t n) {
+  if (n > h.size()) return fail(BSE_EINVAL, "copy of %zu values from a host buffer of %zu", n, h.size());
+  return to_dev(c, h.data(), d, n);
 }
 
 int copy_dev(bse_ctx* c, const double* s, double* d, size_t n) {
@@ -92,7 +98,7 @@ int dots_host(bse_ctx* c, const double* A, const double* B, long rows, long len,
   }
   BSE_TRY(row_dots(A, B, rows, len, scratch, c->rdw, c->rdw_len, c->st));
   out.resize(rows);
-  return to_host(c, scratch, out.data(), rows);
+  return to_host(c, scratch, out, rows);
 }
 
 double elapsed_ms(std::chrono::steady_clock::time_point t0) {
@@ -176,7 +182,7 @@ int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len,
   if (dots_host(c, W, W, k, len, vec, nrm) != BSE_OK) return -BSE_EHIP;
   std::vector<double> sc(k);
   for (long i = 0; i < k; ++i) sc[i] = nrm[i] > 0 ? 1.0 / std::sqrt(nrm[i]) : 0.0;
-  if (to_dev(c, sc.data(), vec, k) != BSE_OK) return -BSE_EHIP;
+  if (to_dev(c, sc, vec, k) != BSE_OK) return -BSE_EHIP;
   if (row_scale(vec, W, k, len, c->st) != BSE_OK) return -BSE_EHIP;
   long kk = k;
   for (int pass = 0; pass < passes; ++pass) {
@@ -187,7 +193,7 @@ int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len,
     }
     if (gram_tall(c, W, kk, W, kk, len, Bm) != BSE_OK) return -BSE_EHIP;
     std::vector<double> G((size_t)kk * kk), lam(kk);
-    if (to_host(c, Bm, G.data(), (size_t)kk * kk) != BSE_OK) return -BSE_EHIP;
+    if (to_host(c, Bm, G, (size_t)kk * kk) != BSE_OK) return -BSE_EHIP;
     if (host_syev((int)kk, G.data(), lam.data())) return -fail(BSE_EINVAL, "Gram eigensolver failed");
     const bool enough = pass == 0 && lam[0] >= 0.5;
     const double thr = (pass == 0) ? drop * drop : 1e-300;
@@ -200,7 +206,7 @@ int orth_block(bse_ctx* c, const double* V, long m, double* W, long k, long len,
       ++knew;
     }
     if (knew == 0) return 0;
-    if (to_dev(c, Bh.data(), Bm, Bh.size()) != BSE_OK) return -BSE_EHIP;
+    if (to_dev(c, Bh, Bm, Bh.size()) != BSE_OK) return -BSE_EHIP;
     if (dgemm(0, 0, knew, len, kk, 1.0, Bm, kk, W, len, 0.0, tmp, len, c->st) != BSE_OK)
       return -BSE_EHIP;
     if (copy_dev(c, tmp, W, (size_t)knew * len) != BSE_OK) return -BSE_EHIP;
@@ -230,12 +236,12 @@ static int chol_orth(bse_ctx* c, double* W, long k, long len, double* tmp) {
     if (!(nrm[i] > 0.0)) return 0;
     sc[i] = 1.0 / std::sqrt(nrm[i]);
   }
-  if (to_dev(c, sc.data(), vec, k) != BSE_OK) return -BSE_EHIP;
+  if (to_dev(c, sc, vec, k) != BSE_OK) return -BSE_EHIP;
   if (row_scale(vec, W, k, len, c->st) != BSE_OK) return -BSE_EHIP;
   std::vector<double> G((size_t)k * k);
   for (int pass = 0; pass < 2; ++pass) {
     if (gram_tall(c, W, k, W, k, len, Gd) != BSE_OK) return -BSE_EHIP;
-    if (to_host(c, Gd, G.data(), G.size()) != BSE_OK) return -BSE_EHIP;
+    if (to_host(c, Gd, G, G.size()) != BSE_OK) return -BSE_EHIP;
     if (host_cholesky((int)k, G.data())) return 0;
     double lmin = G[0], lmax = G[0];
     for (long i = 0; i < k; ++i) {
@@ -244,7 +250,7 @@ static int chol_orth(bse_ctx* c, double* W, long k, long len, double* tmp) {
     }
     if (lmin < 1e-6 * lmax) return 0;
     if (host_trinv_lower((int)k, G.data())) return 0;
-    if (to_dev(c, G.data(), Gd, G.size()) != BSE_OK) return -BSE_EHIP;
+    if (to_dev(c, G, Gd, G.size()) != BSE_OK) return -BSE_EHIP;
     if (dgemm(0, 0, k, len, k, 1.0, Gd, k, W, len, 0.0, tmp, len, c->st) != BSE_OK)
       return -BSE_EHIP;
     if (copy_dev(c, tmp, W, (size_t)k * len) != BSE_OK) return -BSE_EHIP;
@@ -308,7 +314,7 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
     BSE_TRY(learned_features(c, nullptr, F));
     BSE_TRY(learned_eval(c, F, sig, gam, &ok));
     if (ok) {
-      BSE_TRY(to_dev(c, sig.data(), vs.p, nv));
+      BSE_TRY(to_dev(c, sig, vs.p, nv));
       vshift = vs.p;
       pshift = c->scissor;
       learned = true;
@@ -350,7 +356,7 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
     while (k < nb && q < d.size()) {
       double* w = W.p + (size_t)k * L;
       BSE_HIP(hipMemsetAsync(w, 0, sizeof(double) * L, c->st));
-      BSE_TRY(to_dev(c, one.data(), w + d[q].second, 1));
+      BSE_TRY(to_dev(c, one, w + d[q].second, 1));
       ++q;
       BSE_TRY(proj_c(c, w, w, 1));
       BSE_TRY(dots_host(c, w, w, 1, L, vecd, nrm));
@@ -368,7 +374,7 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
     const long nr_ = r1 - r0;
     BSE_TRY(gram_tall(c, V.p + (size_t)r0 * L, nr_, AV.p, r1, L, Cd));
     std::vector<double> blk((size_t)nr_ * r1);
-    BSE_TRY(to_host(c, Cd, blk.data(), blk.size()));
+    BSE_TRY(to_host(c, Cd, blk, blk.size()));
     for (long i = 0; i < nr_; ++i)
       for (long j = 0; j < r1; ++j) {
         Hs[(size_t)(r0 + i) * maxsub + j] = blk[(size_t)i * r1 + j];
@@ -391,7 +397,7 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
     std::vector<double> Ck((size_t)m * kr);
     for (int i = 0; i < m; ++i)
       for (int j = 0; j < kr; ++j) Ck[(size_t)i * kr + j] = A[(size_t)i * m + j];
-    BSE_TRY(to_dev(c, Ck.data(), Cd, Ck.size()));
+    BSE_TRY(to_dev(c, Ck, Cd, Ck.size()));
     {
       PhaseScope ps(c, PH_SOLVER);
       BSE_TRY(dgemm(1, 0, kr, L, m, 1.0, Cd, kr, V.p, L, 0.0, X.p, L, c->st));
@@ -399,7 +405,7 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
     }
     std::vector<double> negth(kr);
     for (int i = 0; i < kr; ++i) negth[i] = -w[i];
-    BSE_TRY(to_dev(c, negth.data(), vecd, kr));
+    BSE_TRY(to_dev(c, negth, vecd, kr));
     BSE_TRY(copy_dev(c, AX.p, W.p, (size_t)kr * L));           // R = AX - theta X
     BSE_TRY(row_axpby(vecd, X.p, nullptr, W.p, kr, L, c->st));
     std::vector<double> r2;
@@ -434,7 +440,7 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
       if (todo[q] != q) BSE_TRY(copy_dev(c, W.p + (size_t)todo[q] * L, W.p + (size_t)q * L, L));
     std::vector<double> th(nt);
     for (int q = 0; q < nt; ++q) th[q] = w[todo[q]];
-    BSE_TRY(to_dev(c, th.data(), vecd, nt));
+    BSE_TRY(to_dev(c, th, vecd, nt));
     auto kin = [&](double* w) {
       return precond_davidson(w, w, c->T, c->eps_d, vecd, pshift, nt, (int)nv, (int)npw, c->st,
                               vshift);
@@ -449,7 +455,7 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
       std::vector<double> Ckeep((size_t)m * keep);
       for (int i = 0; i < m; ++i)
         for (int j = 0; j < keep; ++j) Ckeep[(size_t)i * keep + j] = A[(size_t)i * m + j];
-      BSE_TRY(to_dev(c, Ckeep.data(), Cd, Ckeep.size()));
+      BSE_TRY(to_dev(c, Ckeep, Cd, Ckeep.size()));
       PhaseScope ps(c, PH_SOLVER);
       // AW holds 2 nb rows: use it as the staging buffer
       BSE_TRY(dgemm(1, 0, keep, L, m, 1.0, Cd, keep, V.p, L, 0.0, AW.p, L, c->st));
@@ -520,7 +526,7 @@ int davidson(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double
     th[i] /= xx[i];
     nt[i] = -th[i];
   }
-  BSE_TRY(to_dev(c, nt.data(), sv.p + 32, ns));
+  BSE_TRY(to_dev(c, nt, sv.p + 32, ns));
   BSE_TRY(row_axpby(sv.p + 32, X.p, nullptr, Y.p, ns, L, c->st));
   BSE_TRY(dots_host(c, Y.p, Y.p, ns, L, sv.p, r2));
   double worst = 0;
@@ -602,7 +608,7 @@ int learned_features(bse_ctx* c, const double* U, std::vector<float>& F) {
   BSE_TRY(band_features(c->Phi, c->T, c->eps_d, U, c->phir, kPrecondShift, nv, c->basis.npw,
                         c->basis.nr, o.p, c->st));
   std::vector<double> h(4 * (size_t)nv);
-  BSE_TRY(to_host(c, o.p, h.data(), h.size()));
+  BSE_TRY(to_host(c, o.p, h, h.size()));
   const double eh = c->eps_h[nv - 1], el = c->eps_h[nv], om = c->basis.omega;
   F.assign((size_t)nv * BSE_LEARN_NFEAT, 0.0f);
   for (int v = 0; v < nv; ++v) {
@@ -634,11 +640,9 @@ int learned_eval(bse_ctx* c, const std::vector<float>& F, std::vector<double>& s
   std::vector<float> y((size_t)nv * BSE_LEARN_NOUT);
   if (rc == BSE_OK) {
     auto run = [&]() -> int {
-      BSE_HIP(hipMemcpyAsync(xd, F.data(), sizeof(float) * F.size(), hipMemcpyHostToDevice, c->st));
+      BSE_TRY(stage_h2d(&c->hstage, F.data(), xd, sizeof(float) * F.size(), c->st));
       BSE_TRY(mlp_eval(c->learned, nv, xd, yd, c->st));
-      BSE_HIP(hipMemcpyAsync(y.data(), yd, sizeof(float) * y.size(), hipMemcpyDeviceToHost, c->st));
-      BSE_HIP(hipStreamSynchronize(c->st));
-      return BSE_OK;
+      return stage_d2h(&c->hstage, yd, y.data(), sizeof(float) * y.size(), c->st);
     };
     rc = run();
   }
@@ -753,8 +757,8 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
       al[v] = pap[v] != 0.0 ? rz[v] / pap[v] : 0.0;
       nal[v] = -al[v];
     }
-    BSE_TRY(to_dev(c, al.data(), sv.p + nv, nv));
-    BSE_TRY(to_dev(c, nal.data(), sv.p + 2 * nv, nv));
+    BSE_TRY(to_dev(c, al, sv.p + nv, nv));
+    BSE_TRY(to_dev(c, nal, sv.p + 2 * nv, nv));
     BSE_TRY(row_axpby(sv.p + nv, P.p, nullptr, Z, nv, npw, c->st));
     BSE_TRY(row_axpby(sv.p + 2 * nv, AP.p, nullptr, R.p, nv, npw, c->st));
     BSE_TRY(prec(R.p, AP.p));
@@ -762,7 +766,7 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
     BSE_TRY(dots_host(c, R.p, Zr.p, nv, npw, sv.p, rzn));
     std::vector<double> be(nv);
     for (long v = 0; v < nv; ++v) be[v] = rz[v] != 0.0 ? rzn[v] / rz[v] : 0.0;
-    BSE_TRY(to_dev(c, be.data(), sv.p + 3 * nv, nv));
+    BSE_TRY(to_dev(c, be, sv.p + 3 * nv, nv));
     BSE_TRY(row_axpby(nullptr, Zr.p, sv.p + 3 * nv, P.p, nv, npw, c->st));
     rz = rzn;
   }
@@ -813,7 +817,7 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
     bool ok = false;
     BSE_TRY(learned_eval(c, F, sig, gam, &ok));
     if (ok) {
-      BSE_TRY(to_dev(c, sig.data(), vs.p, nv));
+      BSE_TRY(to_dev(c, sig, vs.p, nv));
       vshift = vs.p;
       learned = true;
     } else {
@@ -824,7 +828,7 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
     BSE_TRY(proj_c(c, o->z0_dev, Z, 1));
   } else if (learned) {  // Z0_v = gamma_v P_c Prec_v(-u_v)
     BSE_TRY(precond_rhs(c, U.p, Z, o->two_level && c->norb > c->nv));
-    BSE_TRY(to_dev(c, gam.data(), sv.p + 16, nv));
+    BSE_TRY(to_dev(c, gam, sv.p + 16, nv));
     BSE_TRY(row_scale(sv.p + 16, Z, nv, npw, c->st));
   } else {
     BSE_HIP(hipMemsetAsync(Z, 0, sizeof(double) * L, c->st));
@@ -1010,9 +1014,9 @@ int ground_state(bse_ctx* c, int n_want, double tol) {
     BSE_TRY(Happly(X.p, HX.p, 0.0));
     BSE_TRY(gram_tall(c, X.p, nsl, HX.p, nsl, npw, Cd));
     std::vector<double> Hs(nsl * nsl);
-    BSE_TRY(to_host(c, Cd, Hs.data(), Hs.size()));
+    BSE_TRY(to_host(c, Cd, Hs, Hs.size()));
     if (host_syev(ns, Hs.data(), theta.data())) return fail(BSE_EINVAL, "ground state: RR failed");
-    BSE_TRY(to_dev(c, Hs.data(), Cd, Hs.size()));
+    BSE_TRY(to_dev(c, Hs, Cd, Hs.size()));
     BSE_TRY(dgemm(1, 0, nsl, npw, nsl, 1.0, Cd, nsl, X.p, npw, 0.0, Z.p, npw, c->st));
     BSE_TRY(copy_dev(c, Z.p, X.p, nsl * npw));
     BSE_TRY(dgemm(1, 0, nsl, npw, nsl, 1.0, Cd, nsl, HX.p, npw, 0.0, Z.p, npw, c->st));
@@ -1021,7 +1025,7 @@ int ground_state(bse_ctx* c, int n_want, double tol) {
   };
   // upper bound of the spectrum: |G|^2/2 <= ecut and <x|V|x> <= max V(r)
   std::vector<double> vr(c->basis.nr);
-  BSE_TRY(to_host(c, c->Vr, vr.data(), vr.size()));
+  BSE_TRY(to_host(c, c->Vr, vr, vr.size()));
   const double vmax = *std::max_element(vr.begin(), vr.end());
   const double bup = c->basis.ecut + std::max(0.0, vmax) + 0.5;
   BSE_TRY(rayleigh_ritz());
@@ -1031,7 +1035,7 @@ int ground_state(bse_ctx* c, int n_want, double tol) {
     // residuals of the wanted states
     std::vector<double> nt(n_want);
     for (int i = 0; i < n_want; ++i) nt[i] = -theta[i];
-    BSE_TRY(to_dev(c, nt.data(), vec, n_want));
+    BSE_TRY(to_dev(c, nt, vec, n_want));
     BSE_TRY(copy_dev(c, HX.p, Z.p, (size_t)n_want * npw));
     BSE_TRY(row_axpby(vec, X.p, nullptr, Z.p, n_want, npw, c->st));
     std::vector<double> r2;

@@ -8,6 +8,10 @@
         the kernels of the last apply in a bench trace (those launched after
         the next-to-last k_tau_stream, up to the last one), in launch order;
 
+    python -m paper_2607_20728_amd.profsummary counters <dir> [match]
+        mean value per dispatch of every counter of a --pmc run
+        (--output-format csv), per kernel whose name contains match;
+
     python -m paper_2607_20728_amd.profsummary traffic --fetch DIR --write DIR
             --copy-fetch DIR --copy-write DIR --match k_tau_stream --out FILE
             [--command TEXT]
@@ -73,6 +77,23 @@ def _counter_rows(d, counter):
     return out
 
 
+def counters(d, match=""):
+    """Mean of each counter per dispatch, per kernel (name contains match)."""
+    vals = collections.defaultdict(list)
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                n = r.get("Kernel_Name", "")
+                if match in n:
+                    m = re.search(r'(k_[a-z_0-9]+(<[^>]*>)?|__amd_rocclr_\w+)', n)
+                    vals[((m.group(1) if m else n[:60]), r["Counter_Name"])].append(
+                        float(r["Counter_Value"]))
+    if not vals:
+        sys.exit(f"no counter rows under {d}")
+    for (k, c), v in sorted(vals.items()):
+        print(f"{k:48s} {c:36s} dispatches {len(v):4d} mean {statistics.mean(v):.6g}")
+
+
 def _copy_factor(d, counter, expected_kib):
     # the 2 GiB copy (and, for WRITE_SIZE, the 2 GiB fill before it) are the
     # only dispatches of that size in the calibration run
@@ -105,6 +126,9 @@ def traffic(a):
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "apply":
         last_apply(sys.argv[2])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
         return
     if len(sys.argv) > 1 and sys.argv[1] == "kernels":
         kernels(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 30)

@@ -5,13 +5,17 @@ between two runs of either is the order of the tau stream's LDS atomic adds,
 so replays agree with the eager result to rounding (asserted: 1e-13 relative
 in max norm).  Each replay is checked with the program's own eager work and
 synchronisations between replays.  Batch results are compared with the same
-systems solved one by one.
+systems solved one by one, and with the oracle's own end-to-end solve of
+each system (dense ground state, Davidson, U, Z-vector CG, Eqs. 4-6): the
+energies and forces are gauge invariant, so the library's ground state and
+exciton may differ from the oracle's by sign or rotation.
 """
+import functools
 import numpy as np
 import pytest
 
 import synth
-from oracle import basis
+from oracle import basis, model, solvers
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -94,3 +98,38 @@ def test_batch_matches_single_system_solves(prec):
               f"stream {r['stream']}  dF {np.abs(r['dwdR'] - F).max():.2e}")
         assert abs(r["omega"] - w[0]) < 1e-9
         assert np.abs(r["dwdR"] - F).max() < 1e-6
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_solution(k):
+    """omega_1 and d omega/d R of small system k from the oracle alone."""
+    sd = _small_systems()[k]
+    b = basis.Basis(sd["cell"], tuple(int(x) for x in sd["grid"]), sd["ecut"])
+    S = model.System(b, sd["site_xyz"], sd["site_depth"], sd["site_width"], sd["pdep"],
+                     sd["lam"], sd["n_val"])
+    S.ground_state(n_extra=8)
+    w, X, info = solvers.davidson(S, 1, tol=1e-10, max_iter=400)
+    assert info["converged"]
+    Z, zi = solvers.zvector_cg(S, solvers.u_vector(S, X[0]), tol=1e-10)
+    assert zi["converged"]
+    return float(w[0]), solvers.dwdR(S, X[0], Z)
+
+
+@pytest.mark.parametrize("prec", [bsex.FP64, bsex.MIXED])
+def test_batch_matches_oracle(prec):
+    """batch_run (2 streams, graphs, autotuning) against the oracle's own
+    solves of the three small systems: |d omega| <= 1e-6 Ha and |dF| <= 1e-5
+    Ha/bohr in FP64; the stated mixed-form bounds 1e-5 Ha and 1e-4 Ha/bohr."""
+    print(f"[gpu] batch of 3 vs oracle prec={prec}", flush=True)
+    systems = _small_systems()
+    bsex.tune_cache_clear()
+    res = bsex.batch_run(systems, tol=1e-8, precision=prec, n_streams=2, autotune=True,
+                         use_graph=True)
+    tol_w, tol_f = (1e-6, 1e-5) if prec == bsex.FP64 else (1e-5, 1e-4)
+    for k, r in enumerate(res):
+        assert r["status"] == 0, r["message"]
+        wo, Fo = _oracle_solution(k)
+        dw, dF = abs(r["omega"] - wo), float(np.abs(r["dwdR"] - Fo).max())
+        print(f"  system b{k}: omega {r['omega']:.10f} oracle {wo:.10f} |dw| {dw:.1e} "
+              f"|dF| {dF:.1e} (max |F| {np.abs(Fo).max():.2e})", flush=True)
+        assert dw <= tol_w and dF <= tol_f
