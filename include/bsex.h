@@ -250,6 +250,23 @@ int bse_zvector_solve(bse_ctx *ctx, const double *Xs_dev, const bse_solver_opts 
  * dwdR_host [n_sites][3].  The excitation-energy force is -dwdR. */
 int bse_forces(bse_ctx *ctx, const double *Xs_dev, const double *Z_dev, double *dwdR_host);
 
+/* bse_forces for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops): the same d omega / d R, written to device
+ * memory, with no allocation of any kind.  Xs_dev, Z_dev [N_v][N_pw] and
+ * dwdR_dev [n_sites][3] are device buffers owned by the caller (dwdR_dev may
+ * be NULL when n_sites = 0).  Stream ordered on the context's stream: the
+ * call returns once the work is queued, without synchronising.
+ * The work buffers are the context's apply buffers (present after
+ * bse_init_system) and one static device scratch array of 64 MiB per device,
+ * whose address is resolved when a context is initialised on that device
+ * and which stays allocated until the process ends.  Calls on one device
+ * share that array: calls that overlap on one device race, so serialise
+ * them (one stream, or events).  EINVAL when the system needs more scratch
+ * (2 N_v^2 doubles plus the per-site partial sums) than the array holds;
+ * ESTATE when the context has no apply buffers for 3 vector sets. */
+int bse_forces_noalloc(bse_ctx *ctx, const double *Xs_dev, const double *Z_dev,
+                       double *dwdR_dev);
+
 /* The ground-state part of the excited-state force: the paper writes the
  * excited-state force as the ground-state force minus d omega / d R (the
  * sentence introducing Eq. 4).  For the synthetic Hamiltonian H = T + V,

@@ -24,7 +24,7 @@ TAU_AUTO, TAU_CACHE, TAU_REBUILD = 0, 1, 2
 
 SYMBOLS = ("bse_abi_version", "bse_last_error", "bse_warm_up", "bse_basis_size", "bse_basis_gvectors",
            "bse_init_system", "bse_get_info", "bse_get_orbitals", "bse_apply",
-           "bse_davidson", "bse_u_vector", "bse_zvector_solve", "bse_forces",
+           "bse_davidson", "bse_u_vector", "bse_zvector_solve", "bse_forces", "bse_forces_noalloc",
            "bse_ground_state_forces",
            "bse_set_precision", "bse_set_profiling", "bse_get_phase_times",
            "bse_mlp_create", "bse_mlp_n_params", "bse_mlp_set_params", "bse_mlp_get_params",
@@ -125,6 +125,7 @@ def lib():
     L.bse_zvector_solve.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(SolverOpts), C.c_void_p,
                                     C.POINTER(SolverStats)]
     L.bse_forces.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp]
+    L.bse_forces_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.bse_ground_state_forces.argtypes = [C.c_void_p, dp]
     L.bse_set_precision.argtypes = [C.c_void_p, C.c_int32]
     fp = C.POINTER(C.c_float)
@@ -403,6 +404,14 @@ def forces(ctx, Xs, Z, n_sites):
     out = np.zeros((max(n_sites, 1), 3))
     _check(lib().bse_forces(ctx.h, _dev(Xs, "Xs"), _dev(Z, "Z"), _dptr(out)))
     return out[:n_sites]
+
+
+def forces_noalloc(ctx, Xs, Z, out):
+    """bse_forces_noalloc: d omega/d R into the caller's device tensor out
+    [n_sites][3] (float64, contiguous); stream ordered, no allocation."""
+    _check(lib().bse_forces_noalloc(ctx.h, _dev(Xs, "Xs"), _dev(Z, "Z"),
+                                    _dev(out, "out") if out.numel() else None))
+    return out
 
 
 def ground_state_forces(ctx, n_sites):

@@ -256,6 +256,10 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
   c->gap_min = d->gap_min;
   c->gs_tol = d->gs_tol > 0 ? d->gs_tol : 1e-10;
   c->n_extra = d->n_extra;
+  // the device work starts here: record the device and its allocation-free
+  // scratch address
+  BSE_HIP(hipGetDevice(&c->dev));
+  BSE_TRY(noalloc_setup(c->dev));
   BSE_TRY(fft_plan_init(&c->fft, d->grid));
   // basis maps and kinetic energy
   BSE_TRY(ctx_alloc_t(c, &c->idx_p, c->basis.nhalf + 1));

@@ -36,6 +36,7 @@ struct bse_ctx {
   int gs_sweeps = 0;
   double t_gs_ms = 0, t_tau_ms = 0, t_tau_alloc_ms = 0, t_init_ms = 0;  // init stages, wall
   hipStream_t st = nullptr;
+  int dev = -1;               // device the context was initialised on
   bsex::HostStage hstage;     // pinned staging of every host <-> device copy
   bsex::FftPlan fft;
   bsex::SphereMap map{};     // sphere <-> full grid
@@ -172,4 +173,8 @@ int apply_H_f(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double 
 int ensure_mixed_work(bse_ctx* c, int nbc);
 int ground_state(bse_ctx* c, int n_want, double tol);
 int gram_tall(bse_ctx* c, const double* A, long m, const double* B, long n, long len, double* C);
+// device address of the allocation-free scratch on `dev` (called once per
+// context initialisation, with that device current)
+int noalloc_setup(int dev);
+long noalloc_scratch_doubles();
 }  // namespace bsex
