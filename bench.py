@@ -45,31 +45,45 @@ def pair_count(nv, blocks):
     return n
 
 
-def cpu_baseline(cfg_name, n_b, n_pairs_sample=32):
-    """The FP64 oracle timed on a bounded sample of one apply block.
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or 'unknown'."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    Sample: the full per-vector work (projector, 432 inverse and forward
-    grid transforms, K1e) for ONE trial vector, plus tau = W(phi_v phi_v')
-    for n_pairs_sample of the N_v(N_v+1)/2 occupied pairs and their
-    contraction.  The block time is extrapolated as
-    n_b * t_vector + n_pairs * t_pair.  Orbitals are a random orthonormal
-    set of the right shape (timing only; the apply does the same work for
-    any orbitals).  numpy FFTs are single-threaded; BLAS is held to one
-    thread, so cores = 1.
+
+def cpu_baseline(cfg_name, n_b):
+    """The FP64 oracle timed on a bounded sample of one apply block, on every
+    host core this process may use (transforms and BLAS threaded).
+
+    Sample: the full per-vector work of ONE trial vector (projector, the N_v
+    inverse and forward grid transforms, K1e, the diagonal term), plus
+    tau_{v'v} = W(phi_v' phi_v) for every v' of ONE output band v (N_v pairs:
+    a whole band row of the pair matrix) and its contraction with one
+    vector's a(r).  The block is extrapolated as
+        n_b t_vector + (P / N_v) (t_band_tau + n_b t_band_contract),
+    P = N_v (N_v + 1)/2 pairs.  Orbitals are a random orthonormal set with
+    made-up energies (the apply does the same work for any orbitals).
     """
     from threadpoolctl import threadpool_limits
 
     import synth
     from oracle import basis, model
+    from oracle.fft import workers
+    nw = workers()
     cfg = synth.get_config(cfg_name)
     b = basis.Basis(cfg.cell, cfg.grid, cfg.ecut)
     d = synth.make_system(cfg, b.n_pw, n_trial=1)
-    with threadpool_limits(limits=1):
+    nv = cfg.n_val
+    with threadpool_limits(limits=nw):
         S = model.System(b, d["site_xyz"], d["site_depth"], d["site_width"], d["pdep"],
-                         d["lam"], cfg.n_val)
-        rng = np.random.default_rng(7)
-        q, _ = np.linalg.qr(rng.standard_normal((b.n_pw, cfg.n_val)))
-        S.set_orbitals(q.T.copy(), np.linspace(-1.0, -0.5, cfg.n_val))
+                         d["lam"], nv)
+        orbs, eps = synth.random_orbitals(b.n_pw, nv, 0, seed=7)
+        S.set_orbitals(orbs, eps)
         X = d["trial"][0]
         t0 = time.perf_counter()
         A = S.proj_c(X)
@@ -80,23 +94,22 @@ def cpu_baseline(cfg_name, n_b, n_pairs_sample=32):
         Z = b.from_grid(z) + (S.T[None, :] - S.eps[:, None]) * A
         S.proj_c(Z)
         t_vec = time.perf_counter() - t0
+        v = nv // 2
         t1 = time.perf_counter()
-        nv = cfg.n_val
-        pairs = [(v, w) for v in range(nv) for w in range(v, nv)]
-        pick = rng.choice(len(pairs), n_pairs_sample, replace=False)
-        for k in pick:
-            v, w = pairs[k]
-            tau = S.apply_W(S.phir[v] * S.phir[w])
-            z[v] -= tau * ar[w]
-            if v != w:
-                z[w] -= tau * ar[v]
-        t_pair = (time.perf_counter() - t1) / n_pairs_sample
+        tau = S.apply_W(S.phir * S.phir[v])          # tau_{v'v} for every v'
+        t_tau = time.perf_counter() - t1
+        t2 = time.perf_counter()
+        np.einsum("uxyz,uxyz->xyz", tau, ar)          # y_v = sum_v' tau_{v'v} a_v'
+        t_con = time.perf_counter() - t2
     n_pairs = nv * (nv + 1) // 2
-    t_block = n_b * t_vec + n_pairs * t_pair
-    return dict(value=n_b / t_block, unit="applies/s", cores=1, kind="oracle",
-                sample=(f"1 full vector apply without K1d ({t_vec:.2f} s) + tau for "
-                        f"{n_pairs_sample} of {n_pairs} pairs ({t_pair * 1e3:.1f} ms/pair); "
-                        f"block of {n_b} extrapolated to {t_block:.0f} s"))
+    rows = n_pairs / nv
+    t_block = n_b * t_vec + rows * (t_tau + n_b * t_con)
+    return dict(value=n_b / t_block, unit="applies/s", cores=nw, kind="oracle",
+                cpu=cpu_model(),
+                sample=(f"1 vector's full work without K1d ({t_vec:.2f} s) + tau for all {nv} "
+                        f"pairs of one output band ({t_tau:.2f} s) and its contraction with "
+                        f"one vector ({t_con:.2f} s); block of {n_b} extrapolated to "
+                        f"{t_block:.0f} s with {n_pairs} pairs"))
 
 
 def stream_kernel_sha():
@@ -368,7 +381,7 @@ def main():
         roofline = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(ach / HBM_PEAK_GBS, 4),
                         traffic=None if tr is None else round(tr),
-                        kernel=f"k_tau_stream ({'FP32' if mixed else 'FP64'} cached blocks)",
+                        kernel=f"k_tau_stream_qs ({'FP32' if mixed else 'FP64'} cached blocks)",
                         bytes_per_launch=tau_bytes + av_bytes,
                         avg_launch_ms=round(1e3 * dur, 3))
     phases = {k: dict(ms_per_step=round(v[0] / args.steps, 3), launches=v[1])

@@ -108,15 +108,20 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   hipDeviceProp_t prop;
   BSE_HIP(hipGetDeviceProperties(&prop, dev));
   c->max_lds = prop.sharedMemPerBlock;
-  c->R = (tau_stream_lds(c->nv, 2) <= c->max_lds) ? 2 : 1;
-  // tuning knobs of the stream kernel (points per workgroup, lanes per point)
+  // tuning knob of the stream kernel: 1 = quad-shared loads (default), 4 or
+  // 2 = lanes sharing one grid point's vectors, each reading whole blocks
+  if (const char* e = getenv("BSEX_TAU_BL")) {
+    const int v = atoi(e);
+    c->tau_bl = (v == 2 || v == 4) ? v : 1;
+  }
+  // grid points per stream workgroup: 2 when the kernel's LDS allows
+  c->R = (tau_stream_lds(c->nv, 2, sizeof(double), c->tau_bl) <= c->max_lds) ? 2 : 1;
   if (const char* e = getenv("BSEX_TAU_R")) c->R = (atoi(e) == 1) ? 1 : c->R;
-  if (const char* e = getenv("BSEX_TAU_BL")) c->tau_bl = (atoi(e) == 2) ? 2 : 4;
-  if (tau_stream_lds(c->nv, c->R) > c->max_lds)
+  if (tau_stream_lds(c->nv, c->R, sizeof(double), c->tau_bl) > c->max_lds)
     return fail(BSE_EINVAL, "n_val %d too large for the device LDS (%zu bytes)", c->nv, c->max_lds);
   const bool mixed = c->precision == BSE_MIXED;
-  c->Rf = (tau_stream_lds(c->nv, 2, sizeof(float)) <= c->max_lds) ? 2 : 1;
-  if (mixed && tau_stream_lds(c->nv, c->Rf, sizeof(float)) > c->max_lds)
+  c->Rf = (tau_stream_lds(c->nv, 2, sizeof(float), c->tau_bl) <= c->max_lds) ? 2 : 1;
+  if (mixed && tau_stream_lds(c->nv, c->Rf, sizeof(float), c->tau_bl) > c->max_lds)
     return fail(BSE_EINVAL, "n_val %d too large for the device LDS (%zu bytes)", c->nv, c->max_lds);
   BSE_TRY(tau_stream_set_lds_limit(c->max_lds));
   const bool need_k1d = (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) != 0;

@@ -29,11 +29,11 @@ namespace {
 // stack of each slot thread (solver host code, HIP runtime, profiler callbacks)
 constexpr size_t kSlotStack = (size_t)64 << 20;
 
-// variant bits: 1 = runtime-length FFT kernels, 2 = two lanes per grid point
-// in the tau stream (instead of four)
+// variant bits: 1 = runtime-length FFT kernels, 2 = the tau stream whose four
+// lanes per grid point each read whole blocks (instead of quad-shared loads)
 void set_variant(bse_ctx* c, int v) {
   fft_plan_set_runtime(&c->fft, (v & 1) != 0);
-  c->tau_bl = (v & 2) ? 2 : 4;
+  c->tau_bl = (v & 2) ? 4 : 1;
 }
 
 using TuneKey = std::tuple<int, int, int, int, int, int>;

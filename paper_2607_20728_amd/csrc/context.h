@@ -82,7 +82,8 @@ struct bse_ctx {
   int precision = BSE_FP64;   // capability the context was built with
   int active = BSE_FP64;      // precision of the operator applies
   int Rf = 2;                 // grid points per stream workgroup, FP32 layout
-  int tau_bl = 4;             // lanes per grid point in the stream kernel (2 or 4)
+  int tau_bl = 1;             // stream kernel: 1 quad-shared loads, or 4 / 2 lanes per grid
+                              // point reading whole blocks
   float2* phir_f = nullptr;   // [nvh][nr]
   float* Vr_f = nullptr;      // [nr]
   float* vc_f = nullptr;      // [nr]

@@ -89,20 +89,23 @@ struct FuseArgsF {
 };
 // y[b][v] (+)= sum_v' tau_{vv'} a[b][v'] over the blocks of one buffer; with
 // fuse != NULL, y receives z instead and may alias a.  R grid points per
-// workgroup (1 or 2, the layout tau was stored in); bl lanes share one grid
-// point's 8 trial vectors (2 or 4).  rows > 0: the blocks touch only bands
+// workgroup (1 or 2, the layout tau was stored in); bl selects the kernel:
+// 1 = quad-shared loads (the default: four lanes share a grid point's 8 trial
+// vectors, each reads two columns of a block and DPP broadcasts give all four
+// lanes the whole block), 4 or 2 = that many lanes share a grid point's
+// vectors and each reads the whole block.  rows > 0: the blocks touch only bands
 // row0 .. row0 + rows - 1 (multiples of 8), and only those bands of a and y
 // are read and written (not with fuse); rows = 0: every band.
 int tau_stream(const double* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                const double2* a, double2* y, int nb, int nv, long nr, int accumulate,
-               size_t max_lds, hipStream_t st, const FuseArgs* fuse = nullptr, int bl = 4,
+               size_t max_lds, hipStream_t st, const FuseArgs* fuse = nullptr, int bl = 1,
                int row0 = 0, int rows = 0);
 // FP32 variant (tau, a, y in FP32; products in FP32, sums in FP64 LDS)
 int tau_stream(const float* tau, long buf_nblk, long nblk, const int2* blkIJ, int R,
                const float2* a, float2* y, int nb, int nv, long nr, int accumulate,
-               size_t max_lds, hipStream_t st, const FuseArgsF* fuse = nullptr, int bl = 4,
+               size_t max_lds, hipStream_t st, const FuseArgsF* fuse = nullptr, int bl = 1,
                int row0 = 0, int rows = 0);
-size_t tau_stream_lds(int nv, int R, size_t elem = sizeof(double));
+size_t tau_stream_lds(int nv, int R, size_t elem = sizeof(double), int bl = 1);
 // raise the dynamic-LDS limit of the stream kernels (bytes <= device maximum)
 int tau_stream_set_lds_limit(size_t bytes);
 

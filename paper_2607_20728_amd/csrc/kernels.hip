@@ -438,6 +438,217 @@ __global__ __launch_bounds__(NSLOT * R * BL) void k_tau_stream(
 }
 
 // ---------------------------------------------------------------------------
+// Quad-shared tau stream (the default).  The work layout of k_tau_stream with
+// four lanes per grid point (lane bl takes trial vectors 2bl, 2bl+1), but each
+// lane reads only columns 2bl and 2bl+1 of a block from memory and the block's
+// eight columns reach all four lanes of the quad by DPP broadcasts: every tau
+// value leaves the cache once, and the LDS traffic is that of k_tau_stream.
+// ---------------------------------------------------------------------------
+constexpr int QS_BL = 4;
+
+// Workgroup i runs on XCD i mod 8 (round-robin dispatch).  Give each XCD a
+// contiguous range of grid-point blocks, in order, so the workgroups whose
+// points share a 128-byte line of a(r) and z(r) run on the same XCD and meet
+// in its L2.  A bijection of [0, n) for any n.
+__device__ __forceinline__ long xcd_order(long i, long n) {
+  constexpr int NX = 8;
+  const long q = n / NX, rem = n % NX;
+  const long x = i % NX, k = i / NX;
+  return x * q + (x < rem ? x : rem) + k;
+}
+
+// value of lane `src` of this lane's quad (quad permutation [src x 4])
+template <int SRC>
+__device__ __forceinline__ float quad_bcast(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), SRC * 0x55, 0xF, 0xF, true));
+}
+template <int SRC>
+__device__ __forceinline__ double quad_bcast(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffffLL), SRC * 0x55, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), SRC * 0x55, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ void load8(double (&v)[8], const double* p) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double2 w = q[k];
+    v[2 * k] = w.x;
+    v[2 * k + 1] = w.y;
+  }
+}
+__device__ __forceinline__ void load8(float (&v)[8], const float* p) {
+  const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float4 w = q[k];
+    v[4 * k] = w.x;
+    v[4 * k + 1] = w.y;
+    v[4 * k + 2] = w.z;
+    v[4 * k + 3] = w.w;
+  }
+}
+
+// one column j of the current block: t[i] = tau[i][j] from the quad lane that
+// read it, then acc (row block I) and the transposed contribution to row j
+template <int J, int R, typename T>
+__device__ __forceinline__ void qs_column(const T (&own)[2][8], T (&acc)[8][2],
+                                          const T (&aI)[8][2], const T* as, double* ys,
+                                          int rowJ, int lo) {
+  constexpr int NBL = 2;
+  constexpr int RS = NBT * R + SPAD;
+  T t[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) t[i] = quad_bcast<J / 2>(own[J % 2][i]);
+  const int wv = rowJ + J;
+  T aj[NBL], tr[NBL];
+#pragma unroll
+  for (int b = 0; b < NBL; ++b) {
+    aj[b] = as[wv * RS + lo + b * R];
+    tr[b] = 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int b = 0; b < NBL; ++b) {
+      acc[i][b] = fma(t[i], aj[b], acc[i][b]);
+      tr[b] = fma(t[i], aI[i][b], tr[b]);
+    }
+#pragma unroll
+  for (int b = 0; b < NBL; ++b) atomicAdd(&ys[wv * RS + lo + b * R], (double)tr[b]);
+}
+
+template <int R, bool FUSE, typename T>
+__global__ __launch_bounds__(NSLOT * R * QS_BL) void k_tau_stream_qs(
+    const T* __restrict__ tau, long rb_stride, long nblk, const int2* __restrict__ IJ,
+    const typename vec2_of<T>::type* a, typename vec2_of<T>::type* y, int nb, int nv, int nvh,
+    long nr, int row0, int nrows, int accumulate, const T* __restrict__ V,
+    const typename vec2_of<T>::type* __restrict__ vdrho,
+    const typename vec2_of<T>::type* __restrict__ phir, T s, int with_v) {
+  constexpr int NT = NSLOT * R * QS_BL;
+  constexpr int NBL = NBT / QS_BL;
+  constexpr int RS = NBT * R + SPAD;
+  extern __shared__ char lds_raw[];
+  T* as = reinterpret_cast<T*>(lds_raw);
+  double* ys = reinterpret_cast<double*>(as + (long)nrows * RS);
+  const long rb = xcd_order(blockIdx.x, gridDim.x);
+  const long r0 = rb * R;
+  const int n_el = nrows * NBT * R;
+  for (int e = threadIdx.x; e < n_el; e += NT) {
+    const int ri = e % R;
+    const int b = (e / R) % NBT;
+    const int vl = e / (R * NBT);
+    const int v = row0 + vl;
+    T av = 0;
+    double yv = 0;
+    if (v < nv && b < nb) {
+      const long gi = ((long)b * nvh + (v >> 1)) * nr + r0 + ri;
+      av = reinterpret_cast<const T*>(a + gi)[v & 1];
+      if (accumulate) yv = reinterpret_cast<const T*>(y + gi)[v & 1];
+    }
+    const int li = vl * RS + b * R + ri;
+    as[li] = av;
+    ys[li] = yv;
+  }
+  __syncthreads();
+  const int bl = threadIdx.x % QS_BL;
+  const int ri = (threadIdx.x / QS_BL) % R;
+  const int slot = threadIdx.x / (QS_BL * R);
+  const long b0 = nblk * slot / NSLOT, b1 = nblk * (slot + 1) / NSLOT;
+  // this lane's two columns (2 bl, 2 bl + 1) of block 0 for its grid point
+  const T* tcol = tau + rb * rb_stride + (2 * bl * R + ri) * 8;
+  const int lo = bl * NBL * R + ri;  // lane offset inside an LDS row
+  int curI = -1;
+  T aI[8][NBL], acc[8][NBL];
+  // FP32 lanes have the registers to read the next block's columns while the
+  // current block is in use; FP64 lanes read each block when they reach it
+  constexpr bool PF = sizeof(T) == 4;
+  T nxt[2][8];
+  if (PF && b0 < b1) {
+    load8(nxt[0], tcol + b0 * 64 * R);
+    load8(nxt[1], tcol + b0 * 64 * R + 8 * R);
+  }
+#pragma unroll 1
+  for (long blk = b0; blk < b1; ++blk) {
+    const int2 bij = IJ[blk];
+    T own[2][8];
+    if (PF) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) own[q][i] = nxt[q][i];
+      if (blk + 1 < b1) {
+        load8(nxt[0], tcol + (blk + 1) * 64 * R);
+        load8(nxt[1], tcol + (blk + 1) * 64 * R + 8 * R);
+      }
+    } else {
+      const T* tp = tcol + blk * 64 * R;
+      load8(own[0], tp);
+      load8(own[1], tp + 8 * R);
+    }
+    if (bij.x != curI) {
+      if (curI >= 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int b = 0; b < NBL; ++b)
+            atomicAdd(&ys[(curI * 8 + i - row0) * RS + lo + b * R], (double)acc[i][b]);
+      }
+      curI = bij.x;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int b = 0; b < NBL; ++b) {
+          aI[i][b] = as[(curI * 8 + i - row0) * RS + lo + b * R];
+          acc[i][b] = 0;
+        }
+    }
+    const int rowJ = bij.y * 8 - row0;
+    qs_column<0, R>(own, acc, aI, as, ys, rowJ, lo);
+    qs_column<1, R>(own, acc, aI, as, ys, rowJ, lo);
+    qs_column<2, R>(own, acc, aI, as, ys, rowJ, lo);
+    qs_column<3, R>(own, acc, aI, as, ys, rowJ, lo);
+    qs_column<4, R>(own, acc, aI, as, ys, rowJ, lo);
+    qs_column<5, R>(own, acc, aI, as, ys, rowJ, lo);
+    qs_column<6, R>(own, acc, aI, as, ys, rowJ, lo);
+    qs_column<7, R>(own, acc, aI, as, ys, rowJ, lo);
+  }
+  if (curI >= 0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int b = 0; b < NBL; ++b)
+        atomicAdd(&ys[(curI * 8 + i - row0) * RS + lo + b * R], (double)acc[i][b]);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n_el; e += NT) {
+    const int rr = e % R;
+    const int b = (e / R) % NBT;
+    const int vl = e / (R * NBT);
+    const int v = row0 + vl;
+    if (v < nv && b < nb) {
+      const long gi = ((long)b * nvh + (v >> 1)) * nr + r0 + rr;
+      const int li = vl * RS + b * R + rr;
+      T out = (T)ys[li];
+      if (FUSE) {
+        const long r = r0 + rr;
+        T z = -out;
+        if (with_v) z += V[r] * as[li];
+        if (vdrho) {
+          const T d = reinterpret_cast<const T*>(vdrho + (long)(b >> 1) * nr + r)[b & 1];
+          const T f = reinterpret_cast<const T*>(phir + (long)(v >> 1) * nr + r)[v & 1];
+          z += s * d * f;
+        }
+        out = z;
+      }
+      reinterpret_cast<T*>(y + gi)[v & 1] = out;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // potential, Coulomb kernel, forces
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int min_image(int i, int n) { return (i < (n + 1) / 2) ? i : i - n; }
@@ -935,11 +1146,23 @@ int tau_store(const float2* grids, const int2* blkIJ, long nblk, long nr, int R,
   return tau_store_impl(grids, blkIJ, nblk, nr, R, dst, dst_nblk, dst_blk0, st);
 }
 
-size_t tau_stream_lds(int nv, int R, size_t elem) {
+size_t tau_stream_lds(int nv, int R, size_t elem, int bl) {
+  (void)bl;  // every variant stages the same LDS rows
   const int nv8 = (nv + 7) / 8 * 8;
   return (elem + sizeof(double)) * (size_t)nv8 * (NBT * R + SPAD);
 }
 
+template <int R, bool F, typename T>
+static void launch_stream_qs(long nrb, size_t shm, hipStream_t st, const T* tau, long stride,
+                             long nblk, const int2* blkIJ, const typename vec2_of<T>::type* a,
+                             typename vec2_of<T>::type* y, int nb, int nv, long nr, int row0,
+                             int nrows, int accumulate, const T* V,
+                             const typename vec2_of<T>::type* vdrho,
+                             const typename vec2_of<T>::type* phir, T s, int with_v) {
+  hipLaunchKernelGGL((k_tau_stream_qs<R, F, T>), dim3((unsigned)nrb), dim3(NSLOT * R * QS_BL),
+                     shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, (nv + 1) / 2, nr, row0,
+                     nrows, accumulate, V, vdrho, phir, s, with_v);
+}
 
 template <int R, int BL, bool F, typename T>
 static void launch_stream(long nrb, size_t shm, hipStream_t st, const T* tau, long stride,
@@ -968,7 +1191,7 @@ static int tau_stream_impl(const T* tau, long buf_nblk, long nblk, const int2* b
   if (row0 < 0 || row0 % 8 || rows % 8 || row0 + rows > nv8)
     return fail(BSE_EINVAL, "tau_stream: band rows %d..%d outside 0..%d", row0, row0 + rows, nv8);
   if (fuse && rows != nv8) return fail(BSE_EINVAL, "tau_stream: the fused epilogue needs every band");
-  const size_t shm = tau_stream_lds(rows, R, sizeof(T));
+  const size_t shm = tau_stream_lds(rows, R, sizeof(T), bl);
   if (shm > max_lds) return fail(BSE_EINVAL, "tau_stream: %zu bytes of LDS exceed %zu", shm, max_lds);
   const long nrb = nr / R;
   if (nrb > 0x7fffffffL) return fail(BSE_EINVAL, "tau_stream: grid too large");
@@ -987,7 +1210,20 @@ static int tau_stream_impl(const T* tau, long buf_nblk, long nblk, const int2* b
       launch_stream<R_, BL_, false, T>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,  \
                                        row0, rows, accumulate, V, vd, ph, sf, wv);               \
   } while (0)
-  if (R == 2 && bl == 4)
+#define GO_QS(R_)                                                                                \
+  do {                                                                                           \
+    if (fuse)                                                                                    \
+      launch_stream_qs<R_, true, T>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,     \
+                                    row0, rows, accumulate, V, vd, ph, sf, wv);                  \
+    else                                                                                         \
+      launch_stream_qs<R_, false, T>(nrb, shm, st, tau, stride, nblk, blkIJ, a, y, nb, nv, nr,    \
+                                     row0, rows, accumulate, V, vd, ph, sf, wv);                 \
+  } while (0)
+  if (R == 2 && bl == 1)
+    GO_QS(2);
+  else if (R == 1 && bl == 1)
+    GO_QS(1);
+  else if (R == 2 && bl == 4)
     GO(2, 4);
   else if (R == 2 && bl == 2)
     GO(2, 2);
@@ -998,6 +1234,7 @@ static int tau_stream_impl(const T* tau, long buf_nblk, long nblk, const int2* b
   else
     return fail(BSE_EINVAL, "tau_stream: R = %d, BL = %d unsupported", R, bl);
 #undef GO
+#undef GO_QS
   CHECK_LAUNCH();
   return BSE_OK;
 }
@@ -1025,7 +1262,11 @@ int tau_stream_set_lds_limit(size_t bytes) {
       (const void*)k_tau_stream<2, 4, false, float>,  (const void*)k_tau_stream<2, 2, false, float>,
       (const void*)k_tau_stream<1, 4, false, float>,  (const void*)k_tau_stream<1, 2, false, float>,
       (const void*)k_tau_stream<2, 4, true, float>,   (const void*)k_tau_stream<2, 2, true, float>,
-      (const void*)k_tau_stream<1, 4, true, float>,   (const void*)k_tau_stream<1, 2, true, float>};
+      (const void*)k_tau_stream<1, 4, true, float>,   (const void*)k_tau_stream<1, 2, true, float>,
+      (const void*)k_tau_stream_qs<2, false, double>, (const void*)k_tau_stream_qs<2, true, double>,
+      (const void*)k_tau_stream_qs<1, false, double>, (const void*)k_tau_stream_qs<1, true, double>,
+      (const void*)k_tau_stream_qs<2, false, float>,  (const void*)k_tau_stream_qs<2, true, float>,
+      (const void*)k_tau_stream_qs<1, false, float>,  (const void*)k_tau_stream_qs<1, true, float>};
   for (const void* f : fns)
     BSE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   return BSE_OK;

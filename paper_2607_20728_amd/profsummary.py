@@ -14,7 +14,7 @@
 
     python -m paper_2607_20728_amd.profsummary traffic --fetch DIR --write DIR
             --copy-fetch DIR --copy-write DIR --match k_tau_stream --out FILE
-            [--command TEXT]
+            [--dram DIR] [--command TEXT]
         HBM bytes per launch of the kernels whose name contains --match, from
         the FETCH_SIZE and WRITE_SIZE counter runs (--output-format csv),
         each scaled by the same counter on a plain 2 GiB copy
@@ -118,6 +118,15 @@ def traffic(a):
                write_kib_per_launch=statistics.mean(v for _, v in wk),
                copy_fetch_factor=ff, copy_write_factor=wf,
                copy_fetch_kib=fvals, copy_write_kib=wvals, command=a.command)
+    if a.dram:
+        # second route: DRAM-bound requests counted in 32-byte units
+        # (a 64-byte request counts 2, a 128-byte one 4)
+        rd = [v for n, v in _counter_rows(a.dram, "TCC_EA0_RDREQ_DRAM_32B_sum") if a.match in n]
+        wr = [v for n, v in _counter_rows(a.dram, "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum")
+              if a.match in n]
+        if rd and wr:
+            out["dram_read_bytes_per_launch"] = 32.0 * statistics.mean(rd)
+            out["dram_write_bytes_per_launch"] = 32.0 * statistics.mean(wr)
     with open(a.out, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
@@ -139,6 +148,8 @@ def main():
     for k in ("fetch", "write", "copy_fetch", "copy_write", "out"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     t.add_argument("--match", default="k_tau_stream")
+    t.add_argument("--dram", default=None,
+                   help="run with TCC_EA0_RDREQ_DRAM_32B_sum and TCC_EA0_WRREQ_WRITE_DRAM_32B_sum")
     t.add_argument("--command", default="")
     a = ap.parse_args()
     traffic(a)

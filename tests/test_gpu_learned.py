@@ -175,8 +175,8 @@ def test_training_on_solver_histories_gains_on_held_out_systems():
     """The whole learned pipeline on small systems of the c1 shape (different
     seeds): histories of the plain solver on 6 systems train the network on
     the GPU kernels; on 2 held-out systems the learned solves reach the plain
-    solution and use no more Z iterations than the same preconditioner form
-    without the network (the gain is printed)."""
+    solution and use strictly fewer Z iterations than the same
+    preconditioner form without the network."""
     print("[gpu] learned pipeline on c1-shaped systems", flush=True)
     from paper_2607_20728_amd import learned
     base = synth.get_config("c1")
@@ -210,5 +210,8 @@ def test_training_on_solver_histories_gains_on_held_out_systems():
         ctx.free()
     print(f"  loss {losses[0]:.3f} -> {losses[-1]:.3f}; held-out Z iterations "
           f"plain {plain_it}, learned {learn_it}")
-    assert learn_it <= plain_it
+    # the trained network must gain: strictly fewer Z iterations on the
+    # held-out systems than the same preconditioner without it (measured:
+    # 30 against 32)
+    assert learn_it < plain_it
     net.free()
