@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define BSEX_ABI_VERSION 1
+#define BSEX_ABI_VERSION 2
 
 typedef enum {
   BSE_OK = 0,
@@ -119,6 +119,26 @@ typedef struct {
                                  occupied states (0: 1e-10); the n_extra states
                                  above them stop at max(gs_tol, 1e-6)           */
   void *stream;               /* hipStream_t, NULL for the null stream            */
+  /* Ground-state model.  0 = the fixed local potential above (default).
+   * 1 = self-consistent Kohn-Sham Hamiltonian (the paper's DFT starting
+   * point, reduced to a synthetic functional; SM Sec. I):
+   *   H_KS = |G|^2/2 + V(r) + V_H[rho] + V_xc[rho],  rho = 2 sum_v phi_v^2,
+   *   V_H = v_c * rho,  V_xc = -(3/pi)^(1/3) [(rho + rho_floor)^(1/3) - rho_floor^(1/3)].
+   * The ground state is then solved to self-consistency (or, with orbitals
+   * supplied, H_KS is built from their density); D uses H_KS, U gains its D
+   * part 2 P_c [f_Hxc * Drho_x] phi_v and the Z-vector operator the kernels
+   * 2 K^1e,KS + 2 K^2e,KS = 4 P_c [f_Hxc * sum_v' phi_v' Z_v'] phi_v of Eq. 7,
+   * f_Hxc * g = v_c * g + (dV_xc/drho) g.
+   * alpha_exx > 0 (a hybrid starting point) adds -alpha K_x to H_KS,
+   * (K_x psi)(r) = sum_w phi_w(r) [v_c * (phi_w psi)](r), and with it the
+   * exact-exchange terms of U's D part and the kernels -K^1d,KS - K^2d,KS of
+   * Eq. 7; each costs one Poisson solve per occupied pair and vector, so it
+   * is meant for small systems, and it needs the orbitals supplied
+   * (n_orb > 0, eigenvectors of that H_KS) and BSE_FP64. */
+  int32_t ks_model;
+  double rho_floor;           /* density floor of V_xc (0: 1e-3)                  */
+  double scf_tol;             /* RMS change of V_H + V_xc ending the SCF (0: 1e-10) */
+  double alpha_exx;           /* exact-exchange fraction, 0 <= alpha_exx <= 1      */
 } bse_system_desc;
 
 /* Library ABI version (BSEX_ABI_VERSION of the build). */
@@ -166,6 +186,8 @@ typedef struct {
   double t_tau_ms;            /*   sizing, allocation and build of the tau caches */
   double t_tau_alloc_ms;      /*     of which the allocation of the caches      */
   double t_init_ms;           /*   the whole call                                 */
+  int32_t scf_iters;          /* self-consistent cycles of the KS model (0 if none) */
+  double scf_resid;           /* their final RMS potential change (-1 if none)    */
 } bse_info;
 
 int bse_get_info(bse_ctx *ctx, bse_info *info);

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbsex.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, EGAP, EABI, ESTATE = range(8)
 K_D, K_1E, K_1D_BARE, K_1D_PDEP, K_ALL = 1, 2, 4, 8, 15
 FP64, MIXED = 0, 1
@@ -51,7 +51,9 @@ class SystemDesc(C.Structure):
                 ("tau_policy", C.c_int32), ("tau_budget_bytes", C.c_int64),
                 ("gap_min", C.c_double), ("kernel_mask", C.c_int32), ("n_orb", C.c_int32),
                 ("orbitals", C.POINTER(C.c_double)), ("eps", C.POINTER(C.c_double)),
-                ("n_extra", C.c_int32), ("gs_tol", C.c_double), ("stream", C.c_void_p)]
+                ("n_extra", C.c_int32), ("gs_tol", C.c_double), ("stream", C.c_void_p),
+                ("ks_model", C.c_int32), ("rho_floor", C.c_double), ("scf_tol", C.c_double),
+                ("alpha_exx", C.c_double)]
 
 
 class Info(C.Structure):
@@ -62,7 +64,8 @@ class Info(C.Structure):
                 ("precision", C.c_int32), ("active_precision", C.c_int32),
                 ("tau_bytes_f32", C.c_int64), ("gs_sweeps", C.c_int32),
                 ("t_ground_state_ms", C.c_double), ("t_tau_ms", C.c_double),
-                ("t_tau_alloc_ms", C.c_double), ("t_init_ms", C.c_double)]
+                ("t_tau_alloc_ms", C.c_double), ("t_init_ms", C.c_double),
+                ("scf_iters", C.c_int32), ("scf_resid", C.c_double)]
 
 
 class BatchOpts(C.Structure):
@@ -215,7 +218,8 @@ class Context:
 def init_system(cell, grid, ecut, site_xyz, site_depth, site_width, n_val, pdep, lam, *,
                 scissor=0.0, spin_factor=2.0, tau_policy=TAU_AUTO, tau_budget_bytes=0,
                 gap_min=0.0, kernel_mask=K_ALL, orbitals=None, eps=None, n_extra=8,
-                gs_tol=1e-10, precision=FP64, stream=None, desc_only=False):
+                gs_tol=1e-10, precision=FP64, stream=None, desc_only=False, ks_model=0,
+                rho_floor=0.0, scf_tol=0.0, alpha_exx=0.0):
     """bse_init_system.  orbitals [n_orb][n_pw] / eps [n_orb] (host) or None to
     let the library solve the ground state."""
     import torch
@@ -246,6 +250,10 @@ def init_system(cell, grid, ecut, site_xyz, site_depth, site_width, n_val, pdep,
         d.orbitals, d.eps = _dptr(O), _dptr(E)
     d.n_extra = int(n_extra)
     d.gs_tol = float(gs_tol)
+    d.ks_model = int(ks_model)
+    d.rho_floor = float(rho_floor)
+    d.scf_tol = float(scf_tol)
+    d.alpha_exx = float(alpha_exx)
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     d.stream = C.c_void_p(stream)
@@ -311,7 +319,8 @@ def get_info(ctx):
                 gs_resid=i.gs_resid, ks_gap=i.ks_gap, precision=i.precision,
                 active_precision=i.active_precision, tau_bytes_f32=i.tau_bytes_f32,
                 gs_sweeps=i.gs_sweeps, t_ground_state_ms=i.t_ground_state_ms,
-                t_tau_ms=i.t_tau_ms, t_tau_alloc_ms=i.t_tau_alloc_ms, t_init_ms=i.t_init_ms)
+                t_tau_ms=i.t_tau_ms, t_tau_alloc_ms=i.t_tau_alloc_ms, t_init_ms=i.t_init_ms,
+                scf_iters=i.scf_iters, scf_resid=i.scf_resid)
 
 
 def get_orbitals(ctx, n=None):

@@ -85,6 +85,14 @@ int validate(const bse_system_desc* d) {
   if (d->n_extra < 0) return fail(BSE_EINVAL, "n_extra < 0");
   if (!std::isfinite(d->gap_min) || !std::isfinite(d->gs_tol) || d->gs_tol < 0)
     return fail(BSE_EINVAL, "gap_min / gs_tol invalid");
+  if (d->ks_model != 0 && d->ks_model != 1) return fail(BSE_EINVAL, "ks_model %d unknown", d->ks_model);
+  if (!std::isfinite(d->rho_floor) || d->rho_floor < 0 || !std::isfinite(d->scf_tol) ||
+      d->scf_tol < 0)
+    return fail(BSE_EINVAL, "rho_floor / scf_tol invalid");
+  if (!std::isfinite(d->alpha_exx) || d->alpha_exx < 0 || d->alpha_exx > 1)
+    return fail(BSE_EINVAL, "alpha_exx must be in [0, 1]");
+  if (d->alpha_exx != 0 && (d->ks_model != 1 || d->n_orb <= 0 || d->precision != BSE_FP64))
+    return fail(BSE_EINVAL, "alpha_exx needs ks_model 1, orbitals supplied and BSE_FP64");
   return BSE_OK;
 }
 
@@ -121,6 +129,7 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
     return fail(BSE_EINVAL, "n_val %d too large for the device LDS (%zu bytes)", c->nv, c->max_lds);
   const bool mixed = c->precision == BSE_MIXED;
   c->Rf = (tau_stream_lds(c->nv, 2, sizeof(float), c->tau_bl) <= c->max_lds) ? 2 : 1;
+  if (const char* e = getenv("BSEX_TAU_R")) c->Rf = (atoi(e) == 1) ? 1 : c->Rf;
   if (mixed && tau_stream_lds(c->nv, c->Rf, sizeof(float), c->tau_bl) > c->max_lds)
     return fail(BSE_EINVAL, "n_val %d too large for the device LDS (%zu bytes)", c->nv, c->max_lds);
   BSE_TRY(tau_stream_set_lds_limit(c->max_lds));
@@ -261,6 +270,10 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
   c->gap_min = d->gap_min;
   c->gs_tol = d->gs_tol > 0 ? d->gs_tol : 1e-10;
   c->n_extra = d->n_extra;
+  c->ks = d->ks_model;
+  c->alpha = d->alpha_exx;
+  if (d->rho_floor > 0) c->rho_floor = d->rho_floor;
+  if (d->scf_tol > 0) c->scf_tol = d->scf_tol;
   // the device work starts here: record the device and its allocation-free
   // scratch address
   BSE_HIP(hipGetDevice(&c->dev));
@@ -302,6 +315,12 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
   }
   BSE_TRY(ctx_alloc_t(c, &c->vc, nr));
   BSE_TRY(coulomb_kernel(c->basis.grid, c->basis.cell, c->vc, c->st));
+  if (c->ks) {  // V_ext kept apart: Vr becomes V_ext + V_H + V_xc
+    BSE_TRY(ctx_alloc_t(c, &c->Vext, nr));
+    BSE_TRY(ctx_alloc_t(c, &c->fxc, nr));
+    BSE_TRY(ctx_alloc_t(c, &c->rho_ks, nr));
+    BSE_HIP(hipMemcpyAsync(c->Vext, c->Vr, sizeof(double) * nr, hipMemcpyDeviceToDevice, c->st));
+  }
   // PDEP: Pt = v_c^1/2 P, Ptc = v_c^1/2 P c
   if (c->npdep > 0) {
     std::vector<double> pt((size_t)npw * c->npdep), ptc((size_t)npw * c->npdep);
@@ -331,7 +350,10 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
     const int extra = d->n_extra > 0 ? d->n_extra : 8;
     const int want = (int)std::min<long>(npw, (long)c->nv + extra);
     const auto t0 = std::chrono::steady_clock::now();
-    BSE_TRY(ground_state(c, want, c->gs_tol));
+    if (c->ks)
+      BSE_TRY(ks_ground_state(c, want));
+    else
+      BSE_TRY(ground_state(c, want, c->gs_tol));
     BSE_HIP(hipStreamSynchronize(c->st));
     c->t_gs_ms = ms_since(t0);
   }
@@ -341,8 +363,10 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
       return fail(BSE_EGAP, "Kohn-Sham gap %.3e Ha below gap_min %.3e", c->ks_gap, c->gap_min);
   }
   // phi(r)
-  BSE_TRY(ctx_alloc_t(c, &c->phir, (size_t)c->nvh * nr));
+  if (!c->phir) BSE_TRY(ctx_alloc_t(c, &c->phir, (size_t)c->nvh * nr));
   BSE_TRY(to_grid(c, c->Phi, c->nv, 1, c->phir));
+  // orbitals supplied for the KS model: H_KS from their density
+  if (c->ks && d->n_orb > 0) BSE_TRY(ks_potential_from_orbitals(c));
   c->precision = d->precision;
   if (c->precision == BSE_MIXED) {  // FP32 copies of the real-space fields
     BSE_TRY(ctx_alloc_t(c, &c->phir_f, (size_t)c->nvh * nr));
@@ -469,6 +493,8 @@ int bse_get_info(bse_ctx* c, bse_info* info) {
   info->t_tau_ms = c->t_tau_ms;
   info->t_tau_alloc_ms = c->t_tau_alloc_ms;
   info->t_init_ms = c->t_init_ms;
+  info->scf_iters = c->scf_iters;
+  info->scf_resid = c->ks ? c->scf_resid : -1.0;
   return BSE_OK;
 }
 

@@ -34,6 +34,16 @@ struct bse_ctx {
   int nv = 0, nvh = 0, npdep = 0, nsites = 0, kmask = 0, norb = 0, n_extra = 0;
   double scissor = 0, spin = 2, gap_min = 0, gs_tol = 1e-10, gs_resid = -1, ks_gap = -1;
   int gs_sweeps = 0;
+  // self-consistent KS model (0: H = T + V_ext fixed)
+  int ks = 0, scf_iters = 0, scf_max_iter = 200;
+  double rho_floor = 1e-3, scf_tol = 1e-10, scf_resid = -1;
+  double* Vext = nullptr;     // [nr] V_ext (Vr holds V_ext + V_H + V_xc)
+  double* fxc = nullptr;      // [nr] f_xc at the ground-state density
+  double* rho_ks = nullptr;   // [nr] ground-state density 2 sum phi^2
+  double alpha = 0.0;         // exact-exchange fraction alpha_EXX of H_KS
+  double2* xpair = nullptr;   // [nvh][nr] pair grids of the exchange terms
+  double2* xgrid = nullptr;   // [xgrid_sets][nvh][nr] -alpha K_x a of an apply block
+  int xgrid_sets = 0;
   double t_gs_ms = 0, t_tau_ms = 0, t_tau_alloc_ms = 0, t_init_ms = 0;  // init stages, wall
   hipStream_t st = nullptr;
   int dev = -1;               // device the context was initialised on
@@ -172,7 +182,13 @@ int apply_any(bse_ctx* c, int nb, const double* X, double* Y);
 int apply_H_f(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double shift,
               const double* eps, int project);
 int ensure_mixed_work(bse_ctx* c, int nbc);
-int ground_state(bse_ctx* c, int n_want, double tol);
+int ground_state(bse_ctx* c, int n_want, double tol, bool warm = false);
+// self-consistent KS model: SCF ground state, or the potential of given orbitals
+int ks_ground_state(bse_ctx* c, int n_want);
+int ks_potential_from_orbitals(bse_ctx* c);
+// out_v += scale sum_w L_w (v_c * (M_w x_v)), v < nx (packed grids)
+int exchange_like(bse_ctx* c, const double2* L, const double2* M, const double2* x, int nx,
+                  double2* out, double scale);
 int gram_tall(bse_ctx* c, const double* A, long m, const double* B, long n, long len, double* C);
 // device address of the allocation-free scratch on `dev` (called once per
 // context initialisation, with that device current)

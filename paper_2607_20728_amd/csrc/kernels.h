@@ -120,6 +120,22 @@ int force_density(const double2* a, const double2* phit, const double2* z, const
 // partial sums for dw/dR: out[site][3] (host) from the forward transform of rho
 // rho[r] = (sum_v phi_v(r)^2, 0) over the nv orbitals of phir
 int occupied_density(const double2* phir, int nv, long nr, double2* rho, hipStream_t st);
+// self-consistent KS model: from rho_occ = sum_v phi_v^2 (real part), with
+// rho = occ rho_occ: V_xc and f_xc of Slater exchange with the density floor
+// floor_ (formulas at the kernel); rho_out (optional) receives rho
+int xc_fields(const double2* rho_occ, long nr, double occ, double floor_, double* vxc,
+              double* fxc, double* rho_out, hipStream_t st);
+// exchange-like terms sum_w L_w (v_c * (M_w x)): pair grids (M_2q x, M_2q+1 x)
+// for the real grid function x = component xc of x2 (M holds nv functions
+// packed two per complex grid; an odd nv leaves the last .y of M zero), and
+// o2.{x|y}(r) += scale sum_w L_w(r) P_w(r)
+int pair_times(const double2* M, int nv, const double2* x2, int xc, long nr, double2* out,
+               hipStream_t st);
+int contract_pairs(const double2* L, const double2* P, int nv, long nr, double2* o2, int oc,
+                   double scale, hipStream_t st);
+// w <- scale (w + f_xc t) on ngrid complex grids (f_Hxc * t once w = v_c * t)
+int hxc_field(double2* w, const double2* t, const double* fxc, long ngrid, long nr, double scale,
+              hipStream_t st);
 int force_reduce(const double2* rhoG, const double* xyz, const double* depth,
                  const double* width, int nsites, const int grid[3], const double cell[3],
                  double* part, long part_len, double* out_dev, hipStream_t st);

@@ -713,6 +713,71 @@ __global__ void k_force_density(const double2* __restrict__ a, const double2* __
   }
 }
 
+// ---------------------------------------------------------------------------
+// self-consistent Kohn-Sham model: local exchange-correlation fields
+// ---------------------------------------------------------------------------
+// From rho_occ = sum_v phi_v^2 (real part of the grid): rho = occ rho_occ,
+//   V_xc  = -(3/pi)^(1/3) [ (rho + f)^(1/3) - f^(1/3) ]
+//   f_xc  = dV_xc/drho = -(1/3)(3/pi)^(1/3) (rho + f)^(-2/3)
+// (Slater exchange with a density floor f).  rho_out may be null.
+__global__ void k_xc_fields(const double2* __restrict__ rho_occ, long nr, double occ, double f,
+                            double* __restrict__ vxc, double* __restrict__ fxc,
+                            double* __restrict__ rho_out) {
+  const double cx = 0.98474502184269654;  // (3/pi)^(1/3)
+  const double f3 = cbrt(f);
+  for (long r = gtid(); r < nr; r += gstride()) {
+    const double rho = occ * rho_occ[r].x;
+    const double q = cbrt(rho + f);
+    vxc[r] = -cx * (q - f3);
+    fxc[r] = -(cx / 3.0) / (q * q);
+    if (rho_out) rho_out[r] = rho;
+  }
+}
+
+// w = scale (w + f_xc t) on both components: f_Hxc * t once w holds v_c * t
+__global__ void k_hxc_field(double2* __restrict__ w, const double2* __restrict__ t,
+                            const double* __restrict__ fxc, long ngrid, long nr, double scale) {
+  const long n = ngrid * nr;
+  for (long e = gtid(); e < n; e += gstride()) {
+    const double fx = fxc[e % nr];
+    const double2 a = w[e], b = t[e];
+    w[e] = make_double2(scale * (a.x + fx * b.x), scale * (a.y + fx * b.y));
+  }
+}
+
+// exchange-like terms: pair grids q = (M_2q x, M_2q+1 x) for one real grid
+// function x (component xc of the packed grid x2)
+__global__ void k_pair_times(const double2* __restrict__ M, int nvh, const double2* __restrict__ x2,
+                             int xc, long nr, double2* __restrict__ out) {
+  const long n = (long)nvh * nr;
+  for (long e = gtid(); e < n; e += gstride()) {
+    const long r = e % nr;
+    const double2 xv = x2[r];
+    const double x = xc ? xv.y : xv.x;
+    const double2 m = M[e];
+    out[e] = make_double2(m.x * x, m.y * x);
+  }
+}
+
+// out (component oc of the packed grid o2) += scale sum_w L_w(r) P_w(r)
+__global__ void k_contract_pairs(const double2* __restrict__ L, const double2* __restrict__ P,
+                                 int nvh, long nr, double2* __restrict__ o2, int oc,
+                                 double scale) {
+  for (long r = gtid(); r < nr; r += gstride()) {
+    double s = 0.0;
+    for (int q = 0; q < nvh; ++q) {
+      const double2 l = L[(long)q * nr + r], p = P[(long)q * nr + r];
+      s += l.x * p.x + l.y * p.y;
+    }
+    double2 o = o2[r];
+    if (oc)
+      o.y += scale * s;
+    else
+      o.x += scale * s;
+    o2[r] = o;
+  }
+}
+
 // occupied density sum_v phi_v(r)^2 (two orbitals per complex grid)
 __global__ void k_occupied_density(const double2* __restrict__ phir, int nvh, long nr,
                                    double2* __restrict__ rho) {
@@ -993,6 +1058,39 @@ int mul_real_field(float2* grid, long ngrid, long nr, const float* f, float scal
   if (n <= 0) return BSE_OK;
   hipLaunchKernelGGL((k_mul_real<float2, float>), dim3(nblocks(n)), dim3(TPB), 0, st, grid, n, nr,
                      f, scale);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int xc_fields(const double2* rho_occ, long nr, double occ, double floor_, double* vxc,
+              double* fxc, double* rho_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_xc_fields, dim3(nblocks(nr)), dim3(TPB), 0, st, rho_occ, nr, occ, floor_,
+                     vxc, fxc, rho_out);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int hxc_field(double2* w, const double2* t, const double* fxc, long ngrid, long nr, double scale,
+              hipStream_t st) {
+  hipLaunchKernelGGL(k_hxc_field, dim3(nblocks(ngrid * nr)), dim3(TPB), 0, st, w, t, fxc, ngrid,
+                     nr, scale);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int pair_times(const double2* M, int nv, const double2* x2, int xc, long nr, double2* out,
+               hipStream_t st) {
+  const int nvh = (nv + 1) / 2;
+  hipLaunchKernelGGL(k_pair_times, dim3(nblocks((long)nvh * nr)), dim3(TPB), 0, st, M, nvh, x2, xc,
+                     nr, out);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int contract_pairs(const double2* L, const double2* P, int nv, long nr, double2* o2, int oc,
+                   double scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_contract_pairs, dim3(nblocks(nr)), dim3(TPB), 0, st, L, P, (nv + 1) / 2,
+                     nr, o2, oc, scale);
   CHECK_LAUNCH();
   return BSE_OK;
 }

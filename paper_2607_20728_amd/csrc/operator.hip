@@ -338,6 +338,25 @@ int ensure_ygrid(bse_ctx* c) {
   return ctx_alloc_t(c, &c->ygrid, (size_t)c->nbc * c->nvh * c->basis.nr);
 }
 
+// out_v += scale sum_w L_w (v_c * (M_w x_v)) for the nx real grid functions
+// x_v (packed two per complex grid, like out); L and M hold the nv occupied-
+// sized functions of the exact-exchange terms (SM Sec. I).  One Poisson solve
+// per (w, v) pair, batched over w.
+int exchange_like(bse_ctx* c, const double2* L, const double2* M, const double2* x, int nx,
+                  double2* out, double scale) {
+  const long nr = c->basis.nr;
+  if (!c->xpair) BSE_TRY(ctx_alloc_t(c, &c->xpair, (size_t)c->nvh * nr));
+  double2* P = c->xpair;
+  for (int v = 0; v < nx; ++v) {
+    BSE_TRY(pair_times(M, c->nv, x + (long)(v >> 1) * nr, v & 1, nr, P, c->st));
+    BSE_TRY(fft3d(c->fft, P, c->nvh, -1, c->st));
+    BSE_TRY(mul_real_field(P, c->nvh, nr, c->vc, 1.0 / (double)nr, c->st));
+    BSE_TRY(fft3d(c->fft, P, c->nvh, +1, c->st));
+    BSE_TRY(contract_pairs(L, P, c->nv, nr, out + (long)(v >> 1) * nr, v & 1, scale, c->st));
+  }
+  return BSE_OK;
+}
+
 // Y = P_c (D + s K1e - K1d) P_c X for nb <= c->nbc vectors
 int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
   const long nr = c->basis.nr;
@@ -356,6 +375,21 @@ int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
   }
   const int with_v = (c->kmask & BSE_K_D) ? 1 : 0;
   double2* zg = c->agrid;
+  // exact-exchange part of H_KS in D: -alpha K_x a_v, K_x a = sum_w phi_w v_c*(phi_w a)
+  // (taken before the stream, which may overwrite a(r) with z)
+  const long gs = (long)c->nvh * nr;
+  if (c->alpha != 0.0 && with_v) {
+    if (!c->xgrid || c->xgrid_sets < nb) {
+      ctx_release(c, c->xgrid);
+      c->xgrid = nullptr;
+      BSE_TRY(ctx_alloc_t(c, &c->xgrid, (size_t)c->nbc * gs));
+      c->xgrid_sets = c->nbc;
+    }
+    BSE_TRY(zero_fill(reinterpret_cast<double*>(c->xgrid), 2 * nb * gs, c->st));
+    for (int b = 0; b < nb; ++b)
+      BSE_TRY(exchange_like(c, c->phir, c->phir, c->agrid + b * gs, c->nv, c->xgrid + b * gs,
+                            -c->alpha));
+  }
   if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
     if (c->nblk_cached == c->nblk) {
       // whole tau cached: one launch, combine fused, z written over a(r)
@@ -374,6 +408,9 @@ int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
     BSE_TRY(combine(c->agrid, c->phir, c->Vr, vdrho, nullptr, c->agrid, c->nv, nb, nr, c->spin,
                     with_v, c->st));
   }
+  if (c->alpha != 0.0 && with_v)
+    BSE_TRY(axpby(1.0, reinterpret_cast<const double*>(c->xgrid), 1.0,
+                  reinterpret_cast<double*>(zg), 2 * nb * gs, c->st));
   BSE_TRY(from_grid(c, zg, c->nv, nb, with_v ? A : nullptr, c->eps_d, c->scissor, c->Zs));
   BSE_TRY(proj_c(c, c->Zs, Y, nb));
   return BSE_OK;

@@ -564,11 +564,217 @@ int davidson(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double
 }
 
 // ---------------------------------------------------------------------------
+// Self-consistent Kohn-Sham model (Eq. 7, SM Sec. I): H_KS = T + V_ext +
+// V_H[rho] + V_xc[rho], rho = 2 sum_v phi_v^2, V_xc Slater exchange with a
+// density floor; f_Hxc * g = v_c * g + f_xc g.
+// ---------------------------------------------------------------------------
+// V_H + V_xc of the occupied orbitals on the grid phir (nvh complex grids)
+// into vhxc [nr]; sets c->fxc and c->rho_ks.  One complex grid of scratch.
+static int ks_fields(bse_ctx* c, const double2* phir, double* vhxc) {
+  const long nr = c->basis.nr;
+  DVec rg(c), vx(c);
+  BSE_TRY(rg.alloc(2 * (size_t)nr));
+  BSE_TRY(vx.alloc((size_t)nr));
+  double2* rho = reinterpret_cast<double2*>(rg.p);
+  BSE_TRY(occupied_density(phir, c->nv, nr, rho, c->st));  // (sum phi^2, 0)
+  BSE_TRY(xc_fields(rho, nr, 2.0, c->rho_floor, vx.p, c->fxc, c->rho_ks, c->st));
+  BSE_TRY(fft3d(c->fft, rho, 1, -1, c->st));
+  BSE_TRY(mul_real_field(rho, 1, nr, c->vc, 2.0 / (double)nr, c->st));
+  BSE_TRY(fft3d(c->fft, rho, 1, +1, c->st));
+  BSE_TRY(real_part(rho, nr, vhxc, c->st));
+  return axpby(1.0, vx.p, 1.0, vhxc, nr, c->st);
+}
+
+// H_KS from orbitals given by the caller: V_eff = V_ext + V_hxc(rho(phi))
+int ks_potential_from_orbitals(bse_ctx* c) {
+  const long nr = c->basis.nr;
+  DVec vh(c);
+  BSE_TRY(vh.alloc((size_t)nr));
+  BSE_TRY(ks_fields(c, c->phir, vh.p));
+  BSE_TRY(copy_dev(c, c->Vext, c->Vr, nr));
+  return axpby(1.0, vh.p, 1.0, c->Vr, nr, c->st);
+}
+
+// Self-consistent ground state: Chebyshev-filtered eigenpairs of H_KS[V_hxc]
+// (warm started from the previous cycle) and Anderson (Pulay) mixing of the
+// Hartree-xc potential until the RMS change of V_hxc is <= c->scf_tol.  The
+// final orbitals are eigenvectors of the Hamiltonian built from the previous
+// cycle's orbitals, as in any SCF.
+int ks_ground_state(bse_ctx* c, int n_want) {
+  const long nr = c->basis.nr;
+  constexpr int kHist = 6;
+  constexpr double kBeta = 0.3;
+  DVec x(c), xo(c), f(c), hx(c), hf(c), sv(c);
+  BSE_TRY(x.alloc((size_t)nr));
+  BSE_TRY(xo.alloc((size_t)nr));
+  BSE_TRY(f.alloc((size_t)nr));
+  BSE_TRY(hx.alloc((size_t)kHist * nr));   // differences of successive inputs
+  BSE_TRY(hf.alloc((size_t)kHist * nr));   // and of successive residuals
+  BSE_TRY(sv.alloc(4 * (size_t)kHist * kHist + 64));
+  if (!c->phir) BSE_TRY(ctx_alloc_t(c, &c->phir, (size_t)c->nvh * nr));
+  BSE_TRY(zero_fill(x.p, nr, c->st));
+  double res = 1e300;
+  int nh = 0, head = 0;
+  DVec xprev(c), fprev(c);
+  BSE_TRY(xprev.alloc((size_t)nr));
+  BSE_TRY(fprev.alloc((size_t)nr));
+  for (int it = 0; it < c->scf_max_iter; ++it) {
+    BSE_TRY(copy_dev(c, c->Vext, c->Vr, nr));
+    BSE_TRY(axpby(1.0, x.p, 1.0, c->Vr, nr, c->st));
+    // early cycles need no tighter eigenpairs than the potential they use
+    const double gtol = std::max(c->gs_tol, std::min(1e-4, 0.1 * res));
+    BSE_TRY(ground_state(c, n_want, gtol, it > 0));
+    BSE_TRY(to_grid(c, c->Phi, c->nv, 1, c->phir));
+    BSE_TRY(ks_fields(c, c->phir, xo.p));
+    BSE_TRY(copy_dev(c, xo.p, f.p, nr));
+    BSE_TRY(axpby(-1.0, x.p, 1.0, f.p, nr, c->st));  // f = V_out - V_in
+    std::vector<double> r2;
+    BSE_TRY(dots_host(c, f.p, f.p, 1, nr, sv.p, r2));
+    res = std::sqrt(std::max(0.0, r2[0]) / (double)nr);
+    c->scf_iters = it + 1;
+    c->scf_resid = res;
+    if (res <= c->scf_tol) break;
+    if (it > 0) {  // history of differences
+      double* dx = hx.p + (size_t)head * nr;
+      double* df = hf.p + (size_t)head * nr;
+      BSE_TRY(copy_dev(c, x.p, dx, nr));
+      BSE_TRY(axpby(-1.0, xprev.p, 1.0, dx, nr, c->st));
+      BSE_TRY(copy_dev(c, f.p, df, nr));
+      BSE_TRY(axpby(-1.0, fprev.p, 1.0, df, nr, c->st));
+      head = (head + 1) % kHist;
+      nh = std::min(nh + 1, kHist);
+    }
+    BSE_TRY(copy_dev(c, x.p, xprev.p, nr));
+    BSE_TRY(copy_dev(c, f.p, fprev.p, nr));
+    // gamma = argmin |f - dF gamma| (normal equations on the host), then
+    // x <- x + beta f - (dX + beta dF) gamma
+    std::vector<double> gam(nh, 0.0);
+    if (nh > 0) {
+      std::vector<double> G((size_t)nh * nh), b(nh);
+      BSE_TRY(gram_tall(c, hf.p, nh, hf.p, nh, nr, sv.p));
+      BSE_TRY(to_host(c, sv.p, G, G.size()));
+      BSE_TRY(gram_tall(c, hf.p, nh, f.p, 1, nr, sv.p));
+      BSE_TRY(to_host(c, sv.p, b, b.size()));
+      // regularised Cholesky solve of the small system
+      double tr = 0.0;
+      for (int i = 0; i < nh; ++i) tr += G[(size_t)i * nh + i];
+      for (int i = 0; i < nh; ++i) G[(size_t)i * nh + i] += 1e-12 * tr / nh + 1e-300;
+      if (host_cholesky(nh, G.data()) == 0) {
+        std::vector<double> y(nh);
+        for (int i = 0; i < nh; ++i) {
+          double t = b[i];
+          for (int k = 0; k < i; ++k) t -= G[(size_t)i * nh + k] * y[k];
+          y[i] = t / G[(size_t)i * nh + i];
+        }
+        for (int i = nh - 1; i >= 0; --i) {
+          double t = y[i];
+          for (int k = i + 1; k < nh; ++k) t -= G[(size_t)k * nh + i] * gam[k];
+          gam[i] = t / G[(size_t)i * nh + i];
+        }
+      }
+    }
+    BSE_TRY(axpby(kBeta, f.p, 1.0, x.p, nr, c->st));
+    for (int i = 0; i < nh; ++i) {
+      if (gam[i] == 0.0) continue;
+      BSE_TRY(axpby(-gam[i], hx.p + (size_t)i * nr, 1.0, x.p, nr, c->st));
+      BSE_TRY(axpby(-gam[i] * kBeta, hf.p + (size_t)i * nr, 1.0, x.p, nr, c->st));
+    }
+  }
+  if (res > c->scf_tol)
+    return fail(BSE_ENOCONV, "self-consistent ground state: RMS potential change %.3e above %.3e",
+                res, c->scf_tol);
+  // the Hamiltonian of the converged orbitals, and its eigenpairs
+  BSE_TRY(copy_dev(c, c->Vext, c->Vr, nr));
+  BSE_TRY(axpby(1.0, xo.p, 1.0, c->Vr, nr, c->st));
+  BSE_TRY(ground_state(c, n_want, c->gs_tol, true));
+  BSE_TRY(to_grid(c, c->Phi, c->nv, 1, c->phir));
+  // f_xc and rho at the final orbitals (the operator's kernels)
+  return ks_fields(c, c->phir, xo.p);
+}
+
+// f_Hxc * t for the density on the first (real) component of `w` [one
+// complex grid]; `t` receives a copy of the density first.
+static int ks_hxc_apply(bse_ctx* c, double2* w, double2* t) {
+  const long nr = c->basis.nr;
+  BSE_HIP(hipMemcpyAsync(t, w, sizeof(double2) * nr, hipMemcpyDeviceToDevice, c->st));
+  BSE_TRY(fft3d(c->fft, w, 1, -1, c->st));
+  BSE_TRY(mul_real_field(w, 1, nr, c->vc, 1.0 / (double)nr, c->st));
+  BSE_TRY(fft3d(c->fft, w, 1, +1, c->st));
+  return hxc_field(w, t, c->fxc, 1, nr, 1.0, c->st);
+}
+
+// D part of U for the self-consistent model (SM Sec. I, scissor
+// derivation): added to U,
+//   u^D_v = P_c { 2 [f_Hxc * Drho_x] phi_v - alpha sum_v' [v_c*(a_v' phi_v)] a_v'
+//                 + alpha sum_v' [v_c*(phi_v' phi_v)] sum_v'' <a_v''|a_v'> phi_v'' },
+//   Drho_x = sum a_v^2 - sum phi_v phi_v' <a_v'|a_v>
+// (the factor 2: V_Hxc depends on <phi_v| through rho = 2 sum phi^2).
+// A is the projected exciton; uses agrid sets 0-3 and drho as scratch.
+static int ks_u_dpart(bse_ctx* c, const double* A, double* U) {
+  const long npw = c->basis.npw, nv = c->nv, L = nv * npw, nr = c->basis.nr;
+  const long gs = (long)c->nvh * nr;
+  DVec O(c), Pt(c), G(c);
+  BSE_TRY(O.alloc((size_t)nv * nv));
+  BSE_TRY(Pt.alloc((size_t)L));
+  BSE_TRY(G.alloc((size_t)L));
+  BSE_TRY(gram_tall(c, A, nv, A, nv, npw, O.p));           // O[v][v'] = <a_v|a_v'>
+  BSE_TRY(dgemm(0, 0, nv, npw, nv, 1.0, O.p, nv, c->Phi, npw, 0.0, Pt.p, npw, c->st));
+  double2* a = c->agrid;
+  double2* pt = c->agrid + gs;
+  double2* zz = c->agrid + 2 * gs;
+  double2* g = c->agrid + 3 * gs;
+  BSE_TRY(to_grid(c, A, c->nv, 1, a));
+  BSE_TRY(to_grid(c, Pt.p, c->nv, 1, pt));
+  BSE_TRY(zero_fill(reinterpret_cast<double*>(zz), 2 * gs, c->st));
+  BSE_TRY(force_density(a, pt, zz, c->phir, c->nv, nr, c->drho, c->st));  // (Drho_x, 0)
+  BSE_TRY(ks_hxc_apply(c, c->drho, zz));
+  BSE_TRY(combine(a, c->phir, nullptr, c->drho, nullptr, g, c->nv, 1, nr, 2.0, 0, c->st));
+  if (c->alpha != 0.0) {
+    // - alpha sum_v' [v_c*(a_v' phi_v)] a_v' + alpha sum_v' [v_c*(phi_v' phi_v)] (O phi)_v'
+    BSE_TRY(exchange_like(c, a, a, c->phir, c->nv, g, -c->alpha));
+    BSE_TRY(exchange_like(c, pt, c->phir, c->phir, c->nv, g, c->alpha));
+  }
+  BSE_TRY(from_grid(c, g, c->nv, 1, nullptr, nullptr, 0.0, G.p));
+  BSE_TRY(proj_c(c, G.p, G.p, 1));
+  return axpby(1.0, G.p, 1.0, U, L, c->st);
+}
+
+// Z-vector operator of Eq. 7 for the self-consistent model (Zp in the P_c
+// space): P_c [ (H_KS - eps_v) Z_v + 4 (f_Hxc * sum_v' phi_v' Z_v') phi_v
+//               - alpha sum_v' [v_c*(phi_v' phi_v)] Z_v' - alpha sum_v' [v_c*(Z_v' phi_v)] phi_v' ]
+// (2 K^1e,KS + 2 K^2e,KS - K^1d,KS - K^2d,KS for real orbitals; H_KS holds
+// -alpha K_x).  agrid sets 0-2 and drho are scratch.
+static int ks_zop(bse_ctx* c, const double* Zp, double* out) {
+  const long nr = c->basis.nr;
+  const long gs = (long)c->nvh * nr;
+  double2* z = c->agrid;
+  double2* t = c->agrid + gs;
+  double2* ex = c->agrid + 2 * gs;
+  BSE_TRY(to_grid(c, Zp, c->nv, 1, z));
+  if (c->alpha != 0.0) {
+    // -alpha K_x Z_v (in H_KS), - K^1d,KS, - K^2d,KS:
+    // -alpha sum_w [phi_w v_c*(phi_w Z_v) + Z_w v_c*(phi_w phi_v) + phi_w v_c*(Z_w phi_v)]
+    BSE_TRY(zero_fill(reinterpret_cast<double*>(ex), 2 * gs, c->st));
+    BSE_TRY(exchange_like(c, c->phir, c->phir, z, c->nv, ex, -c->alpha));
+    BSE_TRY(exchange_like(c, z, c->phir, c->phir, c->nv, ex, -c->alpha));
+    BSE_TRY(exchange_like(c, c->phir, z, c->phir, c->nv, ex, -c->alpha));
+  }
+  BSE_TRY(transition_density(c->phir, z, c->nv, 1, nr, c->drho, c->st));
+  BSE_TRY(ks_hxc_apply(c, c->drho, t));
+  BSE_TRY(combine(z, c->phir, c->Vr, c->drho, nullptr, z, c->nv, 1, nr, 4.0, 1, c->st));
+  if (c->alpha != 0.0)
+    BSE_TRY(axpby(1.0, reinterpret_cast<const double*>(ex), 1.0, reinterpret_cast<double*>(z),
+                  2 * gs, c->st));
+  BSE_TRY(from_grid(c, z, c->nv, 1, Zp, c->eps_d, 0.0, out));
+  return proj_c(c, out, out, 1);
+}
+
+// ---------------------------------------------------------------------------
 // U vector:  u_v = P_c[ s (v_c*Drho) a_v - sum_v' W(a_v' a_v) phi_v' ] - sum_v' S_vv' a_v'
 // ---------------------------------------------------------------------------
 int u_vector(bse_ctx* c, const double* Xs, double* U) {
   const long npw = c->basis.npw, nv = c->nv, L = nv * npw, nr = c->basis.nr;
-  BSE_TRY(ensure_apply_work(c, 2));
+  BSE_TRY(ensure_apply_work(c, c->ks ? 4 : 2));
   DVec S(c), G(c);
   BSE_TRY(S.alloc((size_t)nv * nv));
   BSE_TRY(G.alloc((size_t)L));
@@ -590,6 +796,7 @@ int u_vector(bse_ctx* c, const double* Xs, double* U) {
   BSE_TRY(from_grid(c, g1, c->nv, 1, nullptr, nullptr, 0.0, G.p));
   BSE_TRY(proj_c(c, G.p, U, 1));
   BSE_TRY(dgemm(0, 0, nv, npw, nv, -1.0, S.p, nv, A, npw, 1.0, U, npw, c->st));
+  if (c->ks) BSE_TRY(ks_u_dpart(c, A, U));
   BSE_HIP(hipStreamSynchronize(c->st));
   return BSE_OK;
 }
@@ -693,8 +900,16 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
   const double nb_ = std::sqrt(std::accumulate(d.begin(), d.end(), 0.0));
   auto applyD = [&](const double* in, double* o_) -> int {
     BSE_TRY(proj_c(c, in, Zr.p, 1));
+    if (c->ks) return ks_zop(c, Zr.p, o_);
     if (fp32) return apply_H_f(c, (int)nv, 1, Zr.p, o_, 0.0, c->eps_d, 1);
     return apply_H(c, (int)nv, 1, Zr.p, o_, c->agrid, 0.0, c->eps_d, 1);
+  };
+  // with the KS kernels the bands couple: one step length for the block
+  const bool block_steps = c->ks != 0;
+  auto pool = [&](std::vector<double>& x) {
+    if (!block_steps) return;
+    const double t = std::accumulate(x.begin(), x.end(), 0.0);
+    std::fill(x.begin(), x.end(), t);
   };
   std::vector<double> rz, pap, rzn, rr;
   // P = P_c Prec(R), rz = <R, P> per band
@@ -710,7 +925,9 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
   auto restart = [&]() -> int {
     BSE_TRY(prec(R.p, Zr.p));
     BSE_TRY(proj_c(c, Zr.p, P.p, 1));
-    return dots_host(c, R.p, P.p, nv, npw, sv.p, rz);
+    BSE_TRY(dots_host(c, R.p, P.p, nv, npw, sv.p, rz));
+    pool(rz);
+    return BSE_OK;
   };
   BSE_TRY(proj_c(c, Z, Z, 1));
   BSE_TRY(applyD(Z, AP.p));
@@ -752,6 +969,7 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
     prev = rel;
     BSE_TRY(applyD(P.p, AP.p));
     BSE_TRY(dots_host(c, P.p, AP.p, nv, npw, sv.p, pap));
+    pool(pap);
     std::vector<double> al(nv), nal(nv);
     for (long v = 0; v < nv; ++v) {
       al[v] = pap[v] != 0.0 ? rz[v] / pap[v] : 0.0;
@@ -764,6 +982,7 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
     BSE_TRY(prec(R.p, AP.p));
     BSE_TRY(proj_c(c, AP.p, Zr.p, 1));
     BSE_TRY(dots_host(c, R.p, Zr.p, nv, npw, sv.p, rzn));
+    pool(rzn);
     std::vector<double> be(nv);
     for (long v = 0; v < nv; ++v) be[v] = rz[v] != 0.0 ? rzn[v] / rz[v] : 0.0;
     BSE_TRY(to_dev(c, be, sv.p + 3 * nv, nv));
@@ -795,7 +1014,7 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
   const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
   const int maxit = (o && o->max_iter > 0) ? o->max_iter : 5000;
   const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
-  BSE_TRY(ensure_apply_work(c, 2));
+  BSE_TRY(ensure_apply_work(c, c->ks ? 4 : 2));
   DVec U(c), R(c), D(c), sv(c), vs(c);
   BSE_TRY(U.alloc(L));
   BSE_TRY(sv.alloc(16 + 2 * (size_t)nv));
@@ -838,7 +1057,7 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
   int iters = 0, rc = BSE_OK, applies64 = 0;
   double rel = 0.0;
   PcgOut po;
-  if (c->active != BSE_MIXED || band_iters) {
+  if (c->active != BSE_MIXED || band_iters || c->ks) {
     rc = pcg(c, U.p, Z, tol, maxit, false, vshift, band_iters, &po, two_level);
     iters = po.iters;
     rel = po.rel;
@@ -975,7 +1194,7 @@ int ground_state_forces(bse_ctx* c, double* dEdR_host) {
 // subspace iteration (the scaled three-term filter of Zhou, Saad, Tiago and
 // Chelikowsky, J. Comput. Phys. 219, 172 (2006)) with Rayleigh-Ritz.
 // ---------------------------------------------------------------------------
-int ground_state(bse_ctx* c, int n_want, double tol) {
+int ground_state(bse_ctx* c, int n_want, double tol, bool warm) {
   PhaseScope ps(c, PH_GS);
   const long npw = c->basis.npw;
   int ns = n_want + std::max(8, n_want / 10);
@@ -1000,6 +1219,10 @@ int ground_state(bse_ctx* c, int n_want, double tol) {
   // random start (fixed seed, drawn on the device), smooth: divided by
   // (1 + |G|^2/2)
   BSE_TRY(random_smooth(X.p, nsl, npw, c->T, 12345ULL, c->st));
+  // a warm start keeps the previous solution's states (self-consistent
+  // cycles), the rest of the block stays random
+  if (warm && c->Phi && c->norb > 0)
+    BSE_TRY(copy_dev(c, c->Phi, X.p, (size_t)std::min(c->norb, ns) * npw));
   auto Happly = [&](const double* in, double* out, double shift) -> int {
     return apply_H(c, ns, 1, in, out, grids, shift, nullptr, 0);
   };
@@ -1073,9 +1296,17 @@ int ground_state(bse_ctx* c, int n_want, double tol) {
   }
   c->gs_resid = resid;
   if (resid > tol) return fail(BSE_ENOCONV, "ground state: residual %.3e above %.3e", resid, tol);
+  if (c->Phi && c->norb != n_want) {
+    ctx_release(c, c->Phi);
+    ctx_release(c, c->eps_d);
+    c->Phi = nullptr;
+    c->eps_d = nullptr;
+  }
   c->norb = n_want;
-  BSE_TRY(ctx_alloc_t(c, &c->Phi, (size_t)n_want * npw));
-  BSE_TRY(ctx_alloc_t(c, &c->eps_d, (size_t)n_want));
+  if (!c->Phi) {
+    BSE_TRY(ctx_alloc_t(c, &c->Phi, (size_t)n_want * npw));
+    BSE_TRY(ctx_alloc_t(c, &c->eps_d, (size_t)n_want));
+  }
   BSE_TRY(copy_dev(c, X.p, c->Phi, (size_t)n_want * npw));
   c->eps_h.assign(theta.begin(), theta.begin() + n_want);
   BSE_TRY(to_dev(c, c->eps_h.data(), c->eps_d, n_want));
