@@ -176,6 +176,14 @@ class System:
             z -= np.einsum("uvxyz,uxyz->vxyz", tau, ar)
         return z
 
+    def sigma_grid(self, ar):
+        """sigma_v = sum_v' W(a_v' a_v) phi_v' on the grid (the W term of U)."""
+        g = np.zeros_like(ar)
+        for v in range(self.n_val):
+            sig = self.apply_W(ar * ar[v])               # [v'][grid]
+            g[v] = (sig * self.phir).sum(0)
+        return g
+
     def apply(self, X):
         """Y = P_c M P_c X for X[n_b][N_v][N_pw] (or one [N_v][N_pw])."""
         X = np.asarray(X, dtype=np.float64)

@@ -147,11 +147,7 @@ def u_vector(sys: System, A):
         drho = (sys.phir * ar).sum(0)
         g += sys.spin * sys.poisson(drho) * ar
     if sys.kmask & (K_1D_BARE | K_1D_PDEP):
-        nv = sys.n_val
-        for v in range(nv):
-            # sum_v' W(a_v' a_v) phi_v'
-            sig = sys.apply_W(ar * ar[v])               # [v'][grid]
-            g[v] -= (sig * sys.phir).sum(0)
+        g -= sys.sigma_grid(ar)
     Ktil = b.from_grid(sys.kernel_grid(ar))            # kernel part before P_c
     S = sys.phi @ Ktil.T                               # S[w][v] = <phi_w|K~_v>
     u = sys.proj_c(b.from_grid(g)) - S @ A
