@@ -67,6 +67,7 @@ struct FftPlan {
   size_t max_lds = 65536;
   bool ct_plane[2] = {false, false}, ct_axis[2] = {false, false};  // [FP64, FP32], in use
   bool ct_plane_ok[2] = {false, false}, ct_axis_ok[2] = {false, false};  // available
+  bool prune[2] = {false, false};  // pruned sphere-plane kernels [FP64, FP32]
   FftAxis ax[3];
 };
 int fft_plan_init(FftPlan* p, const int grid[3]);
@@ -82,6 +83,7 @@ int fft3d(const FftPlan& p, float2* data, long batch, int dir, hipStream_t st);
 // of every half-sphere vector, and G = 0) grouped by plane i1.
 struct SpherePlan {
   int nplanes = 0, nent = 0, e_zero = 0, nmax1 = 0;
+  int m2 = 0, m3 = 0;  // largest |n2|, |n3| of the sphere's modes
   int *plane_i1 = nullptr, *plane_off = nullptr, *ent_pos = nullptr, *ent_code = nullptr;
   int *e_plus = nullptr, *e_minus = nullptr;  // entry index of +G_k / -G_k
 };

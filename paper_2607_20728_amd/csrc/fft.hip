@@ -124,6 +124,7 @@ int sphere_plan_build(const FftPlan& p, const Basis& b, SpherePlan* sp) {
   std::vector<int> planes, off, pos(ents.size()), code(ents.size());
   std::vector<int> eplus(b.nhalf), eminus(b.nhalf);
   int ezero = 0, nmax1 = 0;
+  sp->m2 = sp->m3 = 0;
   for (size_t e = 0; e < ents.size(); ++e) {
     if (planes.empty() || planes.back() != ents[e].i1) {
       planes.push_back(ents[e].i1);
@@ -133,6 +134,9 @@ int sphere_plan_build(const FftPlan& p, const Basis& b, SpherePlan* sp) {
     }
     pos[e] = ents[e].pos;
     code[e] = ents[e].code;
+    const int i2 = ents[e].pos / N3, i3 = ents[e].pos % N3;
+    sp->m2 = std::max(sp->m2, std::abs(i2 < (N2 + 1) / 2 ? i2 : i2 - N2));
+    sp->m3 = std::max(sp->m3, std::abs(i3 < (N3 + 1) / 2 ? i3 : i3 - N3));
     if (ents[e].code == 0) ezero = (int)e;
     else if (ents[e].code > 0) eplus[ents[e].code - 1] = (int)e;
     else eminus[-ents[e].code - 1] = (int)e;

@@ -189,6 +189,7 @@ struct PlaneArgs {
   double s0, s1;          // 1/sqrt(Omega), 1/sqrt(2 Omega)
   cplx* compact;       // [grid][nent]
   int LB;                 // lines per scratch batch
+  int m2, m3;             // the sphere's modes have |n2| <= m2 and |n3| <= m3
 };
 
 template <int DIR, int IN, int OUT>
@@ -409,6 +410,244 @@ __global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_ct(cplx* data, Plan
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pruned sphere-plane transforms (compile-time lengths).  The sphere's modes
+// occupy rows |n2| <= m2 and columns |n3| <= m3 of a plane, so
+//  inverse (sphere -> plane): row transforms only on the 2 m2 + 1 rows that
+//    hold modes, kept in a compact block Q; then every column is transformed
+//    reading Q (zeros elsewhere) and its last pass writes the plane straight
+//    to memory, LB adjacent columns per batch (coalesced rows of LB values);
+//  forward (plane -> sphere): rows staged from memory in batches by
+//    coalesced copies and transformed, keeping only the 2 m3 + 1 columns that
+//    hold modes in Q; then those columns are transformed in place and the
+//    plane's modes gathered from Q.
+// Q holds (2 m2 + 1) x N3 or N2 x (2 m3 + 1) values instead of the whole
+// plane, so at 72 x 72 in FP64 two workgroups share a CU.
+// ---------------------------------------------------------------------------
+// one Stockham pass with functor access: element k of line l is read by
+// ld(k, l) and written by st(k, l, value)
+template <int R, int DIR, int N, int NS, int L, int NT, class LD, class ST>
+__device__ __forceinline__ void spass_fn(LD ld, ST st, int nl, const cplx* __restrict__ tw) {
+  constexpr int NQ = N / R;
+  constexpr int TS = N / (NS * R);
+#pragma unroll 2
+  for (int u = threadIdx.x; u < NQ * L; u += NT) {
+    const int l = u % L;
+    if (l >= nl) continue;
+    const int j = u / L;
+    const int k = j % NS;
+    cplx v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cplx x = ld(j + r * NQ, l);
+      if (r > 0 && NS > 1) {
+        cplx w = tw[k * r * TS];
+        if (DIR > 0) w.y = -w.y;
+        x = cmul(x, w);
+      }
+      v[r] = x;
+    }
+    if (R == 2) dft2<DIR>(v);
+    if (R == 3) dft3<DIR>(v);
+    if (R == 4) dft4<DIR>(v);
+    if (R == 5) dft5<DIR>(v);
+    if (R == 8) dft8<DIR>(v);
+    if (R == 9) dft9<DIR>(v);
+    const int base = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) st(base + r * NS, l, v[r]);
+  }
+}
+
+// passes P.. of a length-N transform of L lines: the first reads through ld,
+// intermediate results ping-pong between S0 and S1 ([k][l] layout), the last
+// writes through st
+template <int N, int DIR, int L, int NT, int P, int NS, class LD, class ST>
+__device__ __forceinline__ void fn_passes(LD ld, ST st, cplx* S0, cplx* S1, int nl,
+                                          const cplx* tw) {
+  constexpr Fac F = factor(N);
+  if constexpr (P < F.n) {
+    constexpr int R = F.r[P];
+    if constexpr (P == F.n - 1) {
+      spass_fn<R, DIR, N, NS, L, NT>(ld, st, nl, tw);
+      __syncthreads();
+    } else {
+      cplx* out = (P % 2 == 0) ? S0 : S1;
+      spass_fn<R, DIR, N, NS, L, NT>(
+          ld, [out](int k, int l, cplx v) { out[k * L + l] = v; }, nl, tw);
+      __syncthreads();
+      fn_passes<N, DIR, L, NT, P + 1, NS * R>(
+          [out](int k, int l) { return out[k * L + l]; }, st, S0, S1, nl, tw);
+    }
+  }
+}
+
+__device__ __forceinline__ int min_img(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+
+// lines per batch of the pruned kernels: two candidates per precision (the
+// launch takes the one that pads the line batches least within the LDS)
+constexpr int kSphereLB[2] = {sizeof(cplx) == 16 ? 16 : 32, sizeof(cplx) == 16 ? 18 : 36};
+
+// LDS of the pruned kernels for sphere extents m2, m3 and batch LB
+template <int N2, int N3>
+size_t sphere_inv_lds(int m2, int lb) {
+  constexpr int nm = N2 > N3 ? N2 : N3;
+  return sizeof(cplx) * ((size_t)(2 * m2 + 1) * N3 + (size_t)plane_nscratch<N2, N3>() * nm * lb);
+}
+template <int N2, int N3>
+size_t sphere_fwd_whole_lds(int lb) {
+  constexpr int nm = N2 > N3 ? N2 : N3;
+  return sizeof(cplx) * ((size_t)N2 * N3 + (size_t)plane_nscratch<N2, N3>() * nm * lb);
+}
+template <int N2, int N3>
+size_t sphere_fwd_lds(int m3, int lb) {
+  constexpr int nm = N2 > N3 ? N2 : N3;
+  return sizeof(cplx) * ((size_t)N2 * (2 * m3 + 1) + (size_t)plane_nscratch<N2, N3>() * nm * lb +
+                         (size_t)lb * N3);
+}
+
+template <int N2, int N3, int DIR, int LB>
+__global__ __launch_bounds__(kPlaneThreads) void k_sphere_inv_ct(cplx* data, PlaneArgs pa,
+                                                                  AxisArgs ay, AxisArgs az) {
+  constexpr int NM = N2 > N3 ? N2 : N3;
+  constexpr int NT = kPlaneThreads;
+  static_assert(factor(N2).n >= 2 && factor(N3).n >= 2, "plane lengths need two passes");
+  extern __shared__ cplx lds[];
+  const int m2 = pa.m2, K2 = 2 * pa.m2 + 1;
+  cplx* Q = lds;                       // [K2][N3]
+  cplx* S0 = Q + K2 * N3;
+  cplx* S1 = plane_nscratch<N2, N3>() == 2 ? S0 + NM * LB : S0;
+  const long g = blockIdx.x / pa.nplanes;
+  const int pl = (int)(blockIdx.x % pa.nplanes);
+  const int i1 = pa.plane_i1[pl];
+  cplx* gp = data + g * pa.nr + (long)i1 * (N2 * N3);
+  for (int e = threadIdx.x; e < K2 * N3; e += NT) Q[e] = mk(0.0, 0.0);
+  __syncthreads();
+  {
+    const long set = g / pa.nvh;
+    const int p = (int)(g % pa.nvh);
+    const double* x1 = pa.X + (set * pa.nv + 2 * p) * (long)pa.npw;
+    const double* x2 = (2 * p + 1 < pa.nv) ? x1 + pa.npw : nullptr;
+    for (int e = pa.plane_off[pl] + threadIdx.x; e < pa.plane_off[pl + 1]; e += NT) {
+      const int code = pa.ent_code[e];
+      cplx h;
+      if (code == 0) {
+        h = mk(x1[0] * pa.s0, x2 ? x2[0] * pa.s0 : 0.0);
+      } else {
+        const int k = abs(code) - 1;
+        const double c1 = x1[1 + 2 * k], q1 = x1[2 + 2 * k];
+        const double c2 = x2 ? x2[1 + 2 * k] : 0.0, q2 = x2 ? x2[2 + 2 * k] : 0.0;
+        h = code > 0 ? mk((c1 + q2) * pa.s1, (c2 - q1) * pa.s1)
+                     : mk((c1 - q2) * pa.s1, (q1 + c2) * pa.s1);
+      }
+      const int pos = pa.ent_pos[e];
+      const int q = min_img(pos / N3, N2) + m2;
+      Q[q * N3 + pos % N3] = h;
+    }
+  }
+  __syncthreads();
+  // rows holding modes (axis 3), in place in Q
+#pragma unroll 1
+  for (int l0 = 0; l0 < K2; l0 += LB)
+    ct_passes<N3, DIR, LB, NT, 0, 1, 1, N3, 1, N3>(Q + l0 * N3, S0, S1, Q + l0 * N3,
+                                                  min(LB, K2 - l0), az.tw);
+  // every column (axis 2) from Q, zeros outside its rows; the last pass
+  // writes the plane
+#pragma unroll 1
+  for (int l0 = 0; l0 < N3; l0 += LB) {
+    auto ld = [=](int k, int l) -> cplx {
+      const int q = min_img(k, N2) + m2;
+      return (q >= 0 && q < K2) ? Q[q * N3 + l0 + l] : mk(0.0, 0.0);
+    };
+    auto st = [=](int k, int l, cplx v) { gp[k * N3 + l0 + l] = v; };
+    fn_passes<N2, DIR, LB, NT, 0, 1>(ld, st, S0, S1, min(LB, N3 - l0), ay.tw);
+  }
+}
+
+template <int N2, int N3, int DIR, int LB>
+__global__ __launch_bounds__(kPlaneThreads) void k_sphere_fwd_ct(cplx* data, PlaneArgs pa,
+                                                                  AxisArgs ay, AxisArgs az) {
+  constexpr int NM = N2 > N3 ? N2 : N3;
+  constexpr int NT = kPlaneThreads;
+  static_assert(factor(N2).n >= 2 && factor(N3).n >= 2, "plane lengths need two passes");
+  extern __shared__ cplx lds[];
+  const int m3 = pa.m3, K3 = 2 * pa.m3 + 1;
+  cplx* Q = lds;                       // [N2][K3]
+  cplx* S0 = Q + N2 * K3;
+  cplx* S1 = plane_nscratch<N2, N3>() == 2 ? S0 + NM * LB : S0;
+  cplx* R0 = S0 + plane_nscratch<N2, N3>() * NM * LB;  // staged rows [LB][N3]
+  const long g = blockIdx.x / pa.nplanes;
+  const int pl = (int)(blockIdx.x % pa.nplanes);
+  const int i1 = pa.plane_i1[pl];
+  const cplx* gp = data + g * pa.nr + (long)i1 * (N2 * N3);
+  // rows (axis 3): staged by coalesced copies, only the columns holding
+  // modes kept
+#pragma unroll 1
+  for (int l0 = 0; l0 < N2; l0 += LB) {
+    const int nl = min(LB, N2 - l0);
+    for (int e = threadIdx.x; e < nl * N3; e += NT) R0[e] = gp[l0 * N3 + e];
+    __syncthreads();
+    auto ld = [=](int k, int l) { return R0[l * N3 + k]; };
+    auto st = [=](int k, int l, cplx v) {
+      const int q = min_img(k, N3) + m3;
+      if (q >= 0 && q < K3) Q[(l0 + l) * K3 + q] = v;
+    };
+    fn_passes<N3, DIR, LB, NT, 0, 1>(ld, st, S0, S1, nl, az.tw);
+  }
+  // the kept columns (axis 2), in place in Q
+#pragma unroll 1
+  for (int l0 = 0; l0 < K3; l0 += LB) {
+    auto ld = [=](int k, int l) { return Q[k * K3 + l0 + l]; };
+    auto st = [=](int k, int l, cplx v) { Q[k * K3 + l0 + l] = v; };
+    fn_passes<N2, DIR, LB, NT, 0, 1>(ld, st, S0, S1, min(LB, K3 - l0), ay.tw);
+  }
+  cplx* cg = pa.compact + g * (long)pa.nent;
+  for (int e = pa.plane_off[pl] + threadIdx.x; e < pa.plane_off[pl + 1]; e += NT) {
+    const int pos = pa.ent_pos[e];
+    cg[e] = Q[(pos / N3) * K3 + min_img(pos % N3, N3) + m3];
+  }
+}
+
+// The forward pass with the whole plane in LDS (one coalesced load of all
+// rows, row transforms in place), then only the 2 m3 + 1 columns that hold
+// modes transformed in place: for planes whose LDS fits two workgroups per
+// CU this beats staging rows in batches.
+template <int N2, int N3, int DIR, int LB>
+__global__ __launch_bounds__(kPlaneThreads) void k_sphere_fwd_whole(cplx* data, PlaneArgs pa,
+                                                                     AxisArgs ay, AxisArgs az) {
+  constexpr int NP2 = N2 * N3;
+  constexpr int NM = N2 > N3 ? N2 : N3;
+  constexpr int NT = kPlaneThreads;
+  static_assert(factor(N2).n >= 2 && factor(N3).n >= 2, "plane lengths need two passes");
+  extern __shared__ cplx lds[];
+  const int m3 = pa.m3, K3 = 2 * pa.m3 + 1;
+  cplx* P = lds;
+  cplx* S0 = P + NP2;
+  cplx* S1 = plane_nscratch<N2, N3>() == 2 ? S0 + NM * LB : S0;
+  const long g = blockIdx.x / pa.nplanes;
+  const int pl = (int)(blockIdx.x % pa.nplanes);
+  const int i1 = pa.plane_i1[pl];
+  const cplx* gp = data + g * pa.nr + (long)i1 * NP2;
+#pragma unroll 4
+  for (int e = threadIdx.x; e < NP2; e += NT) P[e] = gp[e];
+  __syncthreads();
+#pragma unroll 1
+  for (int l0 = 0; l0 < N2; l0 += LB)
+    ct_passes<N3, DIR, LB, NT, 0, 1, 1, N3, 1, N3>(P + l0 * N3, S0, S1, P + l0 * N3,
+                                                  min(LB, N2 - l0), az.tw);
+  // column l of the kept set is n3 = l - m3, stored at index (l - m3) mod N3
+#pragma unroll 1
+  for (int l0 = 0; l0 < K3; l0 += LB) {
+    auto col = [=](int l) { const int n = l0 + l - m3; return n < 0 ? n + N3 : n; };
+    auto ld = [=](int k, int l) { return P[k * N3 + col(l)]; };
+    auto st = [=](int k, int l, cplx v) { P[k * N3 + col(l)] = v; };
+    fn_passes<N2, DIR, LB, NT, 0, 1>(ld, st, S0, S1, min(LB, K3 - l0), ay.tw);
+  }
+  cplx* cg = pa.compact + g * (long)pa.nent;
+  for (int e = pa.plane_off[pl] + threadIdx.x; e < pa.plane_off[pl + 1]; e += NT)
+    cg[e] = P[pa.ent_pos[e]];
+}
+
 template <int N>
 constexpr int axis_l() {
   int L = 32;
@@ -577,6 +816,90 @@ int set_ct_lds_limits(int n2, int n3, int n1) {
   return BSE_OK;
 }
 
+// padded lines of the pruned kernel's batches: inverse K2 rows and N3
+// columns, forward N2 rows and K3 columns
+inline long sphere_padded(int nrow, int ncol, int lb) {
+  return (long)((nrow + lb - 1) / lb + (ncol + lb - 1) / lb) * lb;
+}
+
+// pruned sphere-plane launches: false when the size has no compiled kernel
+// or the LDS the extents need exceeds the device's
+bool launch_sphere_ct(int n2, int n3, bool inverse, int m, size_t max_lds, dim3 grid,
+                      hipStream_t st, cplx* data, PlaneArgs pa, AxisArgs ay, AxisArgs az) {
+  // candidates: batch size k in {0, 1}, and for the forward pass the staged
+  // (w = 0) or whole-plane (w = 1) kernel; the score is the padded line
+  // count, doubled when two workgroups do not fit a CU; ties go to the
+  // whole-plane kernel
+#define C(A, B)                                                                               \
+  if (n2 == A && n3 == B) {                                                                   \
+    int pick = -1, pw = 0;                                                                    \
+    long best = 0;                                                                            \
+    size_t shm = 0;                                                                           \
+    for (int w = inverse ? 0 : 1; w >= 0; --w)                                                \
+      for (int k = 0; k < 2; ++k) {                                                           \
+        const int lb = kSphereLB[k];                                                          \
+        const size_t need = inverse ? sphere_inv_lds<A, B>(m, lb)                             \
+                            : w ? sphere_fwd_whole_lds<A, B>(lb) : sphere_fwd_lds<A, B>(m, lb); \
+        if (need > max_lds) continue;                                                         \
+        const long pad = inverse ? sphere_padded(2 * m + 1, B, lb) : sphere_padded(A, 2 * m + 1, lb); \
+        const long score = pad * (need <= 81920 ? 1 : 2);                                     \
+        if (pick < 0 || score < best) {                                                       \
+          pick = k;                                                                           \
+          pw = w;                                                                             \
+          best = score;                                                                       \
+          shm = need;                                                                         \
+        }                                                                                     \
+      }                                                                                       \
+    if (pick < 0) return false;                                                               \
+    if (inverse) {                                                                            \
+      if (pick == 0)                                                                          \
+        hipLaunchKernelGGL((k_sphere_inv_ct<A, B, 1, kSphereLB[0]>), grid, dim3(kPlaneThreads), \
+                           shm, st, data, pa, ay, az);                                        \
+      else                                                                                    \
+        hipLaunchKernelGGL((k_sphere_inv_ct<A, B, 1, kSphereLB[1]>), grid, dim3(kPlaneThreads), \
+                           shm, st, data, pa, ay, az);                                        \
+    } else if (pw) {                                                                          \
+      if (pick == 0)                                                                          \
+        hipLaunchKernelGGL((k_sphere_fwd_whole<A, B, -1, kSphereLB[0]>), grid,                \
+                           dim3(kPlaneThreads), shm, st, data, pa, ay, az);                   \
+      else                                                                                    \
+        hipLaunchKernelGGL((k_sphere_fwd_whole<A, B, -1, kSphereLB[1]>), grid,                \
+                           dim3(kPlaneThreads), shm, st, data, pa, ay, az);                   \
+    } else {                                                                                  \
+      if (pick == 0)                                                                          \
+        hipLaunchKernelGGL((k_sphere_fwd_ct<A, B, -1, kSphereLB[0]>), grid,                   \
+                           dim3(kPlaneThreads), shm, st, data, pa, ay, az);                   \
+      else                                                                                    \
+        hipLaunchKernelGGL((k_sphere_fwd_ct<A, B, -1, kSphereLB[1]>), grid,                   \
+                           dim3(kPlaneThreads), shm, st, data, pa, ay, az);                   \
+    }                                                                                         \
+    return true;                                                                              \
+  }
+  BSEX_PLANE_SIZES(C)
+#undef C
+  return false;
+}
+
+// the pruned kernels may use up to the device's LDS (extents are known only
+// with a sphere)
+int set_sphere_lds_limits(int n2, int n3, size_t max_lds) {
+#define C(A, B)                                                                               \
+  if (n2 == A && n3 == B) {                                                                   \
+    const int lim = (int)max_lds;                                                             \
+    const void* fns[] = {(const void*)k_sphere_inv_ct<A, B, 1, kSphereLB[0]>,                 \
+                         (const void*)k_sphere_inv_ct<A, B, 1, kSphereLB[1]>,                 \
+                         (const void*)k_sphere_fwd_ct<A, B, -1, kSphereLB[0]>,                \
+                         (const void*)k_sphere_fwd_ct<A, B, -1, kSphereLB[1]>,                \
+                         (const void*)k_sphere_fwd_whole<A, B, -1, kSphereLB[0]>,             \
+                         (const void*)k_sphere_fwd_whole<A, B, -1, kSphereLB[1]>};            \
+    for (const void* f : fns)                                                                 \
+      BSE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim));       \
+  }
+  BSEX_PLANE_SIZES(C)
+#undef C
+  return BSE_OK;
+}
+
 }  // namespace
 
 size_t fft_plane_lds(const FftPlan& p, int* LB) {
@@ -651,6 +974,23 @@ static int launch_plane(const FftPlan& p, cplx* data, long batch, PlaneArgs pa, 
   return BSE_OK;
 }
 
+// the sphere-plane passes through the pruned kernels, when they apply
+static bool launch_sphere(const FftPlan& p, const SpherePlan& sp, bool inverse, cplx* data,
+                          long batch, PlaneArgs pa, hipStream_t st) {
+  if (!p.prune[BSEX_FFT_PREC]) return false;
+  const long groups = batch * pa.nplanes;
+  if (groups <= 0 || groups > 0x7fffffffL) return false;
+  pa.N1 = p.N[0];
+  pa.N2 = p.N[1];
+  pa.N3 = p.N[2];
+  pa.nr = p.nr;
+  pa.m2 = sp.m2;
+  pa.m3 = sp.m3;
+  return launch_sphere_ct(p.N[1], p.N[2], inverse, inverse ? sp.m2 : sp.m3, p.max_lds,
+                          dim3((unsigned)groups), st, data, pa, axis_args(p.ax[1]),
+                          axis_args(p.ax[2]));
+}
+
 int init_kernels(FftPlan* p) {
   int lb = 0;
   const size_t need = fft_plane_lds(*p, &lb);
@@ -667,6 +1007,10 @@ int init_kernels(FftPlan* p) {
   }
   p->ct_plane[BSEX_FFT_PREC] = p->ct_plane_ok[BSEX_FFT_PREC] = ctp;
   p->ct_axis[BSEX_FFT_PREC] = p->ct_axis_ok[BSEX_FFT_PREC] = cta;
+  bool prune = plane_ct_supported(p->N[1], p->N[2]);
+  if (const char* e = getenv("BSEX_FFT_PRUNE")) prune = prune && atoi(e) != 0;
+  p->prune[BSEX_FFT_PREC] = prune;
+  if (prune) BSE_TRY(set_sphere_lds_limits(p->N[1], p->N[2], p->max_lds));
   return set_ct_lds_limits(ctp ? p->N[1] : -1, ctp ? p->N[2] : -1, cta ? p->N[0] : -1);
 }
 
@@ -703,7 +1047,9 @@ int sphere_to_grid(const FftPlan& p, const SpherePlan& sp, double omega, const d
   pa.npw = sp.nent;
   pa.s0 = 1.0 / std::sqrt(omega);
   pa.s1 = 1.0 / std::sqrt(2.0 * omega);
-  BSE_TRY((launch_plane<1, 1, 0>(p, grid, batch, pa, st)));
+  if (!launch_sphere(p, sp, true, grid, batch, pa, st))
+    BSE_TRY((launch_plane<1, 1, 0>(p, grid, batch, pa, st)));
+  BSE_HIP(hipGetLastError());
   return x_pass(p, grid, batch, +1, sp.nmax1, p.N[0], st);
 }
 
@@ -719,6 +1065,10 @@ int grid_to_compact(const FftPlan& p, const SpherePlan& sp, cplx* grid, long bat
   pa.ent_code = sp.ent_code;
   pa.nent = sp.nent;
   pa.compact = compact;
+  if (launch_sphere(p, sp, false, grid, batch, pa, st)) {
+    BSE_HIP(hipGetLastError());
+    return BSE_OK;
+  }
   return launch_plane<-1, 0, 1>(p, grid, batch, pa, st);
 }
 

@@ -8,6 +8,14 @@
         the kernels of the last apply in a bench trace (those launched after
         the next-to-last k_tau_stream, up to the last one), in launch order;
 
+    python -m paper_2607_20728_amd.profsummary stages <results.db> --grid N1 N2 N3
+            --planes N1S --npw NPW --nv NV --nb NB --prec f64|f32 --stream-bytes B
+        every stage of the applies in a bench trace against its own roof: the
+        mean duration over the applies (segments between consecutive
+        k_tau_stream launches) and the algorithmic bytes of the stage (N1S =
+        planes along axis 1 that hold sphere modes; B = the stream's bytes
+        per launch as bench.py reports them);
+
     python -m paper_2607_20728_amd.profsummary counters <dir> [match]
         mean value per dispatch of every counter of a --pmc run
         (--output-format csv), per kernel whose name contains match;
@@ -62,6 +70,89 @@ def last_apply(db):
     for n, gx, du in rows[idx[-2] + 1:idx[-1] + 1]:
         m = re.search(r'(k_[a-z_0-9]+(<[^>]*>)?|__amd_rocclr_\w+)', n)
         print(f"{(m.group(1) if m else n[:40]):48s} {gx:10d} {du / 1e3:9.1f}")
+
+
+_SHORT = re.compile(r'(k_[a-z_0-9]+(<[^>]*>)?|__amd_rocclr_\w+)')
+HBM_PEAK = 8.0e12
+FP64_MFMA_PEAK = 78.6e12
+
+
+def _short(n):
+    m = _SHORT.search(n)
+    return m.group(1) if m else n[:40]
+
+
+def stages(a):
+    """Per-stage rooflines of the applies in a bench trace."""
+    con = sqlite3.connect(a.db)
+    rows = [(_short(n), gx, du) for n, gx, du in
+            con.execute("select name, grid_x, duration from kernels order by start").fetchall()]
+    idx = [i for i, r in enumerate(rows) if r[0].startswith("k_tau_stream")]
+    if len(idx) < 2:
+        sys.exit("fewer than two k_tau_stream launches in the trace")
+    N1, N2, N3 = a.grid
+    nr, p2 = N1 * N2 * N3, N2 * N3
+    c = 16 if a.prec == "f64" else 8
+    G = a.nb * ((a.nv + 1) // 2)
+    xb = a.nb * a.nv * a.npw * 8
+    model = [
+        ("inverse plane pass, sphere -> planes", r"k_sphere_inv_ct|k_fft_plane_ct<\d+, \d+, 1, 1, 0>",
+         xb + G * a.planes * p2 * c),
+        ("inverse axis-1 pass", r"k_fft_axis_ct<\d+, 1>", G * nr * c * (a.planes / N1 + 1)),
+        ("transition density (K1e)", r"k_transition_density",
+         (G + (a.nv + 1) // 2 + (a.nb + 1) // 2) * nr * c),
+        ("tau stream + combine", r"k_tau_stream", a.stream_bytes),
+        ("forward axis-1 pass", r"k_fft_axis_ct<\d+, -1>", G * nr * c * (1 + a.planes / N1)),
+        ("forward plane pass, planes -> sphere", r"k_sphere_fwd_ct|k_sphere_fwd_whole|k_fft_plane_ct<\d+, \d+, -1, 0, 1>",
+         G * a.planes * p2 * c + G * a.npw * c),
+        ("gather + diagonal", r"k_gather", G * a.npw * c + 2 * xb),
+    ]
+    gemm = [("S = Phi^T X", "k_dgemm<0, 1,"), ("Y = X - Phi S", "k_dgemm<1, 0,")]
+    segs = [rows[idx[k - 1] + 1:idx[k] + 1] for k in range(1, len(idx))]
+
+    def pick(seg, pat):
+        # the stage's launch: the largest grid among the matching launches
+        # (the K1e Poisson transforms reuse the FFT kernels on a few grids)
+        m = [r for r in seg if re.match(pat, r[0])]
+        if not m:
+            return None, []
+        big = max(r[1] for r in m)
+        return m[0][0], [r[2] for r in m if r[1] == big]
+
+    print(f"{len(segs)} applies; {a.prec}, N_b = {a.nb}, N_v = {a.nv}, grid {N1}x{N2}x{N3}, "
+          f"{a.planes} planes hold sphere modes\n")
+    print("| stage (kernel) | algorithmic bytes | ms | achieved | of 8 TB/s |")
+    print("|---|---|---|---|---|")
+    for label, pat, byt in model:
+        ds, name = [], None
+        for seg in segs:
+            n, d = pick(seg, pat)
+            if n:
+                name = n
+                ds.extend(d)
+        if not ds:
+            continue
+        t = statistics.mean(ds) / 1e9
+        print(f"| {label} (`{name}`) | {byt / 1e9:.2f} GB | {t * 1e3:.2f} | "
+              f"{byt / t / 1e12:.2f} TB/s | {byt / t / HBM_PEAK:.2f} |")
+    flops = 2.0 * a.nv * a.nb * a.nv * a.npw
+    print("\n| GEMM (2 of each per apply) | flops | ms | achieved | of 78.6 TFLOP/s FP64 MFMA |")
+    print("|---|---|---|---|---|")
+    for label, prefix in gemm:
+        ds, name = [], None
+        for seg in segs:
+            m = [r for r in seg if r[0].startswith(prefix)]
+            if m:
+                big = max(r[1] for r in m)
+                name = m[0][0]
+                ds.extend(r[2] for r in m if r[1] == big)
+        if not ds:
+            continue
+        t = statistics.mean(ds) / 1e9
+        print(f"| {label} (`{name}`) | {flops / 1e9:.1f} G | {t * 1e3:.2f} | "
+              f"{flops / t / 1e12:.1f} TFLOP/s | {flops / t / FP64_MFMA_PEAK:.2f} |")
+    seg_ms = [sum(r[2] for r in seg) / 1e6 for seg in segs]
+    print(f"\nkernel time per apply (sum of its launches): {statistics.mean(seg_ms):.2f} ms")
 
 
 def _counter_rows(d, counter):
@@ -151,8 +242,19 @@ def main():
     t.add_argument("--dram", default=None,
                    help="run with TCC_EA0_RDREQ_DRAM_32B_sum and TCC_EA0_WRREQ_WRITE_DRAM_32B_sum")
     t.add_argument("--command", default="")
+    g = sub.add_parser("stages")
+    g.add_argument("db")
+    g.add_argument("--grid", type=int, nargs=3, required=True)
+    g.add_argument("--planes", type=int, required=True)
+    for k in ("npw", "nv", "nb"):
+        g.add_argument("--" + k, type=int, required=True)
+    g.add_argument("--prec", choices=("f64", "f32"), required=True)
+    g.add_argument("--stream-bytes", dest="stream_bytes", type=float, required=True)
     a = ap.parse_args()
-    traffic(a)
+    if a.cmd == "stages":
+        stages(a)
+    else:
+        traffic(a)
 
 
 if __name__ == "__main__":

@@ -40,3 +40,38 @@ def test_kernels_and_last_apply(tmp_path):
     apply = _run("apply", db).splitlines()
     names = [line.split()[0] for line in apply[1:]]
     assert names == ["k_gather<double2>", "k_dgemm<0,", "k_tau_stream<2,"]
+
+
+def test_stage_rooflines(tmp_path):
+    """The stage table: means over the applies between stream launches, the
+    largest-grid launch of each FFT kernel (the K1e Poisson transforms reuse
+    the same kernels on a few grids), and the bytes model (72^3 grid, 35
+    planes with sphere modes, N_v = 432, N_b = 8, FP64: inverse plane pass
+    5.60 GB = X + 1728 grids x 35 planes x 72^2 x 16 B)."""
+    db = str(tmp_path / "s_results.db")
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, grid_x int, workgroup_x int, lds_size int, "
+                "vgpr_count int, accum_vgpr_count int, duration int, start int)")
+    seq = [("k_sphere_inv_ct<72, 72, 1>(x)", 3000, 2_000_000),
+           ("k_fft_axis_ct<72, 1>(x)", 9000, 4_000_000),
+           ("k_fft_axis_ct<72, 1>(x)", 20, 14_000),
+           ("k_dgemm<0, 1, 64>(x)", 100, 1_000_000),
+           ("k_tau_stream_qs<2, true, double>(x)", 5000, 50_000_000)]
+    rows, t = [], 0
+    for _ in range(3):
+        for n, gx, du in seq:
+            rows.append((n, gx, 256, 0, 0, 0, du, t))
+            t += du + 1
+    con.executemany("insert into kernels values (?,?,?,?,?,?,?,?)", rows)
+    con.commit()
+    con.close()
+    out = _run("stages", db, "--grid", "72", "72", "72", "--planes", "35", "--npw", "21079",
+               "--nv", "432", "--nb", "8", "--prec", "f64", "--stream-bytes", "300e9")
+    lines = {ln.split("(`")[0].strip("| ").strip(): ln for ln in out.splitlines() if "(`" in ln}
+    inv = lines["inverse plane pass, sphere -> planes"].split("|")
+    assert inv[2].strip() == "5.60 GB" and inv[3].strip() == "2.00"
+    axis = lines["inverse axis-1 pass"].split("|")
+    assert axis[3].strip() == "4.00"                              # the 20-workgroup launch ignored
+    stream = lines["tau stream + combine"].split("|")
+    assert stream[4].strip() == "6.00 TB/s" and stream[5].strip() == "0.75"
+    assert out.startswith("2 applies")
