@@ -44,7 +44,8 @@ Pruning.  Pair measure s[j][j'] = (Omega/N_r) sum_r |w_j(r) w_j'(r)|, the
 L1 norm of the pair density, which bounds every W integral of the pair by
 the norm of W.  The bands form blocks of 8 (the unit of the tau cache);
 block (I, J), I <= J, is kept when the largest s over its pairs is at least
-the threshold, and then all of its pairs are kept (both orders).
+the threshold, and then all of its pairs are kept (both orders); diagonal
+blocks, which hold the self pairs (s = 1), are always kept.
 
 The pruned model.  Every W integral over a pair of occupied indices in the
 localised frame is restricted to the kept pairs, with a~ = U^T a:
@@ -223,7 +224,7 @@ def kept_blocks(s, threshold):
     for I in range(nb):
         for J in range(I, nb):
             blk = s[I * BLOCK:(I + 1) * BLOCK, J * BLOCK:(J + 1) * BLOCK]
-            if blk.max() >= threshold:
+            if I == J or blk.max() >= threshold:
                 out.append((I, J))
     return out
 
