@@ -136,6 +136,41 @@ def stream_traffic(mixed):
             d["write_kib_per_launch"] * d["copy_write_factor"]) * 1024.0
 
 
+def loc_kw(args):
+    """Wannier-localised pruning options of the library (--prune T)."""
+    if args.prune is None:
+        return {}
+    return dict(localize=1, prune_threshold=args.prune, loc_max_sweeps=args.loc_sweeps)
+
+
+def loc_info(info):
+    return dict(threshold=None, tau_blocks_kept=info["tau_blocks"],
+                tau_blocks_all=info["tau_blocks_all"], spread_bohr2=info["loc_spread"],
+                sweeps=info["loc_sweeps"])
+
+
+def copy_rate(n_bytes=4 << 30, reps=5):
+    """Measured device-to-device copy rate (read + write bytes per second) of
+    a plain torch copy of n_bytes, the practical HBM ceiling beside the 8
+    TB/s peak."""
+    import torch
+    n = n_bytes // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del x, y
+    return dict(gbs=round(2 * 8 * n / t / 1e9, 1), bytes_per_copy=2 * 8 * n,
+                frac_of_peak=round(2 * 8 * n / t / 1e9 / HBM_PEAK_GBS, 4))
+
+
 def copy_calibration(args):
     """A plain device copy of known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters: each launch reads and writes 2 GiB."""
@@ -222,7 +257,7 @@ def time_to_force(args):
     t0 = time.perf_counter()
     prec = bsex.MIXED if args.precision == "mixed" else bsex.FP64
     ctx = bsex.init_from_synth(d, n_extra=args.n_extra, gs_tol=1e-10, gap_min=args.gap_min,
-                               precision=prec)
+                               precision=prec, **loc_kw(args))
     net = None
     if args.learned:
         from paper_2607_20728_amd import learned
@@ -271,6 +306,10 @@ def time_to_force(args):
                             learned=zs["learned"], fallback=zs["fallback"],
                             resid=zs["resid"][0], rc=zs["rc"]),
                max_abs_dwdR=float(np.abs(F).max()), sum_dwdR=list(map(float, F.sum(0))))
+    if args.prune is not None:
+        out["config"]["localized"] = dict(loc_info(info), threshold=args.prune)
+    if args.forces_out:
+        np.save(args.forces_out, F)
     ctx.free()
     if net is not None:
         net.free()
@@ -293,6 +332,11 @@ def main():
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--gap-min", type=float, default=0.0)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--prune", type=float, default=None,
+                    help="Wannier-localised frame with 8x8 blocks of occupied-pair W integrals "
+                         "kept when their pair measure reaches this threshold")
+    ap.add_argument("--loc-sweeps", type=int, default=0, help="Jacobi sweep cap (0: library default)")
+    ap.add_argument("--forces-out", default=None, help="--ttf: save d omega/d R here (.npy)")
     ap.add_argument("--two-level", action="store_true",
                     help="two-level preconditioner on the conduction states held (--ttf)")
     ap.add_argument("--n-extra", type=int, default=8,
@@ -338,7 +382,7 @@ def main():
     mixed = args.precision == "mixed"
     ctx = bsex.init_from_synth(d, n_extra=8, gs_tol=1e-10,
                                tau_budget_bytes=int(args.tau_budget_gb * 1e9),
-                               precision=bsex.MIXED if mixed else bsex.FP64)
+                               precision=bsex.MIXED if mixed else bsex.FP64, **loc_kw(args))
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
     info = bsex.get_info(ctx)
@@ -371,6 +415,11 @@ def main():
     if mixed:  # the FP32 cache holds every block
         ncached = info["tau_blocks"]
     tau_bytes = esz * pair_count(nv, blocks[:ncached]) * nr
+    if args.prune is not None:
+        # kept blocks: every diagonal block (36 pairs) and the rest whole (64)
+        if nv % 8 or ncached != info["tau_blocks"]:
+            sys.exit("pruned roofline needs N_v divisible by 8 and the whole cache")
+        tau_bytes = esz * (36 * nB + 64 * (ncached - nB)) * nr
     av_bytes = 2 * esz * args.nb * nv * nr          # a read + y write
     ms_stream, n_stream = ph.get("tau_stream", (0.0, 0))
     roofline = None
@@ -400,8 +449,11 @@ def main():
                            tau_policy={0: "auto", 1: "cache", 2: "rebuild"}[info["tau_policy"]],
                            init_s=round(t_init, 1), ks_gap_ha=info["ks_gap"]),
                roofline=roofline, phases=phases)
+    if args.prune is not None:
+        out["config"]["localized"] = dict(loc_info(info), threshold=args.prune)
     ctx.free()
     del X, Y
+    out["hbm_copy"] = copy_rate()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(args.config, args.nb)

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define BSEX_ABI_VERSION 2
+#define BSEX_ABI_VERSION 3
 
 typedef enum {
   BSE_OK = 0,
@@ -139,6 +139,31 @@ typedef struct {
   double rho_floor;           /* density floor of V_xc (0: 1e-3)                  */
   double scf_tol;             /* RMS change of V_H + V_xc ending the SCF (0: 1e-10) */
   double alpha_exx;           /* exact-exchange fraction, 0 <= alpha_exx <= 1      */
+  /* Wannier-localised pair pruning (the paper's Wannier-localised W
+   * integrals, main text, computational-cost paragraph after Eq. 7).
+   * localize = 1 rotates the occupied orbitals into maximally localised
+   * Wannier functions w_j = sum_v U[v][j] phi_v: simultaneous
+   * diagonalisation of the six matrices <phi|cos, sin(2 pi x_k/L_k)|phi>
+   * (Gygi, Fattebert and Schwegler 2003) by Jacobi rounds of a round-robin
+   * tournament, the w_j then put in Morton order of their centres.  The
+   * pair measure s_jj' = integral |w_j w_j'| decides which 8x8 blocks of
+   * occupied pairs keep their W integrals: block (I, J) is kept when its
+   * largest s_jj' is >= prune_threshold (diagonal blocks always are).  In
+   * bse_apply the K1d term becomes
+   *   (K1d A)_v = P_c sum_j U[v][j] sum_{j' kept with j} W(w_j' w_j) a~_j',
+   *   a~_j = sum_v U[v][j] a_v,
+   * and the W term of U (bse_u_vector) is restricted to the same pairs in
+   * the same frame; D, K1e, the Z-vector and the force contraction are
+   * unchanged, and every input and output stays in the canonical frame.
+   * With prune_threshold 0 every block is kept and the results equal the
+   * canonical ones.  Needs ks_model 0 (EINVAL otherwise). */
+  int32_t localize;           /* 0: canonical (default), 1: localised and pruned  */
+  double prune_threshold;     /* in [0, 1]                                        */
+  const double *loc_rotation; /* host [n_val][n_val] U[v][j], orthogonal to 1e-8, in the
+                                 order wanted; NULL: the library localises      */
+  int32_t loc_max_sweeps;     /* Jacobi sweep cap (0: 100)                        */
+  double loc_tol;             /* sweeps stop when one lowers the spread by less than
+                                 loc_tol x spread (0: 1e-9)                     */
 } bse_system_desc;
 
 /* Library ABI version (BSEX_ABI_VERSION of the build). */
@@ -188,6 +213,9 @@ typedef struct {
   double t_init_ms;           /*   the whole call                                 */
   int32_t scf_iters;          /* self-consistent cycles of the KS model (0 if none) */
   double scf_resid;           /* their final RMS potential change (-1 if none)    */
+  int64_t tau_blocks_all;     /* 8x8 pair blocks before pruning                   */
+  double loc_spread;          /* spread (bohr^2) of the localised frame (-1: canonical) */
+  int32_t loc_sweeps;         /* Jacobi sweeps run (0 with loc_rotation or canonical) */
 } bse_info;
 
 int bse_get_info(bse_ctx *ctx, bse_info *info);
@@ -197,6 +225,12 @@ int bse_get_info(bse_ctx *ctx, bse_info *info);
  * extra conduction states are returned when n > n_val: orbitals_dev must
  * then hold [n][n_pw] and eps_host [n], n <= n_orb. */
 int bse_get_orbitals(bse_ctx *ctx, int32_t n, double *orbitals_dev, double *eps_host);
+
+/* The localised frame of a context built with localize = 1: U_host
+ * [n_val][n_val] (U[v][j], row-major; columns in the library's order) and
+ * centres_host [n_val][3] (bohr, in [0, L_k)).  Either may be NULL.
+ * ESTATE for a canonical context. */
+int bse_get_frame(bse_ctx *ctx, double *U_host, double *centres_host);
 
 /* The operator of Eqs. 1-2 (scissor form of Table S-I):
  *   Y = P_c (D + s K1e - K1d) P_c X   for n_b trial vectors

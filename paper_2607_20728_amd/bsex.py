@@ -16,14 +16,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbsex.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, EGAP, EABI, ESTATE = range(8)
 K_D, K_1E, K_1D_BARE, K_1D_PDEP, K_ALL = 1, 2, 4, 8, 15
 FP64, MIXED = 0, 1
 TAU_AUTO, TAU_CACHE, TAU_REBUILD = 0, 1, 2
 
 SYMBOLS = ("bse_abi_version", "bse_last_error", "bse_warm_up", "bse_basis_size", "bse_basis_gvectors",
-           "bse_init_system", "bse_get_info", "bse_get_orbitals", "bse_apply",
+           "bse_init_system", "bse_get_info", "bse_get_orbitals", "bse_get_frame", "bse_apply",
            "bse_davidson", "bse_u_vector", "bse_zvector_solve", "bse_forces", "bse_forces_noalloc",
            "bse_ground_state_forces",
            "bse_set_precision", "bse_set_profiling", "bse_get_phase_times",
@@ -53,7 +53,9 @@ class SystemDesc(C.Structure):
                 ("orbitals", C.POINTER(C.c_double)), ("eps", C.POINTER(C.c_double)),
                 ("n_extra", C.c_int32), ("gs_tol", C.c_double), ("stream", C.c_void_p),
                 ("ks_model", C.c_int32), ("rho_floor", C.c_double), ("scf_tol", C.c_double),
-                ("alpha_exx", C.c_double)]
+                ("alpha_exx", C.c_double), ("localize", C.c_int32),
+                ("prune_threshold", C.c_double), ("loc_rotation", C.POINTER(C.c_double)),
+                ("loc_max_sweeps", C.c_int32), ("loc_tol", C.c_double)]
 
 
 class Info(C.Structure):
@@ -65,7 +67,9 @@ class Info(C.Structure):
                 ("tau_bytes_f32", C.c_int64), ("gs_sweeps", C.c_int32),
                 ("t_ground_state_ms", C.c_double), ("t_tau_ms", C.c_double),
                 ("t_tau_alloc_ms", C.c_double), ("t_init_ms", C.c_double),
-                ("scf_iters", C.c_int32), ("scf_resid", C.c_double)]
+                ("scf_iters", C.c_int32), ("scf_resid", C.c_double),
+                ("tau_blocks_all", C.c_int64), ("loc_spread", C.c_double),
+                ("loc_sweeps", C.c_int32)]
 
 
 class BatchOpts(C.Structure):
@@ -121,6 +125,7 @@ def lib():
     L.bse_init_system.argtypes = [C.POINTER(SystemDesc), C.POINTER(C.c_void_p)]
     L.bse_get_info.argtypes = [C.c_void_p, C.POINTER(Info)]
     L.bse_get_orbitals.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, dp]
+    L.bse_get_frame.argtypes = [C.c_void_p, dp, dp]
     L.bse_apply.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
     L.bse_davidson.argtypes = [C.c_void_p, C.c_int32, C.POINTER(SolverOpts), dp, C.c_void_p,
                                C.POINTER(SolverStats)]
@@ -219,7 +224,8 @@ def init_system(cell, grid, ecut, site_xyz, site_depth, site_width, n_val, pdep,
                 scissor=0.0, spin_factor=2.0, tau_policy=TAU_AUTO, tau_budget_bytes=0,
                 gap_min=0.0, kernel_mask=K_ALL, orbitals=None, eps=None, n_extra=8,
                 gs_tol=1e-10, precision=FP64, stream=None, desc_only=False, ks_model=0,
-                rho_floor=0.0, scf_tol=0.0, alpha_exx=0.0):
+                rho_floor=0.0, scf_tol=0.0, alpha_exx=0.0, localize=0, prune_threshold=0.0,
+                loc_rotation=None, loc_max_sweeps=0, loc_tol=0.0):
     """bse_init_system.  orbitals [n_orb][n_pw] / eps [n_orb] (host) or None to
     let the library solve the ground state."""
     import torch
@@ -254,6 +260,14 @@ def init_system(cell, grid, ecut, site_xyz, site_depth, site_width, n_val, pdep,
     d.rho_floor = float(rho_floor)
     d.scf_tol = float(scf_tol)
     d.alpha_exx = float(alpha_exx)
+    d.localize = int(localize)
+    d.prune_threshold = float(prune_threshold)
+    if loc_rotation is not None:
+        Ur = _f64(loc_rotation)
+        keep.append(Ur)
+        d.loc_rotation = _dptr(Ur)
+    d.loc_max_sweeps = int(loc_max_sweeps)
+    d.loc_tol = float(loc_tol)
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     d.stream = C.c_void_p(stream)
@@ -320,7 +334,18 @@ def get_info(ctx):
                 active_precision=i.active_precision, tau_bytes_f32=i.tau_bytes_f32,
                 gs_sweeps=i.gs_sweeps, t_ground_state_ms=i.t_ground_state_ms,
                 t_tau_ms=i.t_tau_ms, t_tau_alloc_ms=i.t_tau_alloc_ms, t_init_ms=i.t_init_ms,
-                scf_iters=i.scf_iters, scf_resid=i.scf_resid)
+                scf_iters=i.scf_iters, scf_resid=i.scf_resid, tau_blocks_all=i.tau_blocks_all,
+                loc_spread=i.loc_spread, loc_sweeps=i.loc_sweeps)
+
+
+def get_frame(ctx):
+    """bse_get_frame: (U [n_val][n_val], centres [n_val][3]) of a localised
+    context."""
+    n = get_info(ctx)["n_val"]
+    U = np.zeros((n, n))
+    cen = np.zeros((n, 3))
+    _check(lib().bse_get_frame(ctx.h, _dptr(U), _dptr(cen)))
+    return U, cen
 
 
 def get_orbitals(ctx, n=None):

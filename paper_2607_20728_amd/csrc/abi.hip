@@ -93,6 +93,26 @@ int validate(const bse_system_desc* d) {
     return fail(BSE_EINVAL, "alpha_exx must be in [0, 1]");
   if (d->alpha_exx != 0 && (d->ks_model != 1 || d->n_orb <= 0 || d->precision != BSE_FP64))
     return fail(BSE_EINVAL, "alpha_exx needs ks_model 1, orbitals supplied and BSE_FP64");
+  if (d->localize != 0 && d->localize != 1) return fail(BSE_EINVAL, "localize %d unknown", d->localize);
+  if (d->localize) {
+    if (d->ks_model != 0) return fail(BSE_EINVAL, "localize needs ks_model 0");
+    if (!std::isfinite(d->prune_threshold) || d->prune_threshold < 0 || d->prune_threshold > 1)
+      return fail(BSE_EINVAL, "prune_threshold must be in [0, 1]");
+    if (d->loc_max_sweeps < 0 || !std::isfinite(d->loc_tol) || d->loc_tol < 0)
+      return fail(BSE_EINVAL, "loc_max_sweeps / loc_tol invalid");
+    if (d->loc_rotation) {
+      const long n = d->n_val;
+      if (!finite_all(d->loc_rotation, n * n)) return fail(BSE_EINVAL, "non-finite loc_rotation");
+      double worst = 0.0;  // U^T U = 1
+      for (long i = 0; i < n; ++i)
+        for (long j = i; j < n; ++j) {
+          double s = 0.0;
+          for (long v = 0; v < n; ++v) s += d->loc_rotation[v * n + i] * d->loc_rotation[v * n + j];
+          worst = std::max(worst, std::fabs(s - (i == j ? 1.0 : 0.0)));
+        }
+      if (worst > 1e-8) return fail(BSE_EINVAL, "loc_rotation is not orthogonal (%.1e)", worst);
+    }
+  }
   return BSE_OK;
 }
 
@@ -103,10 +123,16 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   const long nr = c->basis.nr, npw = c->basis.npw;
   const long nB = (c->nv + 7) / 8;
-  c->nblk = nB * (nB + 1) / 2;
+  c->nblk_all = nB * (nB + 1) / 2;
+  // the upper block triangle in row order, or the blocks a localised frame keeps
   std::vector<int2> ij;
-  for (long I = 0; I < nB; ++I)
-    for (long J = I; J < nB; ++J) ij.push_back(make_int2((int)I, (int)J));
+  if (c->loc) {
+    ij = c->blkIJ_h;
+  } else {
+    for (long I = 0; I < nB; ++I)
+      for (long J = I; J < nB; ++J) ij.push_back(make_int2((int)I, (int)J));
+  }
+  c->nblk = (long)ij.size();
   BSE_TRY(ctx_alloc_t(c, &c->blkIJ, ij.size()));
   BSE_TRY(upload(c, c->blkIJ, ij.data(), sizeof(int2) * ij.size()));
   c->blkIJ_h = ij;
@@ -229,10 +255,10 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
       long nt = std::min(c->tile_blk, nbuild - gb0);
       if (gb0 < ncache) nt = std::min(nt, ncache - gb0);
       if (gb0 < ncache)
-        BSE_TRY(tau_build_range(c, c->phir, gb0, nt, c->tau_cache, ncache, gb0, c->kmask,
+        BSE_TRY(tau_build_range(c, c->phik, gb0, nt, c->tau_cache, ncache, gb0, c->kmask,
                                 c->tau_f));
       else
-        BSE_TRY(tau_build_range_f(c, c->phir_f, gb0, nt, c->tau_f, c->nblk, gb0, c->kmask));
+        BSE_TRY(tau_build_range_f(c, c->phik_f, gb0, nt, c->tau_f, c->nblk, gb0, c->kmask));
       gb0 += nt;
     }
   }
@@ -367,6 +393,14 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
   BSE_TRY(to_grid(c, c->Phi, c->nv, 1, c->phir));
   // orbitals supplied for the KS model: H_KS from their density
   if (c->ks && d->n_orb > 0) BSE_TRY(ks_potential_from_orbitals(c));
+  // localised frame of the occupied-pair W integrals
+  c->phik = c->phir;
+  if (d->localize) {
+    c->loc = 1;
+    c->prune_thr = d->prune_threshold;
+    BSE_TRY(localize(c, d));
+    c->phik = c->phir_loc;
+  }
   c->precision = d->precision;
   if (c->precision == BSE_MIXED) {  // FP32 copies of the real-space fields
     BSE_TRY(ctx_alloc_t(c, &c->phir_f, (size_t)c->nvh * nr));
@@ -375,7 +409,12 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
     BSE_TRY(to_f32((const double*)c->phir, (float*)c->phir_f, 2L * c->nvh * nr, c->st));
     BSE_TRY(to_f32(c->Vr, c->Vr_f, nr, c->st));
     BSE_TRY(to_f32(c->vc, c->vc_f, nr, c->st));
+    if (c->loc) {
+      BSE_TRY(ctx_alloc_t(c, &c->phir_loc_f, (size_t)c->nvh * nr));
+      BSE_TRY(to_f32((const double*)c->phir_loc, (float*)c->phir_loc_f, 2L * c->nvh * nr, c->st));
+    }
   }
+  c->phik_f = c->loc ? c->phir_loc_f : c->phir_f;
   BSE_HIP(hipStreamSynchronize(c->st));
   const auto t1 = std::chrono::steady_clock::now();
   BSE_TRY(plan_tau(c, d));
@@ -495,6 +534,17 @@ int bse_get_info(bse_ctx* c, bse_info* info) {
   info->t_init_ms = c->t_init_ms;
   info->scf_iters = c->scf_iters;
   info->scf_resid = c->ks ? c->scf_resid : -1.0;
+  info->tau_blocks_all = c->nblk_all;
+  info->loc_spread = c->loc ? c->loc_spread : -1.0;
+  info->loc_sweeps = c->loc_sweeps;
+  return BSE_OK;
+}
+
+int bse_get_frame(bse_ctx* c, double* U_host, double* centres_host) {
+  if (!c) return fail(BSE_EINVAL, "ctx is NULL");
+  if (!c->loc) return fail(BSE_ESTATE, "the context has no localised frame");
+  if (U_host) std::copy(c->loc_U_h.begin(), c->loc_U_h.end(), U_host);
+  if (centres_host) std::copy(c->loc_cen_h.begin(), c->loc_cen_h.end(), centres_host);
   return BSE_OK;
 }
 

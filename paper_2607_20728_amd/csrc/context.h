@@ -101,6 +101,22 @@ struct bse_ctx {
   float2 *agrid_f = nullptr, *drho_f = nullptr, *compact_f = nullptr;
   int nbc_f = 0;
   long compact_f_grids = 0;
+  // Wannier-localised frame (localize = 1): K1d, its tau blocks and U's W
+  // term work in it.  phik / phik_f are the orbital grids of those terms:
+  // phir_loc (phir_loc_f) when localised, else phir (phir_f).
+  int loc = 0;
+  double prune_thr = 0.0;
+  double* Uloc = nullptr;         // [nv][nv] U[v][j]
+  double* Phi_loc = nullptr;      // [nv][npw] U^T Phi
+  double2* phir_loc = nullptr;    // [nvh][nr]
+  float2* phir_loc_f = nullptr;   // [nvh][nr] (mixed)
+  double* A_rot = nullptr;        // [nbc][nv][npw] rotated block, then the rotated-back result
+  const double2* phik = nullptr;
+  const float2* phik_f = nullptr;
+  double loc_spread = -1.0;
+  int loc_sweeps = 0;
+  long nblk_all = 0;
+  std::vector<double> loc_U_h, loc_cen_h;  // [nv][nv], [nv][3]
   // learned preconditioner (not owned)
   bse_mlp* learned = nullptr;
   // HIP graphs of the block apply, one per (block size, precision), replayed
@@ -193,5 +209,10 @@ int gram_tall(bse_ctx* c, const double* A, long m, const double* B, long n, long
 // device address of the allocation-free scratch on `dev` (called once per
 // context initialisation, with that device current)
 int noalloc_setup(int dev);
+// Wannier frame and kept blocks of a context built with localize = 1
+int localize(bse_ctx* c, const bse_system_desc* d);
+int rotate_bands(bse_ctx* c, int nb, const double* A, double* out, bool back);
+int diag_axpy(const double* A, const double* Tk, const double* eps, double shift, int nv,
+              long npw, int nb, double* Y, hipStream_t st);
 long noalloc_scratch_doubles();
 }  // namespace bsex

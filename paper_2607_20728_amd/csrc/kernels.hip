@@ -902,6 +902,17 @@ __global__ void k_row_scale(const double* __restrict__ s, double* __restrict__ Y
   for (long e = gtid(); e < rows * len; e += gstride()) Y[e] *= s[e / len];
 }
 
+// Y[b][v][k] += (T_k - eps_v + shift) A[b][v][k]: the diagonal part of D
+__global__ void k_diag_axpy(const double* __restrict__ A, const double* __restrict__ Tk,
+                            const double* __restrict__ eps, double shift, int nv, long npw, long n,
+                            double* __restrict__ Y) {
+  for (long e = gtid(); e < n; e += gstride()) {
+    const long k = e % npw;
+    const int v = (int)((e / npw) % nv);
+    Y[e] += (Tk[k] - eps[v] + shift) * A[e];
+  }
+}
+
 __global__ void k_axpby(double alpha, const double* __restrict__ X, double beta,
                         double* __restrict__ Y, long n) {
   for (long e = gtid(); e < n; e += gstride()) Y[e] = alpha * X[e] + (beta == 0.0 ? 0.0 : beta * Y[e]);
@@ -1467,6 +1478,16 @@ int row_scale(const double* s, double* Y, long rows, long len, hipStream_t st) {
   const long n = rows * len;
   if (n <= 0) return BSE_OK;
   hipLaunchKernelGGL(k_row_scale, dim3(nblocks(n)), dim3(TPB), 0, st, s, Y, rows, len);
+  CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+int diag_axpy(const double* A, const double* Tk, const double* eps, double shift, int nv,
+              long npw, int nb, double* Y, hipStream_t st) {
+  const long n = (long)nb * nv * npw;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(k_diag_axpy, dim3(nblocks(n)), dim3(TPB), 0, st, A, Tk, eps, shift, nv, npw,
+                     n, Y);
   CHECK_LAUNCH();
   return BSE_OK;
 }

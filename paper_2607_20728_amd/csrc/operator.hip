@@ -314,14 +314,16 @@ int ensure_apply_work(bse_ctx* c, int nbc) {
   if (c->nbc >= nbc) return BSE_OK;
   ctx_release(c, c->A_s);
   ctx_release(c, c->Zs);
+  ctx_release(c, c->A_rot);
   ctx_release(c, c->agrid);
   ctx_release(c, c->drho);
-  c->A_s = c->Zs = nullptr;
+  c->A_s = c->Zs = c->A_rot = nullptr;
   c->agrid = c->drho = nullptr;
   c->nbc = 0;
   const size_t npw = c->basis.npw, nr = c->basis.nr;
   BSE_TRY(ctx_alloc_t(c, &c->A_s, (size_t)nbc * c->nv * npw));
   BSE_TRY(ctx_alloc_t(c, &c->Zs, (size_t)nbc * c->nv * npw));
+  if (c->loc) BSE_TRY(ctx_alloc_t(c, &c->A_rot, (size_t)nbc * c->nv * npw));
   BSE_TRY(ctx_alloc_t(c, &c->agrid, (size_t)nbc * c->nvh * nr));
   BSE_TRY(ctx_alloc_t(c, &c->drho, (size_t)((nbc + 1) / 2) * nr));
   c->nbc = nbc;
@@ -357,17 +359,46 @@ int exchange_like(bse_ctx* c, const double2* L, const double2* M, const double2*
   return BSE_OK;
 }
 
-// Y = P_c (D + s K1e - K1d) P_c X for nb <= c->nbc vectors
+// band index of nb vector sets into the localised frame (out_b = U^T A_b)
+// or back (out_b = U A_b)
+int rotate_bands(bse_ctx* c, int nb, const double* A, double* out, bool back) {
+  const long npw = c->basis.npw, L = (long)c->nv * npw;
+  for (int b = 0; b < nb; ++b)
+    BSE_TRY(dgemm(back ? 0 : 1, 0, c->nv, npw, c->nv, 1.0, c->Uloc, c->nv, A + b * L, npw, 0.0,
+                  out + b * L, npw, c->st));
+  return BSE_OK;
+}
+
+// the gathered grid part Zg (in the kernel frame) plus the diagonal of D on
+// A, projected: Y = P_c (Zg + (T - eps_v + Delta) A); in a localised frame
+// Zg is rotated back first and the diagonal added in the canonical frame
+static int finish_apply(bse_ctx* c, int nb, const double* A, int with_v, double* Y) {
+  if (c->loc) {
+    BSE_TRY(rotate_bands(c, nb, c->Zs, c->A_rot, true));
+    if (with_v)
+      BSE_TRY(diag_axpy(A, c->T, c->eps_d, c->scissor, c->nv, c->basis.npw, nb, c->A_rot, c->st));
+    return proj_c(c, c->A_rot, Y, nb);
+  }
+  return proj_c(c, c->Zs, Y, nb);
+}
+
+// Y = P_c (D + s K1e - K1d) P_c X for nb <= c->nbc vectors; in a localised
+// frame the grid part runs on A~ = U^T A with the localised orbitals
 int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
   const long nr = c->basis.nr;
   const double* A = c->in_pc ? X : c->A_s;
   if (!c->in_pc) BSE_TRY(proj_c(c, X, c->A_s, nb));
-  BSE_TRY(to_grid(c, A, c->nv, nb, c->agrid));
+  const double* Ag = A;
+  if (c->loc) {
+    BSE_TRY(rotate_bands(c, nb, A, c->A_rot, false));
+    Ag = c->A_rot;
+  }
+  BSE_TRY(to_grid(c, Ag, c->nv, nb, c->agrid));
   const double2* vdrho = nullptr;
   if (c->kmask & BSE_K_1E) {
     PhaseScope ps(c, PH_K1E);
     const long nbh = (nb + 1) / 2;
-    BSE_TRY(transition_density(c->phir, c->agrid, c->nv, nb, nr, c->drho, c->st));
+    BSE_TRY(transition_density(c->phik, c->agrid, c->nv, nb, nr, c->drho, c->st));
     BSE_TRY(fft3d(c->fft, c->drho, nbh, -1, c->st));
     BSE_TRY(mul_real_field(c->drho, nbh, nr, c->vc, 1.0 / (double)nr, c->st));
     BSE_TRY(fft3d(c->fft, c->drho, nbh, +1, c->st));
@@ -393,27 +424,27 @@ int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {
   if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
     if (c->nblk_cached == c->nblk) {
       // whole tau cached: one launch, combine fused, z written over a(r)
-      FuseArgs f{c->Vr, vdrho, c->phir, c->spin, with_v};
-      BSE_TRY(tau_contract(c, c->phir, c->agrid, c->agrid, nb, c->kmask, true, &f));
+      FuseArgs f{c->Vr, vdrho, c->phik, c->spin, with_v};
+      BSE_TRY(tau_contract(c, c->phik, c->agrid, c->agrid, nb, c->kmask, true, &f));
     } else {
       BSE_TRY(ensure_ygrid(c));
-      BSE_TRY(tau_contract(c, c->phir, c->agrid, c->ygrid, nb, c->kmask, true));
+      BSE_TRY(tau_contract(c, c->phik, c->agrid, c->ygrid, nb, c->kmask, true));
       PhaseScope ps(c, PH_COMBINE);
-      BSE_TRY(combine(c->agrid, c->phir, c->Vr, vdrho, c->ygrid, c->ygrid, c->nv, nb, nr, c->spin,
+      BSE_TRY(combine(c->agrid, c->phik, c->Vr, vdrho, c->ygrid, c->ygrid, c->nv, nb, nr, c->spin,
                       with_v, c->st));
       zg = c->ygrid;
     }
   } else {
     PhaseScope ps(c, PH_COMBINE);
-    BSE_TRY(combine(c->agrid, c->phir, c->Vr, vdrho, nullptr, c->agrid, c->nv, nb, nr, c->spin,
+    BSE_TRY(combine(c->agrid, c->phik, c->Vr, vdrho, nullptr, c->agrid, c->nv, nb, nr, c->spin,
                     with_v, c->st));
   }
   if (c->alpha != 0.0 && with_v)
     BSE_TRY(axpby(1.0, reinterpret_cast<const double*>(c->xgrid), 1.0,
                   reinterpret_cast<double*>(zg), 2 * nb * gs, c->st));
-  BSE_TRY(from_grid(c, zg, c->nv, nb, with_v ? A : nullptr, c->eps_d, c->scissor, c->Zs));
-  BSE_TRY(proj_c(c, c->Zs, Y, nb));
-  return BSE_OK;
+  const bool diag_here = with_v && !c->loc;
+  BSE_TRY(from_grid(c, zg, c->nv, nb, diag_here ? A : nullptr, c->eps_d, c->scissor, c->Zs));
+  return finish_apply(c, nb, A, with_v, Y);
 }
 
 // kernel part of the operator on one exciton, before P_c, gathered:
@@ -427,7 +458,7 @@ int kernel_part(bse_ctx* c, const double2* agrid, double* Kt) {
   double2* y = c->agrid + (long)c->nvh * nr;
   const double2* vdrho = nullptr;
   if (c->kmask & BSE_K_1E) {
-    BSE_TRY(transition_density(c->phir, agrid, c->nv, 1, nr, c->drho, c->st));
+    BSE_TRY(transition_density(c->phik, agrid, c->nv, 1, nr, c->drho, c->st));
     BSE_TRY(fft3d(c->fft, c->drho, 1, -1, c->st));
     BSE_TRY(mul_real_field(c->drho, 1, nr, c->vc, 1.0 / (double)nr, c->st));
     BSE_TRY(fft3d(c->fft, c->drho, 1, +1, c->st));
@@ -450,10 +481,10 @@ int kernel_part(bse_ctx* c, const double2* agrid, double* Kt) {
                    c->st));
     yk = y;
   } else if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
-    BSE_TRY(tau_contract(c, c->phir, agrid, y, 1, c->kmask, true));
+    BSE_TRY(tau_contract(c, c->phik, agrid, y, 1, c->kmask, true));
     yk = y;
   }
-  BSE_TRY(combine(agrid, c->phir, c->Vr, vdrho, yk, y, c->nv, 1, nr, c->spin, 0, c->st));
+  BSE_TRY(combine(agrid, c->phik, c->Vr, vdrho, yk, y, c->nv, 1, nr, c->spin, 0, c->st));
   BSE_TRY(from_grid(c, y, c->nv, 1, nullptr, nullptr, 0.0, Kt));
   return BSE_OK;
 }
@@ -463,8 +494,8 @@ int kernel_part(bse_ctx* c, const double2* agrid, double* Kt) {
 // builds and contracts the tiles in FP32 (a and the sum pass through FP32
 // grids).
 int sigma_phi(bse_ctx* c, const double2* agrid, double2* y) {
-  if (!(c->active == BSE_MIXED && c->vc_f && c->phir_f))
-    return tau_contract(c, agrid, c->phir, y, 1, c->kmask, false);
+  if (!(c->active == BSE_MIXED && c->vc_f && c->phik_f))
+    return tau_contract(c, agrid, c->phik, y, 1, c->kmask, false);
   const long nr = c->basis.nr, ng = (long)c->nvh * nr;
   BSE_TRY(ensure_mixed_work(c, 2));
   float2* af = c->agrid_f;
@@ -481,7 +512,7 @@ int sigma_phi(bse_ctx* c, const double2* agrid, double2* y) {
     PhaseScope ps(c, PH_TAU_TILE);
     int row0 = 0, rows = 0;  // the first launch writes every band of y
     if (gb0 > 0) tile_rows(c, gb0, nt, &row0, &rows);
-    BSE_TRY(tau_stream(buf, nt, nt, c->blkIJ + gb0, c->Rf, c->phir_f, yf, 1, c->nv, nr,
+    BSE_TRY(tau_stream(buf, nt, nt, c->blkIJ + gb0, c->Rf, c->phik_f, yf, 1, c->nv, nr,
                        gb0 == 0 ? 0 : 1, c->max_lds, c->st, nullptr, c->tau_bl, row0, rows));
   }
   return to_f64(reinterpret_cast<const float*>(yf), reinterpret_cast<double*>(y), 2 * ng, c->st);
@@ -530,15 +561,20 @@ int apply_chunk_mixed(bse_ctx* c, int nb, const double* X, double* Y) {
   BSE_TRY(ensure_mixed_work(c, c->nbc));
   const double* A = c->in_pc ? X : c->A_s;
   if (!c->in_pc) BSE_TRY(proj_c(c, X, c->A_s, nb));
+  const double* Ag = A;
+  if (c->loc) {
+    BSE_TRY(rotate_bands(c, nb, A, c->A_rot, false));
+    Ag = c->A_rot;
+  }
   {
     PhaseScope ps(c, PH_FFT_INV);
-    BSE_TRY(sphere_to_grid(c->fft, c->sp, c->basis.omega, A, c->nv, nb, c->agrid_f, c->st));
+    BSE_TRY(sphere_to_grid(c->fft, c->sp, c->basis.omega, Ag, c->nv, nb, c->agrid_f, c->st));
   }
   const float2* vdrho = nullptr;
   if (c->kmask & BSE_K_1E) {
     PhaseScope ps(c, PH_K1E);
     const long nbh = (nb + 1) / 2;
-    BSE_TRY(transition_density(c->phir_f, c->agrid_f, c->nv, nb, nr, c->drho_f, c->st));
+    BSE_TRY(transition_density(c->phik_f, c->agrid_f, c->nv, nb, nr, c->drho_f, c->st));
     BSE_TRY(fft3d(c->fft, c->drho_f, nbh, -1, c->st));
     BSE_TRY(mul_real_field(c->drho_f, nbh, nr, c->vc_f, 1.0f / (float)nr, c->st));
     BSE_TRY(fft3d(c->fft, c->drho_f, nbh, +1, c->st));
@@ -547,18 +583,18 @@ int apply_chunk_mixed(bse_ctx* c, int nb, const double* X, double* Y) {
   const int with_v = (c->kmask & BSE_K_D) ? 1 : 0;
   if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP)) {
     PhaseScope ps(c, PH_TAU_STREAM);
-    FuseArgsF f{c->Vr_f, vdrho, c->phir_f, c->spin, with_v};
+    FuseArgsF f{c->Vr_f, vdrho, c->phik_f, c->spin, with_v};
     BSE_TRY(tau_stream(c->tau_f, c->nblk, c->nblk, c->blkIJ, c->Rf, c->agrid_f, c->agrid_f, nb,
                        c->nv, nr, 0, c->max_lds, c->st, &f, c->tau_bl));
   } else {
     PhaseScope ps(c, PH_COMBINE);
-    BSE_TRY(combine(c->agrid_f, c->phir_f, c->Vr_f, vdrho, nullptr, c->agrid_f, c->nv, nb, nr,
+    BSE_TRY(combine(c->agrid_f, c->phik_f, c->Vr_f, vdrho, nullptr, c->agrid_f, c->nv, nb, nr,
                     c->spin, with_v, c->st));
   }
-  BSE_TRY(from_grid_f(c, c->agrid_f, c->nv, nb, with_v ? A : nullptr, c->eps_d, c->scissor,
+  const bool diag_here = with_v && !c->loc;
+  BSE_TRY(from_grid_f(c, c->agrid_f, c->nv, nb, diag_here ? A : nullptr, c->eps_d, c->scissor,
                       c->Zs));
-  BSE_TRY(proj_c(c, c->Zs, Y, nb));
-  return BSE_OK;
+  return finish_apply(c, nb, A, with_v, Y);
 }
 
 int apply_any(bse_ctx* c, int nb, const double* X, double* Y) {

@@ -780,10 +780,19 @@ int u_vector(bse_ctx* c, const double* Xs, double* U) {
   BSE_TRY(G.alloc((size_t)L));
   double* A = c->A_s;
   BSE_TRY(proj_c(c, Xs, A, 1));
-  BSE_TRY(to_grid(c, A, c->nv, 1, c->agrid));
+  // a localised frame assembles U for A~ = U^T A with the localised
+  // orbitals (its pruned W terms) and rotates the result back
+  const double* Ak = A;
+  const double* Phik = c->Phi;
+  if (c->loc) {
+    BSE_TRY(rotate_bands(c, 1, A, c->A_rot, false));
+    Ak = c->A_rot;
+    Phik = c->Phi_loc;
+  }
+  BSE_TRY(to_grid(c, Ak, c->nv, 1, c->agrid));
   // kernel part before P_c, and S = <phi | K~ A>
   BSE_TRY(kernel_part(c, c->agrid, c->Zs));
-  BSE_TRY(dgemm(0, 1, nv, nv, npw, 1.0, c->Phi, npw, c->Zs, npw, 0.0, S.p, nv, c->st));
+  BSE_TRY(dgemm(0, 1, nv, nv, npw, 1.0, Phik, npw, c->Zs, npw, 0.0, S.p, nv, c->st));
   // g(r) = s (v_c*Drho) a - sum_v' sigma_{v'v} phi_v'  (drho holds v_c*Drho from kernel_part)
   double2* g1 = c->agrid + (long)c->nvh * nr;   // set 1: scratch
   const double2* y = nullptr;
@@ -792,10 +801,14 @@ int u_vector(bse_ctx* c, const double* Xs, double* U) {
     y = g1;
   }
   const double2* vd = (c->kmask & BSE_K_1E) ? c->drho : nullptr;
-  BSE_TRY(combine(c->phir, c->agrid, c->Vr, vd, y, g1, c->nv, 1, nr, c->spin, 0, c->st));
+  BSE_TRY(combine(c->phik, c->agrid, c->Vr, vd, y, g1, c->nv, 1, nr, c->spin, 0, c->st));
   BSE_TRY(from_grid(c, g1, c->nv, 1, nullptr, nullptr, 0.0, G.p));
   BSE_TRY(proj_c(c, G.p, U, 1));
-  BSE_TRY(dgemm(0, 0, nv, npw, nv, -1.0, S.p, nv, A, npw, 1.0, U, npw, c->st));
+  BSE_TRY(dgemm(0, 0, nv, npw, nv, -1.0, S.p, nv, Ak, npw, 1.0, U, npw, c->st));
+  if (c->loc) {
+    BSE_TRY(rotate_bands(c, 1, U, G.p, true));
+    BSE_TRY(copy_dev(c, G.p, U, (size_t)L));
+  }
   if (c->ks) BSE_TRY(ks_u_dpart(c, A, U));
   BSE_HIP(hipStreamSynchronize(c->st));
   return BSE_OK;
