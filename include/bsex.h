@@ -146,9 +146,10 @@ typedef struct {
    * diagonalisation of the six matrices <phi|cos, sin(2 pi x_k/L_k)|phi>
    * (Gygi, Fattebert and Schwegler 2003) by Jacobi rounds of a round-robin
    * tournament, the w_j then put in Morton order of their centres.  The
-   * pair measure s_jj' = integral |w_j w_j'| decides which 8x8 blocks of
-   * occupied pairs keep their W integrals: block (I, J) is kept when its
-   * largest s_jj' is >= prune_threshold (diagonal blocks always are).  In
+   * pair measure s_jj' = ||w_j w_j'|| / (||w_j^2|| ||w_j'^2||)^(1/2) (L2
+   * norms, in [0, 1]) decides which 8x8 blocks of occupied pairs keep their
+   * W integrals: block (I, J) is kept when its largest s_jj' is
+   * >= prune_threshold (diagonal blocks always are).  In
    * bse_apply the K1d term becomes
    *   (K1d A)_v = P_c sum_j U[v][j] sum_{j' kept with j} W(w_j' w_j) a~_j',
    *   a~_j = sum_v U[v][j] a_v,

@@ -40,9 +40,11 @@ Centres and order.  x_k(j) = L_k/(2 pi) arg(C_k[j][j] + i S_k[j][j]) in
 centres on a 1024^3 grid of fractional coordinates (ties by index), so that
 the 8 orbitals of a band block lie close together.
 
-Pruning.  Pair measure s[j][j'] = (Omega/N_r) sum_r |w_j(r) w_j'(r)|, the
-L1 norm of the pair density, which bounds every W integral of the pair by
-the norm of W.  The bands form blocks of 8 (the unit of the tau cache);
+Pruning.  Pair measure s[j][j'] = ||w_j w_j'|| / (||w_j^2|| ||w_j'^2||)^(1/2)
+with the L2 norm on the grid: the norm of the pair density, which bounds the
+norm of tau_jj' = W(w_j w_j') by that of W, made scale free (Cauchy-Schwarz
+puts it in [0, 1], with 1 on the diagonal).  The bands form blocks of 8 (the
+unit of the tau cache);
 block (I, J), I <= J, is kept when the largest s over its pairs is at least
 the threshold, and then all of its pairs are kept (both orders); diagonal
 blocks, which hold the self pairs (s = 1), are always kept.
@@ -211,9 +213,12 @@ def localized_frame(b, phir, tol=1e-9, max_sweeps=100):
 # pruning
 # ---------------------------------------------------------------------------
 def pair_measure(b, wr):
-    """s[j][j'] = (Omega/N_r) sum_r |w_j(r) w_j'(r)|."""
-    a = np.abs(wr.reshape(wr.shape[0], -1))
-    return (a @ a.T) * (b.omega / b.n_r)
+    """s[j][j'] = ||w_j w_j'|| / (||w_j^2|| ||w_j'^2||)^(1/2) (L2 norms, grid
+    quadrature)."""
+    q = wr.reshape(wr.shape[0], -1) ** 2
+    G = (q @ q.T) * (b.omega / b.n_r)                # integral w_j^2 w_j'^2
+    d = np.sqrt(np.diag(G))
+    return np.sqrt(G / np.outer(d, d))
 
 
 def kept_blocks(s, threshold):

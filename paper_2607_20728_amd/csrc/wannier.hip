@@ -19,9 +19,11 @@
 // the localised orbitals are put in Morton order of them (1024 cells per
 // axis, ties by index), so the 8 orbitals of a band block lie together.
 //
-// Pruning: s[j][j'] = integral |w_j w_j'| (one more GEMM, of |w| rows); an
-// 8x8 block (I, J), I <= J, keeps its W integrals when its largest s is at
-// least the threshold.  The kept list replaces the full block triangle in
+// Pruning: s[j][j'] = ||w_j w_j'|| / (||w_j^2|| ||w_j'^2||)^(1/2), L2 norms
+// (one more GEMM, of the squared rows): the norm of the pair density, which
+// bounds that of tau_jj' = W(w_j w_j'), made scale free (in [0, 1], 1 on the
+// diagonal).  An 8x8 block (I, J), I <= J, keeps its W integrals when its
+// largest s is at least the threshold (diagonal blocks always).  The kept list replaces the full block triangle in
 // the tau cache, its rebuild tiles and the stream launches.
 #include <algorithm>
 #include <cmath>
@@ -58,8 +60,8 @@ int get(bse_ctx* c, const double* src, std::vector<double>& h, size_t n) {
 }
 
 // real rows of packed orbital grids: out[v][r] = component v & 1 of grid
-// v >> 1 (its absolute value when absval)
-__global__ void k_unpack_rows(const double2* __restrict__ g, int nv, long nr, int absval,
+// v >> 1 (its square when squared)
+__global__ void k_unpack_rows(const double2* __restrict__ g, int nv, long nr, int squared,
                               double* __restrict__ out) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= (long)nv * nr) return;
@@ -67,7 +69,7 @@ __global__ void k_unpack_rows(const double2* __restrict__ g, int nv, long nr, in
   const long r = i - (long)v * nr;
   const double2 w = g[(long)(v >> 1) * nr + r];
   const double x = (v & 1) ? w.y : w.x;
-  out[i] = absval ? fabs(x) : x;
+  out[i] = squared ? x * x : x;
 }
 
 // out[v][r] = P[v][r] f(2 pi i_k / N_k), f = cos or sin, i_k the grid index
@@ -386,6 +388,13 @@ int localize(bse_ctx* c, const bse_system_desc* d) {
   BSE_TRY(dgemm(0, 1, nv, nv, nr, dv, P.p, nr, P.p, nr, 0.0, M.p, nv, c->st));
   std::vector<double> s((size_t)nn);
   BSE_TRY(get(c, M.p, s, s.size()));
+  {
+    std::vector<double> dg(nv);
+    for (int j = 0; j < nv; ++j) dg[j] = std::sqrt(s[(size_t)j * nv + j]);
+    for (int j = 0; j < nv; ++j)
+      for (int jp = 0; jp < nv; ++jp)
+        s[(size_t)j * nv + jp] = std::sqrt(s[(size_t)j * nv + jp] / (dg[j] * dg[jp]));
+  }
   const long nB = (nv + 7) / 8;
   std::vector<int2> keep;
   for (long I = 0; I < nB; ++I)

@@ -1,6 +1,8 @@
 """Pins of the Wannier localisation and of the pruned model (oracle/wannier.py;
 the paper's Wannier-localised W integrals, main text after Eq. 7).
 
+* the pair measure is symmetric, 1 on the diagonal, at most 1, and equals
+  its definition;
 * the Jacobi angle maximises the pair objective, checked against a
   brute-force search over rotations built as explicit matrices;
 * the tournament visits every pair once per sweep in rounds of disjoint
@@ -145,6 +147,21 @@ def test_recovers_mixed_separated_functions():
     for j in range(8):
         assert np.abs(cen[j] - cs[ov[j].argmax()]).max() < 1e-6
     assert info["spread"][0] > 1.5 * s0
+
+
+def test_pair_measure_bounds(c1):
+    """The pair measure is symmetric, 1 on the diagonal and at most 1
+    (Cauchy-Schwarz), and equals its definition for one pair computed
+    directly on the grid."""
+    S, U, cen, info = c1
+    wr = np.einsum("vj,vxyz->jxyz", U, S.phir)
+    s = wannier.pair_measure(S.b, wr)
+    assert np.abs(s - s.T).max() < 1e-15
+    assert np.abs(np.diag(s) - 1).max() < 1e-14 and s.max() <= 1 + 1e-14
+    j, jp = 2, 11
+    num = np.sqrt(((wr[j] * wr[jp]) ** 2).sum())
+    den = np.sqrt(np.sqrt((wr[j] ** 4).sum()) * np.sqrt((wr[jp] ** 4).sum()))
+    assert abs(s[j, jp] - num / den) < 1e-14
 
 
 # --------------------------------------------------------------------------
