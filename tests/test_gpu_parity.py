@@ -234,11 +234,13 @@ def test_ground_state_forces(name):
 
 
 def test_full_size_c2_properties():
-    """At the benchmark's own size (N_v = 432, 72^3, 21,079 plane waves, in the
-    launch configuration bench.py times: whole FP32 cache, FP64 cache beside
-    it, 8-vector blocks), where the oracle cannot build the ground state:
-    the operator is symmetric, maps occupied directions to zero, and the FP32
-    and FP64 applies agree to the FP32 bound."""
+    """At the benchmark's size (N_v = 432, 72^3, 21,079 plane waves, 8-vector
+    blocks) with the library's own ground state, in a mixed context (whole
+    FP32 cache, a partial FP64 cache beside it, the rest rebuilt): the
+    operator is symmetric, maps occupied directions to zero, and the FP32 and
+    FP64 applies agree to the FP32 bound.  These are properties of the
+    library alone; the element-wise comparison with the oracle at this size,
+    in the bench's own FP64 launch, is in test_gpu_fullsize.py."""
     print("[gpu] full-size C2 properties", flush=True)
     cfg = synth.get_config("c2")
     n_pw = bsex.basis_size(cfg.cell, cfg.grid, cfg.ecut)
