@@ -288,6 +288,30 @@ typedef struct {
 int bse_davidson(bse_ctx *ctx, int32_t n_states, const bse_solver_opts *opts,
                  double *omega_host, double *X_dev, bse_solver_stats *stats);
 
+/* Beyond the Tamm-Dancoff approximation (SM Sec. I, the coupled form with
+ * the A_s and B_s blocks; the paper itself works in the TDA).  For real
+ * Gamma-point orbitals the coupling operators are
+ *   (K2e A)_v = P_c [v_c * sum_v' a_v' phi_v'] phi_v,
+ *   (K2d A)_v = P_c sum_v' [W (a_v' phi_v)] phi_v',
+ * and bse_apply_coupling returns Y = P_c (s K2e - K2d) P_c X (FP64, the
+ * canonical frame, every kernel term switched by kernel_mask like bse_apply;
+ * about N_v^2 Poisson and PDEP solves per vector).  X_dev, Y_dev: device
+ * [n_b][n_val][n_pw], not overlapping.  EINVAL with ks_model 1. */
+int bse_apply_coupling(bse_ctx *ctx, int32_t n_b, const double *X_dev, double *Y_dev);
+
+/* Lowest n_states roots of [[A, B], [B, A]] (X; Y) = omega (X; -Y),
+ * A = P_c M P_c (Eq. 1), B the coupling above, by the subspace method of
+ * Stratmann, Scuseria and Frisch on (A - B)(A + B) in FP64 (the paper gives
+ * no solver for this form).  Converged when ||r+||^2 + ||r-||^2 <= tol^2 with
+ * r+ = (A + B)(X + Y) - omega (X - Y), r- = (A - B)(X - Y) - omega (X + Y)
+ * and X.X - Y.Y = 1.  omega_host [n_states]; X_dev, Y_dev
+ * [n_states][n_val][n_pw] (either may be NULL); stats may be NULL (applies
+ * counts each vector once; each costs one A and one B apply).  EINVAL when
+ * A - B or A + B is not positive definite on the subspace (an unstable
+ * ground state); ENOCONV after max_iter with the last roots in the outputs. */
+int bse_full_bse(bse_ctx *ctx, int32_t n_states, const bse_solver_opts *opts,
+                 double *omega_host, double *X_dev, double *Y_dev, bse_solver_stats *stats);
+
 /* U vector of SM Sec. I for one normalised exciton A (Xs_dev [n_val][n_pw]):
  *   u_v = P_c[ s (v_c*Drho) a_v - sum_v' W(a_v' a_v) phi_v' ] - sum_v' S_vv' a_v'
  *   S_vv' = <phi_v | [(s K1e - K1d) A]_v'>   (kernel part before P_c).

@@ -24,7 +24,7 @@ TAU_AUTO, TAU_CACHE, TAU_REBUILD = 0, 1, 2
 
 SYMBOLS = ("bse_abi_version", "bse_last_error", "bse_warm_up", "bse_basis_size", "bse_basis_gvectors",
            "bse_init_system", "bse_get_info", "bse_get_orbitals", "bse_get_frame", "bse_apply",
-           "bse_davidson", "bse_u_vector", "bse_zvector_solve", "bse_forces", "bse_forces_noalloc",
+           "bse_davidson", "bse_apply_coupling", "bse_full_bse", "bse_u_vector", "bse_zvector_solve", "bse_forces", "bse_forces_noalloc",
            "bse_ground_state_forces",
            "bse_set_precision", "bse_set_profiling", "bse_get_phase_times",
            "bse_mlp_create", "bse_mlp_n_params", "bse_mlp_set_params", "bse_mlp_get_params",
@@ -130,6 +130,9 @@ def lib():
     L.bse_davidson.argtypes = [C.c_void_p, C.c_int32, C.POINTER(SolverOpts), dp, C.c_void_p,
                                C.POINTER(SolverStats)]
     L.bse_u_vector.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.bse_apply_coupling.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+    L.bse_full_bse.argtypes = [C.c_void_p, C.c_int32, C.POINTER(SolverOpts), dp, C.c_void_p,
+                               C.c_void_p, C.POINTER(SolverStats)]
     L.bse_zvector_solve.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(SolverOpts), C.c_void_p,
                                     C.POINTER(SolverStats)]
     L.bse_forces.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp]
@@ -405,6 +408,29 @@ def davidson(ctx, n_states=1, *, tol=1e-8, max_iter=0, block=0, max_subspace=0, 
     if check:
         _check(rc)
     return w, X, dict(_stats(s), rc=rc)
+
+
+def apply_coupling(ctx, X, Y=None):
+    """bse_apply_coupling: Y = P_c (s K2e - K2d) P_c X (beyond the TDA)."""
+    import torch
+    Y = torch.empty_like(X) if Y is None else Y
+    nb = X.shape[0] if X.dim() == 3 else 1
+    _check(lib().bse_apply_coupling(ctx.h, nb, _dev(X, "X"), _dev(Y, "Y")))
+    return Y
+
+
+def full_bse(ctx, n_states=1, *, tol=1e-8, max_iter=0, block=0, max_subspace=0):
+    """bse_full_bse: lowest roots beyond the TDA; returns (omega, X, Y, stats)."""
+    import torch
+    info = get_info(ctx)
+    X = torch.empty((n_states, info["n_val"], info["n_pw"]), dtype=torch.float64, device="cuda")
+    Y = torch.empty_like(X)
+    om = np.zeros(n_states)
+    o = _opts(tol=tol, max_iter=max_iter, block=block, max_subspace=max_subspace)
+    s = SolverStats()
+    _check(lib().bse_full_bse(ctx.h, n_states, C.byref(o), _dptr(om), _dev(X, "X"), _dev(Y, "Y"),
+                              C.byref(s)))
+    return om, X, Y, _stats(s)
 
 
 def u_vector(ctx, Xs):

@@ -627,6 +627,30 @@ int bse_davidson(bse_ctx* c, int32_t n_states, const bse_solver_opts* opts, doub
   return guarded(c, [&] { return davidson(c, n_states, opts, omega_host, X_dev, stats); });
 }
 
+int bse_apply_coupling(bse_ctx* c, int32_t n_b, const double* X_dev, double* Y_dev) {
+  if (!c) return fail(BSE_EINVAL, "ctx is NULL");
+  if (n_b < 0) return fail(BSE_EINVAL, "n_b < 0");
+  if (n_b == 0) return BSE_OK;
+  if (!X_dev || !Y_dev) return fail(BSE_EINVAL, "NULL argument");
+  if (c->ks) return fail(BSE_EINVAL, "the coupling beyond the TDA needs ks_model 0");
+  return guarded(c, [&]() -> int {
+    BSE_TRY(ensure_apply_work(c, std::min(n_b, 8)));
+    BSE_TRY(apply_coupling(c, n_b, X_dev, Y_dev));
+    BSE_HIP(hipStreamSynchronize(c->st));
+    return BSE_OK;
+  });
+}
+
+int bse_full_bse(bse_ctx* c, int32_t n_states, const bse_solver_opts* opts, double* omega_host,
+                 double* X_dev, double* Y_dev, bse_solver_stats* stats) {
+  if (!c || !omega_host) return fail(BSE_EINVAL, "NULL argument");
+  if (n_states < 1 || n_states > 16) return fail(BSE_EINVAL, "n_states must be 1..16");
+  if (opts && opts->block > 0 && opts->block < n_states)
+    return fail(BSE_EINVAL, "block below n_states");
+  if (c->ks) return fail(BSE_EINVAL, "the coupling beyond the TDA needs ks_model 0");
+  return guarded(c, [&] { return full_bse(c, n_states, opts, omega_host, X_dev, Y_dev, stats); });
+}
+
 int bse_u_vector(bse_ctx* c, const double* Xs, double* U) {
   if (!c || !Xs || !U) return fail(BSE_EINVAL, "NULL argument");
   return guarded(c, [&] { return u_vector(c, Xs, U); });

@@ -42,6 +42,9 @@ struct bse_ctx {
   double* rho_ks = nullptr;   // [nr] ground-state density 2 sum phi^2
   double alpha = 0.0;         // exact-exchange fraction alpha_EXX of H_KS
   double2* xpair = nullptr;   // [nvh][nr] pair grids of the exchange terms
+  // PDEP work of the exchange form of W (coupling beyond the TDA):
+  // sphere coefficients [nv][npw], PDEP projections [nv][npdep], result [nv][npw]
+  double *wx_RS = nullptr, *wx_T = nullptr, *wx_F = nullptr;
   double2* xgrid = nullptr;   // [xgrid_sets][nvh][nr] -alpha K_x a of an apply block
   int xgrid_sets = 0;
   double t_gs_ms = 0, t_tau_ms = 0, t_tau_alloc_ms = 0, t_init_ms = 0;  // init stages, wall
@@ -212,6 +215,11 @@ int noalloc_setup(int dev);
 // Wannier frame and kept blocks of a context built with localize = 1
 int localize(bse_ctx* c, const bse_system_desc* d);
 int rotate_bands(bse_ctx* c, int nb, const double* A, double* out, bool back);
+// beyond the TDA: Y = P_c (s K2e - K2d) P_c X (FP64), and the lowest roots of
+// the coupled problem
+int apply_coupling(bse_ctx* c, int nb, const double* X, double* Y);
+int full_bse(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double* Xout,
+             double* Yout, bse_solver_stats* stats);
 int diag_axpy(const double* A, const double* Tk, const double* eps, double shift, int nv,
               long npw, int nb, double* Y, hipStream_t st);
 long noalloc_scratch_doubles();

@@ -382,6 +382,78 @@ static int finish_apply(bse_ctx* c, int nb, const double* A, int with_v, double*
   return proj_c(c, c->Zs, Y, nb);
 }
 
+// out_v += scale sum_w L_w [W (M_w x_v)] for the nx real grid functions x_v
+// (packed like out): the exchange form of W, the bare Coulomb part and, by
+// the kernel mask, the PDEP part of Eq. 3 (two GEMMs on the sphere
+// coefficients of the nv pair densities of each v).
+static int w_exchange_like(bse_ctx* c, const double2* L, const double2* M, const double2* x,
+                           int nx, double2* out, double scale) {
+  const long nr = c->basis.nr, npw = c->basis.npw;
+  const int nv = c->nv;
+  const bool bare = (c->kmask & BSE_K_1D_BARE) != 0;
+  const bool pdep = (c->kmask & BSE_K_1D_PDEP) && c->npdep > 0;
+  if (!c->xpair) BSE_TRY(ctx_alloc_t(c, &c->xpair, (size_t)c->nvh * nr));
+  if (pdep && !c->wx_RS) {
+    BSE_TRY(ctx_alloc_t(c, &c->wx_RS, (size_t)nv * npw));
+    BSE_TRY(ctx_alloc_t(c, &c->wx_T, (size_t)nv * c->npdep));
+    BSE_TRY(ctx_alloc_t(c, &c->wx_F, (size_t)nv * npw));
+  }
+  double2* P = c->xpair;
+  SphereMap m = c->map;
+  for (int v = 0; v < nx; ++v) {
+    BSE_TRY(pair_times(M, nv, x + (long)(v >> 1) * nr, v & 1, nr, P, c->st));
+    BSE_TRY(fft3d(c->fft, P, c->nvh, -1, c->st));
+    if (pdep) {
+      BSE_TRY(gather_sets(m, P, nv, 1, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0, 0.0,
+                          c->wx_RS, c->st));
+      BSE_TRY(gemm(c, 0, 0, nv, c->npdep, npw, 1.0, c->wx_RS, npw, c->Pt, c->npdep, 0.0,
+                   c->wx_T, c->npdep));
+      BSE_TRY(dgemm(0, 1, nv, npw, c->npdep, 1.0, c->wx_T, c->npdep, c->Ptc, c->npdep, 0.0,
+                    c->wx_F, npw, c->st));
+    }
+    if (bare)
+      BSE_TRY(mul_real_field(P, c->nvh, nr, c->vc, 1.0 / (double)nr, c->st));
+    else
+      BSE_TRY(zero_fill(reinterpret_cast<double*>(P), 2L * c->nvh * nr, c->st));
+    if (pdep) BSE_TRY(scatter_sets(m, c->wx_F, nv, 1, P, 1, c->st));
+    BSE_TRY(fft3d(c->fft, P, c->nvh, +1, c->st));
+    BSE_TRY(contract_pairs(L, P, nv, nr, out + (long)(v >> 1) * nr, v & 1, scale, c->st));
+  }
+  return BSE_OK;
+}
+
+// Coupling beyond the TDA (SM Sec. I), real orbitals:
+//   Y = P_c (s K2e - K2d) P_c X,  (K2e A)_v = P_c [v_c * sum a_v' phi_v'] phi_v,
+//   (K2d A)_v = P_c sum_v' [W (a_v' phi_v)] phi_v',
+// in FP64 and in the canonical frame, chunks of at most c->nbc vectors.
+int apply_coupling(bse_ctx* c, int nb, const double* X, double* Y) {
+  const long nr = c->basis.nr, L = (long)c->nv * c->basis.npw, gs = (long)c->nvh * nr;
+  BSE_TRY(ensure_ygrid(c));
+  for (int i0 = 0; i0 < nb; i0 += c->nbc) {
+    const int k = std::min(c->nbc, nb - i0);
+    BSE_TRY(proj_c(c, X + i0 * L, c->A_s, k));
+    BSE_TRY(to_grid(c, c->A_s, c->nv, k, c->agrid));
+    double2* z = c->ygrid;
+    if (c->kmask & BSE_K_1E) {
+      const long nbh = (k + 1) / 2;
+      BSE_TRY(transition_density(c->phir, c->agrid, c->nv, k, nr, c->drho, c->st));
+      BSE_TRY(fft3d(c->fft, c->drho, nbh, -1, c->st));
+      BSE_TRY(mul_real_field(c->drho, nbh, nr, c->vc, 1.0 / (double)nr, c->st));
+      BSE_TRY(fft3d(c->fft, c->drho, nbh, +1, c->st));
+      BSE_TRY(combine(c->agrid, c->phir, c->Vr, c->drho, nullptr, z, c->nv, k, nr, c->spin, 0,
+                      c->st));
+    } else {
+      BSE_TRY(zero_fill(reinterpret_cast<double*>(z), 2 * k * gs, c->st));
+    }
+    if (c->kmask & (BSE_K_1D_BARE | BSE_K_1D_PDEP))
+      for (int b = 0; b < k; ++b)
+        BSE_TRY(w_exchange_like(c, c->phir, c->agrid + b * gs, c->phir, c->nv, z + b * gs, -1.0));
+    BSE_TRY(from_grid(c, z, c->nv, k, nullptr, nullptr, 0.0, c->Zs));
+    BSE_TRY(proj_c(c, c->Zs, Y + i0 * L, k));
+  }
+  return BSE_OK;
+}
+
 // Y = P_c (D + s K1e - K1d) P_c X for nb <= c->nbc vectors; in a localised
 // frame the grid part runs on A~ = U^T A with the localised orbitals
 int apply_chunk(bse_ctx* c, int nb, const double* X, double* Y) {

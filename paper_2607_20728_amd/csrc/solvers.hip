@@ -492,6 +492,248 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
   return BSE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Beyond the TDA (SM Sec. I): lowest roots of
+//   [[A, B], [B, A]] (X; Y) = omega (X; -Y),  A = D + s K1e - K1d,
+//   B = s K2e - K2d,
+// i.e. of (A - B)(A + B) on X + Y, by the subspace method of Stratmann,
+// Scuseria and Frisch (J. Chem. Phys. 109, 8218 (1998)); the paper gives
+// no solver for this form.  With an orthonormal basis b of the P_c space,
+// P = b^T (A + B) b and Q = b^T (A - B) b, Q = L L^T: L^T P L u = omega^2 u,
+// X + Y = b L u, X - Y = b P L u / omega, scaled to X.X - Y.Y = 1.  The
+// residuals r+ = (A + B)(X + Y) - omega (X - Y) and
+// r- = (A - B)(X - Y) - omega (X + Y) of each unconverged root, through the
+// kinetic preconditioner at theta = omega, extend the basis; the basis
+// restarts from the current X + Y and X - Y when full.  FP64 throughout.
+// ---------------------------------------------------------------------------
+int full_bse(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double* Xout,
+             double* Yout, bse_solver_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
+  const int maxit = (o && o->max_iter > 0) ? o->max_iter : 300;
+  int nb = (o && o->block > 0) ? o->block : ns + 4;
+  if (nb < ns) nb = ns;
+  int maxsub = (o && o->max_subspace > 0) ? o->max_subspace : 12 * nb;
+  if (maxsub < 4 * nb) maxsub = 4 * nb;
+  const long npw = c->basis.npw, nv = c->nv, L = nv * npw;
+  const int keep_active = c->active;
+  c->active = BSE_FP64;
+  struct Back {
+    bse_ctx* c;
+    int a;
+    ~Back() { c->active = a; }
+  } back{c, keep_active};
+  BSE_TRY(ensure_apply_work(c, std::min(2 * nb, 8)));
+  DVec V(c), ApB(c), AmB(c), W(c), AW(c), BW(c), Xp(c), Xm(c), sm(c);
+  BSE_TRY(V.alloc((size_t)maxsub * L));
+  BSE_TRY(ApB.alloc((size_t)maxsub * L));
+  BSE_TRY(AmB.alloc((size_t)maxsub * L));
+  BSE_TRY(W.alloc((size_t)2 * nb * L));
+  BSE_TRY(AW.alloc((size_t)2 * nb * L));
+  BSE_TRY(BW.alloc((size_t)2 * nb * L));
+  BSE_TRY(Xp.alloc((size_t)nb * L));
+  BSE_TRY(Xm.alloc((size_t)nb * L));
+  BSE_TRY(sm.alloc(2 * (size_t)maxsub * maxsub + 8 * (size_t)maxsub + 64));
+  double* Cd = sm.p;                                   // coefficient matrices
+  double* vecd = sm.p + 2 * (size_t)maxsub * maxsub;  // small vectors
+  int applies = 0;
+  // initial block: the lowest bare transitions (conduction states held),
+  // then plane waves of lowest kinetic model
+  BSE_HIP(hipMemsetAsync(W.p, 0, sizeof(double) * (size_t)nb * L, c->st));
+  int k = 0;
+  const int nc = c->norb - c->nv;
+  if (nc > 0) {
+    std::vector<std::pair<double, long>> tr;
+    for (long v = 0; v < nv; ++v)
+      for (long cc = 0; cc < nc; ++cc) tr.push_back({c->eps_h[nv + cc] - c->eps_h[v], v * nc + cc});
+    std::stable_sort(tr.begin(), tr.end(),
+                     [](const auto& a, const auto& b) { return a.first < b.first; });
+    for (size_t q = 0; q < tr.size() && k < nb; ++q, ++k) {
+      const long v = tr[q].second / nc, cc = tr[q].second % nc;
+      BSE_TRY(copy_dev(c, c->Phi + (nv + cc) * npw, W.p + (size_t)k * L + v * npw, npw));
+    }
+  }
+  if (k < nb) {
+    std::vector<std::pair<double, long>> d;
+    for (long v = 0; v < nv; ++v)
+      for (long j = 0; j < npw; ++j)
+        d.push_back({0.5 * c->basis.g2[j] - c->eps_h[v], v * npw + j});
+    std::stable_sort(d.begin(), d.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    size_t q = 0;
+    std::vector<double> one(1, 1.0), nrm;
+    while (k < nb && q < d.size()) {
+      double* w = W.p + (size_t)k * L;
+      BSE_HIP(hipMemsetAsync(w, 0, sizeof(double) * L, c->st));
+      BSE_TRY(to_dev(c, one, w + d[q].second, 1));
+      ++q;
+      BSE_TRY(proj_c(c, w, w, 1));
+      BSE_TRY(dots_host(c, w, w, 1, L, vecd, nrm));
+      if (std::sqrt(nrm[0]) > 0.3) ++k;
+    }
+  }
+  BSE_TRY(proj_c(c, W.p, W.p, k));
+  int m = 0;
+  // orthonormalise kn new rows of W against the basis, apply A and B, append
+  auto extend = [&](int kn) -> int {
+    const int kk = orth_block(c, V.p, m, W.p, kn, L, AW.p, 2, 1e-8);
+    if (kk < 0) return -kk;
+    if (kk == 0) return BSE_OK;
+    BSE_TRY(apply_n(c, kk, W.p, AW.p, true));
+    BSE_TRY(apply_coupling(c, kk, W.p, BW.p));
+    applies += kk;
+    BSE_TRY(copy_dev(c, W.p, V.p + (size_t)m * L, (size_t)kk * L));
+    BSE_TRY(copy_dev(c, AW.p, ApB.p + (size_t)m * L, (size_t)kk * L));
+    BSE_TRY(axpby(1.0, BW.p, 1.0, ApB.p + (size_t)m * L, (long)kk * L, c->st));
+    BSE_TRY(copy_dev(c, AW.p, AmB.p + (size_t)m * L, (size_t)kk * L));
+    BSE_TRY(axpby(-1.0, BW.p, 1.0, AmB.p + (size_t)m * L, (long)kk * L, c->st));
+    m += kk;
+    return BSE_OK;
+  };
+  BSE_TRY(extend(k));
+  if (m == 0) return fail(BSE_EINVAL, "full BSE: empty initial block");
+  std::vector<double> om(ns, NAN), rn(nb, 0.0);
+  int it = 0;
+  bool conv = false;
+  for (it = 0; it < maxit; ++it) {
+    std::vector<double> Ph((size_t)m * m), Qh((size_t)m * m);
+    BSE_TRY(gram_tall(c, V.p, m, ApB.p, m, L, Cd));
+    BSE_TRY(to_host(c, Cd, Ph, Ph.size()));
+    BSE_TRY(gram_tall(c, V.p, m, AmB.p, m, L, Cd));
+    BSE_TRY(to_host(c, Cd, Qh, Qh.size()));
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < i; ++j) {
+        const double a = 0.5 * (Ph[(size_t)i * m + j] + Ph[(size_t)j * m + i]);
+        const double b = 0.5 * (Qh[(size_t)i * m + j] + Qh[(size_t)j * m + i]);
+        Ph[(size_t)i * m + j] = Ph[(size_t)j * m + i] = a;
+        Qh[(size_t)i * m + j] = Qh[(size_t)j * m + i] = b;
+      }
+    // Q = L L^T (lower, row-major), then K = L^T P L
+    std::vector<double> Lq = Qh;
+    if (host_cholesky(m, Lq.data()))
+      return fail(BSE_EINVAL, "full BSE: A - B is not positive definite on the subspace");
+    for (int i = 0; i < m; ++i)
+      for (int j = i + 1; j < m; ++j) Lq[(size_t)i * m + j] = 0.0;
+    std::vector<double> PL((size_t)m * m, 0.0), K((size_t)m * m, 0.0), lam(m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        double t = 0.0;
+        for (int q = j; q < m; ++q) t += Ph[(size_t)i * m + q] * Lq[(size_t)q * m + j];
+        PL[(size_t)i * m + j] = t;
+      }
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        double t = 0.0;
+        for (int q = i; q < m; ++q) t += Lq[(size_t)q * m + i] * PL[(size_t)q * m + j];
+        K[(size_t)i * m + j] = t;
+      }
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < i; ++j)
+        K[(size_t)i * m + j] = K[(size_t)j * m + i] = 0.5 * (K[(size_t)i * m + j] + K[(size_t)j * m + i]);
+    if (host_syev(m, K.data(), lam.data())) return fail(BSE_EINVAL, "full BSE: small eigensolver failed");
+    const int kr = std::min(nb, m);
+    // c+ = L u, c- = P c+ / omega, scaled to c+ . c- = 1; layout [m][kr]
+    std::vector<double> cp((size_t)m * kr), cm((size_t)m * kr), w(kr);
+    for (int j = 0; j < kr; ++j) {
+      if (!(lam[j] > 0)) return fail(BSE_EINVAL, "full BSE: A + B is not positive definite");
+      w[j] = std::sqrt(lam[j]);
+    }
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < kr; ++j) {
+        double t = 0.0;
+        for (int q = 0; q <= i; ++q) t += Lq[(size_t)i * m + q] * K[(size_t)q * m + j];
+        cp[(size_t)i * kr + j] = t;
+      }
+    for (int j = 0; j < kr; ++j) {
+      double dot = 0.0;
+      for (int i = 0; i < m; ++i) {
+        double t = 0.0;
+        for (int q = 0; q < m; ++q) t += Ph[(size_t)i * m + q] * cp[(size_t)q * kr + j];
+        cm[(size_t)i * kr + j] = t / w[j];
+        dot += cp[(size_t)i * kr + j] * cm[(size_t)i * kr + j];
+      }
+      const double sc = 1.0 / std::sqrt(dot);
+      for (int i = 0; i < m; ++i) {
+        cp[(size_t)i * kr + j] *= sc;
+        cm[(size_t)i * kr + j] *= sc;
+      }
+    }
+    double* Cp = Cd;
+    double* Cm = Cd + (size_t)m * kr;
+    BSE_TRY(to_dev(c, cp, Cp, cp.size()));
+    BSE_TRY(to_dev(c, cm, Cm, cm.size()));
+    {
+      PhaseScope ps(c, PH_SOLVER);
+      BSE_TRY(dgemm(1, 0, kr, L, m, 1.0, Cp, kr, V.p, L, 0.0, Xp.p, L, c->st));    // X + Y
+      BSE_TRY(dgemm(1, 0, kr, L, m, 1.0, Cm, kr, V.p, L, 0.0, Xm.p, L, c->st));    // X - Y
+      // r+ into W[0..kr), r- into W[kr..2 kr)
+      BSE_TRY(dgemm(1, 0, kr, L, m, 1.0, Cp, kr, ApB.p, L, 0.0, W.p, L, c->st));
+      BSE_TRY(dgemm(1, 0, kr, L, m, 1.0, Cm, kr, AmB.p, L, 0.0, W.p + (size_t)kr * L, L, c->st));
+    }
+    std::vector<double> negw(2 * kr);
+    for (int j = 0; j < kr; ++j) negw[j] = negw[kr + j] = -w[j];
+    BSE_TRY(to_dev(c, negw, vecd, 2 * kr));
+    BSE_TRY(row_axpby(vecd, Xm.p, nullptr, W.p, kr, L, c->st));
+    BSE_TRY(row_axpby(vecd + kr, Xp.p, nullptr, W.p + (size_t)kr * L, kr, L, c->st));
+    std::vector<double> r2;
+    BSE_TRY(dots_host(c, W.p, W.p, 2 * kr, L, vecd + 2 * maxsub, r2));
+    for (int j = 0; j < kr; ++j) rn[j] = std::sqrt(std::max(0.0, r2[j] + r2[kr + j]));
+    for (int i = 0; i < ns && i < kr; ++i) om[i] = w[i];
+    bool all = m >= ns;
+    for (int i = 0; i < ns && i < kr; ++i) all = all && rn[i] <= tol;
+    if (all) {
+      conv = true;
+      break;
+    }
+    // preconditioned residuals of the unconverged roots (both r+ and r-)
+    std::vector<int> todo;
+    for (int j = 0; j < kr; ++j)
+      if (rn[j] > tol) {
+        todo.push_back(j);
+        todo.push_back(kr + j);
+      }
+    const int nt = (int)todo.size();
+    for (int q = 0; q < nt; ++q)
+      if (todo[q] != q) BSE_TRY(copy_dev(c, W.p + (size_t)todo[q] * L, W.p + (size_t)q * L, L));
+    std::vector<double> th(nt);
+    for (int q = 0; q < nt; ++q) th[q] = w[todo[q] % kr];
+    BSE_TRY(to_dev(c, th, vecd, nt));
+    BSE_TRY(precond_davidson(W.p, W.p, c->T, c->eps_d, vecd, c->scissor + kPrecondShift, nt,
+                             (int)nv, (int)npw, c->st));
+    BSE_TRY(proj_c(c, W.p, W.p, nt));
+    if (m + nt > maxsub) {
+      // restart from the current X + Y and X - Y of the kr lowest roots
+      BSE_TRY(copy_dev(c, Xp.p, W.p, (size_t)kr * L));
+      BSE_TRY(copy_dev(c, Xm.p, W.p + (size_t)kr * L, (size_t)kr * L));
+      m = 0;
+      BSE_TRY(extend(2 * kr));
+      continue;
+    }
+    const int m0 = m;
+    BSE_TRY(extend(nt));
+    if (m == m0) break;
+  }
+  for (int i = 0; i < ns; ++i) omega[i] = om[i];
+  // X = (X+Y + X-Y)/2, Y = (X+Y - X-Y)/2
+  if (Xout) {
+    BSE_TRY(copy_dev(c, Xp.p, Xout, (size_t)ns * L));
+    BSE_TRY(axpby(0.5, Xm.p, 0.5, Xout, (long)ns * L, c->st));
+  }
+  if (Yout) {
+    BSE_TRY(copy_dev(c, Xp.p, Yout, (size_t)ns * L));
+    BSE_TRY(axpby(-0.5, Xm.p, 0.5, Yout, (long)ns * L, c->st));
+  }
+  BSE_HIP(hipStreamSynchronize(c->st));
+  if (stats) {
+    stats->iters = it;
+    stats->applies = applies;
+    stats->applies_fp64 = applies;
+    for (int i = 0; i < 16; ++i) stats->resid[i] = i < nb ? rn[i] : 0.0;
+    stats->t_ms = elapsed_ms(t0);
+  }
+  if (!conv) return fail(BSE_ENOCONV, "full BSE: no convergence in %d iterations", it);
+  return BSE_OK;
+}
+
 // Davidson on the operator of the context's precision.  In mixed precision
 // the FP32-kernel operator drives the iteration; the Ritz vectors are then
 // checked with the FP64 operator (tau rebuilt in FP64) and, if the FP64
