@@ -76,10 +76,15 @@ def train(args):
     if not recs:
         sys.exit("no records found")
     t0 = time.perf_counter()
-    net, norm, losses = learned.train(recs, steps=args.steps, lr=args.lr, seed=args.seed)
+    net, norm, losses = learned.train(
+        recs, steps=args.steps, lr=args.lr, seed=args.seed, batch=args.batch,
+        log=lambda k, l: _log(step="train_progress", iteration=k, batch_loss=l,
+                              s=round(time.perf_counter() - t0, 1)))
     learned.save(args.out, net, norm)
     _log(step="train", geometries=len(recs), samples=2 * sum(len(r["gamma"]) for r in recs),
-         loss_first=losses[0], loss_last=losses[-1], train_s=round(time.perf_counter() - t0, 2))
+         batch=args.batch, loss_first=losses[0], loss_last=losses[-1],
+         loss_all_samples=learned.loss_of(net, norm, recs),
+         train_s=round(time.perf_counter() - t0, 2))
 
 
 MODES = {"diagonal": (False, False), "two-level": (True, False),
@@ -142,6 +147,7 @@ def main():
     t.add_argument("--steps", type=int, default=1500)
     t.add_argument("--lr", type=float, default=2e-3)
     t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--batch", type=int, default=4096, help="rows per Adam step (mini-batch)")
     e = sub.add_parser("gain")
     e.add_argument("--weights", required=True)
     e.add_argument("--first", type=int, default=17)

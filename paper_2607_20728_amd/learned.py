@@ -86,8 +86,11 @@ def norm_stats(x, t, w):
     return [np.asarray(a, np.float32) for a in (mu_x, s_x, mu_y, s_y)]
 
 
-def train(records, *, steps=1500, lr=2e-3, seed=0):
-    """Full-batch Adam on the library's BF16 kernels; returns (net, norm, losses)."""
+def train(records, *, steps=1500, lr=2e-3, seed=0, batch=4096, log=None):
+    """Adam on the library's BF16 kernels: full batches when the data has at
+    most `batch` rows, otherwise a fresh random mini-batch of `batch` rows
+    each step (the weight-gradient products then stay short).  log(k, loss)
+    is called every 250 steps.  Returns (net, norm, losses)."""
     import torch
     x, t, w = training_arrays(records)
     norm = norm_stats(x, t, w)
@@ -96,10 +99,29 @@ def train(records, *, steps=1500, lr=2e-3, seed=0):
     xd = torch.tensor(x, device="cuda")
     td = torch.tensor(t, device="cuda")
     wd = torch.tensor(w, device="cuda")
+    n = x.shape[0]
+    rng = np.random.default_rng(seed)
     losses = []
     for k in range(steps):
-        losses.append(net.train_step(xd, td, wd, lr=lr))
+        if n > batch:
+            idx = torch.tensor(rng.choice(n, batch, replace=False), device="cuda")
+            losses.append(net.train_step(xd[idx].contiguous(), td[idx].contiguous(),
+                                         wd[idx].contiguous(), lr=lr))
+        else:
+            losses.append(net.train_step(xd, td, wd, lr=lr))
+        if log and (k % 250 == 0 or k == steps - 1):
+            log(k, losses[-1])
     return net, norm, losses
+
+
+def loss_of(net, norm, records):
+    """Weighted mean squared error of the network on the records' samples
+    (standardised targets, the training loss)."""
+    import torch
+    x, t, w = training_arrays(records)
+    y = net.forward(torch.tensor(x, device="cuda")).cpu().numpy().astype(np.float64)
+    err = (y - t) / norm[3]
+    return float((w * err ** 2).sum() / max(w.sum(), 1.0))
 
 
 def save(path, net, norm):

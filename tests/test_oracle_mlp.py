@@ -61,3 +61,25 @@ def test_adam_first_step_is_signed_lr():
     p1, m, v = mlp.adam_step(p0, g, np.zeros(3), np.zeros(3), 1, 0.01)
     assert np.allclose(p1, p0 - 0.01 * g / (np.abs(g) + mlp.ADAM_EPS), rtol=0, atol=1e-15)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_committed_slab_network_loads_and_predicts():
+    """The committed slab network (paper_2607_20728_amd/data/slab_c5_learned.npz,
+    trained on 180 slab geometries): plain arrays only, the parameter count
+    of an 8-128-128-2 network, finite positive standardisation, and finite
+    predictions of moderate size for features drawn around the training
+    means with the training spread."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "..", "paper_2607_20728_amd", "data",
+                        "slab_c5_learned.npz")
+    d = np.load(path)                                  # allow_pickle stays False
+    assert set(d.files) == {"params", "mu_x", "s_x", "mu_y", "s_y"}
+    assert d["params"].size == mlp.n_params(8, 2)
+    for k in ("mu_x", "s_x", "mu_y", "s_y"):
+        assert np.all(np.isfinite(d[k]))
+    assert np.all(d["s_x"] > 0) and np.all(d["s_y"] > 0)
+    rng = np.random.default_rng(0)
+    x = d["mu_x"] + d["s_x"] * rng.standard_normal((256, 8))
+    y = mlp.forward(d["params"], x, 8, 2, (d["mu_x"], d["s_x"], d["mu_y"], d["s_y"]))
+    assert np.all(np.isfinite(y))
+    assert np.abs(np.median(y, 0)).max() < 10
