@@ -186,6 +186,68 @@ def copy_calibration(args):
                           launches=args.steps)), flush=True)
 
 
+def config_of(name):
+    """A named configuration, or system k of the uneven batch as "c4s<k>"."""
+    import synth
+    if name.startswith("c4s"):
+        return synth.c4_systems()[int(name[3:])]
+    return synth.get_config(name)
+
+
+def beyond_tda(args):
+    """Beyond the TDA on one system (default the defect supercell): the
+    coupling apply P_c (s K2e - K2d) P_c X timed on --nb vectors after one
+    warm-up, then (--full-bse) the lowest root of the coupled problem to
+    --tol, with the TDA root of the same context for comparison."""
+    import torch
+
+    import synth
+    from paper_2607_20728_amd import bsex
+
+    torch.cuda.set_device(0)
+    cfg = config_of(args.config)
+    n_pw = bsex.basis_size(cfg.cell, cfg.grid, cfg.ecut)
+    d = synth.make_system(cfg, n_pw, n_trial=args.nb, seed=args.seed)
+    ctx = bsex.init_from_synth(d, n_extra=args.n_extra, gs_tol=1e-10)
+    X = torch.tensor(d["trial"], dtype=torch.float64, device="cuda")
+    Y = torch.empty_like(X)
+    bsex.apply_coupling(ctx, X[:1], Y[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bsex.apply_coupling(ctx, X, Y)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"[coupling] {cfg.name}: {dt / args.nb:.4f} s per vector")
+    # the TDA apply of the same block, for scale
+    bsex.apply(ctx, X, Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bsex.apply(ctx, X, Y)
+    torch.cuda.synchronize()
+    dt_a = time.perf_counter() - t0
+    nv, nr = cfg.n_val, int(np.prod(cfg.grid))
+    out = dict(metric="coupling applies/s (beyond the TDA)", value=round(args.nb / dt, 4),
+               unit="applies/s", higher_is_better=True, dtype="f64", data="synthetic",
+               config=dict(workload=cfg.name, n_val=nv, n_pw=n_pw, grid=list(cfg.grid),
+                           n_pdep=cfg.n_pdep, n_b=args.nb),
+               s_per_vector=round(dt / args.nb, 5),
+               tda_s_per_vector=round(dt_a / args.nb, 6),
+               coupling_over_tda=round(dt / dt_a, 1),
+               w_pair_grids_per_vector=nv * nv)
+    if args.full_bse:
+        t1 = time.perf_counter()
+        w, Xf, Yf, st = bsex.full_bse(ctx, 1, tol=args.tol)
+        t2 = time.perf_counter()
+        wt, _, dst = bsex.davidson(ctx, 1, tol=args.tol)
+        t3 = time.perf_counter()
+        out["full_bse"] = dict(omega=float(w[0]), iters=st["iters"], vectors=st["applies"],
+                               s=round(t2 - t1, 2), resid=st["resid"][0],
+                               y_norm2=float((Yf[0] ** 2).sum()),
+                               tda_omega=float(wt[0]), tda_s=round(t3 - t2, 2))
+    ctx.free()
+    print(json.dumps(out), flush=True)
+
+
 def batch(args):
     """The uneven batch: the 32 systems of synth.c4_systems, lowest exciton and
     forces each, once one system at a time (one stream, no graphs, default
@@ -257,7 +319,7 @@ def time_to_force(args):
     t0 = time.perf_counter()
     prec = bsex.MIXED if args.precision == "mixed" else bsex.FP64
     ctx = bsex.init_from_synth(d, n_extra=args.n_extra, gs_tol=1e-10, gap_min=args.gap_min,
-                               precision=prec, **loc_kw(args))
+                               precision=prec, ks_model=args.ks_model, **loc_kw(args))
     net = None
     if args.learned:
         from paper_2607_20728_amd import learned
@@ -283,7 +345,8 @@ def time_to_force(args):
     log(f"[ttf] U + Z {t3 - t2:.1f} s, {zs['iters']} iters, resid {zs['resid'][0]:.2e}")
     F = bsex.forces(ctx, X[0], Z, len(d["site_depth"]))
     t4 = time.perf_counter()
-    mode = args.precision + ("+learned" if use else "") + ("+two-level" if tl else "")
+    mode = (args.precision + ("+learned" if use else "") + ("+two-level" if tl else "")
+            + ("+ks" if args.ks_model else ""))
     out = dict(metric=f"time-to-force @{args.tol:g} resid ({mode})",
                value=round(t4 - t0, 2), unit="s", higher_is_better=False,
                dtype="f32+f64" if prec == bsex.MIXED else "f64", data="synthetic",
@@ -308,6 +371,8 @@ def time_to_force(args):
                max_abs_dwdR=float(np.abs(F).max()), sum_dwdR=list(map(float, F.sum(0))))
     if args.prune is not None:
         out["config"]["localized"] = dict(loc_info(info), threshold=args.prune)
+    if args.ks_model:
+        out["config"]["ks_model"] = dict(scf_iters=info["scf_iters"], alpha_exx=0.0)
     if args.forces_out:
         np.save(args.forces_out, F)
     ctx.free()
@@ -337,11 +402,17 @@ def main():
                          "kept when their pair measure reaches this threshold")
     ap.add_argument("--loc-sweeps", type=int, default=0, help="Jacobi sweep cap (0: library default)")
     ap.add_argument("--forces-out", default=None, help="--ttf: save d omega/d R here (.npy)")
+    ap.add_argument("--ks-model", type=int, default=0, choices=(0, 1),
+                    help="--ttf: 1 = self-consistent KS ground state, with its response "
+                         "kernels in U and the Z-vector equation (semilocal, no exact exchange)")
     ap.add_argument("--two-level", action="store_true",
                     help="two-level preconditioner on the conduction states held (--ttf)")
     ap.add_argument("--n-extra", type=int, default=8,
                     help="conduction states the ground-state solve computes (--ttf)")
     ap.add_argument("--batch", action="store_true", help="uneven batch run instead")
+    ap.add_argument("--coupling", action="store_true",
+                    help="beyond the TDA: time the coupling apply (and --full-bse the root)")
+    ap.add_argument("--full-bse", action="store_true", help="--coupling: also the coupled root")
     ap.add_argument("--batch-n", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="plain 2 GiB device copies, for scaling HBM counters")
@@ -361,6 +432,9 @@ def main():
         return
     if args.batch:
         batch(args)
+        return
+    if args.coupling:
+        beyond_tda(args)
         return
 
     import torch
@@ -451,6 +525,8 @@ def main():
                roofline=roofline, phases=phases)
     if args.prune is not None:
         out["config"]["localized"] = dict(loc_info(info), threshold=args.prune)
+    if args.ks_model:
+        out["config"]["ks_model"] = dict(scf_iters=info["scf_iters"], alpha_exx=0.0)
     ctx.free()
     del X, Y
     out["hbm_copy"] = copy_rate()

@@ -16,6 +16,12 @@
         planes along axis 1 that hold sphere modes; B = the stream's bytes
         per launch as bench.py reports them);
 
+    python -m paper_2607_20728_amd.profsummary busy <results.db> [after] [rows]
+        device-busy fraction of a --kernel-trace run: from the end of the last
+        launch whose name contains `after` (default: the first launch) to the
+        last launch, the union of kernel intervals against the window, the
+        gaps between kernels by size, and the kernels of the window by time;
+
     python -m paper_2607_20728_amd.profsummary counters <dir> [match]
         mean value per dispatch of every counter of a --pmc run
         (--output-format csv), per kernel whose name contains match;
@@ -58,6 +64,46 @@ def kernels(db, rows=30):
     for k, v in sorted(g.items(), key=lambda kv: -sum(kv[1]))[:rows]:
         print(f"{k[0]:34s} {k[1]:10d} {k[2]:6d} {len(v):6d} {sum(v) / len(v) / 1e3:10.1f} "
               f"{sum(v) / 1e6:9.1f} {100 * sum(v) / tot:5.1f}")
+
+
+def busy(db, after="", rows=20):
+    con = sqlite3.connect(db)
+    ks = con.execute("select name, start, end from kernels order by start").fetchall()
+    if not ks:
+        sys.exit("no kernels in the trace")
+    t0 = ks[0][1]
+    if after:
+        hits = [e for n, s, e in ks if after in n]
+        if not hits:
+            sys.exit(f"no launch matches {after!r}")
+        t0 = max(hits)
+    win = [(n, max(s, t0), e) for n, s, e in ks if e > t0]
+    t1 = max(e for _, _, e in win)
+    busy_ns, cur_s, cur_e = 0, None, None
+    gaps = []
+    for _, s, e in sorted(win, key=lambda r: r[1]):
+        if cur_e is None:
+            cur_s, cur_e = s, e
+        elif s > cur_e:
+            busy_ns += cur_e - cur_s
+            gaps.append(s - cur_e)
+            cur_s, cur_e = s, e
+        else:
+            cur_e = max(cur_e, e)
+    busy_ns += cur_e - cur_s
+    span = t1 - t0
+    print(f"window {span / 1e6:.1f} ms, kernels busy {busy_ns / 1e6:.1f} ms "
+          f"({100 * busy_ns / max(span, 1):.1f}%), {len(win)} launches")
+    edges = [(0, 10e3), (10e3, 100e3), (100e3, 1e6), (1e6, float("inf"))]
+    for lo, hi in edges:
+        g = [x for x in gaps if lo <= x < hi]
+        print(f"  gaps {lo / 1e3:g}-{hi / 1e3:g} us: {len(g):6d}, {sum(g) / 1e6:9.1f} ms")
+    g = collections.defaultdict(list)
+    for n, s, e in win:
+        g[_short(n)].append(e - s)
+    print(f"{'kernel':48s} {'calls':>7s} {'avg_us':>9s} {'tot_ms':>9s}")
+    for k, v in sorted(g.items(), key=lambda kv: -sum(kv[1]))[:rows]:
+        print(f"{k:48s} {len(v):7d} {sum(v) / len(v) / 1e3:9.1f} {sum(v) / 1e6:9.1f}")
 
 
 def last_apply(db):
@@ -229,6 +275,10 @@ def main():
         return
     if len(sys.argv) > 1 and sys.argv[1] == "counters":
         counters(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "busy":
+        busy(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "",
+             int(sys.argv[4]) if len(sys.argv) > 4 else 20)
         return
     if len(sys.argv) > 1 and sys.argv[1] == "kernels":
         kernels(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 30)

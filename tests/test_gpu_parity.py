@@ -263,3 +263,24 @@ def test_full_size_c2_properties():
     Yp = bsex.apply(ctx, phi.unsqueeze(0).contiguous())
     assert float(Yp.abs().max()) < 1e-12 * float(Yd.abs().max())
     ctx.free()
+
+
+def test_repeat_runs_agree_to_rounding():
+    """Repeatability.  The FP64 tau stream adds the transposed contributions
+    of a block row through LDS FP64 atomics, whose order varies from run to
+    run, so two applies of the same block agree to rounding (a few ulps of
+    the sums), not bitwise; every solver reduction is fixed-order, so two
+    Davidson runs from the same start agree to the same level."""
+    print("[gpu] repeat runs: c1", flush=True)
+    S, d = _oracle("c1")
+    ctx = _lib_ctx(S, d)
+    X = _cuda(d["trial"][:8])
+    Y1 = bsex.apply(ctx, X).cpu().numpy()
+    Y2 = bsex.apply(ctx, X).cpu().numpy()
+    e_apply = _rel(Y2, Y1)
+    w1, _, _ = bsex.davidson(ctx, 2, tol=1e-10)
+    w2, _, _ = bsex.davidson(ctx, 2, tol=1e-10)
+    e_w = np.abs(w1 - w2).max()
+    print(f"  apply {e_apply:.1e}  omega {e_w:.1e}", flush=True)
+    assert e_apply < 1e-14 and e_w < 1e-13
+    ctx.free()

@@ -24,11 +24,14 @@ pytestmark = pytest.mark.gpu
 
 from paper_2607_20728_amd import bsex  # noqa: E402
 
-# c1 (16 bands, two band blocks) and a 24-band system (three band blocks):
-# 12 random sites in a 12-bohr cube, 24^3 grid, 6 Ha cutoff
+# c1 (16 bands, two band blocks), a 24-band system (three band blocks: 12
+# random sites in a 12-bohr cube, 24^3 grid, 6 Ha cutoff) and a 13-band one
 CFGS = {"c1": synth.get_config("c1"),
         "w1": synth.Config("w1", (12.0, 12.0, 12.0), (24, 24, 24), 6.0, 24, 32, -0.8, 8.0,
-                           "uniform:12", seed=1400)}
+                           "uniform:12", seed=1400),
+        # an odd band count (the tournament's idle index) and a partial last block
+        "w2": synth.Config("w2", (11.0, 12.0, 13.0), (24, 24, 24), 6.0, 13, 24, -0.8, 6.0,
+                           "uniform:7", seed=1500)}
 SWEEPS = 30
 
 
@@ -82,7 +85,7 @@ def _ctx(o, **kw):
                                 prune_threshold=o["thr"], **kw)
 
 
-@pytest.mark.parametrize("name", ["c1", "w1"])
+@pytest.mark.parametrize("name", ["c1", "w1", "w2"])
 def test_pruned_model_with_the_oracle_frame(name):
     print(f"[gpu] pruned W integrals, oracle frame: {name}", flush=True)
     o = _oracle(name)
@@ -121,7 +124,7 @@ def test_pruned_model_mixed_context():
     ctx.free()
 
 
-@pytest.mark.parametrize("name", ["c1", "w1"])
+@pytest.mark.parametrize("name", ["c1", "w1", "w2"])
 def test_library_localisation_matches_the_oracle(name):
     print(f"[gpu] library localisation: {name}", flush=True)
     o = _oracle(name)

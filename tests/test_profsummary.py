@@ -75,3 +75,26 @@ def test_stage_rooflines(tmp_path):
     stream = lines["tau stream + combine"].split("|")
     assert stream[4].strip() == "6.00 TB/s" and stream[5].strip() == "0.75"
     assert out.startswith("2 applies")
+
+
+def test_busy_window(tmp_path):
+    """Busy time is the union of kernel intervals in the window after the
+    last launch of the named kernel; gaps are binned by size."""
+    db = str(tmp_path / "b_results.db")
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, start int, end int)")
+    rows = [("void k_tau_store<double>(int)", 0, 1_000),            # before the window
+            ("void k_tau_store<double>(int)", 2_000, 5_000),        # window opens at 5000
+            ("void k_a(int)", 5_000, 8_000),
+            ("void k_b(int)", 7_000, 9_000),                        # overlaps k_a
+            ("void k_a(int)", 9_005, 10_000),                       # 5 ns gap
+            ("void k_b(int)", 210_000, 220_000)]                    # 200 us gap
+    con.executemany("insert into kernels values (?,?,?)", rows)
+    con.commit()
+    con.close()
+    out = _run("busy", db, "k_tau_store").splitlines()
+    # window 5000..220000 = 215 us; busy 4000 + 995 + 10000 ns
+    assert out[0].startswith("window 0.2 ms, kernels busy 0.0 ms (7.0%), 4 launches")
+    assert out[1].split()[-3] == "1," and out[3].split()[-3] == "1,"
+    table = {line.split()[0]: line.split() for line in out[6:]}
+    assert table["k_a"][1] == "2" and table["k_b"][1] == "2"
