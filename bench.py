@@ -308,7 +308,7 @@ def time_to_force(args):
     from paper_2607_20728_amd import bsex
 
     torch.cuda.set_device(0)
-    cfg = synth.get_config(args.config)
+    cfg = config_of(args.config)
     n_pw = bsex.basis_size(cfg.cell, cfg.grid, cfg.ecut)
     d = synth.make_system(cfg, n_pw, seed=args.seed)
     # one-time process start-up (HIP runtime, the library's code objects) is

@@ -144,11 +144,11 @@ def stages(a):
     model = [
         ("inverse plane pass, sphere -> planes", r"k_sphere_inv_ct|k_fft_plane_ct<\d+, \d+, 1, 1, 0>",
          xb + G * a.planes * p2 * c),
-        ("inverse axis-1 pass", r"k_fft_axis_ct<\d+, 1>", G * nr * c * (a.planes / N1 + 1)),
+        ("inverse axis-1 pass", r"k_fft_axis_(ct|gd)<\d+, 1>", G * nr * c * (a.planes / N1 + 1)),
         ("transition density (K1e)", r"k_transition_density",
          (G + (a.nv + 1) // 2 + (a.nb + 1) // 2) * nr * c),
         ("tau stream + combine", r"k_tau_stream", a.stream_bytes),
-        ("forward axis-1 pass", r"k_fft_axis_ct<\d+, -1>", G * nr * c * (1 + a.planes / N1)),
+        ("forward axis-1 pass", r"k_fft_axis_(ct|gd)<\d+, -1>", G * nr * c * (1 + a.planes / N1)),
         ("forward plane pass, planes -> sphere", r"k_sphere_fwd_ct|k_sphere_fwd_whole|k_fft_plane_ct<\d+, \d+, -1, 0, 1>",
          G * a.planes * p2 * c + G * a.npw * c),
         ("gather + diagonal", r"k_gather", G * a.npw * c + 2 * xb),
