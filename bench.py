@@ -171,6 +171,26 @@ def copy_rate(n_bytes=4 << 30, reps=5):
                 frac_of_peak=round(2 * 8 * n / t / 1e9 / HBM_PEAK_GBS, 4))
 
 
+def read_rate(n_bytes=4 << 30, reps=5):
+    """Measured read rate of the device: torch's sum over n_bytes of float64
+    (a read-only stream, the practical ceiling of a kernel that mostly
+    reads)."""
+    import torch
+    x = torch.ones(n_bytes // 8, dtype=torch.float64, device="cuda")
+    x.sum()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        x.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del x
+    return dict(gbs=round(n_bytes / t / 1e9, 1), bytes_per_read=n_bytes,
+                frac_of_peak=round(n_bytes / t / 1e9 / HBM_PEAK_GBS, 4))
+
+
 def copy_calibration(args):
     """A plain device copy of known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters: each launch reads and writes 2 GiB."""
@@ -525,11 +545,11 @@ def main():
                roofline=roofline, phases=phases)
     if args.prune is not None:
         out["config"]["localized"] = dict(loc_info(info), threshold=args.prune)
-    if args.ks_model:
-        out["config"]["ks_model"] = dict(scf_iters=info["scf_iters"], alpha_exx=0.0)
     ctx.free()
     del X, Y
     out["hbm_copy"] = copy_rate()
+    out["hbm_read"] = read_rate()
+    out["roofline"]["frac_of_read"] = round(out["roofline"]["achieved"] / out["hbm_read"]["gbs"], 4)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(args.config, args.nb)

@@ -11,6 +11,27 @@
 
 namespace bsex {
 
+// ---- XCD grouping of workgroups ----------------------------------------------
+// Workgroup b of a launch runs on XCD b mod 8 (round-robin dispatch), and each
+// XCD has its own L2.  For a launch of nsub workgroups per item over items
+// rounded up to a multiple of 8 (round8), xcd_item maps b to (item, sub) so
+// that every workgroup of one item runs on the same XCD and the item's shared
+// inputs are fetched into one L2 only; a bijection of [0, nsub * round8(n)).
+// BSEX_XCD_GROUP=0 keeps the plain order (item = b / nsub).
+constexpr int kXcds = 8;
+inline long round8(long n) { return (n + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ void xcd_item(long b, int nsub, bool group, long& item, int& sub) {
+  if (!group) {
+    item = b / nsub;
+    sub = (int)(b % nsub);
+    return;
+  }
+  const long i = b / kXcds;
+  item = (i / nsub) * kXcds + (b % kXcds);
+  sub = (int)(i % nsub);
+}
+bool xcd_group_on();
+
 // ---- error reporting --------------------------------------------------------
 void set_error(const char* fmt, ...);
 int fail(int code, const char* fmt, ...);
@@ -68,6 +89,7 @@ struct FftPlan {
   bool ct_plane[2] = {false, false}, ct_axis[2] = {false, false};  // [FP64, FP32], in use
   bool ct_plane_ok[2] = {false, false}, ct_axis_ok[2] = {false, false};  // available
   bool prune[2] = {false, false};  // pruned sphere-plane kernels [FP64, FP32]
+  bool axis_direct[2] = {false, false};  // axis-1 pass with direct first/last pass
   FftAxis ax[3];
 };
 int fft_plan_init(FftPlan* p, const int grid[3]);

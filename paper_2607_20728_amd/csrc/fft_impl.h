@@ -190,6 +190,8 @@ struct PlaneArgs {
   cplx* compact;       // [grid][nent]
   int LB;                 // lines per scratch batch
   int m2, m3;             // the sphere's modes have |n2| <= m2 and |n3| <= m3
+  long batch;             // grids (pruned inverse kernel: workgroups beyond are idle)
+  int group;              // pruned inverse kernel: the planes of a grid on one XCD
 };
 
 template <int DIR, int IN, int OUT>
@@ -484,9 +486,11 @@ __device__ __forceinline__ void fn_passes(LD ld, ST st, cplx* S0, cplx* S1, int 
 
 __device__ __forceinline__ int min_img(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
 
-// lines per batch of the pruned kernels: two candidates per precision (the
-// launch takes the one that pads the line batches least within the LDS)
-constexpr int kSphereLB[2] = {sizeof(cplx) == 16 ? 16 : 32, sizeof(cplx) == 16 ? 18 : 36};
+// lines per batch of the pruned kernels: three candidates per precision for
+// the inverse pass, the first two for the forward pass (the launch scores
+// them, below)
+constexpr int kSphereLB[3] = {sizeof(cplx) == 16 ? 16 : 32, sizeof(cplx) == 16 ? 18 : 36,
+                              sizeof(cplx) == 16 ? 36 : 56};
 
 // LDS of the pruned kernels for sphere extents m2, m3 and batch LB
 template <int N2, int N3>
@@ -517,8 +521,12 @@ __global__ __launch_bounds__(kPlaneThreads) void k_sphere_inv_ct(cplx* data, Pla
   cplx* Q = lds;                       // [K2][N3]
   cplx* S0 = Q + K2 * N3;
   cplx* S1 = plane_nscratch<N2, N3>() == 2 ? S0 + NM * LB : S0;
-  const long g = blockIdx.x / pa.nplanes;
-  const int pl = (int)(blockIdx.x % pa.nplanes);
+  // the planes of one grid share its coefficient rows: with pa.group they
+  // run on one XCD and read those rows into one L2
+  long g;
+  int pl;
+  xcd_item(blockIdx.x, pa.nplanes, pa.group != 0, g, pl);
+  if (g >= pa.batch) return;
   const int i1 = pa.plane_i1[pl];
   cplx* gp = data + g * pa.nr + (long)i1 * (N2 * N3);
   for (int e = threadIdx.x; e < K2 * N3; e += NT) Q[e] = mk(0.0, 0.0);
@@ -698,6 +706,61 @@ __global__ __launch_bounds__(kThreads) void k_fft_axis_ct(cplx* __restrict__ dat
   }
 }
 
+// Axis pass with direct memory access: the first Stockham pass reads the
+// grid and the last writes it, so only the intermediate results pass through
+// LDS (one buffer for a two-pass length).  Lines per workgroup: the largest
+// power of two (at most 32) that gives every thread at most one butterfly of
+// the first pass.  In place is safe: every element of the tile is read in the
+// first pass, which a barrier separates from the last.  Lengths of one pass
+// keep the staged kernel.
+template <int N>
+constexpr int axis_gd_l() {
+  constexpr Fac F = factor(N);
+  int L = 32;
+  while (L > 4 && (N / F.r[0]) * L > kThreads) L /= 2;
+  return L;
+}
+template <int N>
+constexpr bool axis_gd_ok() {
+  return factor(N).n >= 2;
+}
+template <int N>
+constexpr size_t axis_gd_lds() {
+  return (factor(N).n >= 3 ? 2 : 1) * sizeof(cplx) * (size_t)N * axis_gd_l<N>();
+}
+
+template <int N, int DIR>
+__global__ __launch_bounds__(kThreads) void k_fft_axis_gd(cplx* __restrict__ data, AxisArgs ax,
+                                                          int es, int n_inner, long s_in, int n_o2,
+                                                          long s_o2, long s_o1, int ld_lim,
+                                                          int st_lim) {
+  constexpr int L = axis_gd_l<N>();
+  static_assert(factor(N).n >= 2, "");
+  extern __shared__ cplx lds[];
+  cplx* S0 = lds;
+  cplx* S1 = lds + N * L;
+  const int tiles = (n_inner + L - 1) / L;
+  long w = blockIdx.x;
+  const int tile = (int)(w % tiles);
+  w /= tiles;
+  const int o2 = (int)(w % n_o2);
+  const long o1 = w / n_o2;
+  const int i0 = tile * L;
+  const int nl = min(L, n_inner - i0);
+  cplx* base = data + o1 * s_o1 + (long)o2 * s_o2 + (long)i0 * s_in;
+  auto ld = [=](int k, int l) {
+    const int nk = (k < (N + 1) / 2) ? k : k - N;
+    cplx x = mk(0.0, 0.0);
+    if (abs(nk) <= ld_lim) x = base[(long)l * s_in + (long)k * es];
+    return x;
+  };
+  auto st = [=](int k, int l, cplx v) {
+    const int nk = (k < (N + 1) / 2) ? k : k - N;
+    if (abs(nk) <= st_lim) base[(long)l * s_in + (long)k * es] = v;
+  };
+  fn_passes<N, DIR, L, kThreads, 0, 1>(ld, st, S0, S1, nl, ax.tw);
+}
+
 int lines_per_group(int n) {
   // about 16 KB of LDS per buffer; at least 4 lines
   int L = 16384 / ((int)sizeof(cplx) * n);
@@ -744,6 +807,30 @@ size_t plane_ct_lds(int n2, int n3) {
   return 0;
 }
 
+bool axis_gd_supported(int n) {
+#define C(N) \
+  if (n == N) return axis_gd_ok<N>();
+  BSEX_AXIS_SIZES(C)
+#undef C
+  return false;
+}
+
+size_t axis_gd_lds_of(int n) {
+#define C(N) \
+  if (n == N) return axis_gd_lds<N>();
+  BSEX_AXIS_SIZES(C)
+#undef C
+  return 0;
+}
+
+int axis_gd_lines(int n) {
+#define C(N) \
+  if (n == N) return axis_gd_l<N>();
+  BSEX_AXIS_SIZES(C)
+#undef C
+  return 0;
+}
+
 size_t axis_ct_lds(int n) {
 #define C(N) \
   if (n == N) return 2 * sizeof(cplx) * (size_t)N * axis_l<N>();
@@ -775,6 +862,46 @@ void launch_axis_ct(int n, int dir, dim3 grid, size_t shm, hipStream_t st, cplx*
   }
   BSEX_AXIS_SIZES(C)
 #undef C
+}
+
+template <int N>
+bool launch_axis_gd_n(int n, int dir, dim3 grid, size_t shm, hipStream_t st, cplx* data,
+                      AxisArgs ax, int es, int n_inner, long s_in, int n_o2, long s_o2,
+                      long s_o1, int ld_lim, int st_lim) {
+  if constexpr (axis_gd_ok<N>()) {
+    if (n != N) return false;
+    if (dir < 0)
+      hipLaunchKernelGGL((k_fft_axis_gd<N, -1>), grid, dim3(kThreads), shm, st, data, ax, es,
+                         n_inner, s_in, n_o2, s_o2, s_o1, ld_lim, st_lim);
+    else
+      hipLaunchKernelGGL((k_fft_axis_gd<N, 1>), grid, dim3(kThreads), shm, st, data, ax, es,
+                         n_inner, s_in, n_o2, s_o2, s_o1, ld_lim, st_lim);
+    return true;
+  }
+  return false;
+}
+
+void launch_axis_gd(int n, int dir, dim3 grid, size_t shm, hipStream_t st, cplx* data,
+                    AxisArgs ax, int es, int n_inner, long s_in, int n_o2, long s_o2, long s_o1,
+                    int ld_lim, int st_lim) {
+#define C(N)                                                                               \
+  if (launch_axis_gd_n<N>(n, dir, grid, shm, st, data, ax, es, n_inner, s_in, n_o2, s_o2, \
+                          s_o1, ld_lim, st_lim))                                           \
+    return;
+  BSEX_AXIS_SIZES(C)
+#undef C
+}
+
+template <int N>
+int set_axis_gd_lds() {
+  if constexpr (axis_gd_ok<N>()) {
+    const int g = (int)axis_gd_lds<N>();
+    BSE_HIP(hipFuncSetAttribute((const void*)k_fft_axis_gd<N, -1>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, g));
+    BSE_HIP(hipFuncSetAttribute((const void*)k_fft_axis_gd<N, 1>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, g));
+  }
+  return BSE_OK;
 }
 
 template <int DIR, int IN, int OUT>
@@ -810,39 +937,58 @@ int set_ct_lds_limits(int n2, int n3, int n1) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, need));             \
     BSE_HIP(hipFuncSetAttribute((const void*)k_fft_axis_ct<N, 1>,                               \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, need));             \
+    BSE_TRY(set_axis_gd_lds<N>());                                                              \
   }
   BSEX_AXIS_SIZES(C)
 #undef C
   return BSE_OK;
 }
 
-// padded lines of the pruned kernel's batches: inverse K2 rows and N3
-// columns, forward N2 rows and K3 columns
+// padded lines of the pruned kernels' batches (same line counts as below)
 inline long sphere_padded(int nrow, int ncol, int lb) {
   return (long)((nrow + lb - 1) / lb + (ncol + lb - 1) / lb) * lb;
+}
+// rounds of butterflies (at most one per thread each) of the line
+// transforms of length n in batches of lb lines
+inline long pass_rounds(int n, int lb) {
+  const Fac f = factor(n);
+  long r = 0;
+  for (int p = 0; p < f.n; ++p) r += ((long)(n / f.r[p]) * lb + kPlaneThreads - 1) / kPlaneThreads;
+  return r;
+}
+// rounds of the pruned kernels: nrow row transforms of length lrow, then
+// ncol column transforms of length lcol (inverse: K2 rows of N3, N3 columns
+// of N2; forward: N2 rows of N3, K3 columns of N2)
+inline long sphere_rounds(int nrow, int lrow, int ncol, int lcol, int lb) {
+  return (long)((nrow + lb - 1) / lb) * pass_rounds(lrow, lb) +
+         (long)((ncol + lb - 1) / lb) * pass_rounds(lcol, lb);
 }
 
 // pruned sphere-plane launches: false when the size has no compiled kernel
 // or the LDS the extents need exceeds the device's
 bool launch_sphere_ct(int n2, int n3, bool inverse, int m, size_t max_lds, dim3 grid,
                       hipStream_t st, cplx* data, PlaneArgs pa, AxisArgs ay, AxisArgs az) {
-  // candidates: batch size k in {0, 1}, and for the forward pass the staged
-  // (w = 0) or whole-plane (w = 1) kernel; the score is the padded line
-  // count, doubled when two workgroups do not fit a CU; ties go to the
-  // whole-plane kernel
+  // inverse pass: batch size k in {0, 1, 2}, scored by the rounds of
+  // butterflies over the workgroup's threads (each ending at a barrier),
+  // tripled when two workgroups do not fit a CU.  Forward pass: batch size k
+  // in {0, 1} and the staged (w = 0) or whole-plane (w = 1) kernel, scored by
+  // the padded line count, doubled when two workgroups do not fit a CU (the
+  // choices measured fastest at the grids in use).  Ties go to the
+  // whole-plane kernel and the smaller batch.
 #define C(A, B)                                                                               \
   if (n2 == A && n3 == B) {                                                                   \
     int pick = -1, pw = 0;                                                                    \
     long best = 0;                                                                            \
     size_t shm = 0;                                                                           \
     for (int w = inverse ? 0 : 1; w >= 0; --w)                                                \
-      for (int k = 0; k < 2; ++k) {                                                           \
+      for (int k = 0; k < (inverse ? 3 : 2); ++k) {                                           \
         const int lb = kSphereLB[k];                                                          \
         const size_t need = inverse ? sphere_inv_lds<A, B>(m, lb)                             \
                             : w ? sphere_fwd_whole_lds<A, B>(lb) : sphere_fwd_lds<A, B>(m, lb); \
         if (need > max_lds) continue;                                                         \
-        const long pad = inverse ? sphere_padded(2 * m + 1, B, lb) : sphere_padded(A, 2 * m + 1, lb); \
-        const long score = pad * (need <= 81920 ? 1 : 2);                                     \
+        const long score = inverse                                                            \
+            ? sphere_rounds(2 * m + 1, B, B, A, lb) * (need <= 81920 ? 1 : 3)                 \
+            : sphere_padded(A, 2 * m + 1, lb) * (need <= 81920 ? 1 : 2);                      \
         if (pick < 0 || score < best) {                                                       \
           pick = k;                                                                           \
           pw = w;                                                                             \
@@ -855,8 +1001,11 @@ bool launch_sphere_ct(int n2, int n3, bool inverse, int m, size_t max_lds, dim3 
       if (pick == 0)                                                                          \
         hipLaunchKernelGGL((k_sphere_inv_ct<A, B, 1, kSphereLB[0]>), grid, dim3(kPlaneThreads), \
                            shm, st, data, pa, ay, az);                                        \
-      else                                                                                    \
+      else if (pick == 1)                                                                     \
         hipLaunchKernelGGL((k_sphere_inv_ct<A, B, 1, kSphereLB[1]>), grid, dim3(kPlaneThreads), \
+                           shm, st, data, pa, ay, az);                                        \
+      else                                                                                    \
+        hipLaunchKernelGGL((k_sphere_inv_ct<A, B, 1, kSphereLB[2]>), grid, dim3(kPlaneThreads), \
                            shm, st, data, pa, ay, az);                                        \
     } else if (pw) {                                                                          \
       if (pick == 0)                                                                          \
@@ -888,6 +1037,7 @@ int set_sphere_lds_limits(int n2, int n3, size_t max_lds) {
     const int lim = (int)max_lds;                                                             \
     const void* fns[] = {(const void*)k_sphere_inv_ct<A, B, 1, kSphereLB[0]>,                 \
                          (const void*)k_sphere_inv_ct<A, B, 1, kSphereLB[1]>,                 \
+                         (const void*)k_sphere_inv_ct<A, B, 1, kSphereLB[2]>,                 \
                          (const void*)k_sphere_fwd_ct<A, B, -1, kSphereLB[0]>,                \
                          (const void*)k_sphere_fwd_ct<A, B, -1, kSphereLB[1]>,                \
                          (const void*)k_sphere_fwd_whole<A, B, -1, kSphereLB[0]>,             \
@@ -913,8 +1063,19 @@ size_t fft_plane_lds(const FftPlan& p, int* LB) {
 
 static int launch_axis(const FftAxis& a, cplx* data, int dir, int es, int n_inner, long s_in,
                        int n_o2, long s_o2, long n_o1, long s_o1, int ld_lim, int st_lim,
-                       hipStream_t st, bool ct) {
+                       hipStream_t st, bool ct, bool gd = false) {
   const AxisArgs ax = axis_args(a);
+  if (ct && gd && axis_gd_supported(a.n)) {
+    const int L = axis_gd_lines(a.n);
+    const long tiles = (n_inner + L - 1) / L;
+    const long groups = tiles * n_o2 * n_o1;
+    if (groups <= 0) return BSE_OK;
+    if (groups > 0x7fffffffL) return fail(BSE_EINVAL, "FFT batch too large");
+    launch_axis_gd(a.n, dir, dim3((unsigned)groups), axis_gd_lds_of(a.n), st, data, ax, es,
+                   n_inner, s_in, n_o2, s_o2, s_o1, ld_lim, st_lim);
+    BSE_HIP(hipGetLastError());
+    return BSE_OK;
+  }
   if (ct) {
     const int L = axis_ct_lines(a.n);
     const long tiles = (n_inner + L - 1) / L;
@@ -949,7 +1110,7 @@ static int x_pass(const FftPlan& p, cplx* data, long batch, int dir, int ld_lim,
                   hipStream_t st) {
   const int np2 = p.N[1] * p.N[2];
   return launch_axis(p.ax[0], data, dir, np2, np2, 1, 1, 0, batch, p.nr, ld_lim, st_lim, st,
-                     p.ct_axis[BSEX_FFT_PREC]);
+                     p.ct_axis[BSEX_FFT_PREC], p.axis_direct[BSEX_FFT_PREC]);
 }
 
 template <int DIR, int IN, int OUT>
@@ -978,7 +1139,9 @@ static int launch_plane(const FftPlan& p, cplx* data, long batch, PlaneArgs pa, 
 static bool launch_sphere(const FftPlan& p, const SpherePlan& sp, bool inverse, cplx* data,
                           long batch, PlaneArgs pa, hipStream_t st) {
   if (!p.prune[BSEX_FFT_PREC]) return false;
-  const long groups = batch * pa.nplanes;
+  pa.group = inverse && xcd_group_on() ? 1 : 0;
+  pa.batch = batch;
+  const long groups = (pa.group ? round8(batch) : batch) * pa.nplanes;
   if (groups <= 0 || groups > 0x7fffffffL) return false;
   pa.N1 = p.N[0];
   pa.N2 = p.N[1];
@@ -1010,6 +1173,9 @@ int init_kernels(FftPlan* p) {
   bool prune = plane_ct_supported(p->N[1], p->N[2]);
   if (const char* e = getenv("BSEX_FFT_PRUNE")) prune = prune && atoi(e) != 0;
   p->prune[BSEX_FFT_PREC] = prune;
+  bool direct = true;
+  if (const char* e = getenv("BSEX_FFT_AXIS_DIRECT")) direct = atoi(e) != 0;
+  p->axis_direct[BSEX_FFT_PREC] = direct;
   if (prune) BSE_TRY(set_sphere_lds_limits(p->N[1], p->N[2], p->max_lds));
   return set_ct_lds_limits(ctp ? p->N[1] : -1, ctp ? p->N[2] : -1, cta ? p->N[0] : -1);
 }

@@ -1,9 +1,18 @@
 // Element-wise, sphere<->grid and tau kernels of the DMPT BSE operator (FP64).
 #include <cmath>
+#include <cstdlib>
 
 #include "kernels.h"
 
 namespace bsex {
+
+bool xcd_group_on() {
+  static const bool on = [] {
+    const char* e = getenv("BSEX_XCD_GROUP");
+    return !e || atoi(e) != 0;
+  }();
+  return on;
+}
 
 namespace {
 
@@ -73,16 +82,21 @@ __global__ void k_scatter(const int* __restrict__ idx_p, const int* __restrict__
   }
 }
 
+// one workgroup per (grid, range of modes); the workgroups of one grid run on
+// one XCD (xcd_item), which then holds that grid's entries in its L2
 template <typename V2>
 __global__ void k_gather(const int* __restrict__ idx_p, const int* __restrict__ idx_m, int nhalf,
                          int npw, long nr, long zero, const V2* __restrict__ grid, int nv,
-                         int nvh,
-                         long ngrid, double c0, double c1, const double* __restrict__ A,
-                         const double* __restrict__ T, const double* __restrict__ eps,
-                         double shift, double beta, double* __restrict__ Y) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > nhalf) return;
-  for (long g = blockIdx.y; g < ngrid; g += gridDim.y) {
+                         int nvh, long ngrid, int nbx, int group, double c0, double c1,
+                         const double* __restrict__ A, const double* __restrict__ T,
+                         const double* __restrict__ eps, double shift, double beta,
+                         double* __restrict__ Y) {
+  long g;
+  int bx;
+  xcd_item(blockIdx.x, nbx, group != 0, g, bx);
+  const int t = bx * blockDim.x + threadIdx.x;
+  if (t > nhalf || g >= ngrid) return;
+  {
     const long set = g / nvh;
     const int p = (int)(g % nvh);
     const int v1 = 2 * p, v2 = 2 * p + 1;
@@ -1033,10 +1047,14 @@ static int gather_impl(const SphereMap& m, const V2* grid, int nv, int nset, dou
   const int nvh = (nv + 1) / 2;
   const long ngrid = (long)nset * nvh;
   if (ngrid <= 0) return BSE_OK;
-  const dim3 g((unsigned)((m.nhalf + 1 + TPB - 1) / TPB), (unsigned)std::min(ngrid, 65535L));
-  hipLaunchKernelGGL(k_gather<V2>, g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr,
-                     m.zero, grid, nv, nvh, ngrid, scale * std::sqrt(m.omega), scale * std::sqrt(2.0 * m.omega),
-                     A, T, eps, shift, beta, Y);
+  const int nbx = (m.nhalf + 1 + TPB - 1) / TPB;
+  const bool group = xcd_group_on();
+  const long nblk = (long)nbx * (group ? round8(ngrid) : ngrid);
+  if (nblk > 0x7fffffffL) return fail(BSE_EINVAL, "gather: %ld workgroups", nblk);
+  hipLaunchKernelGGL(k_gather<V2>, dim3((unsigned)nblk), dim3(TPB), 0, st, m.idx_p, m.idx_m,
+                     m.nhalf, m.npw, m.nr, m.zero, grid, nv, nvh, ngrid, nbx, (int)group,
+                     scale * std::sqrt(m.omega), scale * std::sqrt(2.0 * m.omega), A, T, eps,
+                     shift, beta, Y);
   CHECK_LAUNCH();
   return BSE_OK;
 }

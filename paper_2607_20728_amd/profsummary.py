@@ -23,7 +23,7 @@
         gaps between kernels by size, and the kernels of the window by time;
 
     python -m paper_2607_20728_amd.profsummary counters <dir> [match]
-        mean value per dispatch of every counter of a --pmc run
+        mean and largest value per dispatch of every counter of a --pmc run
         (--output-format csv), per kernel whose name contains match;
 
     python -m paper_2607_20728_amd.profsummary traffic --fetch DIR --write DIR
@@ -228,7 +228,8 @@ def counters(d, match=""):
     if not vals:
         sys.exit(f"no counter rows under {d}")
     for (k, c), v in sorted(vals.items()):
-        print(f"{k:48s} {c:36s} dispatches {len(v):4d} mean {statistics.mean(v):.6g}")
+        print(f"{k:48s} {c:36s} dispatches {len(v):4d} mean {statistics.mean(v):.6g} "
+              f"max {max(v):.6g}")
 
 
 def _copy_factor(d, counter, expected_kib):
