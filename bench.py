@@ -268,6 +268,64 @@ def beyond_tda(args):
     print(json.dumps(out), flush=True)
 
 
+def relaxation(args):
+    """Excited-state relaxation on one system (default C1): BFGS on the
+    excited-state surface to |dE/dR| < --relax-gtol, once with every
+    geometry solved from scratch and once warm started (each geometry's
+    Davidson from the previous exciton, its Z-vector solve from the previous
+    Z), then the ground-state relaxation for the displacement Delta Q."""
+    import torch
+
+    import synth
+    from paper_2607_20728_amd import bsex, relax
+
+    torch.cuda.set_device(0)
+    cfg = config_of(args.config)
+    n_pw = bsex.basis_size(cfg.cell, cfg.grid, cfg.ecut)
+    d = synth.make_system(cfg, n_pw, seed=args.seed)
+    bsex.warm_up()
+    runs = {}
+    for label, warm in (("cold", False), ("warm", True)):
+        state = dict(warm=warm)
+
+        def ev(sysd, xyz, state=state, label=label, **kw):
+            r = relax.evaluate(sysd, xyz, state=state, **kw)
+            if state["evals"] % 10 == 0:
+                log(f"[relax] {label}: {state['evals']} evaluations")
+            return r
+
+        t0 = time.perf_counter()
+        xyz, E, hist = relax.relax(d, surface="es", gtol=args.relax_gtol, max_steps=60,
+                                   evaluator=ev, tol=1e-9)
+        dt = time.perf_counter() - t0
+        runs[label] = dict(s=round(dt, 2), bfgs_steps=len(hist) - 1, evaluations=state["evals"],
+                           davidson_iters=state["davidson_iters"],
+                           zvector_iters=state["zvector_iters"],
+                           s_init=round(state["s_init"], 2),
+                           s_davidson=round(state["s_davidson"], 2),
+                           s_zvector=round(state["s_zvector"], 2), E_es=E,
+                           max_abs_grad=hist[-1][1], xyz=xyz)
+        log(f"[relax] {label}: {dt:.1f} s, {len(hist) - 1} steps, {state['evals']} evaluations, "
+            f"Davidson {state['davidson_iters']} / Z {state['zvector_iters']} iterations")
+    t0 = time.perf_counter()
+    xg, Eg, hg = relax.relax(d, surface="gs", gtol=args.relax_gtol, max_steps=60)
+    t_gs = time.perf_counter() - t0
+    dxyz = float(np.abs(runs["warm"]["xyz"] - runs["cold"]["xyz"]).max())
+    dq = relax.delta_q(xg, runs["warm"]["xyz"])
+    for r in runs.values():
+        del r["xyz"]
+    out = dict(metric=f"excited-state relaxation, |dE/dR| < {args.relax_gtol:g} Ha/bohr",
+               value=runs["warm"]["s"], unit="s", higher_is_better=False, dtype="f64",
+               data="synthetic",
+               config=dict(workload=cfg.name, n_val=cfg.n_val, n_pw=n_pw, grid=list(cfg.grid),
+                           n_sites=len(d["site_depth"]), spring_ha_bohr2=5.0),
+               cold=runs["cold"], warm=runs["warm"],
+               max_site_difference_warm_vs_cold_bohr=dxyz,
+               ground_state=dict(s=round(t_gs, 2), bfgs_steps=len(hg) - 1, E_gs=Eg),
+               delta_q_bohr=dq)
+    print(json.dumps(out), flush=True)
+
+
 def batch(args):
     """The uneven batch: the 32 systems of synth.c4_systems, lowest exciton and
     forces each, once one system at a time (one stream, no graphs, default
@@ -406,7 +464,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default=None,
+                    help="system (default: the defect supercell c2; c1 for --relax)")
     ap.add_argument("--nb", type=int, default=8)
     # an explicit budget lets the tau cache use the memory a Davidson subspace
     # would otherwise keep in reserve (this run only applies the operator)
@@ -430,6 +489,9 @@ def main():
     ap.add_argument("--n-extra", type=int, default=8,
                     help="conduction states the ground-state solve computes (--ttf)")
     ap.add_argument("--batch", action="store_true", help="uneven batch run instead")
+    ap.add_argument("--relax", action="store_true",
+                    help="excited-state relaxation (cold and warm-started) instead")
+    ap.add_argument("--relax-gtol", type=float, default=1e-5)
     ap.add_argument("--coupling", action="store_true",
                     help="beyond the TDA: time the coupling apply (and --full-bse the root)")
     ap.add_argument("--full-bse", action="store_true", help="--coupling: also the coupled root")
@@ -439,6 +501,8 @@ def main():
     ap.add_argument("--learned", default=None,
                     help="trained preconditioner weights (.npz) for the --ttf run")
     args = ap.parse_args()
+    if args.config is None:
+        args.config = "c1" if args.relax else "c2"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "sharding of this path is a design note, not a measured run.", file=sys.stderr)
@@ -449,6 +513,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration(args)
+        return
+    if args.relax:
+        relaxation(args)
         return
     if args.batch:
         batch(args)

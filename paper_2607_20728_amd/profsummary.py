@@ -16,11 +16,13 @@
         planes along axis 1 that hold sphere modes; B = the stream's bytes
         per launch as bench.py reports them);
 
-    python -m paper_2607_20728_amd.profsummary busy <results.db> [after] [rows]
+    python -m paper_2607_20728_amd.profsummary busy <results.db> [after] [rows] [before]
         device-busy fraction of a --kernel-trace run: from the end of the last
-        launch whose name contains `after` (default: the first launch) to the
-        last launch, the union of kernel intervals against the window, the
-        gaps between kernels by size, and the kernels of the window by time;
+        launch whose name contains `after` (default: the first launch; NAME@k
+        for the k-th launch, counting from 1) to the start of the launch
+        `before` names (default: the end of the trace), the union of kernel
+        intervals against the window, the gaps between kernels by size, and
+        the kernels of the window by time;
 
     python -m paper_2607_20728_amd.profsummary counters <dir> [match]
         mean and largest value per dispatch of every counter of a --pmc run
@@ -66,19 +68,32 @@ def kernels(db, rows=30):
               f"{sum(v) / 1e6:9.1f} {100 * sum(v) / tot:5.1f}")
 
 
-def busy(db, after="", rows=20):
+def _launch(ks, spec, last_default):
+    """(start, end) of the launch `spec` names: NAME (the last launch, or the
+    first when last_default is false) or NAME@k (the k-th, from 1)."""
+    name, _, k = spec.partition("@")
+    hits = [(s, e) for n, s, e in ks if name in n]
+    if not hits:
+        sys.exit(f"no launch matches {name!r}")
+    if k:
+        if int(k) > len(hits):
+            sys.exit(f"{name!r} has {len(hits)} launches")
+        return hits[int(k) - 1]
+    return hits[-1] if last_default else hits[0]
+
+
+def busy(db, after="", rows=20, before=""):
     con = sqlite3.connect(db)
     ks = con.execute("select name, start, end from kernels order by start").fetchall()
     if not ks:
         sys.exit("no kernels in the trace")
-    t0 = ks[0][1]
-    if after:
-        hits = [e for n, s, e in ks if after in n]
-        if not hits:
-            sys.exit(f"no launch matches {after!r}")
-        t0 = max(hits)
-    win = [(n, max(s, t0), e) for n, s, e in ks if e > t0]
-    t1 = max(e for _, _, e in win)
+    t0 = _launch(ks, after, True)[1] if after else ks[0][1]
+    tb = _launch(ks, before, False)[0] if before else None
+    win = [(n, max(s, t0), e if tb is None else min(e, tb)) for n, s, e in ks
+           if e > t0 and (tb is None or s < tb)]
+    if not win:
+        sys.exit("empty window")
+    t1 = max(e for _, _, e in win) if tb is None else tb
     busy_ns, cur_s, cur_e = 0, None, None
     gaps = []
     for _, s, e in sorted(win, key=lambda r: r[1]):
@@ -279,7 +294,8 @@ def main():
         return
     if len(sys.argv) > 1 and sys.argv[1] == "busy":
         busy(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "",
-             int(sys.argv[4]) if len(sys.argv) > 4 else 20)
+             int(sys.argv[4]) if len(sys.argv) > 4 else 20,
+             sys.argv[5] if len(sys.argv) > 5 else "")
         return
     if len(sys.argv) > 1 and sys.argv[1] == "kernels":
         kernels(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 30)

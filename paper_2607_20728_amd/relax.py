@@ -20,31 +20,72 @@ backtracking line search.
 """
 from __future__ import annotations
 
+import time
+
 import numpy as np
 
 from . import bsex
 
 
 def evaluate(sysd, xyz, *, surface="es", spring=5.0, f_occ=2.0, tol=1e-9, n_extra=8,
-             precision=bsex.FP64):
+             precision=bsex.FP64, state=None):
     """(E, dE/dR [n_sites][3]) of the ground- ("gs") or excited-state ("es")
-    surface at site positions xyz, from a fresh context."""
+    surface at site positions xyz, from a fresh context.
+
+    state (a dict, optional) carries solver state between the geometries of
+    a relaxation: with state["warm"] true (the default) the Davidson solve
+    starts from the previous geometry's exciton and the Z-vector solve from
+    its Z; the exciton and Z of this geometry are stored back, and the solver
+    iterations are added to state["davidson_iters"], state["zvector_iters"]
+    with state["evals"] counting the evaluations.
+
+    Both pair each occupied band v with an orbital phi_v, whose sign (and,
+    within a degenerate level, whose rotation) a fresh ground-state solve
+    fixes arbitrarily.  The guesses are therefore re-expressed on this
+    geometry's orbitals through the transition density matrix,
+    a_v <- Delta rho_old phi_v = sum_v' <phi_v'^old|phi_v> a_v'^old (the same
+    for Z), and the library then projects them onto the new conduction
+    space."""
     if surface not in ("gs", "es"):
         raise ValueError(f"surface {surface!r}: 'gs' or 'es'")
     d = dict(sysd)
     d["site_xyz"] = np.ascontiguousarray(xyz, dtype=float)
     x0 = np.asarray(sysd["site_xyz"], dtype=float)
     n = x0.shape[0]
+    t0 = time.perf_counter()
     ctx = bsex.init_from_synth(d, n_extra=n_extra, precision=precision)
+    if state is not None:
+        state["s_init"] = state.get("s_init", 0.0) + time.perf_counter() - t0
     try:
-        _, eps = bsex.get_orbitals(ctx)
+        phi, eps = bsex.get_orbitals(ctx)
         E = f_occ * float(np.sum(eps)) + 0.5 * spring * float(np.sum((d["site_xyz"] - x0) ** 2))
         G = f_occ * bsex.ground_state_forces(ctx, n) + spring * (d["site_xyz"] - x0)
         if surface == "es":
-            w, X, _ = bsex.davidson(ctx, 1, tol=tol)
-            Z, _ = bsex.zvector_solve(ctx, X[0], tol=tol)
+            warm = state is not None and state.get("warm", True)
+            x0 = z0 = None
+            phi_h = phi.cpu().numpy()
+            if warm and state.get("X") is not None:
+                import torch
+                S = state["phi"] @ phi_h.T                    # <phi_v'^old|phi_v>
+                x0 = torch.tensor((S.T @ state["X"])[None], dtype=torch.float64,
+                                  device=phi.device)
+                z0 = torch.tensor(S.T @ state["Z"], dtype=torch.float64, device=phi.device)
+            t1 = time.perf_counter()
+            w, X, ds = bsex.davidson(ctx, 1, tol=tol, x0=x0)
+            t2 = time.perf_counter()
+            Z, zs = bsex.zvector_solve(ctx, X[0], tol=tol, z0=z0)
+            t3 = time.perf_counter()
             E += float(w[0])
             G = G + bsex.forces(ctx, X[0], Z, n)
+            if state is not None:
+                state["phi"] = phi_h
+                state["X"], state["Z"] = X[0].cpu().numpy(), Z.cpu().numpy()
+                state["davidson_iters"] = state.get("davidson_iters", 0) + ds["iters"]
+                state["zvector_iters"] = state.get("zvector_iters", 0) + zs["iters"]
+                state["s_davidson"] = state.get("s_davidson", 0.0) + t2 - t1
+                state["s_zvector"] = state.get("s_zvector", 0.0) + t3 - t2
+        if state is not None:
+            state["evals"] = state.get("evals", 0) + 1
     finally:
         ctx.free()
     return E, G

@@ -1,7 +1,7 @@
 """Excited-state relaxation through the library (GPU): the composed energy
 and gradient against the oracle at a displaced geometry, the gradient
 against a central difference of the library's own energies, and a BFGS run
-on both surfaces of the tiny system."""
+on both surfaces of the tiny system; warm-started solves along a path."""
 import numpy as np
 import pytest
 
@@ -66,3 +66,28 @@ def test_relaxation_on_both_surfaces():
     dq = relax.delta_q(out["gs"][0], out["es"][0])
     print(f"  steps gs {out['gs'][2]} es {out['es'][2]}; Delta Q (unit masses) {dq:.4f} bohr")
     assert dq > 1e-4
+
+
+def test_warm_start_reaches_the_cold_result_in_fewer_iterations():
+    """Along a relaxation path (C1), each geometry's solves started from the
+    previous geometry's exciton and Z give the energy and gradient of a cold
+    solve, in fewer Davidson and Z-vector iterations."""
+    print("[gpu] relax: warm-started solves along a path (c1)", flush=True)
+    cfg, b, d = _system("c1")
+    x0 = np.asarray(d["site_xyz"], dtype=float)
+    u = np.random.default_rng(5).standard_normal(x0.shape)
+    u *= 0.02 / np.abs(u).max()
+    warm, cold = dict(warm=True), dict(warm=False)
+    worst_e, worst_g = 0.0, 0.0
+    for k in range(4):
+        xyz = x0 + k * u
+        Ew, Gw = relax.evaluate(d, xyz, surface="es", tol=1e-10, state=warm)
+        Ec, Gc = relax.evaluate(d, xyz, surface="es", tol=1e-10, state=cold)
+        worst_e = max(worst_e, abs(Ew - Ec))
+        worst_g = max(worst_g, np.abs(Gw - Gc).max())
+    print(f"  |dE| {worst_e:.1e}  |dG| {worst_g:.1e}  Davidson {warm['davidson_iters']} vs "
+          f"{cold['davidson_iters']}, Z {warm['zvector_iters']} vs {cold['zvector_iters']}",
+          flush=True)
+    assert worst_e < 1e-9 and worst_g < 1e-7
+    assert warm["davidson_iters"] < cold["davidson_iters"]
+    assert warm["zvector_iters"] < cold["zvector_iters"]

@@ -98,3 +98,21 @@ def test_busy_window(tmp_path):
     assert out[1].split()[-3] == "1," and out[3].split()[-3] == "1,"
     table = {line.split()[0]: line.split() for line in out[6:]}
     assert table["k_a"][1] == "2" and table["k_b"][1] == "2"
+
+
+def test_busy_window_between_launches(tmp_path):
+    """NAME@k picks the k-th launch; the window ends where `before` starts."""
+    db = str(tmp_path / "w_results.db")
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, start int, end int)")
+    rows = [("void k_mark(int)", 0, 1_000), ("void k_a(int)", 1_000, 5_000),
+            ("void k_mark(int)", 5_000, 6_000), ("void k_b(int)", 6_000, 16_000),
+            ("void k_mark(int)", 20_000, 21_000)]
+    con.executemany("insert into kernels values (?,?,?)", rows)
+    con.commit()
+    con.close()
+    out = _run("busy", db, "k_mark@2", "5", "k_mark@3").splitlines()
+    # window 6000..20000 = 14 us, busy 10 us
+    assert out[0].startswith("window 0.0 ms, kernels busy 0.0 ms (71.4%), 1 launches")
+    out = _run("busy", db, "k_mark@1", "5", "k_mark@2").splitlines()
+    assert "(100.0%)" in out[0]
