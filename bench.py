@@ -300,6 +300,7 @@ def relaxation(args):
         dt = time.perf_counter() - t0
         runs[label] = dict(s=round(dt, 2), bfgs_steps=len(hist) - 1, evaluations=state["evals"],
                            davidson_iters=state["davidson_iters"],
+                           davidson_applies=state["davidson_applies"],
                            zvector_iters=state["zvector_iters"],
                            s_init=round(state["s_init"], 2),
                            s_davidson=round(state["s_davidson"], 2),
@@ -409,17 +410,22 @@ def time_to_force(args):
     info = bsex.get_info(ctx)
     log(f"[ttf] init {t_init:.1f} s, gap {info['ks_gap']:.3e}, cached "
         f"{info['tau_blocks_cached']}/{info['tau_blocks']}")
+    if args.phases:
+        bsex.set_profiling(ctx, True)
+        bsex.phase_times(ctx, reset=True)
     t1 = time.perf_counter()
     tl = args.two_level
     w, X, ds = bsex.davidson(ctx, cfg.n_states, tol=args.tol, use_learned=use, two_level=tl,
                              check=False)
     t2 = time.perf_counter()
+    ph_dav = bsex.phase_times(ctx, reset=True) if args.phases else None
     log(f"[ttf] davidson {t2 - t1:.1f} s, {ds['iters']} iters, {ds['applies']} applies "
         f"({ds['applies_fp64']} FP64), "
         f"omega {w}, resid {ds['resid'][:cfg.n_states]}")
     Z, zs = bsex.zvector_solve(ctx, X[0], tol=args.tol, use_learned=use, two_level=tl,
                                check=False)
     t3 = time.perf_counter()
+    ph_uz = bsex.phase_times(ctx, reset=True) if args.phases else None
     log(f"[ttf] U + Z {t3 - t2:.1f} s, {zs['iters']} iters, resid {zs['resid'][0]:.2e}")
     F = bsex.forces(ctx, X[0], Z, len(d["site_depth"]))
     t4 = time.perf_counter()
@@ -451,6 +457,11 @@ def time_to_force(args):
         out["config"]["localized"] = dict(loc_info(info), threshold=args.prune)
     if args.ks_model:
         out["config"]["ks_model"] = dict(scf_iters=info["scf_iters"], alpha_exx=0.0)
+    if args.phases:
+        # device time per phase (ms, launches) with profiling on (no graphs)
+        out["phases_ms"] = dict(
+            davidson={k: [round(v[0], 1), v[1]] for k, v in ph_dav.items() if v[1]},
+            u_z={k: [round(v[0], 1), v[1]] for k, v in ph_uz.items() if v[1]})
     if args.forces_out:
         np.save(args.forces_out, F)
     ctx.free()
@@ -484,6 +495,8 @@ def main():
     ap.add_argument("--ks-model", type=int, default=0, choices=(0, 1),
                     help="--ttf: 1 = self-consistent KS ground state, with its response "
                          "kernels in U and the Z-vector equation (semilocal, no exact exchange)")
+    ap.add_argument("--phases", action="store_true",
+                    help="--ttf: device time per library phase (profiling on) in the JSON")
     ap.add_argument("--two-level", action="store_true",
                     help="two-level preconditioner on the conduction states held (--ttf)")
     ap.add_argument("--n-extra", type=int, default=8,

@@ -1153,11 +1153,13 @@ static int pcg(bse_ctx* c, const double* rhs, double* Z, double tol, int maxit, 
   std::vector<double> d;
   BSE_TRY(dots_host(c, rhs, rhs, nv, npw, sv.p, d));
   const double nb_ = std::sqrt(std::accumulate(d.begin(), d.end(), 0.0));
+  // the operator on vectors already in the P_c space (Z after its initial
+  // projection, and the search directions, built from projected
+  // preconditioned residuals); its output is projected
   auto applyD = [&](const double* in, double* o_) -> int {
-    BSE_TRY(proj_c(c, in, Zr.p, 1));
-    if (c->ks) return ks_zop(c, Zr.p, o_);
-    if (fp32) return apply_H_f(c, (int)nv, 1, Zr.p, o_, 0.0, c->eps_d, 1);
-    return apply_H(c, (int)nv, 1, Zr.p, o_, c->agrid, 0.0, c->eps_d, 1);
+    if (c->ks) return ks_zop(c, in, o_);
+    if (fp32) return apply_H_f(c, (int)nv, 1, in, o_, 0.0, c->eps_d, 1);
+    return apply_H(c, (int)nv, 1, in, o_, c->agrid, 0.0, c->eps_d, 1);
   };
   // with the KS kernels the bands couple: one step length for the block
   const bool block_steps = c->ks != 0;

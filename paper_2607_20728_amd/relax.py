@@ -81,6 +81,7 @@ def evaluate(sysd, xyz, *, surface="es", spring=5.0, f_occ=2.0, tol=1e-9, n_extr
                 state["phi"] = phi_h
                 state["X"], state["Z"] = X[0].cpu().numpy(), Z.cpu().numpy()
                 state["davidson_iters"] = state.get("davidson_iters", 0) + ds["iters"]
+                state["davidson_applies"] = state.get("davidson_applies", 0) + ds["applies"]
                 state["zvector_iters"] = state.get("zvector_iters", 0) + zs["iters"]
                 state["s_davidson"] = state.get("s_davidson", 0.0) + t2 - t1
                 state["s_zvector"] = state.get("s_zvector", 0.0) + t3 - t2
