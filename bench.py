@@ -285,7 +285,9 @@ def relaxation(args):
     d = synth.make_system(cfg, n_pw, seed=args.seed)
     bsex.warm_up()
     runs = {}
-    for label, warm in (("cold", False), ("warm", True)):
+    order = (("warm", True), ("cold", False)) if args.relax_warm_first else \
+        (("cold", False), ("warm", True))
+    for label, warm in order:
         state = dict(warm=warm)
 
         def ev(sysd, xyz, state=state, label=label, **kw):
@@ -416,7 +418,7 @@ def time_to_force(args):
     t1 = time.perf_counter()
     tl = args.two_level
     w, X, ds = bsex.davidson(ctx, cfg.n_states, tol=args.tol, use_learned=use, two_level=tl,
-                             check=False)
+                             check=False, max_subspace=args.max_subspace)
     t2 = time.perf_counter()
     ph_dav = bsex.phase_times(ctx, reset=True) if args.phases else None
     log(f"[ttf] davidson {t2 - t1:.1f} s, {ds['iters']} iters, {ds['applies']} applies "
@@ -439,13 +441,15 @@ def time_to_force(args):
                            tau_blocks_cached=info["tau_blocks_cached"],
                            tau_blocks=info["tau_blocks"], ks_gap_ha=info["ks_gap"]),
                split_s=dict(init=round(t_init, 2), davidson=round(t2 - t1, 2),
-                            u_z=round(t3 - t2, 2), forces=round(t4 - t3, 3)),
+                            u_z=round(t3 - t2, 2), u=round(zs["t_u_ms"] / 1e3, 2),
+                            z=round(t3 - t2 - zs["t_u_ms"] / 1e3, 2), forces=round(t4 - t3, 3)),
                init_s=dict(ground_state=round(info["t_ground_state_ms"] / 1e3, 2),
                            gs_sweeps=info["gs_sweeps"], tau=round(info["t_tau_ms"] / 1e3, 2),
                            tau_alloc=round(info["t_tau_alloc_ms"] / 1e3, 2),
                            library=round(info["t_init_ms"] / 1e3, 2)),
                process_start_s=round(t_start, 2),
                davidson=dict(iters=ds["iters"], applies=ds["applies"],
+                             max_subspace=args.max_subspace or None,
                              applies_fp64=ds["applies_fp64"], rc=ds["rc"],
                              learned=ds["learned"], fallback=ds["fallback"],
                              omega=list(map(float, w)), resid=ds["resid"][:cfg.n_states]),
@@ -495,6 +499,8 @@ def main():
     ap.add_argument("--ks-model", type=int, default=0, choices=(0, 1),
                     help="--ttf: 1 = self-consistent KS ground state, with its response "
                          "kernels in U and the Z-vector equation (semilocal, no exact exchange)")
+    ap.add_argument("--max-subspace", type=int, default=0,
+                    help="--ttf: Davidson subspace size (0: the library default, 16 blocks)")
     ap.add_argument("--phases", action="store_true",
                     help="--ttf: device time per library phase (profiling on) in the JSON")
     ap.add_argument("--two-level", action="store_true",
@@ -505,6 +511,8 @@ def main():
     ap.add_argument("--relax", action="store_true",
                     help="excited-state relaxation (cold and warm-started) instead")
     ap.add_argument("--relax-gtol", type=float, default=1e-5)
+    ap.add_argument("--relax-warm-first", action="store_true",
+                    help="--relax: run the warm-started relaxation before the cold one")
     ap.add_argument("--coupling", action="store_true",
                     help="beyond the TDA: time the coupling apply (and --full-bse the root)")
     ap.add_argument("--full-bse", action="store_true", help="--coupling: also the coupled root")

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define BSEX_ABI_VERSION 3
+#define BSEX_ABI_VERSION 4
 
 typedef enum {
   BSE_OK = 0,
@@ -278,6 +278,8 @@ typedef struct {
   int32_t fallback;           /* 1 when the solve dropped them for the diagonal
                                  preconditioner (residual grew twice in a row, or
                                  a non-finite output)                             */
+  double t_u_ms;              /* Z-vector: wall time of its right-hand side U (SM
+                                 Sec. I), included in t_ms; 0 otherwise           */
 } bse_solver_stats;
 
 /* Lowest n_states eigenpairs of P_c M P_c (Eq. 1) by block Davidson with a

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbsex.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, EGAP, EABI, ESTATE = range(8)
 K_D, K_1E, K_1D_BARE, K_1D_PDEP, K_ALL = 1, 2, 4, 8, 15
 FP64, MIXED = 0, 1
@@ -96,7 +96,7 @@ class SolverOpts(C.Structure):
 class SolverStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("applies", C.c_int32), ("resid", C.c_double * 16),
                 ("t_ms", C.c_double), ("applies_fp64", C.c_int32), ("learned", C.c_int32),
-                ("fallback", C.c_int32)]
+                ("fallback", C.c_int32), ("t_u_ms", C.c_double)]
 
 
 class PhaseTimes(C.Structure):
@@ -391,7 +391,8 @@ def _opts(tol=0.0, max_iter=0, block=0, max_subspace=0, x0=None, z0=None, use_le
 
 def _stats(s):
     return dict(iters=s.iters, applies=s.applies, resid=list(s.resid), t_ms=s.t_ms,
-                applies_fp64=s.applies_fp64, learned=s.learned, fallback=s.fallback)
+                applies_fp64=s.applies_fp64, learned=s.learned, fallback=s.fallback,
+                t_u_ms=s.t_u_ms)
 
 
 def davidson(ctx, n_states=1, *, tol=1e-8, max_iter=0, block=0, max_subspace=0, x0=None,

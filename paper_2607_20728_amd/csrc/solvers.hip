@@ -487,6 +487,7 @@ static int davidson_core(bse_ctx* c, int ns, const bse_solver_opts* o, double* o
     stats->fallback = fallback ? 1 : 0;
     for (int i = 0; i < 16; ++i) stats->resid[i] = i < nb ? rn[i] : 0.0;
     stats->t_ms = elapsed_ms(t0);
+    stats->t_u_ms = 0.0;
   }
   if (!conv) return fail(BSE_ENOCONV, "Davidson: no convergence in %d iterations", it);
   return BSE_OK;
@@ -729,6 +730,7 @@ int full_bse(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double
     stats->applies_fp64 = applies;
     for (int i = 0; i < 16; ++i) stats->resid[i] = i < nb ? rn[i] : 0.0;
     stats->t_ms = elapsed_ms(t0);
+    stats->t_u_ms = 0.0;
   }
   if (!conv) return fail(BSE_ENOCONV, "full BSE: no convergence in %d iterations", it);
   return BSE_OK;
@@ -801,6 +803,7 @@ int davidson(bse_ctx* c, int ns, const bse_solver_opts* o, double* omega, double
     stats->fallback = (s1.fallback || s2.fallback) ? 1 : 0;
     for (int i = 0; i < 16; ++i) stats->resid[i] = i < ns ? s2.resid[i] : 0.0;
     stats->t_ms = elapsed_ms(t0);
+    stats->t_u_ms = 0.0;
   }
   return BSE_OK;
 }
@@ -1279,6 +1282,8 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
   BSE_TRY(u_vector(c, Xs, U.p));
   BSE_TRY(proj_c(c, U.p, U.p, 1));
   BSE_TRY(axpby(-1.0, U.p, 0.0, U.p, L, c->st));  // U <- -U: the right-hand side
+  BSE_HIP(hipStreamSynchronize(c->st));
+  const double t_u = elapsed_ms(t0);
   // per-band preconditioner shifts and initial guess
   const double* vshift = nullptr;
   bool learned = false, fallback = false;
@@ -1358,6 +1363,7 @@ int zvector(bse_ctx* c, const double* Xs, const bse_solver_opts* o, double* Z,
     stats->applies_fp64 = applies64;
     stats->resid[0] = rel;
     stats->t_ms = elapsed_ms(t0);
+    stats->t_u_ms = t_u;
     stats->learned = learned ? 1 : 0;
     stats->fallback = fallback ? 1 : 0;
   }
