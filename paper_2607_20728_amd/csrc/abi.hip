@@ -409,6 +409,15 @@ int init_impl(const bse_system_desc* d, bse_ctx* c) {
     BSE_TRY(to_f32((const double*)c->phir, (float*)c->phir_f, 2L * c->nvh * nr, c->st));
     BSE_TRY(to_f32(c->Vr, c->Vr_f, nr, c->st));
     BSE_TRY(to_f32(c->vc, c->vc_f, nr, c->st));
+    // the FP32 tiles' PDEP projections as FP32 GEMMs (BSEX_PDEP_FP32=0: FP64)
+    const char* e = getenv("BSEX_PDEP_FP32");
+    if (c->npdep > 0 && !(e && atoi(e) == 0)) {
+      const size_t n = (size_t)npw * c->npdep;
+      BSE_TRY(ctx_alloc_t(c, &c->Pt_f, n));
+      BSE_TRY(ctx_alloc_t(c, &c->Ptc_f, n));
+      BSE_TRY(to_f32(c->Pt, c->Pt_f, (long)n, c->st));
+      BSE_TRY(to_f32(c->Ptc, c->Ptc_f, (long)n, c->st));
+    }
     if (c->loc) {
       BSE_TRY(ctx_alloc_t(c, &c->phir_loc_f, (size_t)c->nvh * nr));
       BSE_TRY(to_f32((const double*)c->phir_loc, (float*)c->phir_loc_f, 2L * c->nvh * nr, c->st));

@@ -130,6 +130,9 @@ int grid_to_compact(const FftPlan& p, const SpherePlan& sp, float2* grid, long b
 // op(A) = A[M][K] (ta = 0) or A^T with A[K][M] (ta = 1); op(B) likewise.
 int dgemm(int ta, int tb, long M, long N, long K, double alpha, const double* A, long lda,
           const double* B, long ldb, double beta, double* C, long ldc, hipStream_t st);
+// the same in FP32 (FP32 MFMA, FP32 accumulation)
+int sgemm(int ta, int tb, long M, long N, long K, float alpha, const float* A, long lda,
+          const float* B, long ldb, float beta, float* C, long ldc, hipStream_t st);
 // the same with the beta term read from Cin (same layout and ldc) instead of
 // C: C = alpha op(A) op(B) + beta Cin.  Cin = NULL reads C; otherwise Cin
 // must not overlap C.

@@ -100,6 +100,7 @@ struct bse_ctx {
   float2* phir_f = nullptr;   // [nvh][nr]
   float* Vr_f = nullptr;      // [nr]
   float* vc_f = nullptr;      // [nr]
+  float *Pt_f = nullptr, *Ptc_f = nullptr;  // FP32 copies of Pt, Ptc (mixed: FP32 PDEP GEMMs)
   float* tau_f = nullptr;     // [nr/Rf][nblk][64 Rf] FP32 cache (always whole)
   float2 *agrid_f = nullptr, *drho_f = nullptr, *compact_f = nullptr;
   int nbc_f = 0;

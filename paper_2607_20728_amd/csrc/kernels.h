@@ -24,6 +24,8 @@ int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, double2*
                  int accumulate, hipStream_t st);
 int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, float2* grid,
                  int accumulate, hipStream_t st);
+int scatter_sets(const SphereMap& m, const float* X, int nv, int nset, float2* grid,
+                 int accumulate, hipStream_t st);
 // Y[set][v][j] = scale * <e_j | grid>  (+ (T_j + shift - eps_v) * A[set][v][j] if A)
 // (+ beta * Y).  The grid holds N_r times the Fourier coefficients when it
 // comes straight from a forward transform, so callers pass scale = 1/N_r.
@@ -33,6 +35,9 @@ int gather_sets(const SphereMap& m, const double2* grid, int nv, int nset, doubl
 int gather_sets(const SphereMap& m, const float2* grid, int nv, int nset, double scale,
                 const double* A, const double* T, const double* eps, double shift, double beta,
                 double* Y, hipStream_t st);
+// the coefficients alone, in FP32: Y[set][v][j] = scale * <e_j | grid>
+int gather_sets(const SphereMap& m, const float2* grid, int nv, int nset, double scale, float* Y,
+                hipStream_t st);
 // grid[g][r] *= f[r] * scale  (real field f of length nr)
 int mul_real_field(double2* grid, long ngrid, long nr, const double* f, double scale,
                    hipStream_t st);

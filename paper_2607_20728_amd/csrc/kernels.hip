@@ -41,19 +41,24 @@ __device__ __forceinline__ V2 make2(double x, double y) {
   return v;
 }
 
-template <typename V2>
+// one workgroup per (grid, range of modes); the workgroups of one grid run on
+// one XCD (xcd_item), so the scattered updates of a grid meet in one L2
+template <typename V2, typename XT>
 __global__ void k_scatter(const int* __restrict__ idx_p, const int* __restrict__ idx_m, int nhalf,
-                          int npw, long nr, long zero, const double* __restrict__ X, int nv,
-                          int nvh, long ngrid, V2* __restrict__ grid, int acc, double s0,
-                          double s1) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > nhalf) return;
-  for (long g = blockIdx.y; g < ngrid; g += gridDim.y) {
+                          int npw, long nr, long zero, const XT* __restrict__ X, int nv,
+                          int nvh, long ngrid, int nbx, int group, V2* __restrict__ grid, int acc,
+                          double s0, double s1) {
+  long g;
+  int bx;
+  xcd_item(blockIdx.x, nbx, group != 0, g, bx);
+  const int t = bx * blockDim.x + threadIdx.x;
+  if (t > nhalf || g >= ngrid) return;
+  {
     const long set = g / nvh;
     const int p = (int)(g % nvh);
     const int v1 = 2 * p, v2 = 2 * p + 1;
-    const double* x1 = X + (set * nv + v1) * (long)npw;
-    const double* x2 = (v2 < nv) ? X + (set * nv + v2) * (long)npw : nullptr;
+    const XT* x1 = X + (set * nv + v1) * (long)npw;
+    const XT* x2 = (v2 < nv) ? X + (set * nv + v2) * (long)npw : nullptr;
     V2* G = grid + g * nr;
     if (t == 0) {
       double2 h = make_double2(x1[0] * s0, x2 ? x2[0] * s0 : 0.0);
@@ -84,13 +89,13 @@ __global__ void k_scatter(const int* __restrict__ idx_p, const int* __restrict__
 
 // one workgroup per (grid, range of modes); the workgroups of one grid run on
 // one XCD (xcd_item), which then holds that grid's entries in its L2
-template <typename V2>
+template <typename V2, typename YT>
 __global__ void k_gather(const int* __restrict__ idx_p, const int* __restrict__ idx_m, int nhalf,
                          int npw, long nr, long zero, const V2* __restrict__ grid, int nv,
                          int nvh, long ngrid, int nbx, int group, double c0, double c1,
                          const double* __restrict__ A, const double* __restrict__ T,
                          const double* __restrict__ eps, double shift, double beta,
-                         double* __restrict__ Y) {
+                         YT* __restrict__ Y) {
   long g;
   int bx;
   xcd_item(blockIdx.x, nbx, group != 0, g, bx);
@@ -132,8 +137,8 @@ __global__ void k_gather(const int* __restrict__ idx_p, const int* __restrict__ 
         if (j < 0) break;
         double val = q ? vb : va;
         if (A) val += (T[j] + shift - (eps ? eps[v] : 0.0)) * A[row + j];
-        if (beta != 0.0) val += beta * Y[row + j];
-        Y[row + j] = val;
+        if (beta != 0.0) val += beta * (double)Y[row + j];
+        Y[row + j] = (YT)val;
       }
     }
   }
@@ -1016,16 +1021,19 @@ __global__ __launch_bounds__(256) void k_band_features(
 // ============================================================================
 #define CHECK_LAUNCH() BSE_HIP(hipGetLastError())
 
-template <typename V2>
-static int scatter_impl(const SphereMap& m, const double* X, int nv, int nset, V2* grid,
+template <typename V2, typename XT>
+static int scatter_impl(const SphereMap& m, const XT* X, int nv, int nset, V2* grid,
                         int accumulate, hipStream_t st) {
   const int nvh = (nv + 1) / 2;
   const long ngrid = (long)nset * nvh;
   if (ngrid <= 0) return BSE_OK;
-  const dim3 g((unsigned)((m.nhalf + 1 + TPB - 1) / TPB), (unsigned)std::min(ngrid, 65535L));
-  hipLaunchKernelGGL((k_scatter<V2>), g, dim3(TPB), 0, st, m.idx_p, m.idx_m, m.nhalf, m.npw, m.nr,
-                     m.zero, X, nv, nvh, ngrid, grid, accumulate, 1.0 / std::sqrt(m.omega),
-                     1.0 / std::sqrt(2.0 * m.omega));
+  const int nbx = (m.nhalf + 1 + TPB - 1) / TPB;
+  const bool group = xcd_group_on();
+  const long nblk = (long)nbx * (group ? round8(ngrid) : ngrid);
+  if (nblk > 0x7fffffffL) return fail(BSE_EINVAL, "scatter: %ld workgroups", nblk);
+  hipLaunchKernelGGL((k_scatter<V2, XT>), dim3((unsigned)nblk), dim3(TPB), 0, st, m.idx_p, m.idx_m,
+                     m.nhalf, m.npw, m.nr, m.zero, X, nv, nvh, ngrid, nbx, (int)group, grid,
+                     accumulate, 1.0 / std::sqrt(m.omega), 1.0 / std::sqrt(2.0 * m.omega));
   CHECK_LAUNCH();
   return BSE_OK;
 }
@@ -1040,10 +1048,15 @@ int scatter_sets(const SphereMap& m, const double* X, int nv, int nset, float2* 
   return scatter_impl(m, X, nv, nset, grid, accumulate, st);
 }
 
-template <typename V2>
+int scatter_sets(const SphereMap& m, const float* X, int nv, int nset, float2* grid,
+                 int accumulate, hipStream_t st) {
+  return scatter_impl(m, X, nv, nset, grid, accumulate, st);
+}
+
+template <typename V2, typename YT>
 static int gather_impl(const SphereMap& m, const V2* grid, int nv, int nset, double scale,
                        const double* A, const double* T, const double* eps, double shift,
-                       double beta, double* Y, hipStream_t st) {
+                       double beta, YT* Y, hipStream_t st) {
   const int nvh = (nv + 1) / 2;
   const long ngrid = (long)nset * nvh;
   if (ngrid <= 0) return BSE_OK;
@@ -1051,7 +1064,7 @@ static int gather_impl(const SphereMap& m, const V2* grid, int nv, int nset, dou
   const bool group = xcd_group_on();
   const long nblk = (long)nbx * (group ? round8(ngrid) : ngrid);
   if (nblk > 0x7fffffffL) return fail(BSE_EINVAL, "gather: %ld workgroups", nblk);
-  hipLaunchKernelGGL(k_gather<V2>, dim3((unsigned)nblk), dim3(TPB), 0, st, m.idx_p, m.idx_m,
+  hipLaunchKernelGGL((k_gather<V2, YT>), dim3((unsigned)nblk), dim3(TPB), 0, st, m.idx_p, m.idx_m,
                      m.nhalf, m.npw, m.nr, m.zero, grid, nv, nvh, ngrid, nbx, (int)group,
                      scale * std::sqrt(m.omega), scale * std::sqrt(2.0 * m.omega), A, T, eps,
                      shift, beta, Y);
@@ -1069,6 +1082,12 @@ int gather_sets(const SphereMap& m, const float2* grid, int nv, int nset, double
                 const double* A, const double* T, const double* eps, double shift, double beta,
                 double* Y, hipStream_t st) {
   return gather_impl(m, grid, nv, nset, scale, A, T, eps, shift, beta, Y, st);
+}
+
+int gather_sets(const SphereMap& m, const float2* grid, int nv, int nset, double scale, float* Y,
+                hipStream_t st) {
+  return gather_impl(m, grid, nv, nset, scale, (const double*)nullptr, (const double*)nullptr,
+                     (const double*)nullptr, 0.0, 0.0, Y, st);
 }
 
 int mul_real_field(double2* grid, long ngrid, long nr, const double* f, double scale,

@@ -249,7 +249,19 @@ int tau_build_range_f(bse_ctx* c, const float2* orbr, long gb0, long nblk, float
   BSE_TRY(fft3d(c->fft, tg, ng, -1, c->st));
   SphereMap m64 = c->map;
   const bool pdep = (mask & BSE_K_1D_PDEP) && c->npdep > 0;
-  if (pdep) {
+  // PDEP part (Eq. 3) in FP32 when the context holds FP32 copies of the
+  // basis (the tile buffers hold twice the floats needed), else FP64
+  const bool f32 = pdep && c->Pt_f;
+  float* rs = reinterpret_cast<float*>(c->tile_RS);
+  float* tt = reinterpret_cast<float*>(c->tile_T);
+  float* tf = reinterpret_cast<float*>(c->tile_F);
+  if (f32) {
+    BSE_TRY(gather_sets(m64, tg, 64, (int)nblk, 1.0 / (double)nr, rs, c->st));
+    BSE_TRY(sgemm(0, 0, ne, c->npdep, npw, 1.0f, rs, npw, c->Pt_f, c->npdep, 0.0f, tt,
+                  c->npdep, c->st));
+    BSE_TRY(sgemm(0, 1, ne, npw, c->npdep, 1.0f, tt, c->npdep, c->Ptc_f, c->npdep, 0.0f, tf,
+                  npw, c->st));
+  } else if (pdep) {
     BSE_TRY(gather_sets(m64, tg, 64, (int)nblk, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0,
                         0.0, c->tile_RS, c->st));
     BSE_TRY(gemm(c, 0, 0, ne, c->npdep, npw, 1.0, c->tile_RS, npw, c->Pt, c->npdep, 0.0,
@@ -261,7 +273,10 @@ int tau_build_range_f(bse_ctx* c, const float2* orbr, long gb0, long nblk, float
     BSE_TRY(mul_real_field(tg, ng, nr, c->vc_f, 1.0f / (float)nr, c->st));
   else  // one float2 per double
     BSE_TRY(zero_fill(reinterpret_cast<double*>(tg), ng * nr, c->st));
-  if (pdep) BSE_TRY(scatter_sets(m64, c->tile_F, 64, (int)nblk, tg, 1, c->st));
+  if (f32)
+    BSE_TRY(scatter_sets(m64, tf, 64, (int)nblk, tg, 1, c->st));
+  else if (pdep)
+    BSE_TRY(scatter_sets(m64, c->tile_F, 64, (int)nblk, tg, 1, c->st));
   BSE_TRY(fft3d(c->fft, tg, ng, +1, c->st));
   return tau_store(tg, c->blkIJ + gb0, nblk, nr, c->Rf, dst, dst_nblk, dst_blk0, c->st);
 }
