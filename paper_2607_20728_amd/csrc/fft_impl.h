@@ -338,7 +338,14 @@ constexpr int plane_lb() {
     for (int d = 64; d >= 4; --d)
       if (N2 % d == 0 && (int)sizeof(cplx) * (N2 * N3 + d * nmax) <= budget) return d;
   }
-  // lines per scratch batch: largest power of two (<= 32) fitting 160 KB
+  // lines per scratch batch: largest power of two (<= 32) fitting 160 KB; in
+  // FP32 at least 16 lines within 80 KB when that fits, for two workgroups
+  // per CU (48 x 120: 16 lines, 77 KB, instead of 32 lines, 107 KB)
+  if (sizeof(cplx) == 8 && (int)sizeof(cplx) * (N2 * N3 + ns * 16 * nmax) <= 81920) {
+    int lb = 32;
+    while (lb > 16 && (int)sizeof(cplx) * (N2 * N3 + ns * lb * nmax) > 81920) lb /= 2;
+    return lb;
+  }
   int lb = 32;
   while (lb > 4 && (int)sizeof(cplx) * (N2 * N3 + ns * lb * nmax) > 163840) lb /= 2;
   return lb;
