@@ -291,6 +291,60 @@ __global__ void k_tau_store(const G2* __restrict__ grids, const int2* __restrict
   }
 }
 
+// The same store through LDS: a workgroup takes TS_P consecutive grid points
+// and TS_NB blocks (TS_NB * 32 complex grids), reads each grid's points as
+// one contiguous run into LDS and writes, for every point block rb, the
+// TS_NB blocks' contiguous 64 R values of the cache layout.  Both the reads
+// and the writes are coalesced; k_tau_store reads 16-byte pieces of 16
+// different grids per wave.
+constexpr int TS_P = 64, TS_NB = 2;
+template <typename G2, typename TD, int R>
+__global__ __launch_bounds__(256) void k_tau_store_lds(const G2* __restrict__ grids,
+                                                       const int2* __restrict__ IJ, long nblk,
+                                                       long nr, TD* __restrict__ dst,
+                                                       long dst_nblk, long dst_blk0) {
+  constexpr int NG = TS_NB * 32;  // complex grids of a workgroup
+  constexpr int RB = TS_P / R;    // point blocks of a workgroup
+  __shared__ G2 buf[NG][TS_P + 1];
+  const long nrb = nr / R;
+  const long npg = (nrb + RB - 1) / RB;
+  const long pg = blockIdx.x % npg;
+  const long blk0 = (blockIdx.x / npg) * TS_NB;
+  const long p0 = pg * TS_P;                  // first point
+  const long ngrid = nblk * 32;
+  for (int e = threadIdx.x; e < NG * TS_P; e += 256) {
+    const int g = e / TS_P, p = e % TS_P;
+    const long gg = blk0 * 32 + g, pp = p0 + p;
+    G2 v;
+    v.x = 0;
+    v.y = 0;
+    if (gg < ngrid && pp < nrb * R) v = grids[gg * nr + pp];
+    buf[g][p] = v;
+  }
+  __syncthreads();
+  constexpr int PER_RB = TS_NB * 64 * R;
+  for (int e = threadIdx.x; e < RB * PER_RB; e += 256) {
+    const int rbl = e / PER_RB;
+    const int rem = e % PER_RB;
+    const int bl = rem / (64 * R);
+    const int w = rem % (64 * R);
+    const int i = w % 8, ri = (w / 8) % R, j = w / (8 * R);
+    const long rb = pg * RB + rbl, blk = blk0 + bl;
+    if (rb >= nrb || blk >= nblk) continue;
+    const int el = bl * 64 + j * 8 + i;
+    const G2 g = buf[el >> 1][rbl * R + ri];
+    double v = (el & 1) ? g.y : g.x;
+    const int2 b = IJ[blk];
+    if (b.x == b.y) {
+      if (i > j)
+        v = 0.0;
+      else if (i == j)
+        v *= 0.5;
+    }
+    dst[rb * dst_nblk * 64 * R + (dst_blk0 + blk) * 64 * R + w] = (TD)v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // tau stream: for every grid point r, y[b][v](r) += sum_v' tau_{vv'}(r) a[b][v'](r)
 // with tau stored once per unordered pair as 8x8 blocks (diagonal blocks hold
@@ -1266,11 +1320,33 @@ int pair_density(const float2* phir, int nv, const int2* blkIJ, long nblk, long 
   return pair_density_impl(phir, nv, blkIJ, nblk, nr, grids, st);
 }
 
+static bool tau_store_lds_on() {
+  static const bool on = [] {
+    const char* e = getenv("BSEX_TAU_STORE_LDS");
+    return !e || atoi(e) != 0;
+  }();
+  return on;
+}
+
 template <typename G2, typename TD>
 static int tau_store_impl(const G2* grids, const int2* blkIJ, long nblk, long nr, int R,
                           TD* dst, long dst_nblk, long dst_blk0, hipStream_t st) {
   const long n = (nr / R) * nblk * 64 * R;
   if (n <= 0) return BSE_OK;
+  if (tau_store_lds_on() && (R == 1 || R == 2)) {
+    const long nrb = nr / R;
+    const long npg = (nrb + TS_P / R - 1) / (TS_P / R);
+    const long nwg = npg * ((nblk + TS_NB - 1) / TS_NB);
+    if (nwg > 0x7fffffffL) return fail(BSE_EINVAL, "tau store: %ld workgroups", nwg);
+    if (R == 2)
+      hipLaunchKernelGGL((k_tau_store_lds<G2, TD, 2>), dim3((unsigned)nwg), dim3(256), 0, st,
+                         grids, blkIJ, nblk, nr, dst, dst_nblk, dst_blk0);
+    else
+      hipLaunchKernelGGL((k_tau_store_lds<G2, TD, 1>), dim3((unsigned)nwg), dim3(256), 0, st,
+                         grids, blkIJ, nblk, nr, dst, dst_nblk, dst_blk0);
+    CHECK_LAUNCH();
+    return BSE_OK;
+  }
   hipLaunchKernelGGL((k_tau_store<G2, TD>), dim3(nblocks(n)), dim3(TPB), 0, st, grids, blkIJ, nblk,
                      nr, R, dst, dst_nblk, dst_blk0);
   CHECK_LAUNCH();
