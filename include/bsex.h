@@ -491,6 +491,16 @@ int bse_tune_cache_clear(void);
 
 int bse_free(bse_ctx *ctx);
 
+/* Device memory across contexts (this library's own; for callers that build
+ * one context per geometry, such as a relaxation).  on = 1: bse_free hands
+ * a context's device blocks, once its stream has drained, to a process-wide
+ * cache, and later contexts on the same device take their blocks from it
+ * (best fit, at most twice the size asked) before allocating; an allocation
+ * that fails returns the device's cached blocks and tries again.  on = 0:
+ * frees every cached block and stops caching.  The cached memory stays
+ * held (unavailable to other allocators) until then.  Default off. */
+int bse_memory_cache(int32_t on);
+
 #ifdef __cplusplus
 }
 #endif

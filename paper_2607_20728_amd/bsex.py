@@ -30,7 +30,7 @@ SYMBOLS = ("bse_abi_version", "bse_last_error", "bse_warm_up", "bse_basis_size",
            "bse_mlp_create", "bse_mlp_n_params", "bse_mlp_set_params", "bse_mlp_get_params",
            "bse_mlp_set_norm", "bse_mlp_forward", "bse_mlp_train_step", "bse_mlp_free",
            "bse_set_learned", "bse_learned_features", "bse_set_graphs", "bse_batch_run",
-           "bse_tune_cache_clear", "bse_free")
+           "bse_tune_cache_clear", "bse_free", "bse_memory_cache")
 LEARN_NFEAT, LEARN_NOUT = 8, 2
 
 
@@ -139,6 +139,7 @@ def lib():
     L.bse_forces_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.bse_ground_state_forces.argtypes = [C.c_void_p, dp]
     L.bse_set_precision.argtypes = [C.c_void_p, C.c_int32]
+    L.bse_memory_cache.argtypes = [C.c_int32]
     fp = C.POINTER(C.c_float)
     L.bse_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
                                  C.POINTER(C.c_void_p)]
@@ -590,3 +591,8 @@ def phase_times(ctx, reset=False):
 
 def free(ctx):
     ctx.free()
+
+
+def memory_cache(on=True):
+    """bse_memory_cache: keep freed contexts' device memory for later ones."""
+    _check(lib().bse_memory_cache(1 if on else 0))

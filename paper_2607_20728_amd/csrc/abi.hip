@@ -34,8 +34,14 @@ void ctx_destroy(bse_ctx* c) {
   if (c->st) (void)hipStreamSynchronize(c->st);
   graphs_destroy(c);
   if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
-  for (auto& b : c->allocs) (void)hipFree(b.p);
-  for (auto& b : c->pool) (void)hipFree(b.p);
+  if (cache_keeps()) {  // once the stream (the null stream too) has drained
+    (void)hipStreamSynchronize(c->st);
+    for (auto& b : c->allocs) cache_put(b);
+    for (auto& b : c->pool) cache_put(b);
+  } else {
+    for (auto& b : c->allocs) (void)hipFree(b.p);
+    for (auto& b : c->pool) (void)hipFree(b.p);
+  }
   c->allocs.clear();
   c->pool.clear();
   fft_plan_free(&c->fft);
@@ -171,7 +177,7 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   const double blk_tile_bytes = 8.0 * 64 * (2.0 * nr + 2.0 * npw + std::max(c->npdep, 1));
   size_t freeb = 0, totalb = 0;
   ctx_pool_flush(c);  // scratch of the ground-state solve goes back first
-  BSE_HIP(hipMemGetInfo(&freeb, &totalb));
+  BSE_TRY(mem_info(&freeb, &totalb));
   const bool has_budget = d->tau_budget_bytes > 0;
   // without an explicit budget, keep room for the solvers: a 128-vector
   // Davidson subspace and its products, the blocks beside them, graph
@@ -199,7 +205,7 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
     BSE_TRY(ctx_alloc_t(c, &c->tau_f, (size_t)c->nblk * 64 * nr));
     c->t_tau_alloc_ms += ms_since(ta);
     budget_left -= fbytes;
-    BSE_HIP(hipMemGetInfo(&freeb, &totalb));
+    BSE_TRY(mem_info(&freeb, &totalb));
   }
   bool full = false;
   if (d->tau_policy != BSE_TAU_REBUILD) {
@@ -234,7 +240,7 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   if (full) {
     ncache = c->nblk;
   } else if (d->tau_policy != BSE_TAU_REBUILD) {
-    BSE_HIP(hipMemGetInfo(&freeb, &totalb));
+    BSE_TRY(mem_info(&freeb, &totalb));
     double budget = (double)freeb - reserve;
     if (has_budget) budget = std::min(budget, budget_left);
     const long fit = budget > 0 ? (long)(budget / blk_bytes) : 0;
@@ -710,5 +716,7 @@ int bse_free(bse_ctx* c) {
   ctx_destroy(c);
   return BSE_OK;
 }
+
+int bse_memory_cache(int32_t on) { return memory_cache(on); }
 
 }  // extern "C"

@@ -26,6 +26,12 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
 };
+// process-wide cache of device blocks across contexts (bse_memory_cache)
+bool cache_keeps();
+void cache_put(const DevBuf& b);
+int memory_cache(int on);
+// hipMemGetInfo with this device's cached blocks counted as free
+int mem_info(size_t* freeb, size_t* totalb);
 
 }  // namespace bsex
 

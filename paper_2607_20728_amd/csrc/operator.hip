@@ -1,6 +1,7 @@
 // The DMPT BSE operator on the device: projector, transforms, K1e, tau
 // build and stream, combine, diagonal term (Eqs. 1-3).
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 
 #include "context.h"
@@ -17,16 +18,110 @@ namespace bsex {
 // batch.  Blocks are reused on the context's own stream only, so stream order
 // keeps every earlier use of a block ahead of its next one.  The cache is
 // returned to the device when an allocation fails, and at bse_free.
+//
+// Across contexts (bse_memory_cache): with the cache on, a context's blocks
+// go at bse_free to a process-wide cache (after its stream has drained),
+// and later contexts on the same device take their blocks from it before
+// calling hipMalloc.  A run that builds one context per geometry then
+// reuses the same memory instead of freeing and allocating ~10^11 bytes
+// per geometry (a fresh allocation of memory the device has just freed
+// can wait seconds while the driver clears it).
+namespace {
+std::mutex g_cache_mu;
+struct CachedBuf {
+  DevBuf b;
+  int dev;
+};
+std::vector<CachedBuf> g_cache;
+bool g_keep = false;
+
+int cur_dev() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d;
+}
+
+// best fit (at most twice the request) among blocks of `v`
+template <class V, class Get>
+long best_fit(const V& v, size_t bytes, Get get) {
+  long best = -1;
+  for (size_t i = 0; i < v.size(); ++i) {
+    const size_t b = get(v[i]).bytes;
+    if (b >= bytes && b <= 2 * bytes + (1u << 20) &&
+        (best < 0 || b < get(v[(size_t)best]).bytes))
+      best = (long)i;
+  }
+  return best;
+}
+
+bool cache_take(size_t bytes, DevBuf* out) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (g_cache.empty()) return false;
+  const int dev = cur_dev();
+  long best = -1;
+  for (size_t i = 0; i < g_cache.size(); ++i) {
+    const size_t b = g_cache[i].b.bytes;
+    if (g_cache[i].dev == dev && b >= bytes && b <= 2 * bytes + (1u << 20) &&
+        (best < 0 || b < g_cache[(size_t)best].b.bytes))
+      best = (long)i;
+  }
+  if (best < 0) return false;
+  *out = g_cache[(size_t)best].b;
+  g_cache.erase(g_cache.begin() + best);
+  return true;
+}
+
+// return this device's cached blocks to the device
+void cache_flush_dev() {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  const int dev = cur_dev();
+  std::vector<CachedBuf> keep;
+  for (auto& cb : g_cache) {
+    if (cb.dev == dev)
+      (void)hipFree(cb.b.p);
+    else
+      keep.push_back(cb);
+  }
+  g_cache.swap(keep);
+}
+}  // namespace
+
+int mem_info(size_t* freeb, size_t* totalb) {
+  BSE_HIP(hipMemGetInfo(freeb, totalb));
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  const int dev = cur_dev();
+  for (auto& cb : g_cache)
+    if (cb.dev == dev) *freeb += cb.b.bytes;
+  return BSE_OK;
+}
+
+bool cache_keeps() {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  return g_keep;
+}
+
+void cache_put(const DevBuf& b) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache.push_back(CachedBuf{b, cur_dev()});
+}
+
+int memory_cache(int on) {
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_keep = on != 0;
+  }
+  if (!on) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto& cb : g_cache) (void)hipFree(cb.b.p);
+    g_cache.clear();
+  }
+  return BSE_OK;
+}
+
 int ctx_alloc(bse_ctx* c, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
-  long best = -1;
-  for (size_t i = 0; i < c->pool.size(); ++i) {
-    const size_t b = c->pool[i].bytes;
-    if (b >= bytes && b <= 2 * bytes + (1u << 20) &&
-        (best < 0 || b < c->pool[(size_t)best].bytes))
-      best = (long)i;
-  }
+  const long best = best_fit(c->pool, bytes, [](const DevBuf& d) -> const DevBuf& { return d; });
   if (best >= 0) {
     const DevBuf d = c->pool[(size_t)best];
     c->pool.erase(c->pool.begin() + best);
@@ -34,13 +129,20 @@ int ctx_alloc(bse_ctx* c, void** p, size_t bytes) {
     *p = d.p;
     return BSE_OK;
   }
+  DevBuf cd;
+  if (cache_take(bytes, &cd)) {
+    c->allocs.push_back(cd);
+    *p = cd.p;
+    return BSE_OK;
+  }
   void* q = nullptr;
   hipError_t e = hipMalloc(&q, bytes);
-  if (e != hipSuccess && !c->pool.empty()) {
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     if (c->st) (void)hipStreamSynchronize(c->st);
     for (auto& b : c->pool) (void)hipFree(b.p);
     c->pool.clear();
+    cache_flush_dev();
     e = hipMalloc(&q, bytes);
   }
   if (e != hipSuccess) {

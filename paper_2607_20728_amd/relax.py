@@ -28,9 +28,10 @@ from . import bsex
 
 
 def evaluate(sysd, xyz, *, surface="es", spring=5.0, f_occ=2.0, tol=1e-9, n_extra=8,
-             precision=bsex.FP64, state=None):
+             precision=bsex.FP64, state=None, two_level=False):
     """(E, dE/dR [n_sites][3]) of the ground- ("gs") or excited-state ("es")
-    surface at site positions xyz, from a fresh context.
+    surface at site positions xyz, from a fresh context (two_level: the
+    solves use the two-level preconditioner on the n_extra conduction states).
 
     state (a dict, optional) carries solver state between the geometries of
     a relaxation: with state["warm"] true (the default) the Davidson solve
@@ -71,9 +72,9 @@ def evaluate(sysd, xyz, *, surface="es", spring=5.0, f_occ=2.0, tol=1e-9, n_extr
                                   device=phi.device)
                 z0 = torch.tensor(S.T @ state["Z"], dtype=torch.float64, device=phi.device)
             t1 = time.perf_counter()
-            w, X, ds = bsex.davidson(ctx, 1, tol=tol, x0=x0)
+            w, X, ds = bsex.davidson(ctx, 1, tol=tol, x0=x0, two_level=two_level)
             t2 = time.perf_counter()
-            Z, zs = bsex.zvector_solve(ctx, X[0], tol=tol, z0=z0)
+            Z, zs = bsex.zvector_solve(ctx, X[0], tol=tol, z0=z0, two_level=two_level)
             t3 = time.perf_counter()
             E += float(w[0])
             G = G + bsex.forces(ctx, X[0], Z, n)
@@ -145,10 +146,16 @@ def bfgs(fun, x0, *, gtol=1e-5, max_steps=50, max_step=0.2):
     return x, f, g, hist
 
 
-def relax(sysd, *, surface="es", start=None, gtol=1e-5, max_steps=50, evaluator=None, **kw):
+def relax(sysd, *, surface="es", start=None, gtol=1e-5, max_steps=50, evaluator=None,
+          keep_memory=None, **kw):
     """Relax the sites of a synth.make_system dict on one surface.
     evaluator(sysd, xyz, surface=..., **kw) -> (E, dE/dR) defaults to
-    evaluate (the library).  Returns (xyz [n_sites][3], E, history)."""
+    evaluate (the library).  keep_memory (default: with the library's own
+    evaluator): the library keeps each geometry's device memory for the next
+    (bse_memory_cache) while the relaxation runs.  Returns (xyz [n_sites][3],
+    E, history)."""
+    if keep_memory is None:
+        keep_memory = evaluator is None
     ev = evaluator or evaluate
     x0 = np.asarray(sysd["site_xyz"] if start is None else start, dtype=float)
     shape = x0.shape
@@ -157,7 +164,13 @@ def relax(sysd, *, surface="es", start=None, gtol=1e-5, max_steps=50, evaluator=
         E, G = ev(sysd, x.reshape(shape), surface=surface, **kw)
         return E, np.asarray(G, dtype=float).reshape(-1)
 
-    x, E, _, hist = bfgs(fun, x0.reshape(-1), gtol=gtol, max_steps=max_steps)
+    if keep_memory:
+        bsex.memory_cache(True)
+    try:
+        x, E, _, hist = bfgs(fun, x0.reshape(-1), gtol=gtol, max_steps=max_steps)
+    finally:
+        if keep_memory:
+            bsex.memory_cache(False)
     return x.reshape(shape), E, hist
 
 
