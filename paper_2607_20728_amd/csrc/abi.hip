@@ -233,6 +233,7 @@ int plan_tau(bse_ctx* c, const bse_system_desc* d) {
   BSE_TRY(ctx_alloc_t(c, &c->rebuild_buf, (size_t)c->tile_blk * 64 * nr));
   if (c->npdep > 0) {
     BSE_TRY(ctx_alloc_t(c, &c->tile_RS, (size_t)te * npw));
+    BSE_TRY(ctx_alloc_t(c, &c->tile_cmp, (size_t)c->tile_blk * 32 * npw));
     BSE_TRY(ctx_alloc_t(c, &c->tile_F, (size_t)te * npw));
     BSE_TRY(ctx_alloc_t(c, &c->tile_T, (size_t)te * c->npdep));
   }

@@ -108,6 +108,7 @@ struct SpherePlan {
   int m2 = 0, m3 = 0;  // largest |n2|, |n3| of the sphere's modes
   int *plane_i1 = nullptr, *plane_off = nullptr, *ent_pos = nullptr, *ent_code = nullptr;
   int *e_plus = nullptr, *e_minus = nullptr;  // entry index of +G_k / -G_k
+  int* plane_sp = nullptr;  // [N1]: sphere plane of grid plane i1, -1 when it holds no mode
 };
 int sphere_plan_build(const FftPlan& p, const Basis& b, SpherePlan* sp);
 void sphere_plan_free(SpherePlan* sp);
@@ -124,6 +125,33 @@ int grid_to_compact(const FftPlan& p, const SpherePlan& sp, double2* grid, long 
                     double2* compact, hipStream_t st);
 int grid_to_compact(const FftPlan& p, const SpherePlan& sp, float2* grid, long batch,
                     float2* compact, hipStream_t st);
+// Forward 3-D FFT of the pair grids of a W build (Eqs. 2c, 3), the pointwise
+// work fused into the last (plane) pass: each grid leaves as its transform
+// times f(G) * s (zero when f is NULL: no bare Coulomb part) and, when
+// compact is set, the transform's sphere entries (unscaled) go to
+// compact[g][e] as grid_to_compact writes them (the PDEP projection reads
+// them there).
+int fft3d_fwd_w(const FftPlan& p, const SpherePlan& sp, double2* data, long batch,
+                const double* f, double s, double2* compact, hipStream_t st);
+int fft3d_fwd_w(const FftPlan& p, const SpherePlan& sp, float2* data, long batch, const float* f,
+                float s, float2* compact, hipStream_t st);
+// The same transform with the pair grids formed inside its first pass from
+// the packed orbitals orb and the block list IJ (nblk blocks of 32 grids, the
+// tile layout of pair_density), when the axis-1 length has a direct-access
+// pass (fwd_pairs_supported; fails otherwise).
+bool fwd_pairs_supported(const FftPlan& p, bool f32);
+int fft3d_fwd_pairs(const FftPlan& p, const SpherePlan& sp, const double2* orb, int nv,
+                    const int2* IJ, long nblk, double2* data, const double* f, double s,
+                    double2* compact, hipStream_t st);
+int fft3d_fwd_pairs(const FftPlan& p, const SpherePlan& sp, const float2* orb, int nv,
+                    const int2* IJ, long nblk, float2* data, const float* f, float s,
+                    float2* compact, hipStream_t st);
+// ... and with grid q < nm formed as M[q] times the real field x
+// (component xc of the packed grid x2), the pair products of the
+// exchange-like terms
+int fft3d_fwd_times(const FftPlan& p, const SpherePlan& sp, const double2* M, long nm,
+                    const double2* x2, int xc, double2* data, const double* f, double s,
+                    double2* compact, hipStream_t st);
 
 // ---- GEMM -----------------------------------------------------------------------
 // C[M][N] = alpha op(A) op(B) + beta C, row-major, FP64 MFMA.

@@ -51,6 +51,7 @@ struct bse_ctx {
   // PDEP work of the exchange form of W (coupling beyond the TDA):
   // sphere coefficients [nv][npw], PDEP projections [nv][npdep], result [nv][npw]
   double *wx_RS = nullptr, *wx_T = nullptr, *wx_F = nullptr;
+  double2* wx_cmp = nullptr;  // [nvh][npw] sphere entries of the pair transforms
   double2* xgrid = nullptr;   // [xgrid_sets][nvh][nr] -alpha K_x a of an apply block
   int xgrid_sets = 0;
   double t_gs_ms = 0, t_tau_ms = 0, t_tau_alloc_ms = 0, t_init_ms = 0;  // init stages, wall
@@ -88,6 +89,7 @@ struct bse_ctx {
   double* tau_cache = nullptr;
   double2* tile_grids = nullptr;
   double *tile_RS = nullptr, *tile_T = nullptr, *tile_F = nullptr;
+  double2* tile_cmp = nullptr;  // sphere entries of the tile's transforms [grid][n_pw]
   double* rebuild_buf = nullptr;
   // apply work, chunks of at most nbc vectors
   int nbc = 0;

@@ -122,11 +122,12 @@ int sphere_plan_build(const FftPlan& p, const Basis& b, SpherePlan* sp) {
     return x.i1 != y.i1 ? x.i1 < y.i1 : x.pos < y.pos;
   });
   std::vector<int> planes, off, pos(ents.size()), code(ents.size());
-  std::vector<int> eplus(b.nhalf), eminus(b.nhalf);
+  std::vector<int> eplus(b.nhalf), eminus(b.nhalf), plane_sp(N1, -1);
   int ezero = 0, nmax1 = 0;
   sp->m2 = sp->m3 = 0;
   for (size_t e = 0; e < ents.size(); ++e) {
     if (planes.empty() || planes.back() != ents[e].i1) {
+      plane_sp[ents[e].i1] = (int)planes.size();
       planes.push_back(ents[e].i1);
       off.push_back((int)e);
       const int n1 = (ents[e].i1 < (N1 + 1) / 2) ? ents[e].i1 : ents[e].i1 - N1;
@@ -159,12 +160,13 @@ int sphere_plan_build(const FftPlan& p, const Basis& b, SpherePlan* sp) {
   BSE_TRY(up(&sp->ent_code, code));
   BSE_TRY(up(&sp->e_plus, eplus));
   BSE_TRY(up(&sp->e_minus, eminus));
+  BSE_TRY(up(&sp->plane_sp, plane_sp));
   return BSE_OK;
 }
 
 void sphere_plan_free(SpherePlan* sp) {
   int** ptrs[] = {&sp->plane_i1, &sp->plane_off, &sp->ent_pos, &sp->ent_code, &sp->e_plus,
-                  &sp->e_minus};
+                  &sp->e_minus, &sp->plane_sp};
   for (int** q : ptrs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -176,6 +178,32 @@ int fft3d(const FftPlan& p, double2* data, long batch, int dir, hipStream_t st) 
 }
 int fft3d(const FftPlan& p, float2* data, long batch, int dir, hipStream_t st) {
   return f32::fft3d(p, data, batch, dir, st);
+}
+int fft3d_fwd_w(const FftPlan& p, const SpherePlan& sp, double2* data, long batch,
+                const double* f, double s, double2* compact, hipStream_t st) {
+  return f64::fft3d_fwd_w(p, sp, data, batch, f, s, compact, st);
+}
+int fft3d_fwd_w(const FftPlan& p, const SpherePlan& sp, float2* data, long batch, const float* f,
+                float s, float2* compact, hipStream_t st) {
+  return f32::fft3d_fwd_w(p, sp, data, batch, f, s, compact, st);
+}
+bool fwd_pairs_supported(const FftPlan& p, bool f32) {
+  return f32 ? f32::fwd_pairs_supported(p) : f64::fwd_pairs_supported(p);
+}
+int fft3d_fwd_pairs(const FftPlan& p, const SpherePlan& sp, const double2* orb, int nv,
+                    const int2* IJ, long nblk, double2* data, const double* f, double s,
+                    double2* compact, hipStream_t st) {
+  return f64::fft3d_fwd_pairs(p, sp, orb, nv, IJ, nblk, data, f, s, compact, st);
+}
+int fft3d_fwd_times(const FftPlan& p, const SpherePlan& sp, const double2* M, long nm,
+                    const double2* x2, int xc, double2* data, const double* f, double s,
+                    double2* compact, hipStream_t st) {
+  return f64::fft3d_fwd_times(p, sp, M, nm, x2, xc, data, f, s, compact, st);
+}
+int fft3d_fwd_pairs(const FftPlan& p, const SpherePlan& sp, const float2* orb, int nv,
+                    const int2* IJ, long nblk, float2* data, const float* f, float s,
+                    float2* compact, hipStream_t st) {
+  return f32::fft3d_fwd_pairs(p, sp, orb, nv, IJ, nblk, data, f, s, compact, st);
 }
 int sphere_to_grid(const FftPlan& p, const SpherePlan& sp, double omega, const double* X, int nv,
                    int nset, double2* grid, hipStream_t st) {

@@ -192,7 +192,33 @@ struct PlaneArgs {
   int m2, m3;             // the sphere's modes have |n2| <= m2 and |n3| <= m3
   long batch;             // grids (pruned inverse kernel: workgroups beyond are idle)
   int group;              // pruned inverse kernel: the planes of a grid on one XCD
+  const int* plane_sp;    // OUT == 2: [N1] sphere plane of grid plane i1 (-1: none)
+  const real* mulf;       // OUT == 2: real field the plane leaves multiplied by (NULL: 0)
+  real muls;              //           and its scale
 };
+
+// OUT == 2 (forward transform of a W build): the finished plane P of grid g
+// goes back times mulf * muls, and its sphere entries, unscaled, to the
+// compact output when one is set
+__device__ __forceinline__ void plane_store_w(const cplx* P, cplx* gp, const PlaneArgs& pa,
+                                              long g, int i1, int np2, int nt) {
+  const real* f = pa.mulf ? pa.mulf + (long)i1 * np2 : nullptr;
+  for (int e = threadIdx.x; e < np2; e += nt) {
+    const real m = f ? f[e] * pa.muls : (real)0;
+    cplx x = P[e];
+    x.x *= m;
+    x.y *= m;
+    gp[e] = x;
+  }
+  if (pa.compact) {
+    const int sp = pa.plane_sp[i1];
+    if (sp >= 0) {
+      cplx* cg = pa.compact + g * (long)pa.nent;
+      for (int e = pa.plane_off[sp] + threadIdx.x; e < pa.plane_off[sp + 1]; e += nt)
+        cg[e] = P[pa.ent_pos[e]];
+    }
+  }
+}
 
 template <int DIR, int IN, int OUT>
 __global__ __launch_bounds__(kPlaneThreads) void k_fft_plane(cplx* data, PlaneArgs pa,
@@ -237,6 +263,8 @@ __global__ __launch_bounds__(kPlaneThreads) void k_fft_plane(cplx* data, PlaneAr
   plane_lines<DIR>(P, N3, 1, N3, ay, S0, S1, pa.LB, kPlaneThreads);
   if (OUT == 0) {
     for (int e = threadIdx.x; e < np2; e += kPlaneThreads) gp[e] = P[e];
+  } else if (OUT == 2) {
+    plane_store_w(P, gp, pa, g, i1, np2, kPlaneThreads);
   } else {
     cplx* cg = pa.compact + g * (long)pa.nent;
     for (int e = pa.plane_off[pl] + threadIdx.x; e < pa.plane_off[pl + 1]; e += kPlaneThreads)
@@ -412,6 +440,8 @@ __global__ __launch_bounds__(kPlaneThreads) void k_fft_plane_ct(cplx* data, Plan
   if (OUT == 0) {
 #pragma unroll 4
     for (int e = threadIdx.x; e < NP2; e += NT) gp[e] = P[e];
+  } else if (OUT == 2) {
+    plane_store_w(P, gp, pa, g, i1, NP2, NT);
   } else {
     cplx* cg = pa.compact + g * (long)pa.nent;
     for (int e = pa.plane_off[pl] + threadIdx.x; e < pa.plane_off[pl + 1]; e += NT)
@@ -768,6 +798,69 @@ __global__ __launch_bounds__(kThreads) void k_fft_axis_gd(cplx* __restrict__ dat
   fn_passes<N, DIR, L, kThreads, 0, 1>(ld, st, S0, S1, nl, ax.tw);
 }
 
+// Forward axis-1 pass over the pair grids of a W build (Eqs. 2c, 3) with the
+// pair products formed in its first pass, so the pair grids are never
+// written before their transform.  Two sources:
+//  * IJ set (tau build): grid q = 32 blk + 4 j + m of block blk = (I, J)
+//    holds phi_{8I+2m} phi_{8J+j} + i phi_{8I+2m+1} phi_{8J+j} (the tile
+//    layout of the pair-density kernel); orbital v is the real (v even) or
+//    imaginary (v odd) part of packed grid v / 2 of orb, zero for v >= nv;
+//  * IJ NULL (exchange-like terms): grid q < ngrid holds orb[q] times the
+//    real field x (component xc of the packed grid x2).
+// The 32 grids of one group of 32 and one line tile run on one XCD
+// (xcd_item), where they share their common factors' lines in L2.
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_fft_axis_pairs(cplx* __restrict__ data, AxisArgs ax,
+                                                             const cplx* __restrict__ orb, int nv,
+                                                             const int2* __restrict__ IJ,
+                                                             const cplx* __restrict__ x2, int xc,
+                                                             long ngrid, int np2, long nr,
+                                                             int group) {
+  constexpr int L = axis_gd_l<N>();
+  static_assert(factor(N).n >= 2, "");
+  extern __shared__ cplx lds[];
+  cplx* S0 = lds;
+  cplx* S1 = lds + N * L;
+  const int tiles = (np2 + L - 1) / L;
+  const long nblk = (ngrid + 31) / 32;
+  long item;
+  int sub;
+  xcd_item(blockIdx.x, 32, group != 0, item, sub);
+  if (item >= nblk * tiles) return;
+  const int tile = (int)(item % tiles);
+  const long blk = item / tiles;
+  const long q = blk * 32 + sub;
+  if (q >= ngrid) return;
+  const int i0 = tile * L;
+  const int nl = min(L, np2 - i0);
+  const cplx *oa, *ow;
+  bool a_ok = true, a1_ok = true, w_ok = true, w_im = xc != 0;
+  if (IJ) {
+    const int2 b = IJ[blk];
+    const int va = 8 * b.x + 2 * (sub & 3), vw = 8 * b.y + (sub >> 2);
+    a_ok = va < nv;
+    a1_ok = va + 1 < nv;
+    w_ok = vw < nv;
+    w_im = (vw & 1) != 0;
+    // va is even: phi_va and phi_va+1 are the two parts of one packed grid
+    oa = orb + (long)(va >> 1) * nr + i0;
+    ow = orb + (long)(vw >> 1) * nr + i0;
+  } else {
+    oa = orb + q * nr + i0;
+    ow = x2 + i0;
+  }
+  cplx* out = data + q * nr + i0;
+  auto ld = [=](int k, int l) {
+    const long r = (long)k * np2 + l;
+    const cplx a = a_ok ? oa[r] : mk(0.0, 0.0);
+    const cplx wv = w_ok ? ow[r] : mk(0.0, 0.0);
+    const real w = w_im ? wv.y : wv.x;
+    return mk(a.x * w, a1_ok ? a.y * w : (real)0);
+  };
+  auto st = [=](int k, int l, cplx v) { out[(long)k * np2 + l] = v; };
+  fn_passes<N, -1, L, kThreads, 0, 1>(ld, st, S0, S1, nl, ax.tw);
+}
+
 int lines_per_group(int n) {
   // about 16 KB of LDS per buffer; at least 4 lines
   int L = 16384 / ((int)sizeof(cplx) * n);
@@ -888,6 +981,19 @@ bool launch_axis_gd_n(int n, int dir, dim3 grid, size_t shm, hipStream_t st, cpl
   return false;
 }
 
+template <int N>
+bool launch_axis_pairs_n(int n, dim3 grid, size_t shm, hipStream_t st, cplx* data, AxisArgs ax,
+                         const cplx* orb, int nv, const int2* IJ, const cplx* x2, int xc,
+                         long ngrid, int np2, long nr, int group) {
+  if constexpr (axis_gd_ok<N>()) {
+    if (n != N) return false;
+    hipLaunchKernelGGL((k_fft_axis_pairs<N>), grid, dim3(kThreads), shm, st, data, ax, orb, nv,
+                       IJ, x2, xc, ngrid, np2, nr, group);
+    return true;
+  }
+  return false;
+}
+
 void launch_axis_gd(int n, int dir, dim3 grid, size_t shm, hipStream_t st, cplx* data,
                     AxisArgs ax, int es, int n_inner, long s_in, int n_o2, long s_o2, long s_o1,
                     int ld_lim, int st_lim) {
@@ -906,6 +1012,8 @@ int set_axis_gd_lds() {
     BSE_HIP(hipFuncSetAttribute((const void*)k_fft_axis_gd<N, -1>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, g));
     BSE_HIP(hipFuncSetAttribute((const void*)k_fft_axis_gd<N, 1>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, g));
+    BSE_HIP(hipFuncSetAttribute((const void*)k_fft_axis_pairs<N>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, g));
   }
   return BSE_OK;
@@ -931,7 +1039,8 @@ int set_ct_lds_limits(int n2, int n3, int n1) {
     const void* fns[] = {(const void*)k_fft_plane_ct<A, B, -1, 0, 0>,                            \
                          (const void*)k_fft_plane_ct<A, B, 1, 0, 0>,                             \
                          (const void*)k_fft_plane_ct<A, B, 1, 1, 0>,                             \
-                         (const void*)k_fft_plane_ct<A, B, -1, 0, 1>};                           \
+                         (const void*)k_fft_plane_ct<A, B, -1, 0, 1>,                            \
+                         (const void*)k_fft_plane_ct<A, B, -1, 0, 2>};                           \
     for (const void* f : fns)                                                                    \
       BSE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, need));         \
   }
@@ -1167,7 +1276,8 @@ int init_kernels(FftPlan* p) {
   if (need > p->max_lds)
     return fail(BSE_EINVAL, "FFT plane %dx%d does not fit the device LDS", p->N[1], p->N[2]);
   const void* fns[] = {(const void*)k_fft_plane<-1, 0, 0>, (const void*)k_fft_plane<1, 0, 0>,
-                       (const void*)k_fft_plane<1, 1, 0>, (const void*)k_fft_plane<-1, 0, 1>};
+                       (const void*)k_fft_plane<1, 1, 0>, (const void*)k_fft_plane<-1, 0, 1>,
+                       (const void*)k_fft_plane<-1, 0, 2>};
   for (const void* f : fns)
     BSE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
   bool ctp = plane_ct_supported(p->N[1], p->N[2]) && plane_ct_lds(p->N[1], p->N[2]) <= p->max_lds;
@@ -1200,6 +1310,77 @@ int fft3d(const FftPlan& p, cplx* data, long batch, int dir, hipStream_t st) {
     BSE_TRY((launch_plane<-1, 0, 0>(p, data, batch, pa, st)));
   }
   return BSE_OK;
+}
+
+// the plane pass of a W build's forward transform (OUT == 2)
+static int plane_fwd_w(const FftPlan& p, const SpherePlan& sp, cplx* data, long batch,
+                       const real* f, real s, cplx* compact, hipStream_t st) {
+  if (compact && !sp.plane_sp) return fail(BSE_EINVAL, "fused W transform: no sphere plan");
+  const int all = p.N[0];
+  PlaneArgs pa{};
+  pa.nplanes = all;
+  pa.plane_sp = sp.plane_sp;
+  pa.plane_off = sp.plane_off;
+  pa.ent_pos = sp.ent_pos;
+  pa.nent = sp.nent;
+  pa.compact = compact;
+  pa.mulf = f;
+  pa.muls = s;
+  return launch_plane<-1, 0, 2>(p, data, batch, pa, st);
+}
+
+int fft3d_fwd_w(const FftPlan& p, const SpherePlan& sp, cplx* data, long batch, const real* f,
+                real s, cplx* compact, hipStream_t st) {
+  if (batch <= 0) return BSE_OK;
+  BSE_TRY(x_pass(p, data, batch, -1, p.N[0], p.N[0], st));
+  return plane_fwd_w(p, sp, data, batch, f, s, compact, st);
+}
+
+bool fwd_pairs_supported(const FftPlan& p) {
+  return p.ct_axis[BSEX_FFT_PREC] && p.axis_direct[BSEX_FFT_PREC] && axis_gd_supported(p.N[0]);
+}
+
+// first pass of fft3d_fwd_pairs / fft3d_fwd_times (k_fft_axis_pairs)
+static int axis_pairs(const FftPlan& p, const cplx* orb, int nv, const int2* IJ, const cplx* x2,
+                      int xc, long ngrid, cplx* data, hipStream_t st) {
+  if (!fwd_pairs_supported(p))
+    return fail(BSE_EINVAL, "pair-forming transform: axis length %d", p.N[0]);
+  const int np2 = p.N[1] * p.N[2];
+  const long tiles = (np2 + axis_gd_lines(p.N[0]) - 1) / axis_gd_lines(p.N[0]);
+  const long items = (ngrid + 31) / 32 * tiles;
+  const int group = xcd_group_on() ? 1 : 0;
+  const long groups = 32 * (group ? round8(items) : items);
+  if (groups > 0x7fffffffL) return fail(BSE_EINVAL, "FFT batch too large");
+  const AxisArgs ax = axis_args(p.ax[0]);
+  const dim3 grid((unsigned)groups);
+  const size_t shm = axis_gd_lds_of(p.N[0]);
+  const int n1 = p.N[0];
+  bool done = false;
+#define C(K)                                                                               \
+  if (!done)                                                                               \
+    done = launch_axis_pairs_n<K>(n1, grid, shm, st, data, ax, orb, nv, IJ, x2, xc, ngrid, \
+                                  np2, p.nr, group);
+  BSEX_AXIS_SIZES(C)
+#undef C
+  if (!done) return fail(BSE_EINVAL, "pair-forming transform: axis length %d", p.N[0]);
+  BSE_HIP(hipGetLastError());
+  return BSE_OK;
+}
+
+int fft3d_fwd_pairs(const FftPlan& p, const SpherePlan& sp, const cplx* orb, int nv,
+                    const int2* IJ, long nblk, cplx* data, const real* f, real s, cplx* compact,
+                    hipStream_t st) {
+  if (nblk <= 0) return BSE_OK;
+  BSE_TRY(axis_pairs(p, orb, nv, IJ, nullptr, 0, nblk * 32, data, st));
+  return plane_fwd_w(p, sp, data, nblk * 32, f, s, compact, st);
+}
+
+int fft3d_fwd_times(const FftPlan& p, const SpherePlan& sp, const cplx* M, long nm,
+                    const cplx* x2, int xc, cplx* data, const real* f, real s, cplx* compact,
+                    hipStream_t st) {
+  if (nm <= 0) return BSE_OK;
+  BSE_TRY(axis_pairs(p, M, 0, nullptr, x2, xc, nm, data, st));
+  return plane_fwd_w(p, sp, data, nm, f, s, compact, st);
 }
 
 int sphere_to_grid(const FftPlan& p, const SpherePlan& sp, double omega, const double* X, int nv,

@@ -303,28 +303,64 @@ int apply_H(bse_ctx* c, int nvs, int nset, const double* X, double* Y, double2* 
 //   bare part: v_c(G) on every grid frequency; PDEP part (Eq. 3):
 //   sum_j e_j [V^1/2 P C P^T V^1/2 rho_S]_j  via two GEMMs per tile.
 // ---------------------------------------------------------------------------
+// the forward transform of a W build with the bare Coulomb multiply (or the
+// zero fill) fused into its last pass and the PDEP projection's sphere
+// entries taken there (fft3d_fwd_w); BSEX_W_FUSED=0 selects the separate
+// transform, gather and multiply kernels
+static bool w_fused_on() {
+  static const bool on = [] {
+    const char* e = getenv("BSEX_W_FUSED");
+    return !e || atoi(e) != 0;
+  }();
+  return on;
+}
+// ... and with the pair products formed in its first pass (fft3d_fwd_pairs)
+// where the axis-1 length allows; BSEX_W_PAIRS=0 keeps the pair-density kernel
+static bool w_pairs_on(const bse_ctx* c, bool f32) {
+  static const bool on = [] {
+    const char* e = getenv("BSEX_W_PAIRS");
+    return !e || atoi(e) != 0;
+  }();
+  return on && w_fused_on() && fwd_pairs_supported(c->fft, f32);
+}
+
 int tau_build_range(bse_ctx* c, const double2* orbr, long gb0, long nblk, double* dst,
                     long dst_nblk, long dst_blk0, int mask, float* dstf) {
   if (nblk <= 0) return BSE_OK;
   if (nblk > c->tile_blk) return fail(BSE_EINVAL, "tau build: tile of %ld blocks too large", nblk);
   const long nr = c->basis.nr, npw = c->basis.npw;
   const long ng = nblk * 32, ne = nblk * 64;
-  BSE_TRY(pair_density(orbr, c->nv, c->blkIJ + gb0, nblk, nr, c->tile_grids, c->st));
-  BSE_TRY(fft3d(c->fft, c->tile_grids, ng, -1, c->st));
   SphereMap m64 = c->map;
   const bool pdep = (mask & BSE_K_1D_PDEP) && c->npdep > 0;
+  const bool bare = (mask & BSE_K_1D_BARE) != 0;
+  const bool fused = w_fused_on();
+  // the grids leave the forward transform times v_c / N_r, their sphere
+  // entries in tile_cmp
+  if (w_pairs_on(c, false)) {
+    BSE_TRY(fft3d_fwd_pairs(c->fft, c->sp, orbr, c->nv, c->blkIJ + gb0, nblk, c->tile_grids,
+                            bare ? c->vc : nullptr, 1.0 / (double)nr,
+                            pdep ? c->tile_cmp : nullptr, c->st));
+  } else {
+    BSE_TRY(pair_density(orbr, c->nv, c->blkIJ + gb0, nblk, nr, c->tile_grids, c->st));
+    if (fused)
+      BSE_TRY(fft3d_fwd_w(c->fft, c->sp, c->tile_grids, ng, bare ? c->vc : nullptr,
+                          1.0 / (double)nr, pdep ? c->tile_cmp : nullptr, c->st));
+    else
+      BSE_TRY(fft3d(c->fft, c->tile_grids, ng, -1, c->st));
+  }
   if (pdep) {
     // rho_S[e][j] = <e_j | rho_e>
-    BSE_TRY(gather_sets(m64, c->tile_grids, 64, (int)nblk, 1.0 / (double)nr, nullptr, nullptr,
-                        nullptr, 0.0, 0.0, c->tile_RS, c->st));
+    BSE_TRY(gather_sets(fused ? c->cmap : m64, fused ? c->tile_cmp : c->tile_grids, 64,
+                        (int)nblk, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0, 0.0,
+                        c->tile_RS, c->st));
     BSE_TRY(gemm(c, 0, 0, ne, c->npdep, npw, 1.0, c->tile_RS, npw, c->Pt, c->npdep, 0.0,
                  c->tile_T, c->npdep));
     BSE_TRY(dgemm(0, 1, ne, npw, c->npdep, 1.0, c->tile_T, c->npdep, c->Ptc, c->npdep, 0.0,
                   c->tile_F, npw, c->st));
   }
-  if (mask & BSE_K_1D_BARE)
+  if (!fused && bare)
     BSE_TRY(mul_real_field(c->tile_grids, ng, nr, c->vc, 1.0 / (double)nr, c->st));
-  else  // a fill kernel, not a memset: this may run inside a captured graph
+  else if (!fused)  // a fill kernel, not a memset: this may run inside a captured graph
     BSE_TRY(zero_fill(reinterpret_cast<double*>(c->tile_grids), 2 * ng * nr, c->st));
   if (pdep) BSE_TRY(scatter_sets(m64, c->tile_F, 64, (int)nblk, c->tile_grids, 1, c->st));
   BSE_TRY(fft3d(c->fft, c->tile_grids, ng, +1, c->st));
@@ -347,10 +383,25 @@ int tau_build_range_f(bse_ctx* c, const float2* orbr, long gb0, long nblk, float
   const long nr = c->basis.nr, npw = c->basis.npw;
   const long ng = nblk * 32, ne = nblk * 64;
   float2* tg = reinterpret_cast<float2*>(c->tile_grids);
-  BSE_TRY(pair_density(orbr, c->nv, c->blkIJ + gb0, nblk, nr, tg, c->st));
-  BSE_TRY(fft3d(c->fft, tg, ng, -1, c->st));
   SphereMap m64 = c->map;
   const bool pdep = (mask & BSE_K_1D_PDEP) && c->npdep > 0;
+  const bool bare = (mask & BSE_K_1D_BARE) != 0;
+  const bool fused = w_fused_on();
+  float2* cmp = reinterpret_cast<float2*>(c->tile_cmp);
+  if (w_pairs_on(c, true)) {
+    BSE_TRY(fft3d_fwd_pairs(c->fft, c->sp, orbr, c->nv, c->blkIJ + gb0, nblk, tg,
+                            bare ? c->vc_f : nullptr, 1.0f / (float)nr, pdep ? cmp : nullptr,
+                            c->st));
+  } else {
+    BSE_TRY(pair_density(orbr, c->nv, c->blkIJ + gb0, nblk, nr, tg, c->st));
+    if (fused)
+      BSE_TRY(fft3d_fwd_w(c->fft, c->sp, tg, ng, bare ? c->vc_f : nullptr, 1.0f / (float)nr,
+                          pdep ? cmp : nullptr, c->st));
+    else
+      BSE_TRY(fft3d(c->fft, tg, ng, -1, c->st));
+  }
+  const SphereMap& mg = fused ? c->cmap : m64;
+  const float2* src = fused ? cmp : tg;
   // PDEP part (Eq. 3) in FP32 when the context holds FP32 copies of the
   // basis (the tile buffers hold twice the floats needed), else FP64
   const bool f32 = pdep && c->Pt_f;
@@ -358,22 +409,22 @@ int tau_build_range_f(bse_ctx* c, const float2* orbr, long gb0, long nblk, float
   float* tt = reinterpret_cast<float*>(c->tile_T);
   float* tf = reinterpret_cast<float*>(c->tile_F);
   if (f32) {
-    BSE_TRY(gather_sets(m64, tg, 64, (int)nblk, 1.0 / (double)nr, rs, c->st));
+    BSE_TRY(gather_sets(mg, src, 64, (int)nblk, 1.0 / (double)nr, rs, c->st));
     BSE_TRY(sgemm(0, 0, ne, c->npdep, npw, 1.0f, rs, npw, c->Pt_f, c->npdep, 0.0f, tt,
                   c->npdep, c->st));
     BSE_TRY(sgemm(0, 1, ne, npw, c->npdep, 1.0f, tt, c->npdep, c->Ptc_f, c->npdep, 0.0f, tf,
                   npw, c->st));
   } else if (pdep) {
-    BSE_TRY(gather_sets(m64, tg, 64, (int)nblk, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0,
+    BSE_TRY(gather_sets(mg, src, 64, (int)nblk, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0,
                         0.0, c->tile_RS, c->st));
     BSE_TRY(gemm(c, 0, 0, ne, c->npdep, npw, 1.0, c->tile_RS, npw, c->Pt, c->npdep, 0.0,
                  c->tile_T, c->npdep));
     BSE_TRY(dgemm(0, 1, ne, npw, c->npdep, 1.0, c->tile_T, c->npdep, c->Ptc, c->npdep, 0.0,
                   c->tile_F, npw, c->st));
   }
-  if (mask & BSE_K_1D_BARE)
+  if (!fused && bare)
     BSE_TRY(mul_real_field(tg, ng, nr, c->vc_f, 1.0f / (float)nr, c->st));
-  else  // one float2 per double
+  else if (!fused)  // one float2 per double
     BSE_TRY(zero_fill(reinterpret_cast<double*>(tg), ng * nr, c->st));
   if (f32)
     BSE_TRY(scatter_sets(m64, tf, 64, (int)nblk, tg, 1, c->st));
@@ -514,23 +565,35 @@ static int w_exchange_like(bse_ctx* c, const double2* L, const double2* M, const
     BSE_TRY(ctx_alloc_t(c, &c->wx_RS, (size_t)nv * npw));
     BSE_TRY(ctx_alloc_t(c, &c->wx_T, (size_t)nv * c->npdep));
     BSE_TRY(ctx_alloc_t(c, &c->wx_F, (size_t)nv * npw));
+    BSE_TRY(ctx_alloc_t(c, &c->wx_cmp, (size_t)c->nvh * npw));
   }
   double2* P = c->xpair;
   SphereMap m = c->map;
+  const bool fused = w_fused_on(), pairs = w_pairs_on(c, false);
   for (int v = 0; v < nx; ++v) {
-    BSE_TRY(pair_times(M, nv, x + (long)(v >> 1) * nr, v & 1, nr, P, c->st));
-    BSE_TRY(fft3d(c->fft, P, c->nvh, -1, c->st));
+    const double2* xv = x + (long)(v >> 1) * nr;
+    if (pairs) {
+      BSE_TRY(fft3d_fwd_times(c->fft, c->sp, M, c->nvh, xv, v & 1, P, bare ? c->vc : nullptr,
+                              1.0 / (double)nr, pdep ? c->wx_cmp : nullptr, c->st));
+    } else {
+      BSE_TRY(pair_times(M, nv, xv, v & 1, nr, P, c->st));
+      if (fused)
+        BSE_TRY(fft3d_fwd_w(c->fft, c->sp, P, c->nvh, bare ? c->vc : nullptr, 1.0 / (double)nr,
+                            pdep ? c->wx_cmp : nullptr, c->st));
+      else
+        BSE_TRY(fft3d(c->fft, P, c->nvh, -1, c->st));
+    }
     if (pdep) {
-      BSE_TRY(gather_sets(m, P, nv, 1, 1.0 / (double)nr, nullptr, nullptr, nullptr, 0.0, 0.0,
-                          c->wx_RS, c->st));
+      BSE_TRY(gather_sets(fused ? c->cmap : m, fused ? c->wx_cmp : P, nv, 1, 1.0 / (double)nr,
+                          nullptr, nullptr, nullptr, 0.0, 0.0, c->wx_RS, c->st));
       BSE_TRY(gemm(c, 0, 0, nv, c->npdep, npw, 1.0, c->wx_RS, npw, c->Pt, c->npdep, 0.0,
                    c->wx_T, c->npdep));
       BSE_TRY(dgemm(0, 1, nv, npw, c->npdep, 1.0, c->wx_T, c->npdep, c->Ptc, c->npdep, 0.0,
                     c->wx_F, npw, c->st));
     }
-    if (bare)
+    if (!fused && bare)
       BSE_TRY(mul_real_field(P, c->nvh, nr, c->vc, 1.0 / (double)nr, c->st));
-    else
+    else if (!fused)
       BSE_TRY(zero_fill(reinterpret_cast<double*>(P), 2L * c->nvh * nr, c->st));
     if (pdep) BSE_TRY(scatter_sets(m, c->wx_F, nv, 1, P, 1, c->st));
     BSE_TRY(fft3d(c->fft, P, c->nvh, +1, c->st));
