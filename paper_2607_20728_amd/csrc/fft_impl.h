@@ -204,10 +204,13 @@ __device__ __forceinline__ void plane_store_w(const cplx* P, cplx* gp, const Pla
                                               long g, int i1, int np2, int nt) {
   const real* f = pa.mulf ? pa.mulf + (long)i1 * np2 : nullptr;
   for (int e = threadIdx.x; e < np2; e += nt) {
-    const real m = f ? f[e] * pa.muls : (real)0;
-    cplx x = P[e];
-    x.x *= m;
-    x.y *= m;
+    cplx x = mk(0.0, 0.0);  // no bare part: exact zeros, as a fill would leave
+    if (f) {
+      const real m = f[e] * pa.muls;
+      x = P[e];
+      x.x *= m;
+      x.y *= m;
+    }
     gp[e] = x;
   }
   if (pa.compact) {
