@@ -137,8 +137,9 @@ int fft3d_fwd_w(const FftPlan& p, const SpherePlan& sp, float2* data, long batch
                 float s, float2* compact, hipStream_t st);
 // The same transform with the pair grids formed inside its first pass from
 // the packed orbitals orb and the block list IJ (nblk blocks of 32 grids, the
-// tile layout of pair_density), when the axis-1 length has a direct-access
-// pass (fwd_pairs_supported; fails otherwise).
+// tile layout of pair_density).  It needs a direct-access pass for the
+// axis-1 length in that precision (fwd_pairs_supported(p, f32) tells; the
+// call fails otherwise).
 bool fwd_pairs_supported(const FftPlan& p, bool f32);
 int fft3d_fwd_pairs(const FftPlan& p, const SpherePlan& sp, const double2* orb, int nv,
                     const int2* IJ, long nblk, double2* data, const double* f, double s,
